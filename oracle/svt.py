@@ -24,7 +24,8 @@ import scipy.sparse.linalg as spla
 
 from .philox import omega_block
 
-DROP_TOL = 1e-10  # column kept only if its norm after projection exceeds DROP_TOL * norm before
+DROP_TOL = 1e-10  # a projected column at most this fraction of its norm before lies in span(Q)
+DEP_TOL = 1e-6    # an R diagonal at most this fraction of the projected column norm means dependence
 
 
 # ----------------------------------------------------------------------------------------------
@@ -150,16 +151,17 @@ def _orthonormal_block(X, pre_norms):
     A column whose norm after projection is at most DROP_TOL times its norm
     before projection lies in span(Q) to working precision and is dropped.
     The kept columns go through numpy's Householder QR; a column whose R
-    diagonal falls below the same relative level is also dropped.
+    diagonal is at most DEP_TOL times its projected norm depends on the
+    columns before it and is also dropped.
     """
     post = np.linalg.norm(X, axis=0)
     keep = post > DROP_TOL * pre_norms
     X = X[:, keep]
-    pre = pre_norms[keep]
+    post = post[keep]
     if X.shape[1] == 0:
         return X
     Qb, R = np.linalg.qr(X)
-    ok = np.abs(np.diag(R)) > DROP_TOL * pre
+    ok = np.abs(np.diag(R)) > DEP_TOL * post
     if not ok.all():
         Qb, _ = np.linalg.qr(X[:, ok]) if ok.any() else (X[:, :0], None)
     return Qb
