@@ -1,0 +1,186 @@
+/*
+ * svt.h -- C-ABI of the MI355X (gfx950) implementation of fast singular value
+ * thresholding with recycling rank-revealing randomized SVD (R4SVD).
+ *
+ * Paper: Y. Li, W. Yu, "A Fast Implementation of Singular Value Thresholding
+ * Algorithm using Recycling Rank Revealing Randomized Singular Value
+ * Decomposition" (arXiv 1704.05528).
+ *
+ * Problem (Sec. 1, Eq. 1-3): complete an m x n matrix A from its entries on an
+ * observed set Lambda.  SVT iterates (Eq. 4)
+ *     X^(i)   = D_tau(Y^(i))                       (Eq. 5, soft-thresholded SVD)
+ *     Y^(i+1) = Y^(i) + delta * P_Lambda(A - X^(i))
+ * where Y lives on Lambda only and X is never formed densely.  D_tau(Y) is
+ * evaluated by R4SVD (Sec. 2.4, Alg. 3): the left singular vectors of the
+ * previous iteration are recycled as the starting basis Q, and Gaussian blocks
+ * of Delta-t columns orthogonal to Q are appended until the error percentage
+ * (||Y||_F^2 - ||Q^T Y||_F^2) / ||Y||_F^2 (Eq. 8, 10, 11) falls to
+ * eps_threshold.  The first iteration starts from a t-column block (R3SVD,
+ * Alg. 2).  eps_threshold is multiplied by beta whenever the residual fails to
+ * decrease (Sec. 2.5, Eq. 13-14, Alg. 4).
+ *
+ * Conventions
+ *  - All pointers in these calls are HOST pointers unless a parameter says
+ *    otherwise.  Inputs are copied; the library keeps no caller pointer.
+ *  - Index arrays are 0-based int32.  Lambda is given as COO (rows[p], cols[p]),
+ *    p = 0..nnz-1, in any order, without duplicates.  Vectors "on Lambda"
+ *    (values, y, x, residuals) are in that caller order.
+ *  - Dense matrices crossing the ABI are row-major float64.
+ *  - Every call returns an svt_status.  On error the outputs are unspecified,
+ *    svt_last_error() describes the failure, and the handle stays usable
+ *    unless the status is SVT_E_HIP.
+ *  - Non-convergence is not an error; it is reported in svt_step_stats.flags.
+ *  - A handle is bound to the device that was current at svt_init and to the
+ *    stream given there.  Calls on one handle must not overlap.
+ */
+#ifndef SVT_H
+#define SVT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svt_handle svt_handle;
+
+typedef enum {
+  SVT_OK = 0,
+  SVT_E_INVALID_ARG = -1, /* bad size, index out of range, duplicate entry, bad parameter */
+  SVT_E_OOM = -2,         /* device or host allocation failed */
+  SVT_E_HIP = -3,         /* a HIP runtime call failed; the handle must be destroyed */
+  SVT_E_NUMERIC = -4,     /* NaN/Inf in a reduction, or a non-positive ||Y||_F */
+  SVT_E_STATE = -5,       /* call not valid in the handle's current state */
+  SVT_E_LIMIT = -6        /* more singular values above tau than the tracked maximum (kmax) */
+} svt_status;
+
+/* Precision forms. */
+enum {
+  SVT_FP64 = 0,  /* every stored value and every accumulation in float64 */
+  SVT_MIXED = 1  /* y, a, W, factors float32; basis Q bfloat16; Gram/Cholesky/eig float64 */
+};
+
+/* Bits of svt_step_stats.flags. */
+enum {
+  SVT_F_CONVERGED = 1, /* relative residual fell below tol; Y was not updated */
+  SVT_F_MAXIT = 2,     /* svt_iterate reached maxit */
+  SVT_F_RMAX_HIT = 4,  /* growth stopped because the basis reached r_max */
+  SVT_F_EXHAUSTED = 8, /* a growth block had no direction outside span(Q) */
+  SVT_F_ANNEALED = 16, /* eps_threshold was multiplied by beta in this iteration */
+  SVT_F_EIG_INEXACT = 32 /* the top-eigenpair solver stopped at its iteration cap */
+};
+
+/* Inputs of Alg. 4 plus the values the paper leaves open.  Fill with
+ * svt_default_params() and override.  "<= 0 => default" fields take the
+ * paper's experimental settings of Sec. 3 where it gives them. */
+typedef struct {
+  double tau;      /* threshold parameter tau (> 0) */
+  double delta;    /* step size delta (> 0) */
+  double tol;      /* stop when ||P_Lambda(A - X)||_F / ||P_Lambda A||_F < tol */
+  double beta;     /* annealing factor, 0 < beta < 1 (Sec. 3: 0.95) */
+  double eta;      /* residual counts as decreasing only if rel < eps_min * (1 - eta); default 0 */
+  double eps_thr0; /* initial eps_threshold; < 0 => (1 + eps_1) / 2 with eps_1 from the first t-block */
+  int32_t maxit;   /* iteration cap for svt_iterate (default 500) */
+  int32_t t0;      /* first block width t; <= 0 => floor(0.05 min(m, n)), at least 1 */
+  int32_t dt;      /* growth block width Delta-t; <= 0 => 10 */
+  int32_t npow;    /* power iterations per sampled block, X <- Y (Y^T X) after re-orthonormalisation */
+  int32_t r_max;   /* basis width cap; <= 0 => m */
+  int32_t k0;      /* kicking count; < 0 => ceil(tau / (delta ||P_Lambda A||_2)) */
+  uint64_t seed;   /* key of the Philox4x64-10 Omega stream */
+  int32_t precision; /* SVT_FP64 or SVT_MIXED */
+  int32_t kmax;    /* most singular values above tau the eigensolver tracks; <= 0 => 64 (max 96) */
+} svt_params;
+
+/* Per-iteration report. */
+typedef struct {
+  int32_t iter;      /* SVT iteration number i (1-based) */
+  int32_t r;         /* basis width after R4SVD */
+  int32_t k;         /* number of singular values of B above tau */
+  int32_t blocks;    /* growth blocks appended in this iteration */
+  int32_t annealed;  /* 1 if eps_threshold was multiplied by beta */
+  int32_t stopped;   /* 1 if rel_res < tol (Y not updated) */
+  int32_t flags;     /* SVT_F_* bits */
+  int32_t eig_iters; /* subspace iterations spent by the top-eigenpair solver */
+  double eps;        /* error percentage when R4SVD returned */
+  double eps_thr;    /* eps_threshold R4SVD ran with */
+  double rel_res;    /* ||P_Lambda(A - X)||_F / ||P_Lambda A||_F */
+  double normY;      /* ||Y||_F^2 */
+  double normB;      /* ||Q^T Y||_F^2 */
+  double sigma1;     /* largest singular value of B */
+  double sigmak;     /* smallest singular value above tau (0 if k = 0) */
+  double grow_margin;   /* min over growth tests of |eps - eps_thr| / eps_thr */
+  double anneal_margin; /* (rel - eps_min (1 - eta)) / eps_min before the update */
+} svt_step_stats;
+
+/* Fill *p with defaults (tau and delta are set to 0 and must be given). */
+void svt_default_params(svt_params* p);
+
+/* Create a handle for the problem (Alg. 4 inputs).  Copies the COO triplets to
+ * the device, builds the column-major (CSC) and row-major (CSR) orders,
+ * computes ||P_Lambda A||_F and, when p->k0 < 0, ||P_Lambda A||_2 by power
+ * iteration, and sets Y^(0) = k0 * delta * P_Lambda(A) (kicking, Alg. 4
+ * initialisation).  stream: a hipStream_t, or NULL for the default stream.
+ * Errors: SVT_E_INVALID_ARG for m, n, nnz <= 0, indices out of range,
+ * duplicate (row, col), tau <= 0, delta <= 0, beta outside (0, 1), dt < 1,
+ * kmax > 96, non-finite values. */
+svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows,
+                    const int32_t* cols, const double* vals, const svt_params* p, void* stream);
+
+/* One R4SVD (Alg. 3; Alg. 2 when no basis exists yet) on the current iterate
+ * Y, followed by the thresholded factors of D_tau(Y) (Eq. 5).  The iteration
+ * state (Y, basis, thresholds, counters) is left unchanged; the factors can be
+ * read with svt_factors.  Uses the Omega blocks of the next iteration. */
+svt_status r4svd_step(svt_handle* h, svt_step_stats* st);
+
+/* Up to max_steps iterations of Alg. 4, stopping early at convergence or at
+ * maxit.  *last receives the report of the last iteration run (may be NULL).
+ * Returns SVT_E_STATE if the run had already converged. */
+svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last);
+
+/* Thresholded factors of the last X = U diag(s) V^T (s = sigma - tau > 0):
+ * k receives their count; U (m x kcap), V (n x kcap) row-major and s (kcap)
+ * receive min(k, kcap) columns.  Any output pointer may be NULL. */
+svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V);
+
+/* X of the last iteration sampled on nq arbitrary entries (qi[l], qj[l]). */
+svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out);
+
+/* Current state: y (nnz, caller order), basis Q (m x r row-major; pass
+ * qcap >= r columns, or NULL), r, eps_threshold (NaN before the first
+ * iteration), eps_min, iterations completed. */
+svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,
+                         double* eps_min, int32_t* iter);
+
+/* Replace the state (for step-by-step comparisons and restarts).  Q (m x r
+ * row-major, orthonormal columns) may be NULL with r = 0.  eps_thr NaN means
+ * "not yet fixed".  iter is the number of iterations already completed; the
+ * next iteration draws the Omega blocks of iteration iter + 1. */
+svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_t r, double eps_thr,
+                         double eps_min, int32_t iter);
+
+/* Force the two discrete decisions of the next len iterations: blocks[l]
+ * growth blocks and annealed[l] (0/1).  len = 0 clears the replay. */
+svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* annealed, int32_t len);
+
+/* Derivative of a held-out loss through T unrolled iterations of Alg. 4
+ * (frozen-basis convention: every discrete decision and every basis Q_i of
+ * the forward run is held fixed).  Runs T iterations from Y^(0), with Y
+ * checkpointed every ckpt iterations and recomputed during the reverse sweep,
+ * then back-propagates gx_h = dL/dX on the held-out set H (nh entries).
+ * Outputs: dtau, ddelta (scalars) and da (nnz, caller order) = dL/dA on
+ * Lambda.  The forward run restarts from the initial state; the handle's
+ * state afterwards is that after T iterations. */
+svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
+                    const double* gx_h, double* dtau, double* ddelta, double* da);
+
+/* Text of the last error on this handle (or of the last failed svt_init when h is NULL). */
+const char* svt_last_error(const svt_handle* h);
+
+/* Release every device and host buffer of the handle.  NULL is allowed. */
+void svt_destroy(svt_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVT_H */

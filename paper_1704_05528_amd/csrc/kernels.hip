@@ -1,0 +1,660 @@
+// Streaming kernels of the SVT / R4SVD hot path for gfx950 (wave64).
+//
+// Every reduction is deterministic: per-workgroup partial sums in a fixed
+// butterfly order, then one workgroup adds the partials in index order.
+// No floating-point atomics are used anywhere.
+#include "svt_internal.h"
+
+#include <algorithm>
+
+namespace svt {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum over a 256-thread workgroup; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += lds[i];
+  return t;
+}
+
+// ------------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: the Gaussian sampling matrix Omega of
+// Alg. 2 / Alg. 3.  Counter = (row j, 4-column group q, block, iteration), key = (seed, 0).
+// ------------------------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+__device__ inline double word_to_uniform(uint64_t w) {
+  return ((double)(w >> 11) + 0.5) * 0x1p-53;
+}
+
+__device__ inline void gaussian4(uint64_t j, uint64_t q, uint64_t blk, uint64_t it, uint64_t seed, double z[4]) {
+  uint64_t c[4] = {j, q, blk, it};
+  philox4x64_10(c, seed, 0ull);
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const double ur = word_to_uniform(c[2 * pr]), ua = word_to_uniform(c[2 * pr + 1]);
+    const double rad = sqrt(-2.0 * log(ur));
+    const double ang = 2.0 * M_PI * ua;
+    z[2 * pr] = rad * cos(ang);
+    z[2 * pr + 1] = rad * sin(ang);
+  }
+}
+
+// om[j, c] for rows j < n and block columns c0 <= c < c0 + w (c0 a multiple of 4), stored at om[j*ld + c - c0].
+__global__ void k_omega(double* __restrict__ om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
+                        uint64_t it) {
+  const int ng = (w + 3) / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * ng) return;
+  const int j = (int)(t / ng), g = (int)(t % ng);
+  double z[4];
+  gaussian4((uint64_t)j, (uint64_t)(c0 / 4 + g), blk, it, seed, z);
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+    if (4 * g + l < w) om[(int64_t)j * ld + 4 * g + l] = z[l];
+}
+
+// Gaussian fill of columns [c0, c1) of a rows x ld block, rows >= valid_rows set to zero (warm starts).
+__global__ void k_fill_random(double* __restrict__ V, int rows, int ld, int c0, int c1, uint64_t seed, uint64_t tag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = c1 - c0;
+  if (t >= (int64_t)rows * w) return;
+  const int i = (int)(t / w), c = c0 + (int)(t % w);
+  double z[4];
+  gaussian4((uint64_t)i, (uint64_t)c, tag, 0xFFFFFFFFull, seed, z);
+  V[(int64_t)i * ld + c] = z[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// Segment-gather SpMM: out[row, :] = sum_{p in seg(row)} val[vperm(p)] * D[idx[p], :].
+// With CSC segments (idx = row indices, D = Q) this is W = Y^T Q; with CSR segments
+// (idx = column indices, vperm = CSR->CSC map, D = Omega) it is X = Y Omega.
+// ------------------------------------------------------------------------------------------
+
+// Narrow blocks (w <= 16): lanes stride over the nonzeros, each keeps w partial sums.
+template <int WN>
+__global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ idx,
+                                                         const int32_t* __restrict__ vperm,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ D, int ldd,
+                                                         double* __restrict__ out, int ldo, int w) {
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (row >= nrows) return;
+  double acc[WN];
+#pragma unroll
+  for (int c = 0; c < WN; ++c) acc[c] = 0.0;
+  const int p0 = ptr[row], p1 = ptr[row + 1];
+  for (int p = p0 + lane; p < p1; p += kWave) {
+    const double v = val[vperm ? vperm[p] : p];
+    const double* d = D + (int64_t)idx[p] * ldd;
+#pragma unroll
+    for (int c = 0; c < WN; ++c)
+      if (c < w) acc[c] = fma(v, d[c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < WN; ++c) {
+    const double s = wave_sum(acc[c]);
+    if (lane == 0 && c < w) out[(int64_t)row * ldo + c] = s;
+  }
+}
+
+// Wide blocks: lanes over output columns (CPL per lane), nonzeros broadcast across the wave.
+template <int CPL>
+__global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ vperm,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ D, int ldd,
+                                                       double* __restrict__ out, int ldo, int w) {
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (row >= nrows) return;
+  const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
+  double acc[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+  const int p0 = ptr[row], p1 = ptr[row + 1];
+  for (int base = p0; base < p1; base += kWave) {
+    const int p = base + lane;
+    int my_i = 0;
+    double my_v = 0.0;
+    if (p < p1) {
+      my_i = idx[p];
+      my_v = val[vperm ? vperm[p] : p];
+    }
+    const int cnt = min(kWave, p1 - base);
+    for (int t = 0; t < cnt; ++t) {
+      const int ii = __shfl(my_i, t, kWave);
+      const double vv = __shfl(my_v, t, kWave);
+      const double* d = D + (int64_t)ii * ldd + c0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (c0 + c < w) acc[c] = fma(vv, d[c], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+    if (c0 + c < w) out[(int64_t)row * ldo + c0 + c] = acc[c];
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-wise small product: out[i, g0:g0+16] = beta * out + alpha * A[i, 0:K] M[0:K, g0:g0+16].
+// One wave per row, lanes stride over K.  Used for X -= Q (Q^T X), X R^-1, Q C, W D, G V.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const double* __restrict__ A, int lda,
+                                                const double* __restrict__ M, int ldm, double* __restrict__ out,
+                                                int ldo, int w, double alpha, double beta) {
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (row >= rows) return;
+  const int g0 = blockIdx.y * 16;
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  const double* a = A + (int64_t)row * lda;
+  for (int c = lane; c < K; c += kWave) {
+    const double av = a[c];
+    const double* mr = M + (int64_t)c * ldm + g0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (g0 + j < w) acc[j] = fma(av, mr[j], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double s = wave_sum(acc[j]);
+    if (lane == 0 && g0 + j < w) {
+      double* o = out + (int64_t)row * ldo + g0 + j;
+      *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Tall-skinny A^T B with a narrow B (nb columns in groups of 16), split over rows.
+// partial[s][a][b] = sum_{i in split s} A[i, a] B[i, b]; then k_tn_finish sums the splits.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tn_narrow(int rows, const double* __restrict__ A, int lda, int na,
+                                                   const double* __restrict__ B, int ldb, int nb,
+                                                   double* __restrict__ partial, int rows_per_split) {
+  __shared__ double red[4][16][kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int a = blockIdx.x * kWave + lane;
+  const int g0 = blockIdx.y * 16;
+  const int s = blockIdx.z;
+  const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  if (a < na) {
+    for (int i = i0 + wid; i < i1; i += 4) {
+      const double av = A[(int64_t)i * lda + a];
+      const double* br = B + (int64_t)i * ldb + g0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (g0 + j < nb) acc[j] = fma(av, br[j], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) red[wid][j][lane] = acc[j];
+  __syncthreads();
+  // 4 waves -> one value per (a, j): thread t handles j = t / 64 * 4 .. +3 for its lane
+  for (int e = threadIdx.x; e < 16 * kWave; e += blockDim.x) {
+    const int j = e / kWave, l = e % kWave;
+    const int aa = blockIdx.x * kWave + l;
+    if (aa < na && g0 + j < nb) {
+      const double v = ((red[0][j][l] + red[1][j][l]) + red[2][j][l]) + red[3][j][l];
+      partial[((int64_t)s * na + aa) * nb + g0 + j] = v;
+    }
+  }
+}
+
+__global__ void k_tn_finish(const double* __restrict__ partial, int splits, int na, int nb, double* __restrict__ out,
+                            int ldo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)na * nb) return;
+  const int a = (int)(t / nb), b = (int)(t % nb);
+  double v = 0.0;
+  for (int s = 0; s < splits; ++s) v += partial[((int64_t)s * na + a) * nb + b];
+  out[(int64_t)a * ldo + b] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Gram G = A^T A (na x na) for a tall A: 64 x 64 output tiles of the upper triangle,
+// 16-row LDS stages, 4 x 4 outputs per thread, split over rows; k_gram_finish mirrors.
+// ------------------------------------------------------------------------------------------
+constexpr int kGT = 64, kGK = 16;
+
+__global__ __launch_bounds__(256) void k_gram_tiles(int rows, const double* __restrict__ A, int lda, int na,
+                                                    double* __restrict__ partial, int rows_per_split,
+                                                    int ntile) {
+  __shared__ double sa[kGK][kGT + 1], sb[kGK][kGT + 1];
+  // map blockIdx.x to an upper-triangular tile pair (ti <= tj)
+  int t = blockIdx.x, ti = 0;
+  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  const int tj = ti + t;
+  const int s = blockIdx.y;
+  const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 16 x 16 threads, 4 x 4 outputs each
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  const int a0 = ti * kGT, b0 = tj * kGT;
+  for (int ib = i0; ib < i1; ib += kGK) {
+    for (int e = threadIdx.x; e < kGK * kGT; e += blockDim.x) {
+      const int rr = e / kGT, cc = e % kGT;
+      const int i = ib + rr;
+      sa[rr][cc] = (i < i1 && a0 + cc < na) ? A[(int64_t)i * lda + a0 + cc] : 0.0;
+      sb[rr][cc] = (i < i1 && b0 + cc < na) ? A[(int64_t)i * lda + b0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = sa[kk][ty * 4 + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sb[kk][tx * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* P = partial + (int64_t)s * na * na;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = a0 + ty * 4 + u, b = b0 + tx * 4 + v;
+      if (a < na && b < na) P[(int64_t)a * na + b] = acc[u][v];
+    }
+}
+
+__global__ void k_gram_finish(const double* __restrict__ partial, int splits, int na, double* __restrict__ G,
+                              int ldg) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)na * na) return;
+  const int a = (int)(t / na), b = (int)(t % na);
+  const int ta = a / kGT, tb = b / kGT;
+  // tiles below the diagonal were not computed: read the transposed element
+  const int64_t src = (ta <= tb) ? (int64_t)a * na + b : (int64_t)b * na + a;
+  double v = 0.0;
+  for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * na * na + src];
+  G[(int64_t)a * ldg + b] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Reductions
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sumsq_cols(int rows, const double* __restrict__ A, int lda, int c0, int w,
+                                                    double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double v = 0.0;
+  const int64_t total = (int64_t)rows * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / w), c = (int)(e % w);
+    const double x = A[(int64_t)i * lda + c0 + c];
+    v = fma(x, x, v);
+  }
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq(int64_t len, const double* __restrict__ x,
+                                               double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
+    v = fma(x[e], x[e], v);
+  const double s = block_sum(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// scal[slot + q] = sum_b partial[b * stride + q] for q < nq, summed in block order by one thread each
+__global__ void k_finish(const double* __restrict__ partial, int nblocks, int stride, int nq, double* scal, int slot) {
+  const int q = threadIdx.x;
+  if (q >= nq) return;
+  double v = 0.0;
+  for (int b = 0; b < nblocks; ++b) v += partial[(int64_t)b * stride + q];
+  scal[slot + q] = v;
+}
+
+__global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < w) out[c] = sqrt(fmax(G[(int64_t)c * ldg + c], 0.0));
+}
+
+// ------------------------------------------------------------------------------------------
+// Orthonormalising transform of a block (CholeskyQR with column dropping), one workgroup.
+// Input: the w x w Gram of the projected block and the column norms before projection.
+// A column c is dropped when its projected norm is at most drop_tol * prenorm[c] (it lies in
+// the span of the basis it was projected against; skipped when prenorm == nullptr), or when
+// its Cholesky pivot is at most dep_tol times its projected norm (it depends on the kept
+// columns before it; a Gram-based pivot cannot resolve dependence much below 1e-8).  The kept
+// columns are packed to the left: X_new = X Minv has wk orthonormal columns followed by
+// zero columns.  If wk_in >= 0 only the first wk_in columns take part (second pass of
+// CholeskyQR2 reads the count of the first pass from scal[wk_slot_in]).  scal[slot] = wk.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int w,
+                                                    const double* __restrict__ prenorm, double drop_tol,
+                                                    double dep_tol, double* __restrict__ Minv, int ldm,
+                                                    double* scal, int slot, int wk_slot_in) {
+  extern __shared__ double Rsm[];  // w x (w + 1) upper Cholesky factor
+  __shared__ int keep[kEigMax], pos[kEigMax];
+  __shared__ int wk_s;
+  const int tid = threadIdx.x;
+  int wa = w;
+  if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    Rsm[(i) * (w + 1) + (j)] = (i < wa && j < wa) ? gram[(int64_t)i * ldg + j] : 0.0;
+    Minv[(int64_t)i * ldm + j] = 0.0;
+  }
+  for (int c = tid; c < w; c += blockDim.x) {
+    const double lim = prenorm ? drop_tol * prenorm[c] : 0.0;
+    keep[c] = (c < wa) && (sqrt(fmax(gram[(int64_t)c * ldg + c], 0.0)) > lim) ? 1 : 0;
+  }
+  __syncthreads();
+  // upper Cholesky R^T R = G on the kept columns, in place in R (row c holds Rsm[(c) * (w + 1) + (c..)])
+  for (int c = 0; c < wa; ++c) {
+    if (keep[c]) {
+      if (tid == 0) {
+        double d = Rsm[(c) * (w + 1) + (c)];
+        for (int l = 0; l < c; ++l)
+          if (keep[l]) d -= Rsm[(l) * (w + 1) + (c)] * Rsm[(l) * (w + 1) + (c)];
+        const double lim2 = dep_tol * dep_tol * gram[(int64_t)c * ldg + c];
+        if (!(d > lim2) || !(d > 0.0)) {
+          keep[c] = 0;
+        } else {
+          Rsm[(c) * (w + 1) + (c)] = sqrt(d);
+        }
+      }
+      __syncthreads();
+      if (keep[c]) {
+        for (int j = c + 1 + tid; j < wa; j += blockDim.x) {
+          double v = Rsm[(c) * (w + 1) + (j)];
+          for (int l = 0; l < c; ++l)
+            if (keep[l]) v -= Rsm[(l) * (w + 1) + (c)] * Rsm[(l) * (w + 1) + (j)];
+          Rsm[(c) * (w + 1) + (j)] = v / Rsm[(c) * (w + 1) + (c)];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    int q = 0;
+    for (int c = 0; c < w; ++c) {
+      pos[c] = keep[c] ? q : -1;
+      q += keep[c];
+    }
+    wk_s = q;
+  }
+  __syncthreads();
+  // Minv[:, pos[jj]] = column jj of R_kept^{-1}, by back substitution (one thread per column).
+  // Row c of Minv multiplies column c of the input block; dropped rows and columns stay zero.
+  for (int jj = tid; jj < wa; jj += blockDim.x) {
+    if (!keep[jj]) continue;
+    double* zc = Minv + pos[jj];
+    for (int i = jj; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double v = (i == jj) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= jj; ++l)
+        if (keep[l]) v -= Rsm[(i) * (w + 1) + (l)] * zc[(int64_t)l * ldm];
+      zc[(int64_t)i * ldm] = v / Rsm[(i) * (w + 1) + (i)];
+    }
+  }
+  if (tid == 0) scal[slot] = (double)wk_s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused sampled product and dual update on Lambda (CSC order), Eq. 4 with X = Ut Vt^T:
+//   x = <Ut[i,:], Vt[j,:]>, res = a - x, y_next = y + delta res, sums of res^2 and y_next^2.
+// One wave per column j; Vt[j, :] staged in LDS.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __restrict__ colptr,
+                                                      const int32_t* __restrict__ rowidx,
+                                                      const double* __restrict__ a, const double* __restrict__ y,
+                                                      double* __restrict__ y_next, double* __restrict__ x_out,
+                                                      const double* __restrict__ Ut, const double* __restrict__ Vt,
+                                                      int ld, int k, double delta, double* __restrict__ partial) {
+  __shared__ double vs[4][kEigMax];
+  __shared__ double lds[4];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int j = blockIdx.x * 4 + wid;
+  double s_res = 0.0, s_y = 0.0;
+  if (j < n) {
+    for (int l = lane; l < k; l += kWave) vs[wid][l] = Vt[(int64_t)j * ld + l];
+  }
+  __syncthreads();
+  if (j < n) {
+    const int p0 = colptr[j], p1 = colptr[j + 1];
+    for (int p = p0 + lane; p < p1; p += kWave) {
+      const double* u = Ut + (int64_t)rowidx[p] * ld;
+      double x = 0.0;
+      for (int l = 0; l < k; ++l) x = fma(u[l], vs[wid][l], x);
+      const double res = a[p] - x;
+      const double yn = fma(delta, res, y[p]);
+      y_next[p] = yn;
+      if (x_out) x_out[p] = x;
+      s_res = fma(res, res, s_res);
+      s_y = fma(yn, yn, s_y);
+    }
+  }
+  const double t0 = block_sum(s_res, lds);
+  const double t1 = block_sum(s_y, lds);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = t0;
+    partial[2 * blockIdx.x + 1] = t1;
+  }
+}
+
+__global__ void k_sample(int64_t nq, const int32_t* __restrict__ qi, const int32_t* __restrict__ qj,
+                         const double* __restrict__ Ut, const double* __restrict__ Vt, int ld, int k,
+                         double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq) return;
+  const double* u = Ut + (int64_t)qi[t] * ld;
+  const double* v = Vt + (int64_t)qj[t] * ld;
+  double x = 0.0;
+  for (int l = 0; l < k; ++l) x = fma(u[l], v[l], x);
+  out[t] = x;
+}
+
+__global__ void k_scale_copy(int64_t len, const double* __restrict__ src, double alpha, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) dst[t] = alpha * src[t];
+}
+
+__global__ void k_copy_cols(int rows, const double* __restrict__ src, int lds_, double* __restrict__ dst, int ldd,
+                            int w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * w) return;
+  const int i = (int)(t / w), c = (int)(t % w);
+  dst[(int64_t)i * ldd + c] = src[(int64_t)i * lds_ + c];
+}
+
+inline unsigned grid1(int64_t work, int per = 256) { return (unsigned)((work + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+hipError_t launch_omega(hipStream_t s, double* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
+                        uint64_t it) {
+  const int64_t work = (int64_t)n * ((w + 3) / 4);
+  if (work == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_omega, dim3(grid1(work)), dim3(256), 0, s, om, n, c0, w, ld, seed, blk, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0, int c1, uint64_t seed,
+                              uint64_t tag) {
+  const int64_t work = (int64_t)rows * (c1 - c0);
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_random, dim3(grid1(work)), dim3(256), 0, s, V, rows, ld, c0, c1, seed, tag);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
+                           const double* val, const double* D, int ldd, double* out, int ldo, int w) {
+  if (nrows == 0 || w == 0) return hipSuccess;
+  const unsigned gx = (unsigned)((nrows + 3) / 4);
+  if (w <= kNarrow) {
+    hipLaunchKernelGGL(k_seg_spmm_narrow<kNarrow>, dim3(gx), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
+                       out, ldo, w);
+  } else {
+    constexpr int CPL = 4;
+    const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
+    hipLaunchKernelGGL(k_seg_spmm_wide<CPL>, dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
+                       out, ldo, w);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rowmul(hipStream_t s, int rows, int K, const double* A, int lda, const double* M, int ldm,
+                         double* out, int ldo, int w, double alpha, double beta) {
+  if (rows == 0 || w == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rowmul, dim3((rows + 3) / 4, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M, ldm, out,
+                     ldo, w, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_tn_narrow(hipStream_t s, int rows, const double* A, int lda, int na, const double* B, int ldb,
+                            int nb, double* out, int ldo, double* partial, int64_t partial_cap) {
+  if (na == 0 || nb == 0) return hipSuccess;
+  const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
+  int splits = std::max(1, std::min(rows / 512, 1024 / std::max(1, gx * gy)));
+  while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
+  splits = std::max(1, std::min(splits, std::max(1, rows)));
+  const int rps = (rows + splits - 1) / splits;
+  hipLaunchKernelGGL(k_tn_narrow, dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb, partial,
+                     std::max(rps, 1));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tn_finish, dim3(grid1((int64_t)na * nb)), dim3(256), 0, s, partial, splits, na, nb, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(hipStream_t s, int rows, const double* A, int lda, int na, double* G, int ldg,
+                       double* partial, int64_t partial_cap) {
+  if (na == 0) return hipSuccess;
+  const int nt = (na + kGT - 1) / kGT;
+  const int ntri = nt * (nt + 1) / 2;
+  int splits = std::max(1, std::min(512 / ntri, rows / 256));
+  while (splits > 1 && (int64_t)splits * na * na > partial_cap) --splits;
+  const int rps = (rows + splits - 1) / splits;
+  hipLaunchKernelGGL(k_gram_tiles, dim3(ntri, splits), dim3(256), 0, s, rows, A, lda, na, partial, std::max(rps, 1),
+                     nt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gram_finish, dim3(grid1((int64_t)na * na)), dim3(256), 0, s, partial, splits, na, G, ldg);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_cols(hipStream_t s, int rows, const double* A, int lda, int c0, int w, double* partial,
+                             double* scal, int slot) {
+  const int64_t total = (int64_t)rows * w;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (total + 255) / 256));
+  hipLaunchKernelGGL(k_sumsq_cols, dim3(nb), dim3(256), 0, s, rows, A, lda, c0, w, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 1, 1, scal, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(hipStream_t s, int64_t len, const double* v, double* partial, double* scal, int slot) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (len + 255) / 256));
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, s, len, v, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 1, 1, scal, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_colnorms(hipStream_t s, int rows, const double* A, int lda, int w, double* gram_scratch,
+                           double* partial, int64_t partial_cap, double* out) {
+  hipError_t e = launch_tn_narrow(s, rows, A, lda, w, A, lda, w, gram_scratch, w, partial, partial_cap);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_sqrt, dim3(1), dim3(128), 0, s, gram_scratch, w, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
+                             double drop_tol, double dep_tol, double* Minv, int ldm, double* scal, int slot,
+                             int wk_slot_in) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_block_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kEigMax * (kEigMax + 1) * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const size_t lds = (size_t)w * (w + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Minv, ldm, scal, slot,
+                     wk_slot_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* a,
+                               const double* y, double* y_next, double* x_out, const double* Ut, const double* Vt,
+                               int ld, int k, double delta, double* partial, double* scal, int slot) {
+  const int nb = (n + 3) / 4;
+  hipLaunchKernelGGL(k_sddmm_update, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, x_out, Ut, Vt, ld,
+                     k, delta, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 2, 2, scal, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const double* Ut,
+                         const double* Vt, int ld, int k, double* out) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample, dim3(grid1(nq)), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(hipStream_t s, int64_t len, const double* src, double alpha, double* dst) {
+  if (len == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid1(len)), dim3(256), 0, s, len, src, alpha, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(hipStream_t s, int rows, const double* src, int lds_, double* dst, int ldd, int w) {
+  const int64_t work = (int64_t)rows * w;
+  if (work == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_cols, dim3(grid1(work)), dim3(256), 0, s, rows, src, lds_, dst, ldd, w);
+  return hipGetLastError();
+}
+
+}  // namespace svt

@@ -1,0 +1,757 @@
+// Host control of the SVT / R4SVD hot path and the C-ABI of libsvt.
+//
+// The device kernels live in kernels.hip and eig.hip.  This file owns the handle,
+// the order in which the kernels run (Alg. 2-4 of Li & Yu), and the discrete
+// decisions the paper takes on scalars: the rank-revealing test eps > eps_threshold
+// (Alg. 3), the annealing test on the residual (Eq. 13-14) and the stop test (Alg. 4).
+// Each decision reads back a few float64 scalars produced by deterministic device
+// reductions.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "svt_internal.h"
+
+struct svt_handle : svt::Handle {};
+
+using namespace svt;
+
+namespace {
+
+thread_local std::string g_init_err;
+
+constexpr double kDropTol = 1e-10;   // a projected column this small relative to its norm before lies in span(Q)
+constexpr double kDepTol = 1e-6;     // a Cholesky pivot this small relative to the column norm means dependence
+constexpr double kEigTol = 1e-13;    // Ritz residual relative to the largest Ritz value
+constexpr int kEigIters = 300;       // cap on subspace iterations per SVT iteration
+
+// scalar slots of the device readback buffer
+enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_RES2 = 4, S_YN2 = 5, S_SWEEPS = 6, S_NORMY = 7,
+       S_A = 8, S_B = 9 };
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      h->err = std::string(#expr) + " failed: " + hipGetErrorString(e_);             \
+      return SVT_E_HIP;                                                              \
+    }                                                                                \
+  } while (0)
+
+#define CHK(expr)                         \
+  do {                                    \
+    svt_status st_ = (expr);              \
+    if (st_ != SVT_OK) return st_;        \
+  } while (0)
+
+svt_status fail(Handle* h, svt_status st, const std::string& msg) {
+  h->err = msg;
+  return st;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+svt_status readback(Handle* h, int count) {
+  HIPCHK(hipMemcpyAsync(h->hscal, h->scal, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SVT_OK;
+}
+
+svt_status to_host(Handle* h, double* dst, const double* src, size_t count) {
+  HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SVT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Block orthonormalisation (CholeskyQR2 with the column-drop rule) of X (m x wc, ld w_cap).
+// prenorm == nullptr: no drop rule (re-orthonormalisation inside power iterations).
+// The orthonormal columns are packed to the left of X; scal[S_WK2] holds their count.
+// ------------------------------------------------------------------------------------------
+svt_status orthonormalize_block(Handle* h, int rows, double* X, double* X2, int ld, int wc, const double* prenorm) {
+  hipStream_t s = h->stream;
+  HIPCHK(launch_tn_narrow(s, rows, X, ld, wc, X, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
+  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1,
+                           -1));
+  HIPCHK(launch_rowmul(s, rows, wc, X, ld, h->Minv, kEigMax, X2, ld, wc, 1.0, 0.0));
+  HIPCHK(launch_tn_narrow(s, rows, X2, ld, wc, X2, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
+  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2,
+                           S_WK1));
+  HIPCHK(launch_rowmul(s, rows, wc, X2, ld, h->Minv, kEigMax, X, ld, wc, 1.0, 0.0));
+  return SVT_OK;
+}
+
+// X = Y Om (CSR order, values through the CSR->CSC map)
+svt_status spmm_y(Handle* h, const double* Om, int ldo_in, double* X, int ldx, int w) {
+  HIPCHK(launch_seg_spmm(h->stream, (int)h->m, h->rowptr, h->colidx, h->csr2csc, h->y, Om, ldo_in, X, ldx, w));
+  return SVT_OK;
+}
+
+// out = Y^T D (CSC order)
+svt_status spmm_yt(Handle* h, const double* D, int ldd, double* out, int ldo, int w) {
+  HIPCHK(launch_seg_spmm(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, h->y, D, ldd, out, ldo, w));
+  return SVT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Append one sampled block of width w (Alg. 2 initial block when blk == 0, Alg. 3 growth
+// block otherwise): Omega from Philox, X = Y Omega, power iterations, projection against the
+// current basis (twice), CholeskyQR2, Q <- [Q, Q'], W <- [W, Y^T Q'], normB += ||Y^T Q'||^2.
+// Blocks wider than 64 columns are processed in 64-column chunks, each chunk orthogonalised
+// against the basis including the previous chunks (the same span as one wide block).
+// ------------------------------------------------------------------------------------------
+svt_status append_block(Handle* h, int it, int blk, int w, int* got, double* add) {
+  hipStream_t s = h->stream;
+  const int m = (int)h->m, n = (int)h->n;
+  const int ld = h->w_cap;
+  *got = 0;
+  *add = 0.0;
+  for (int c0 = 0; c0 < w; c0 += 64) {
+    const int wc = std::min(64, w - c0);
+    const int rq = h->r + *got;
+    HIPCHK(launch_omega(s, h->Om, n, c0, wc, ld, h->p.seed, (uint64_t)blk, (uint64_t)it));
+    CHK(spmm_y(h, h->Om, ld, h->X, ld, wc));
+    for (int pi = 0; pi < h->p.npow; ++pi) {
+      CHK(orthonormalize_block(h, m, h->X, h->X2, ld, wc, nullptr));
+      CHK(spmm_yt(h, h->X, ld, h->Om, ld, wc));
+      CHK(spmm_y(h, h->Om, ld, h->X, ld, wc));
+    }
+    HIPCHK(launch_colnorms(s, m, h->X, ld, wc, h->small, h->partial, h->partial_cap, h->prenorm));
+    if (rq > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        HIPCHK(launch_tn_narrow(s, m, h->Q, h->r_cap, rq, h->X, ld, wc, h->T, ld, h->partial, h->partial_cap));
+        HIPCHK(launch_rowmul(s, m, rq, h->Q, h->r_cap, h->T, ld, h->X, ld, wc, -1.0, 1.0));
+      }
+    }
+    CHK(orthonormalize_block(h, m, h->X, h->X2, ld, wc, h->prenorm));
+    HIPCHK(launch_copy_cols(s, m, h->X, ld, h->Q + rq, h->r_cap, wc));
+    CHK(spmm_yt(h, h->Q + rq, h->r_cap, h->W + rq, h->r_cap, wc));
+    HIPCHK(launch_sumsq_cols(s, n, h->W, h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
+    CHK(readback(h, S_NADD + 1));
+    const int kept = (int)h->hscal[S_WK2];
+    *got += kept;
+    *add += h->hscal[S_NADD];
+  }
+  return SVT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// R4SVD (Alg. 3; Alg. 2 for the first call): leaves Q[:, 0:r], W = Y^T Q, and st->eps.
+// ------------------------------------------------------------------------------------------
+svt_status r4svd_core(Handle* h, int it, int replay_blocks, svt_step_stats* st) {
+  double normB = 0.0;
+  if (h->r == 0) {
+    int got = 0;
+    double add = 0.0;
+    CHK(append_block(h, it, 0, h->p.t0, &got, &add));
+    if (got == 0) return fail(h, SVT_E_NUMERIC, "the first sampled block has no nonzero direction (Y = 0?)");
+    h->r = got;
+    normB = add;
+  } else {
+    CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
+    HIPCHK(launch_sumsq_cols(h->stream, (int)h->n, h->W, h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+    CHK(readback(h, S_NORMB + 1));
+    normB = h->hscal[S_NORMB];
+  }
+  const double normY = h->normY;
+  double eps = (normY - normB) / normY;
+  if (!std::isfinite(eps)) return fail(h, SVT_E_NUMERIC, "non-finite error percentage");
+  if (!h->eps_thr_set) {
+    h->eps_thr = h->p.eps_thr0 >= 0.0 ? h->p.eps_thr0 : 0.5 * (1.0 + eps);
+    h->eps_thr_set = true;
+  }
+  st->eps_thr = h->eps_thr;
+  st->grow_margin = std::numeric_limits<double>::infinity();
+  int blk = 0;
+  for (;;) {
+    const int room = std::min(h->p.dt, h->p.r_max - h->r);
+    bool grow;
+    if (replay_blocks >= 0) {
+      grow = blk < replay_blocks;
+    } else {
+      grow = eps > h->eps_thr;
+      if (h->eps_thr > 0.0) st->grow_margin = std::min(st->grow_margin, std::fabs(eps - h->eps_thr) / h->eps_thr);
+    }
+    if (!grow) break;
+    if (room <= 0) {
+      st->flags |= SVT_F_RMAX_HIT;
+      break;
+    }
+    ++blk;
+    int got = 0;
+    double add = 0.0;
+    CHK(append_block(h, it, blk, room, &got, &add));
+    if (got == 0) {
+      st->flags |= SVT_F_EXHAUSTED;
+      break;
+    }
+    h->r += got;
+    normB += add;
+    eps = (normY - normB) / normY;
+  }
+  st->blocks = blk;
+  st->eps = eps;
+  st->normY = normY;
+  st->normB = normB;
+  st->r = h->r;
+  return SVT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// svd(B) through eig(W^T W): eigenpairs with sigma > tau, factor matrices Ut = Q C, Vt = W D.
+// ------------------------------------------------------------------------------------------
+svt_status projected_svd(Handle* h, svt_step_stats* st) {
+  hipStream_t s = h->stream;
+  const int r = h->r;
+  const double tau2 = h->p.tau * h->p.tau;
+  HIPCHK(launch_gram(s, (int)h->n, h->W, h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
+  std::vector<double> theta(kEigMax), res(kEigMax);
+  const double* S = nullptr;
+  int k = 0;
+  st->eig_iters = 0;
+  if (r <= kEigMax) {
+    HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+    CHK(to_host(h, theta.data(), h->Eval, r));
+    while (k < r && theta[k] > tau2) ++k;
+    S = h->ES;
+    // keep the leading eigenvectors as the warm start of the block solver
+    const int keep = std::min(r, h->b_cap);
+    HIPCHK(launch_copy_cols(s, r, h->ES, kEigMax, h->EV, kEigMax, keep));
+    h->ev_valid = keep;
+    h->ev_rows = r;
+    st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
+  } else {
+    // warm-started block subspace iteration with Rayleigh-Ritz
+    int b = std::min(h->b_cap, std::max(32, ((2 * h->k + 16 + 15) / 16) * 16));
+    int valid = (h->ev_valid > 0 && h->ev_rows <= r) ? std::min(h->ev_valid, b) : 0;
+    if (valid > 0 && h->ev_rows < r) {
+      // new basis columns were appended: zero the new rows of the kept vectors
+      HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
+                              valid * sizeof(double), r - h->ev_rows, s));
+    }
+    HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+    CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
+    bool done = false;
+    int iters = 0;
+    while (!done) {
+      if (iters >= kEigIters) {
+        st->flags |= SVT_F_EIG_INEXACT;
+        break;
+      }
+      ++iters;
+      // power step: V <- orth(G V)
+      HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
+      CHK(orthonormalize_block(h, r, h->EZ, h->EZ2, kEigMax, b, nullptr));
+      // Rayleigh-Ritz on span(V): H = V^T G V, H = S Theta S^T, V <- V S, Z <- Z S
+      HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EZ, kEigMax, h->EZ2, kEigMax, b, 1.0, 0.0));
+      HIPCHK(launch_tn_narrow(s, r, h->EZ, kEigMax, b, h->EZ2, kEigMax, b, h->EH, kEigMax, h->partial, h->partial_cap));
+      HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+      HIPCHK(launch_rowmul(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EV, kEigMax, b, 1.0, 0.0));   // V = V S
+      HIPCHK(launch_rowmul(s, r, b, h->EZ2, kEigMax, h->ES, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));  // Z = G V
+      HIPCHK(launch_ritz_residual(s, r, h->EZ, h->EV, kEigMax, b, h->Eval, h->partial, h->EZ3));
+      CHK(to_host(h, theta.data(), h->Eval, b));
+      CHK(to_host(h, res.data(), h->EZ3, b));
+      k = 0;
+      while (k < b && theta[k] > tau2) ++k;
+      if (k >= b - 4) {
+        if (b >= h->b_cap) {
+          if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks (kmax)");
+        } else {
+          const int nb = std::min(h->b_cap, b + 32);
+          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)iters));
+          b = nb;
+          CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
+          continue;
+        }
+      }
+      const double lim = kEigTol * std::max(theta[0], 0.0);
+      done = true;
+      for (int c = 0; c < std::min(b, k + 1); ++c) {
+        const double tolc = (c < k) ? lim : 1e3 * lim;
+        if (!(res[c] <= tolc)) {
+          done = false;
+          break;
+        }
+      }
+    }
+    st->eig_iters = iters;
+    S = h->EV;
+    h->ev_valid = b;
+    h->ev_rows = r;
+    st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
+  }
+  if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
+  h->k = k;
+  h->sigma_k.assign(theta.begin(), theta.begin() + k);
+  for (auto& v : h->sigma_k) v = std::sqrt(v);
+  st->k = k;
+  st->sigmak = k > 0 ? h->sigma_k[k - 1] : 0.0;
+  if (k > 0) {
+    HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
+    HIPCHK(launch_copy_cols(s, r, S, kEigMax, h->Sk, kEigMax, k));
+    HIPCHK(launch_rowmul(s, (int)h->m, r, h->Q, h->r_cap, h->C, kEigMax, h->Ut, kEigMax, k, 1.0, 0.0));
+    HIPCHK(launch_rowmul(s, (int)h->n, r, h->W, h->r_cap, h->D, kEigMax, h->Vt, kEigMax, k, 1.0, 0.0));
+  }
+  h->have_factors = true;
+  return SVT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// One iteration of Alg. 4 (reading: X^(i) on Lambda, residual, annealing, stop, update).
+// ------------------------------------------------------------------------------------------
+svt_status do_iteration(Handle* h, svt_step_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  const int it = h->iter + 1;
+  st->iter = it;
+  int rb = -1, ra = -1;
+  if (h->replay_pos < h->replay_blocks.size()) {
+    rb = h->replay_blocks[h->replay_pos];
+    ra = h->replay_anneal[h->replay_pos];
+    ++h->replay_pos;
+  }
+  CHK(r4svd_core(h, it, rb, st));
+  CHK(projected_svd(h, st));
+  HIPCHK(launch_sddmm_update(h->stream, (int)h->n, h->colptr, h->rowidx, h->a, h->y, h->y_next, nullptr, h->Ut, h->Vt,
+                             kEigMax, h->k, h->p.delta, h->partial, h->scal, S_RES2));
+  CHK(readback(h, S_YN2 + 1));
+  const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
+  const double rel = std::sqrt(res2) / h->norm_a;
+  if (!std::isfinite(rel) || !std::isfinite(yn2)) return fail(h, SVT_E_NUMERIC, "non-finite residual");
+  st->rel_res = rel;
+  const double target = h->eps_min * (1.0 - h->p.eta);
+  st->anneal_margin = std::isfinite(h->eps_min) ? (rel - target) / h->eps_min : -std::numeric_limits<double>::infinity();
+  const bool annealed = (ra >= 0) ? (ra != 0) : !(rel < target);
+  if (annealed) {
+    h->eps_thr *= h->p.beta;
+    st->flags |= SVT_F_ANNEALED;
+  } else {
+    h->eps_min = rel;
+  }
+  st->annealed = annealed ? 1 : 0;
+  h->iter = it;
+  if (rel < h->p.tol) {
+    st->stopped = 1;
+    st->flags |= SVT_F_CONVERGED;
+    h->converged = true;
+    return SVT_OK;
+  }
+  std::swap(h->y, h->y_next);
+  h->normY = yn2;
+  return SVT_OK;
+}
+
+void release(Handle* h) {
+  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->a, h->y, h->y_next, h->x, h->Q, h->W,
+                  h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2, h->EZ3,
+                  h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->C, h->D, h->Sk, h->Utmp, h->partial, h->scal};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (h->hscal) (void)hipHostFree(h->hscal);
+}
+
+}  // namespace
+
+// ==============================================================================================
+// C-ABI
+// ==============================================================================================
+extern "C" {
+
+void svt_default_params(svt_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-4;
+  p->beta = 0.95;
+  p->eta = 0.0;
+  p->eps_thr0 = -1.0;
+  p->maxit = 500;
+  p->t0 = 0;
+  p->dt = 10;
+  p->npow = 0;
+  p->r_max = 0;
+  p->k0 = -1;
+  p->seed = 0;
+  p->precision = SVT_FP64;
+  p->kmax = 0;
+}
+
+const char* svt_last_error(const svt_handle* h) { return h ? h->err.c_str() : g_init_err.c_str(); }
+
+void svt_destroy(svt_handle* h) {
+  if (!h) return;
+  release(h);
+  delete h;
+}
+
+svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows, const int32_t* cols,
+                    const double* vals, const svt_params* pin, void* stream) {
+  if (!out) {
+    g_init_err = "out is NULL";
+    return SVT_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  auto bad = [&](const std::string& msg) {
+    g_init_err = msg;
+    return SVT_E_INVALID_ARG;
+  };
+  if (!rows || !cols || !vals || !pin) return bad("NULL input pointer");
+  if (m <= 0 || n <= 0 || nnz <= 0) return bad("m, n and nnz must be positive");
+  if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31)) return bad("m, n, nnz must be below 2^31");
+  if (nnz > m * n) return bad("nnz exceeds m * n");
+  svt_params p = *pin;
+  if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return bad("tau must be positive and finite");
+  if (!(p.delta > 0.0) || !std::isfinite(p.delta)) return bad("delta must be positive and finite");
+  if (!(p.beta > 0.0 && p.beta < 1.0)) return bad("beta must lie in (0, 1)");
+  if (!(p.tol >= 0.0)) return bad("tol must be non-negative");
+  if (!(p.eta >= 0.0 && p.eta < 1.0)) return bad("eta must lie in [0, 1)");
+  if (p.dt <= 0) p.dt = 10;
+  if (p.maxit <= 0) p.maxit = 500;
+  if (p.npow < 0) return bad("npow must be non-negative");
+  if (p.kmax <= 0) p.kmax = 64;
+  if (p.kmax > kEigMax) return bad("kmax must not exceed 96");
+  if (p.precision != SVT_FP64) return bad("precision form not available");
+  const int64_t mn = std::min(m, n);
+  if (p.t0 <= 0) p.t0 = (int32_t)std::max<int64_t>(1, (int64_t)std::floor(0.05 * (double)mn));
+  p.r_max = (p.r_max <= 0) ? (int32_t)m : (int32_t)std::min<int64_t>(p.r_max, m);
+  p.t0 = std::min(p.t0, p.r_max);
+
+  // host-side validation and orders
+  std::vector<int64_t> key(nnz), order(nnz);
+  for (int64_t q = 0; q < nnz; ++q) {
+    if (rows[q] < 0 || rows[q] >= m || cols[q] < 0 || cols[q] >= n) return bad("index out of range");
+    if (!std::isfinite(vals[q])) return bad("non-finite observed value");
+    key[q] = (int64_t)cols[q] * m + rows[q];
+  }
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+  for (int64_t q = 1; q < nnz; ++q)
+    if (key[order[q]] == key[order[q - 1]]) return bad("duplicate (row, col) entry");
+
+  auto* h = new svt_handle();
+  h->m = m;
+  h->n = n;
+  h->nnz = nnz;
+  h->p = p;
+  h->stream = (hipStream_t)stream;
+  (void)hipGetDevice(&h->device);
+  h->user2csc.resize(nnz);
+  std::vector<int32_t> colptr(n + 1, 0), rowidx(nnz), rowptr(m + 1, 0), colidx(nnz), csr2csc(nnz);
+  std::vector<double> a_csc(nnz);
+  for (int64_t q = 0; q < nnz; ++q) {
+    const int64_t u = order[q];
+    h->user2csc[u] = q;
+    rowidx[q] = rows[u];
+    a_csc[q] = vals[u];
+    colptr[cols[u] + 1]++;
+  }
+  for (int64_t j = 0; j < n; ++j) colptr[j + 1] += colptr[j];
+  for (int64_t q = 0; q < nnz; ++q) key[q] = (int64_t)rows[q] * n + cols[q];
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+  for (int64_t q = 0; q < nnz; ++q) {
+    const int64_t u = order[q];
+    colidx[q] = cols[u];
+    csr2csc[q] = (int32_t)h->user2csc[u];
+    rowptr[rows[u] + 1]++;
+  }
+  for (int64_t i = 0; i < m; ++i) rowptr[i + 1] += rowptr[i];
+
+  h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
+  h->w_cap = 64;
+  h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
+  h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
+  h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
+
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  A(dalloc(&h->colptr, n + 1));
+  A(dalloc(&h->rowidx, nnz));
+  A(dalloc(&h->rowptr, m + 1));
+  A(dalloc(&h->colidx, nnz));
+  A(dalloc(&h->csr2csc, nnz));
+  A(dalloc(&h->a, nnz));
+  A(dalloc(&h->y, nnz));
+  A(dalloc(&h->y_next, nnz));
+  A(dalloc(&h->x, nnz));
+  A(dalloc(&h->Q, (size_t)m * h->r_cap));
+  A(dalloc(&h->W, (size_t)n * h->r_cap));
+  A(dalloc(&h->X, (size_t)m * h->w_cap));
+  A(dalloc(&h->X2, (size_t)m * h->w_cap));
+  A(dalloc(&h->Om, (size_t)std::max(m, n) * h->w_cap));
+  A(dalloc(&h->T, (size_t)h->r_cap * h->w_cap));
+  A(dalloc(&h->G, (size_t)h->r_cap * h->r_cap));
+  A(dalloc(&h->small, (size_t)kEigMax * kEigMax));
+  A(dalloc(&h->Minv, (size_t)kEigMax * kEigMax));
+  A(dalloc(&h->prenorm, kEigMax));
+  A(dalloc(&h->EV, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EZ, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EZ2, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EZ3, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EH, (size_t)kEigMax * kEigMax));
+  A(dalloc(&h->ES, (size_t)kEigMax * kEigMax));
+  A(dalloc(&h->Eval, kEigMax));
+  A(dalloc(&h->Ut, (size_t)m * kEigMax));
+  A(dalloc(&h->Vt, (size_t)n * kEigMax));
+  A(dalloc(&h->Utmp, (size_t)std::max(m, n) * kEigMax));
+  A(dalloc(&h->C, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->D, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->Sk, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->partial, (size_t)h->partial_cap));
+  A(dalloc(&h->scal, kScalars));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
+    svt_destroy(h);
+    return (e == hipErrorOutOfMemory) ? SVT_E_OOM : SVT_E_HIP;
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
+  };
+  up(h->colptr, colptr.data(), (n + 1) * sizeof(int32_t));
+  up(h->rowidx, rowidx.data(), nnz * sizeof(int32_t));
+  up(h->rowptr, rowptr.data(), (m + 1) * sizeof(int32_t));
+  up(h->colidx, colidx.data(), nnz * sizeof(int32_t));
+  up(h->csr2csc, csr2csc.data(), nnz * sizeof(int32_t));
+  up(h->a, a_csc.data(), nnz * sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * sizeof(double), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    g_init_err = std::string("upload failed: ") + hipGetErrorString(e);
+    svt_destroy(h);
+    return SVT_E_HIP;
+  }
+
+  // ||P_Lambda A||_F and the kicking count (Alg. 4 initialisation)
+  svt_status st = SVT_OK;
+  auto finish_fail = [&](svt_status s2) {
+    g_init_err = h->err;
+    svt_destroy(h);
+    return s2;
+  };
+  if ((e = launch_sumsq(h->stream, nnz, h->a, h->partial, h->scal, S_A)) != hipSuccess) {
+    h->err = hipGetErrorString(e);
+    return finish_fail(SVT_E_HIP);
+  }
+  if ((st = readback(h, S_A + 1)) != SVT_OK) return finish_fail(st);
+  h->norm_a = std::sqrt(h->hscal[S_A]);
+  if (!(h->norm_a > 0.0)) {
+    h->err = "P_Lambda(A) is zero";
+    return finish_fail(SVT_E_NUMERIC);
+  }
+  if (p.k0 < 0) {
+    // ||P_Lambda A||_2 by power iteration on (P_Lambda A)^T (P_Lambda A)
+    double* v = h->Utmp;  // n-vector (Utmp holds max(m, n) * kEigMax doubles)
+    double* u = h->X2;    // m-vector (X2 holds m * w_cap doubles)
+    if ((e = launch_fill_random(h->stream, h->Om, (int)n, 1, 0, 1, p.seed ^ 0x3C3C3C3Cull, 7)) != hipSuccess ||
+        (e = launch_scale_copy(h->stream, n, h->Om, 1.0, v)) != hipSuccess) {
+      h->err = hipGetErrorString(e);
+      return finish_fail(SVT_E_HIP);
+    }
+    double sig_prev = 0.0, sig = 0.0, vnorm2 = 0.0;
+    if ((e = launch_sumsq(h->stream, n, v, h->partial, h->scal, S_B)) != hipSuccess) {
+      h->err = hipGetErrorString(e);
+      return finish_fail(SVT_E_HIP);
+    }
+    if ((st = readback(h, S_B + 1)) != SVT_OK) return finish_fail(st);
+    vnorm2 = h->hscal[S_B];
+    if ((e = launch_scale_copy(h->stream, n, v, 1.0 / std::sqrt(vnorm2), v)) != hipSuccess) {
+      h->err = hipGetErrorString(e);
+      return finish_fail(SVT_E_HIP);
+    }
+    for (int itp = 0; itp < 5000; ++itp) {
+      e = launch_seg_spmm(h->stream, (int)m, h->rowptr, h->colidx, h->csr2csc, h->a, v, 1, u, 1, 1);
+      if (e == hipSuccess) e = launch_seg_spmm(h->stream, (int)n, h->colptr, h->rowidx, nullptr, h->a, u, 1, v, 1, 1);
+      if (e == hipSuccess) e = launch_sumsq(h->stream, m, u, h->partial, h->scal, S_A);
+      if (e == hipSuccess) e = launch_sumsq(h->stream, n, v, h->partial + 2048, h->scal, S_B);
+      if (e != hipSuccess) {
+        h->err = hipGetErrorString(e);
+        return finish_fail(SVT_E_HIP);
+      }
+      if ((st = readback(h, S_B + 1)) != SVT_OK) return finish_fail(st);
+      sig = std::sqrt(h->hscal[S_A]);          // ||A v|| with ||v|| = 1
+      const double nv = std::sqrt(h->hscal[S_B]);
+      if (!(nv > 0.0)) break;
+      if ((e = launch_scale_copy(h->stream, n, v, 1.0 / nv, v)) != hipSuccess) {
+        h->err = hipGetErrorString(e);
+        return finish_fail(SVT_E_HIP);
+      }
+      if (itp > 3 && std::fabs(sig - sig_prev) <= 1e-15 * sig) break;
+      sig_prev = sig;
+    }
+    h->k0 = (int32_t)std::ceil(p.tau / (p.delta * sig));
+  } else {
+    h->k0 = p.k0;
+  }
+  if ((e = launch_scale_copy(h->stream, nnz, h->a, (double)h->k0 * p.delta, h->y)) != hipSuccess ||
+      (e = launch_sumsq(h->stream, nnz, h->y, h->partial, h->scal, S_NORMY)) != hipSuccess) {
+    h->err = hipGetErrorString(e);
+    return finish_fail(SVT_E_HIP);
+  }
+  if ((st = readback(h, S_NORMY + 1)) != SVT_OK) return finish_fail(st);
+  h->normY = h->hscal[S_NORMY];
+  h->r = 0;
+  h->iter = 0;
+  h->eps_thr_set = false;
+  h->eps_min = std::numeric_limits<double>::infinity();
+  *out = h;
+  return SVT_OK;
+}
+
+svt_status r4svd_step(svt_handle* h, svt_step_stats* st) {
+  if (!h) return SVT_E_INVALID_ARG;
+  svt_step_stats local;
+  if (!st) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  const int r_save = h->r;
+  const bool thr_set = h->eps_thr_set;
+  const double thr = h->eps_thr;
+  st->iter = h->iter + 1;
+  svt_status s1 = r4svd_core(h, h->iter + 1, -1, st);
+  if (s1 == SVT_OK) s1 = projected_svd(h, st);
+  h->r = r_save;
+  h->eps_thr_set = thr_set;
+  h->eps_thr = thr;
+  if (h->ev_rows > h->r) h->ev_valid = 0;
+  return s1;
+}
+
+svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (max_steps < 0) return fail(h, SVT_E_INVALID_ARG, "max_steps must be non-negative");
+  if (h->converged) return fail(h, SVT_E_STATE, "the iteration has already converged");
+  svt_step_stats st;
+  std::memset(&st, 0, sizeof(st));
+  for (int s = 0; s < max_steps; ++s) {
+    if (h->iter >= h->p.maxit) {
+      st.flags |= SVT_F_MAXIT;
+      break;
+    }
+    CHK(do_iteration(h, &st));
+    if (h->iter >= h->p.maxit && !st.stopped) st.flags |= SVT_F_MAXIT;
+    if (st.stopped) break;
+  }
+  if (last) *last = st;
+  return SVT_OK;
+}
+
+svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
+  if (k) *k = h->k;
+  const int kk = std::min<int>(std::max(kcap, 0), h->k);
+  if (kk == 0) return SVT_OK;
+  if (s)
+    for (int c = 0; c < kk; ++c) s[c] = h->sigma_k[c] - h->p.tau;
+  std::vector<double> buf;
+  if (U) {
+    HIPCHK(launch_rowmul(h->stream, (int)h->m, h->r, h->Q, h->r_cap, h->Sk, kEigMax, h->Utmp, kEigMax, kk, 1.0, 0.0));
+    buf.resize((size_t)h->m * kEigMax);
+    CHK(to_host(h, buf.data(), h->Utmp, buf.size()));
+    for (int64_t i = 0; i < h->m; ++i)
+      for (int c = 0; c < kk; ++c) U[i * kcap + c] = buf[i * kEigMax + c];
+  }
+  if (V) {
+    buf.resize((size_t)h->n * kEigMax);
+    CHK(to_host(h, buf.data(), h->Vt, buf.size()));
+    for (int64_t j = 0; j < h->n; ++j)
+      for (int c = 0; c < kk; ++c) V[j * kcap + c] = buf[j * kEigMax + c];
+  }
+  return SVT_OK;
+}
+
+svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (nq < 0 || (nq > 0 && (!qi || !qj || !x_out))) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
+  if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
+  for (int64_t l = 0; l < nq; ++l)
+    if (qi[l] < 0 || qi[l] >= h->m || qj[l] < 0 || qj[l] >= h->n) return fail(h, SVT_E_INVALID_ARG, "query out of range");
+  if (nq == 0) return SVT_OK;
+  int32_t *di = nullptr, *dj = nullptr;
+  double* dx = nullptr;
+  HIPCHK(dalloc(&di, nq));
+  HIPCHK(dalloc(&dj, nq));
+  HIPCHK(dalloc(&dx, nq));
+  hipError_t e = hipMemcpyAsync(di, qi, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dj, qj, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_sample(h->stream, nq, di, dj, h->Ut, h->Vt, kEigMax, h->k, dx);
+  if (e == hipSuccess) e = hipMemcpyAsync(x_out, dx, nq * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(di);
+  (void)hipFree(dj);
+  (void)hipFree(dx);
+  HIPCHK(e);
+  return SVT_OK;
+}
+
+svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,
+                         double* eps_min, int32_t* iter) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (y) {
+    std::vector<double> buf(h->nnz);
+    CHK(to_host(h, buf.data(), h->y, h->nnz));
+    for (int64_t u = 0; u < h->nnz; ++u) y[u] = buf[h->user2csc[u]];
+  }
+  if (Q && h->r > 0) {
+    if (qcap < h->r) return fail(h, SVT_E_INVALID_ARG, "qcap smaller than r");
+    HIPCHK(hipMemcpy2DAsync(Q, qcap * sizeof(double), h->Q, h->r_cap * sizeof(double), h->r * sizeof(double), h->m,
+                            hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (r) *r = h->r;
+  if (eps_thr) *eps_thr = h->eps_thr_set ? h->eps_thr : std::numeric_limits<double>::quiet_NaN();
+  if (eps_min) *eps_min = h->eps_min;
+  if (iter) *iter = h->iter;
+  return SVT_OK;
+}
+
+svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_t r, double eps_thr,
+                         double eps_min, int32_t iter) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (!y) return fail(h, SVT_E_INVALID_ARG, "y is NULL");
+  if (r < 0 || r > h->p.r_max || (r > 0 && !Q)) return fail(h, SVT_E_INVALID_ARG, "bad basis width");
+  if (iter < 0) return fail(h, SVT_E_INVALID_ARG, "iter must be non-negative");
+  std::vector<double> buf(h->nnz);
+  for (int64_t u = 0; u < h->nnz; ++u) buf[h->user2csc[u]] = y[u];
+  HIPCHK(hipMemcpyAsync(h->y, buf.data(), h->nnz * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (r > 0)
+    HIPCHK(hipMemcpy2DAsync(h->Q, h->r_cap * sizeof(double), Q, r * sizeof(double), r * sizeof(double), h->m,
+                            hipMemcpyHostToDevice, h->stream));
+  HIPCHK(launch_sumsq(h->stream, h->nnz, h->y, h->partial, h->scal, S_NORMY));
+  CHK(readback(h, S_NORMY + 1));
+  h->normY = h->hscal[S_NORMY];
+  h->r = r;
+  h->eps_thr_set = !std::isnan(eps_thr);
+  h->eps_thr = h->eps_thr_set ? eps_thr : 0.0;
+  h->eps_min = eps_min;
+  h->iter = iter;
+  h->converged = false;
+  h->have_factors = false;
+  h->ev_valid = 0;
+  h->ev_rows = 0;
+  h->k = 0;
+  return SVT_OK;
+}
+
+svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* annealed, int32_t len) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (len < 0 || (len > 0 && (!blocks || !annealed))) return fail(h, SVT_E_INVALID_ARG, "bad replay arrays");
+  h->replay_blocks.assign(blocks, blocks + len);
+  h->replay_anneal.assign(annealed, annealed + len);
+  h->replay_pos = 0;
+  return SVT_OK;
+}
+
+svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
+                    const double* gx_h, double* dtau, double* ddelta, double* da) {
+  (void)T; (void)ckpt; (void)nh; (void)hi; (void)hj; (void)gx_h; (void)dtau; (void)ddelta; (void)da;
+  if (!h) return SVT_E_INVALID_ARG;
+  return fail(h, SVT_E_STATE, "svt_grad is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad arguments on the host (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1704_05528_amd as svt
+from paper_1704_05528_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svt.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("svt_", "r4svd_"))))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ["svt_init", "r4svd_step", "svt_iterate", "svt_grad"]:
+        assert required in names
+    assert sorted(_capi.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    L = svt.load()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+        assert C.cast(getattr(L, name), C.c_void_p).value
+
+
+def test_struct_layouts_match_header():
+    # svt_params: 6 doubles, 6 int32, uint64, 2 int32 (+ tail padding)
+    assert C.sizeof(_capi.Params) == 6 * 8 + 6 * 4 + 8 + 2 * 4
+    assert C.sizeof(_capi.StepStats) == 8 * 4 + 9 * 8
+
+
+def test_default_params():
+    p = svt.default_params()
+    assert p.tol == 1e-4 and p.beta == 0.95 and p.dt == 10 and p.maxit == 500
+    assert p.k0 == -1 and p.eps_thr0 < 0 and p.precision == svt.SVT_FP64 and p.t0 == 0
+
+
+def _init(m, n, rows, cols, vals, **kw):
+    params = svt.default_params(**kw)
+    h = C.c_void_p()
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    L = svt.load()
+    st = L.svt_init(C.byref(h), m, n, r.size, r.ctypes.data_as(C.POINTER(C.c_int32)),
+                    c.ctypes.data_as(C.POINTER(C.c_int32)), v.ctypes.data_as(C.POINTER(C.c_double)),
+                    C.byref(params), None)
+    return st, h, L.svt_last_error(None).decode()
+
+
+GOOD = dict(tau=1.0, delta=1.0)
+
+
+@pytest.mark.parametrize("case,args,kw", [
+    ("m zero", (0, 3, [0], [0], [1.0]), GOOD),
+    ("row out of range", (3, 3, [0, 3], [0, 1], [1.0, 2.0]), GOOD),
+    ("negative col", (3, 3, [0, 1], [0, -1], [1.0, 2.0]), GOOD),
+    ("duplicate", (3, 3, [1, 1], [2, 2], [1.0, 2.0]), GOOD),
+    ("nan value", (3, 3, [0, 1], [0, 1], [1.0, float("nan")]), GOOD),
+    ("tau", (3, 3, [0], [0], [1.0]), dict(tau=0.0, delta=1.0)),
+    ("delta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=-2.0)),
+    ("beta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, beta=1.0)),
+    ("kmax", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, kmax=97)),
+    ("npow", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, npow=-1)),
+])
+def test_init_rejects_bad_arguments_on_host(case, args, kw):
+    st, h, msg = _init(*args, **kw)
+    assert st == svt.SVTError(-1, "").status == _capi.SVT_E_INVALID_ARG, case
+    assert not h.value
+    assert msg
+
+
+def test_null_handles_are_rejected():
+    L = svt.load()
+    assert L.svt_iterate(None, 1, None) == _capi.SVT_E_INVALID_ARG
+    assert L.r4svd_step(None, None) == _capi.SVT_E_INVALID_ARG
+    assert L.svt_grad(None, 1, 1, 0, None, None, None, None, None, None) == _capi.SVT_E_INVALID_ARG
+    L.svt_destroy(None)

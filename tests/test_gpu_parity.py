@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the same seeded inputs.
+
+Bar (FP64 form): every real-valued result within 1e-10 relative (max-abs error over
+max-abs value); integers (r, k, growth blocks, decisions) exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import svt_workloads as W
+from oracle import Params, Problem, State, initial_state, svt_run, svt_step
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    if a.size == 0 and b.size == 0:
+        return 0.0
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _problem(w):
+    return Problem(w.m, w.n, w.rows, w.cols, w.a)
+
+
+def _gpu(svt, w, k0, **kw):
+    return svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, **kw)
+
+
+def _compare_step(st, info, h, w, ctx):
+    assert st.r == info.r, (ctx, "r", st.r, info.r)
+    assert st.k == info.k, (ctx, "k", st.k, info.k)
+    assert st.blocks == info.blocks, (ctx, "blocks", st.blocks, info.blocks)
+    assert bool(st.annealed) == bool(info.annealed), (ctx, "annealed")
+    assert bool(st.stopped) == bool(info.stopped), (ctx, "stopped")
+    assert abs(st.eps - info.eps) <= TOL, (ctx, "eps", st.eps, info.eps)
+    assert abs(st.rel_res - info.rel) <= TOL * info.rel, (ctx, "rel", st.rel_res, info.rel)
+    x = h.sample(w.rows, w.cols)
+    assert rel_err(x, info.x) <= TOL, (ctx, "x", rel_err(x, info.x))
+    if info.k > 0:
+        assert rel_err(st.sigma1, info.sigma[0]) <= TOL, (ctx, "sigma1")
+        assert rel_err(st.sigmak, info.sigma[info.k - 1]) <= TOL, (ctx, "sigmak")
+
+
+SHAPES = [
+    # (m, n, rank, frac, seed, extra params)
+    (90, 70, 3, 0.40, 31, {}),
+    (70, 90, 3, 0.40, 32, {}),
+    (130, 110, 4, 0.35, 33, {"dt": 7}),          # ragged sizes, basis grows past one eigen block
+    (64, 64, 2, 0.5, 34, {"t0": 5, "npow": 1}),   # power iterations
+    (150, 40, 3, 0.6, 35, {"eps_thr0": 0.3}),     # tall, explicit threshold
+]
+
+
+@pytest.mark.parametrize("m,n,rank,frac,seed,extra", SHAPES)
+def test_free_run_with_replayed_decisions(gpu_lib, m, n, rank, frac, seed, extra):
+    """Both sides run 25 iterations; the GPU replays the oracle's two discrete decisions so that
+    rounding-level ties cannot split the trajectories; all results agree to 1e-10."""
+    w = W.tiny_dense(m, n, rank, frac, seed=seed)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=seed, maxit=25, **extra)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=seed, maxit=25, **extra)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        st = h.iterate(1)
+        _compare_step(st, info, h, w, (m, n, info.it))
+    s = h.get_state()
+    assert s["iter"] == infos[-1].it
+
+
+def test_free_run_decisions_agree(gpu_lib):
+    """Without replay the device takes the same discrete decisions while margins are clear."""
+    w = W.tiny_dense(100, 80, 3, 0.4, seed=41)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=3, maxit=40)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=3, maxit=40)
+    for info in infos:
+        margins = [abs(g) for g in info.grow_margins] + [abs(info.anneal_margin)]
+        st = h.iterate(1)
+        if min(margins) < 1e-9:
+            pytest.skip(f"near-tie decision at iteration {info.it}: replay test covers it")
+        _compare_step(st, info, h, w, info.it)
+
+
+def test_step_parity_from_oracle_state(gpu_lib):
+    """Load the oracle's state after 15 iterations, run one step on both sides."""
+    w = W.tiny_dense(120, 100, 4, 0.4, seed=42)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=8, maxit=40)
+    state, k0 = initial_state(prob, p)
+    for _ in range(15):
+        state, _ = svt_step(prob, p, state)
+    h = _gpu(gpu_lib, w, k0, seed=8)
+    h.set_state(state.y, state.Q, state.eps_thr, state.eps_min, state.it)
+    nxt, info = svt_step(prob, p, state)
+    st = h.iterate(1)
+    _compare_step(st, info, h, w, "step")
+    s = h.get_state()
+    assert rel_err(s["y"], nxt.y) <= TOL
+    # the device keeps an unrotated basis: compare projectors
+    Pg = s["Q"] @ s["Q"].T
+    Po = nxt.Q @ nxt.Q.T
+    assert np.abs(Pg - Po).max() <= 1e-10
+
+
+def test_state_roundtrip_and_orthonormal_basis(gpu_lib):
+    w = W.tiny_dense(80, 60, 3, 0.5, seed=43)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=4)
+    _, k0 = initial_state(prob, p)
+    h = _gpu(gpu_lib, w, k0, seed=4)
+    h.iterate(8)
+    s = h.get_state()
+    Q = s["Q"]
+    assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-13
+    h2 = _gpu(gpu_lib, w, k0, seed=4)
+    h2.set_state(s["y"], Q, s["eps_thr"], s["eps_min"], s["iter"])
+    s2 = h2.get_state()
+    np.testing.assert_array_equal(s2["y"], s["y"])
+    np.testing.assert_array_equal(s2["Q"], Q)
+    a = h.iterate(1)
+    b = h2.iterate(1)
+    assert a.r == b.r and a.k == b.k and a.rel_res == b.rel_res
+
+
+def test_factors_are_thresholded_svd(gpu_lib):
+    """svt_factors returns orthonormal U, V and s = sigma - tau > 0 with X = U diag(s) V^T (Eq. 5)."""
+    w = W.tiny_dense(90, 75, 3, 0.45, seed=44)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=6)
+    state, k0 = initial_state(prob, p)
+    for _ in range(10):
+        state, info = svt_step(prob, p, state)
+    h = _gpu(gpu_lib, w, k0, seed=6)
+    h.iterate(10)
+    k, s, U, V = h.factors()
+    assert k == info.k and k > 0
+    assert (s > 0).all()
+    np.testing.assert_allclose(s, info.s_minus_tau, rtol=TOL)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
+    X = (U * s) @ V.T
+    Xo = (info.U * info.s_minus_tau) @ info.V.T
+    assert rel_err(X, Xo) <= TOL
+    qi, qj = np.divmod(np.arange(w.m * w.n), w.n)
+    assert rel_err(h.sample(qi, qj), X.ravel()) <= 1e-12
+
+
+def test_r4svd_step_leaves_state_unchanged(gpu_lib):
+    w = W.tiny_dense(70, 70, 3, 0.4, seed=45)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=2)
+    _, k0 = initial_state(prob, p)
+    h = _gpu(gpu_lib, w, k0, seed=2)
+    h.iterate(5)
+    before = h.get_state()
+    st = h.r4svd_step()
+    after = h.get_state()
+    np.testing.assert_array_equal(before["y"], after["y"])
+    assert before["r"] == after["r"] and before["iter"] == after["iter"]
+    nxt = h.iterate(1)
+    assert nxt.r == st.r and nxt.k == st.k
+
+
+def test_run_twice_bitwise_identical(gpu_lib):
+    """Deterministic reductions: two handles on the same input give bit-identical trajectories."""
+    w = W.tiny_dense(110, 90, 3, 0.4, seed=46)
+    _, k0 = initial_state(_problem(w), Params(tau=w.tau, delta=w.delta))
+    outs = []
+    for _ in range(2):
+        h = _gpu(gpu_lib, w, k0, seed=9)
+        st = h.iterate(20)
+        outs.append((st.rel_res, st.r, h.get_state()["y"]))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
+def test_rmax_and_range_exhaustion_flags(gpu_lib):
+    import paper_1704_05528_amd as svt
+    w = W.tiny_dense(60, 50, 3, 0.5, seed=47)
+    _, k0 = initial_state(_problem(w), Params(tau=w.tau, delta=w.delta))
+    h = _gpu(gpu_lib, w, k0, seed=1, r_max=12, t0=4, dt=5, eps_thr0=0.0)
+    st = h.iterate(1)
+    assert st.r == 12 and (st.flags & svt.SVT_F_RMAX_HIT)
+    # rank-2 data fully observed: growth runs out of directions
+    rng = np.random.default_rng(0)
+    A = np.outer(rng.standard_normal(20), rng.standard_normal(15)) + np.outer(rng.standard_normal(20), rng.standard_normal(15))
+    qi, qj = np.divmod(np.arange(300), 15)
+    h2 = svt.svt_init(20, 15, qi, qj, A.ravel(), tau=1e-3, delta=1.0, k0=1, t0=1, dt=3, eps_thr0=0.0, seed=2)
+    st2 = h2.iterate(1)
+    assert st2.r == 2 or (st2.flags & svt.SVT_F_EXHAUSTED)
+
+
+def test_empty_rows_and_columns(gpu_lib):
+    """Rows and columns without observations (and a single-entry column) follow the oracle."""
+    w = W.tiny_dense(80, 70, 3, 0.4, seed=48)
+    keep = (w.rows % 7 != 3) & (w.cols % 9 != 4)
+    keep |= (w.cols == 4) & (w.rows == w.rows[w.cols == 4].min())
+    w.rows, w.cols, w.a = w.rows[keep], w.cols[keep], w.a[keep]
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=5, maxit=12)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=5, maxit=12)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        _compare_step(h.iterate(1), info, h, w, info.it)
+
+
+def test_kicking_count_matches_spectral_norm(gpu_lib):
+    """The device computes ||P_Lambda A||_2 by power iteration; the kicked Y^(0) matches the oracle's."""
+    w = W.tiny_dense(100, 90, 3, 0.3, seed=49)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta)
+    state, k0 = initial_state(prob, p)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta)
+    np.testing.assert_allclose(h.get_state()["y"], state.y, rtol=1e-14)
+
+
+def test_planted_1000_first_iterations(gpu_lib):
+    """The 1000 x 1000 rank-10 problem at 20% sampling: first 6 iterations against the oracle."""
+    w = W.planted()
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=11, maxit=6)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=11, maxit=6)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        _compare_step(h.iterate(1), info, h, w, info.it)
+
+
+def test_image_workload_wide_basis_step(gpu_lib):
+    """Image workload (1024^2, 50% observed) from a state with a 300-column basis: one step on both
+    sides exercises the warm-started block eigensolver at full size."""
+    w = W.image()
+    prob = _problem(w)
+    rng = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(rng.standard_normal((w.m, 300)))
+    y = 3.0 * w.delta * w.a + 0.05 * rng.standard_normal(w.nnz)
+    st0 = State(it=7, y=y, Q=Q, eps_thr=0.2, eps_min=0.05)
+    p = Params(tau=w.tau, delta=w.delta, seed=12)
+    _, info = svt_step(prob, p, st0)
+    h = _gpu(gpu_lib, w, 2, seed=12)
+    h.set_state(y, Q, 0.2, 0.05, 7)
+    st = h.iterate(1)
+    _compare_step(st, info, h, w, "image")
