@@ -173,6 +173,27 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
                     const double* gx_h, double* dtau, double* ddelta, double* da);
 
+/* Instrumentation.  Phases of one iteration whose device time can be measured with hipEvents
+ * recorded on the handle's stream around the launches of that phase. */
+enum {
+  SVT_PH_SPMM_T = 0,  /* W = Y^T Q on the recycled basis (one sparse-times-dense kernel) */
+  SVT_PH_GROW = 1,    /* growth blocks: Omega, Y Omega, projections, CholeskyQR2, Y^T Q' */
+  SVT_PH_GRAM = 2,    /* G = W^T W */
+  SVT_PH_EIG = 3,     /* eigenpairs of G above tau^2 (Jacobi / block subspace iteration) */
+  SVT_PH_FACTORS = 4, /* Ut = Q C, Vt = W D */
+  SVT_PH_SDDMM = 5,   /* fused sampled product, residual and dual update (one kernel) */
+  SVT_PH_REDUCE = 6,  /* norms and their deterministic final sums */
+  SVT_PH_COUNT = 7
+};
+
+/* enable = 1 resets the counters and starts recording; enable = 0 stops.  Recording adds two
+ * hipEventRecord calls per measured launch. */
+svt_status svt_profile(svt_handle* h, int32_t enable);
+
+/* Per phase (arrays of SVT_PH_COUNT entries, any may be NULL): device milliseconds, algorithmic
+ * bytes moved (each operand counted once per launch), algorithmic flops, number of launches. */
+svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* flops, int64_t* launches);
+
 /* Text of the last error on this handle (or of the last failed svt_init when h is NULL). */
 const char* svt_last_error(const svt_handle* h);
 

@@ -627,13 +627,17 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
 
 hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* a,
                                const double* y, double* y_next, double* x_out, const double* Ut, const double* Vt,
-                               int ld, int k, double delta, double* partial, double* scal, int slot) {
+                               int ld, int k, double delta, double* partial, int* nblocks) {
   const int nb = (n + 3) / 4;
+  *nblocks = nb;
   hipLaunchKernelGGL(k_sddmm_update, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, x_out, Ut, Vt, ld,
                      k, delta, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 2, 2, scal, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal,
+                         int slot) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nblocks, stride, nq, scal, slot);
   return hipGetLastError();
 }
 

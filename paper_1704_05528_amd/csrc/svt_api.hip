@@ -56,15 +56,62 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
 }
 
+// ------------------------------------------------------------------------------------------
+// Instrumentation: an event pair around the launches of one phase, resolved after a sync.
+// ------------------------------------------------------------------------------------------
+hipEvent_t pool_event(Handle* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseTimer {
+  Handle* h;
+  int ph;
+  hipEvent_t e0 = nullptr;
+  PhaseTimer(Handle* hh, int phase, double bytes = 0.0, double flops = 0.0) : h(hh), ph(phase) {
+    if (!h->prof) return;
+    e0 = pool_event(h);
+    if (e0) (void)hipEventRecord(e0, h->stream);
+    h->ph_bytes[ph] += bytes;
+    h->ph_flops[ph] += flops;
+    h->ph_launch[ph] += 1;
+  }
+  ~PhaseTimer() {
+    if (!h->prof || !e0) return;
+    hipEvent_t e1 = pool_event(h);
+    if (!e1) return;
+    (void)hipEventRecord(e1, h->stream);
+    h->pending.push_back({ph, e0, e1});
+  }
+};
+
+void resolve_pending(Handle* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) h->ph_ms[p.ph] += ms;
+    h->event_pool.push_back(p.e0);
+    h->event_pool.push_back(p.e1);
+  }
+  h->pending.clear();
+}
+
 svt_status readback(Handle* h, int count) {
   HIPCHK(hipMemcpyAsync(h->hscal, h->scal, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  resolve_pending(h);
   return SVT_OK;
 }
 
 svt_status to_host(Handle* h, double* dst, const double* src, size_t count) {
   HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  resolve_pending(h);
   return SVT_OK;
 }
 
@@ -114,6 +161,8 @@ svt_status append_block(Handle* h, int it, int blk, int w, int* got, double* add
   for (int c0 = 0; c0 < w; c0 += 64) {
     const int wc = std::min(64, w - c0);
     const int rq = h->r + *got;
+    {
+    PhaseTimer tm(h, SVT_PH_GROW);
     HIPCHK(launch_omega(s, h->Om, n, c0, wc, ld, h->p.seed, (uint64_t)blk, (uint64_t)it));
     CHK(spmm_y(h, h->Om, ld, h->X, ld, wc));
     for (int pi = 0; pi < h->p.npow; ++pi) {
@@ -132,6 +181,7 @@ svt_status append_block(Handle* h, int it, int blk, int w, int* got, double* add
     HIPCHK(launch_copy_cols(s, m, h->X, ld, h->Q + rq, h->r_cap, wc));
     CHK(spmm_yt(h, h->Q + rq, h->r_cap, h->W + rq, h->r_cap, wc));
     HIPCHK(launch_sumsq_cols(s, n, h->W, h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
+    }
     CHK(readback(h, S_NADD + 1));
     const int kept = (int)h->hscal[S_WK2];
     *got += kept;
@@ -153,8 +203,15 @@ svt_status r4svd_core(Handle* h, int it, int replay_blocks, svt_step_stats* st) 
     h->r = got;
     normB = add;
   } else {
-    CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
-    HIPCHK(launch_sumsq_cols(h->stream, (int)h->n, h->W, h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+    {
+      const double r = h->r, nnz = (double)h->nnz;
+      PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * 12.0 + 4.0 * (h->n + 1) + 8.0 * r * (double)(h->m + h->n), 2.0 * nnz * r);
+      CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
+    }
+    {
+      PhaseTimer tm(h, SVT_PH_REDUCE);
+      HIPCHK(launch_sumsq_cols(h->stream, (int)h->n, h->W, h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+    }
     CHK(readback(h, S_NORMB + 1));
     normB = h->hscal[S_NORMB];
   }
@@ -209,13 +266,19 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
   hipStream_t s = h->stream;
   const int r = h->r;
   const double tau2 = h->p.tau * h->p.tau;
-  HIPCHK(launch_gram(s, (int)h->n, h->W, h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
+  {
+    PhaseTimer tm(h, SVT_PH_GRAM, 8.0 * (double)h->n * r + 8.0 * (double)r * r, (double)h->n * r * (r + 1.0));
+    HIPCHK(launch_gram(s, (int)h->n, h->W, h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
+  }
   std::vector<double> theta(kEigMax), res(kEigMax);
   const double* S = nullptr;
   int k = 0;
   st->eig_iters = 0;
   if (r <= kEigMax) {
-    HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+    {
+      PhaseTimer tm(h, SVT_PH_EIG);
+      HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+    }
     CHK(to_host(h, theta.data(), h->Eval, r));
     while (k < r && theta[k] > tau2) ++k;
     S = h->ES;
@@ -234,8 +297,11 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
       HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
                               valid * sizeof(double), r - h->ev_rows, s));
     }
-    HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
-    CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
+    {
+      PhaseTimer tm(h, SVT_PH_EIG);
+      HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+      CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
+    }
     bool done = false;
     int iters = 0;
     while (!done) {
@@ -244,6 +310,8 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
         break;
       }
       ++iters;
+      {
+      PhaseTimer tm(h, SVT_PH_EIG);
       // power step: V <- orth(G V)
       HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
       CHK(orthonormalize_block(h, r, h->EZ, h->EZ2, kEigMax, b, nullptr));
@@ -254,6 +322,7 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
       HIPCHK(launch_rowmul(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EV, kEigMax, b, 1.0, 0.0));   // V = V S
       HIPCHK(launch_rowmul(s, r, b, h->EZ2, kEigMax, h->ES, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));  // Z = G V
       HIPCHK(launch_ritz_residual(s, r, h->EZ, h->EV, kEigMax, b, h->Eval, h->partial, h->EZ3));
+      }
       CHK(to_host(h, theta.data(), h->Eval, b));
       CHK(to_host(h, res.data(), h->EZ3, b));
       k = 0;
@@ -292,6 +361,8 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
   st->k = k;
   st->sigmak = k > 0 ? h->sigma_k[k - 1] : 0.0;
   if (k > 0) {
+    PhaseTimer tm(h, SVT_PH_FACTORS, 8.0 * (double)(h->m + h->n) * (r + k) + 16.0 * r * k,
+                  2.0 * (double)(h->m + h->n) * r * k);
     HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
     HIPCHK(launch_copy_cols(s, r, S, kEigMax, h->Sk, kEigMax, k));
     HIPCHK(launch_rowmul(s, (int)h->m, r, h->Q, h->r_cap, h->C, kEigMax, h->Ut, kEigMax, k, 1.0, 0.0));
@@ -316,8 +387,18 @@ svt_status do_iteration(Handle* h, svt_step_stats* st) {
   }
   CHK(r4svd_core(h, it, rb, st));
   CHK(projected_svd(h, st));
-  HIPCHK(launch_sddmm_update(h->stream, (int)h->n, h->colptr, h->rowidx, h->a, h->y, h->y_next, nullptr, h->Ut, h->Vt,
-                             kEigMax, h->k, h->p.delta, h->partial, h->scal, S_RES2));
+  int nbl = 0;
+  {
+    const double nnz = (double)h->nnz, k = h->k;
+    PhaseTimer tm(h, SVT_PH_SDDMM, nnz * 28.0 + 4.0 * (h->n + 1) + 8.0 * k * (double)(h->m + h->n),
+                  nnz * (2.0 * k + 3.0));
+    HIPCHK(launch_sddmm_update(h->stream, (int)h->n, h->colptr, h->rowidx, h->a, h->y, h->y_next, nullptr, h->Ut,
+                               h->Vt, kEigMax, h->k, h->p.delta, h->partial, &nbl));
+  }
+  {
+    PhaseTimer tm(h, SVT_PH_REDUCE);
+    HIPCHK(launch_finish(h->stream, h->partial, nbl, 2, 2, h->scal, S_RES2));
+  }
   CHK(readback(h, S_YN2 + 1));
   const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
   const double rel = std::sqrt(res2) / h->norm_a;
@@ -352,6 +433,11 @@ void release(Handle* h) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
+  for (auto& p : h->pending) {
+    h->event_pool.push_back(p.e0);
+    h->event_pool.push_back(p.e1);
+  }
+  for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
 }
 
 }  // namespace
@@ -744,6 +830,33 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
   h->replay_blocks.assign(blocks, blocks + len);
   h->replay_anneal.assign(annealed, annealed + len);
   h->replay_pos = 0;
+  return SVT_OK;
+}
+
+svt_status svt_profile(svt_handle* h, int32_t enable) {
+  if (!h) return SVT_E_INVALID_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  resolve_pending(h);
+  if (enable) {
+    for (int i = 0; i < SVT_PH_COUNT; ++i) {
+      h->ph_ms[i] = h->ph_bytes[i] = h->ph_flops[i] = 0.0;
+      h->ph_launch[i] = 0;
+    }
+  }
+  h->prof = enable != 0;
+  return SVT_OK;
+}
+
+svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* flops, int64_t* launches) {
+  if (!h) return SVT_E_INVALID_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  resolve_pending(h);
+  for (int i = 0; i < SVT_PH_COUNT; ++i) {
+    if (ms) ms[i] = h->ph_ms[i];
+    if (bytes) bytes[i] = h->ph_bytes[i];
+    if (flops) flops[i] = h->ph_flops[i];
+    if (launches) launches[i] = h->ph_launch[i];
+  }
   return SVT_OK;
 }
 

@@ -84,6 +84,19 @@ struct Handle {
   std::vector<int32_t> replay_blocks, replay_anneal;
   size_t replay_pos = 0;
 
+  // instrumentation: hipEvent pairs per phase, resolved at the next host synchronisation
+  struct Pending {
+    int ph;
+    hipEvent_t e0, e1;
+  };
+  bool prof = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  double ph_ms[SVT_PH_COUNT] = {};
+  double ph_bytes[SVT_PH_COUNT] = {};
+  double ph_flops[SVT_PH_COUNT] = {};
+  int64_t ph_launch[SVT_PH_COUNT] = {};
+
   std::string err;
 };
 
@@ -124,10 +137,13 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
                              double drop_tol, double dep_tol, double* Minv, int ldm, double* scal, int slot,
                              int wk_slot_in);
 
-// sampled product on Lambda (CSC order) with residual, dual update and norms
+// sampled product on Lambda (CSC order) with residual and dual update; per-block partial sums of
+// res^2 and y_next^2 land in partial[2 b], partial[2 b + 1]; returns the number of blocks
 hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* a,
                                const double* y, double* y_next, double* x_out, const double* Ut, const double* Vt,
-                               int ld, int k, double delta, double* partial, double* scal, int slot);
+                               int ld, int k, double delta, double* partial, int* nblocks);
+// scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
+hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
 // X on arbitrary entries
 hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const double* Ut,
                          const double* Vt, int ld, int k, double* out);

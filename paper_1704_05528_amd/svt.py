@@ -129,6 +129,20 @@ class SVT:
         a, ap = _i32(annealed)
         check(load().svt_set_replay(self._h, bp, ap, int(b.size)), self._h)
 
+    def profile(self, enable=True):
+        check(load().svt_profile(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self):
+        """{phase: dict(ms, bytes, flops, launches)} accumulated since profile(True)."""
+        from ._capi import PHASES
+        nph = len(PHASES)
+        ms, by, fl = np.zeros(nph), np.zeros(nph), np.zeros(nph)
+        ln = np.zeros(nph, dtype=np.int64)
+        check(load().svt_profile_read(self._h, ms.ctypes.data_as(_f64p), by.ctypes.data_as(_f64p),
+                                      fl.ctypes.data_as(_f64p), ln.ctypes.data_as(C.POINTER(C.c_int64))), self._h)
+        return {ph: dict(ms=float(ms[i]), bytes=float(by[i]), flops=float(fl[i]), launches=int(ln[i]))
+                for i, ph in enumerate(PHASES)}
+
     def grad(self, T, ckpt, hi, hj, gx_h):
         hi, ip = _i32(hi)
         hj, jp = _i32(hj)
