@@ -19,12 +19,14 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Cyclic Jacobi (Golub & Van Loan, sym.schur2 rotations) with round-robin ordering: in each
-// round the bb/2 disjoint pairs rotate simultaneously, rows first, then columns of A and V.
-// A (bb x ld) and V live in LDS.  Sweeps stop when the off-diagonal mass is below
-// 1e-30 of the total squared Frobenius norm, or after 40 sweeps.
+// round the bb/2 disjoint pairs rotate at once.  With J block-diagonal over the pairs, every
+// 2 x 2 block (P, R) of J^T A J depends only on the same block of A, so one pass over the
+// blocks applies the round (rows and columns together), and V <- V J in the same pass.
+// A and V live in LDS.  Sweeps stop when the off-diagonal mass is below 1e-30 of the total
+// squared Frobenius norm, or after max_sweeps.
 __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, int ldh, int b,
                                                 double* __restrict__ eval, double* __restrict__ evec, int ldv,
-                                                double* scal, int slot) {
+                                                double* scal, int slot, int max_sweeps) {
   extern __shared__ double sm[];
   const int bb = b + (b & 1);
   const int ld = bb + 1;
@@ -32,11 +34,11 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
   double* V = sm + bb * ld;
   __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
   __shared__ int pp[kEigMax / 2], qq[kEigMax / 2];
-  __shared__ double red[4];
+  __shared__ double red[8];
   __shared__ int perm[kEigMax];
-  __shared__ int stop_flag;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wid = tid / kWave;
+  const int half = bb / 2;
 
   for (int e = tid; e < bb * bb; e += blockDim.x) {
     const int i = e / bb, j = e % bb;
@@ -45,33 +47,22 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
   }
   __syncthreads();
 
+  // A rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|) (the relative test of Demmel and
+  // Veselic for positive semidefinite matrices) or when |a_pq| is below 1e-19 of the largest
+  // diagonal entry (irrelevant at working precision); a sweep without any rotation ends it.
+  __shared__ int rotated;
+  __shared__ double dmax_s;
+  if (tid == 0) {
+    double d = 0.0;
+    for (int i = 0; i < b; ++i) d = fmax(d, fabs(A[i * ld + i]));
+    dmax_s = d;
+  }
+  __syncthreads();
+  const double dmax = dmax_s;
   int sweep = 0;
-  const int half = bb / 2;
-  for (; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < bb * bb; e += blockDim.x) {
-      const int i = e / bb, j = e % bb;
-      const double v = A[i * ld + j];
-      tot = fma(v, v, tot);
-      if (i != j) off = fma(v, v, off);
-    }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    if (lane == 0) red[wid] = off;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rotated = 0;
     __syncthreads();
-    if (tid == 0) {
-      const double o = red[0] + red[1] + red[2] + red[3];
-      red[0] = o;
-    }
-    __syncthreads();
-    const double off_all = red[0];
-    __syncthreads();
-    if (lane == 0) red[wid] = tot;
-    __syncthreads();
-    if (tid == 0) stop_flag = (off_all <= 1e-30 * (red[0] + red[1] + red[2] + red[3])) ? 1 : 0;
-    __syncthreads();
-    if (stop_flag) break;
-
     for (int round = 0; round < bb - 1; ++round) {
       if (tid < half) {
         const int t = tid;
@@ -80,7 +71,9 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
         const int p = min(pa, pb), q = max(pa, pb);
         const double apq = A[p * ld + q];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
+        if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(A[p * ld + p] * A[q * ld + q])) &&
+            fabs(apq) > 1e-19 * dmax) {
+          rotated = 1;
           const double app = A[p * ld + p], aqq = A[q * ld + q];
           const double th = (aqq - app) / (2.0 * apq);
           double tt;
@@ -98,30 +91,33 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
         qq[t] = q;
       }
       __syncthreads();
-      // rows p, q of A  (A <- J^T A)
-      for (int e = tid; e < half * bb; e += blockDim.x) {
-        const int t = e / bb, j = e % bb;
-        const int p = pp[t], q = qq[t];
-        const double c = cs[t], s = sn[t];
-        const double ap = A[p * ld + j], aq = A[q * ld + j];
-        A[p * ld + j] = c * ap - s * aq;
-        A[q * ld + j] = s * ap + c * aq;
+      // blocks (P, R): rows p1, q1 rotate by pair P, columns p2, q2 by pair R
+      for (int e = tid; e < half * half; e += blockDim.x) {
+        const int P = e / half, R = e % half;
+        const int p1 = pp[P], q1 = qq[P], p2 = pp[R], q2 = qq[R];
+        const double c1 = cs[P], s1 = sn[P], c2 = cs[R], s2 = sn[R];
+        const double a00 = A[p1 * ld + p2], a01 = A[p1 * ld + q2];
+        const double a10 = A[q1 * ld + p2], a11 = A[q1 * ld + q2];
+        const double r00 = c1 * a00 - s1 * a10, r01 = c1 * a01 - s1 * a11;
+        const double r10 = s1 * a00 + c1 * a10, r11 = s1 * a01 + c1 * a11;
+        A[p1 * ld + p2] = c2 * r00 - s2 * r01;
+        A[p1 * ld + q2] = s2 * r00 + c2 * r01;
+        A[q1 * ld + p2] = c2 * r10 - s2 * r11;
+        A[q1 * ld + q2] = s2 * r10 + c2 * r11;
       }
-      __syncthreads();
-      // columns p, q of A and V  (A <- A J, V <- V J)
-      for (int e = tid; e < half * bb; e += blockDim.x) {
-        const int t = e / bb, i = e % bb;
-        const int p = pp[t], q = qq[t];
-        const double c = cs[t], s = sn[t];
-        const double ap = A[i * ld + p], aq = A[i * ld + q];
-        A[i * ld + p] = c * ap - s * aq;
-        A[i * ld + q] = s * ap + c * aq;
+      for (int e = tid; e < bb * half; e += blockDim.x) {
+        const int i = e / half, R = e % half;
+        const int p = pp[R], q = qq[R];
+        const double c = cs[R], s = sn[R];
         const double vp = V[i * ld + p], vq = V[i * ld + q];
         V[i * ld + p] = c * vp - s * vq;
         V[i * ld + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
+    const int any = rotated;
+    __syncthreads();   // every thread has read the flag before thread 0 clears it again
+    if (!any) break;
   }
 
   // sort eigenvalues descending (the padding index of odd b has eigenvalue 0 and is excluded)
@@ -179,7 +175,7 @@ __global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int 
 }  // namespace
 
 hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double* eval, double* evec, int ldv,
-                         double* scal, int slot) {
+                         double* scal, int slot, int max_sweeps) {
   const int bb = b + (b & 1);
   const size_t lds = (size_t)2 * bb * (bb + 1) * sizeof(double);
   static bool attr_set = false;
@@ -189,7 +185,7 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, H, ldh, b, eval, evec, ldv, scal, slot);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, H, ldh, b, eval, evec, ldv, scal, slot, max_sweeps);
   return hipGetLastError();
 }
 

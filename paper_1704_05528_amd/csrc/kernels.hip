@@ -89,6 +89,14 @@ __global__ void k_fill_random(double* __restrict__ V, int rows, int ld, int c0, 
   V[(int64_t)i * ld + c] = z[0];
 }
 
+// columns c0 .. c0+count-1 of a rows x ld block set to the unit vectors e_{row0}, e_{row0+1}, ...
+__global__ void k_set_unit(double* __restrict__ V, int rows, int ld, int c0, int count, int row0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * count) return;
+  const int i = (int)(t / count), q = (int)(t % count);
+  V[(int64_t)i * ld + c0 + q] = (i == row0 + q) ? 1.0 : 0.0;
+}
+
 // ------------------------------------------------------------------------------------------
 // Segment-gather SpMM: out[row, :] = sum_{p in seg(row)} val[vperm(p)] * D[idx[p], :].
 // With CSC segments (idx = row indices, D = Q) this is W = Y^T Q; with CSR segments
@@ -339,13 +347,97 @@ __global__ __launch_bounds__(256) void k_sumsq(int64_t len, const double* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// scal[slot + q] = sum_b partial[b * stride + q] for q < nq, summed in block order by one thread each
-__global__ void k_finish(const double* __restrict__ partial, int nblocks, int stride, int nq, double* scal, int slot) {
-  const int q = threadIdx.x;
-  if (q >= nq) return;
+// scal[slot + q] = sum_b partial[b * stride + q] for q < nq (nq <= 4): one workgroup, each thread
+// sums a fixed strided subset, then a fixed butterfly and wave order (deterministic).
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int nblocks, int stride, int nq,
+                                                double* scal, int slot) {
+  __shared__ double lds[4];
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(int64_t)b * stride + q];
+    const double t = block_sum(v, lds);
+    if (threadIdx.x == 0) scal[slot + q] = t;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// LDS-tiled W = Y^T Q for inputs where most RT x JB tiles of Y hold observed entries (image-
+// like sampling densities).  A workgroup owns JB columns of Y (rows of W) and CB columns of Q;
+// for each RT-row tile it scatters the tile's observed values into a zero-filled LDS tile,
+// stages Q[i0:i0+RT, c0:c0+CB], and accumulates 4 x 4 register blocks.  tstart[j*(nt+1)+t] is
+// the first CSC position of column j with row >= t*RT (built once from the fixed pattern).
+// Row tiles are split over blockIdx.z; split s writes its sum to out + s * split_stride.
+// ------------------------------------------------------------------------------------------
+constexpr int kTR = 32, kTJ = 64, kTC = 64;
+
+__global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_t* __restrict__ rowidx,
+                                                      const int32_t* __restrict__ tstart, int nt,
+                                                      const double* __restrict__ val, const double* __restrict__ Q,
+                                                      int ldq, int r, double* __restrict__ out, int ldo,
+                                                      int tiles_per_split, int64_t split_stride) {
+  __shared__ double Ys[kTR][kTJ + 2];
+  __shared__ double Qs[kTR][kTC + 2];
+  const int tid = threadIdx.x;
+  const int j0 = blockIdx.x * kTJ, c0 = blockIdx.y * kTC;
+  const int tj = tid / 16, tc = tid % 16;
+  const int t_begin = blockIdx.z * tiles_per_split, t_end = min(nt, t_begin + tiles_per_split);
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  // scatter roles: 4 threads per column j of the tile
+  const int sj = tid / 4, ssub = tid % 4;
+  const int gj = j0 + sj;
+  for (int t = t_begin; t < t_end; ++t) {
+    const int i0 = t * kTR;
+    for (int e = tid; e < kTR * kTJ; e += 256) Ys[e / kTJ][e % kTJ] = 0.0;
+    for (int e = tid; e < kTR * kTC; e += 256) {
+      const int i = e / kTC, c = e % kTC;
+      Qs[i][c] = (i0 + i < m && c0 + c < r) ? Q[(int64_t)(i0 + i) * ldq + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (gj < n) {
+      const int p1 = tstart[(int64_t)gj * (nt + 1) + t + 1];
+      for (int p = tstart[(int64_t)gj * (nt + 1) + t] + ssub; p < p1; p += 4) Ys[rowidx[p] - i0][sj] = val[p];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = 0; i < kTR; ++i) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Ys[i][tj * 4 + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Qs[i][tc * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double* o = out + blockIdx.z * split_stride;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + tj * 4 + u;
+    if (j >= n) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = c0 + tc * 4 + v;
+      if (c < r) o[(int64_t)j * ldo + c] = acc[u][v];
+    }
+  }
+}
+
+// W[j, c] = sum_s partial[s][j][c] in split order
+__global__ void k_split_sum(int n, int r, const double* __restrict__ partial, int splits, int64_t split_stride,
+                            int ldp, double* __restrict__ W, int ldw) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * r) return;
+  const int j = (int)(t / r), c = (int)(t % r);
   double v = 0.0;
-  for (int b = 0; b < nblocks; ++b) v += partial[(int64_t)b * stride + q];
-  scal[slot + q] = v;
+  for (int s = 0; s < splits; ++s) v += partial[s * split_stride + (int64_t)j * ldp + c];
+  W[(int64_t)j * ldw + c] = v;
 }
 
 __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double* __restrict__ out) {
@@ -360,79 +452,106 @@ __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double
 // the span of the basis it was projected against; skipped when prenorm == nullptr), or when
 // its Cholesky pivot is at most dep_tol times its projected norm (it depends on the kept
 // columns before it; a Gram-based pivot cannot resolve dependence much below 1e-8).  The kept
-// columns are packed to the left: X_new = X Minv has wk orthonormal columns followed by
-// zero columns.  If wk_in >= 0 only the first wk_in columns take part (second pass of
-// CholeskyQR2 reads the count of the first pass from scal[wk_slot_in]).  scal[slot] = wk.
+// factor R (upper, R^T R = Gram of the kept columns) goes to Rout for k_trsm_rows, which writes
+// X_new = X[:, kept] R^{-1}: wk orthonormal columns followed by zero columns.  If wk_in >= 0
+// only the first wk_in columns take part (second pass of CholeskyQR2 reads the count of the
+// first pass from scal[wk_slot_in]).  scal[slot] = wk.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int w,
                                                     const double* __restrict__ prenorm, double drop_tol,
-                                                    double dep_tol, double* __restrict__ Minv, int ldm,
+                                                    double dep_tol, double* __restrict__ Rout, int ldm,
                                                     double* scal, int slot, int wk_slot_in) {
-  extern __shared__ double Rsm[];  // w x (w + 1) upper Cholesky factor
-  __shared__ int keep[kEigMax], pos[kEigMax];
-  __shared__ int wk_s;
+  extern __shared__ double sm[];
+  const int ld = w + 1;
+  double* A = sm;            // w x (w + 1): Gram, overwritten by the Schur complements / rows of R
+  __shared__ int keep[kEigMax];
+  __shared__ double gdiag[kEigMax];
   const int tid = threadIdx.x;
   int wa = w;
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
   for (int e = tid; e < w * w; e += blockDim.x) {
     const int i = e / w, j = e % w;
-    Rsm[(i) * (w + 1) + (j)] = (i < wa && j < wa) ? gram[(int64_t)i * ldg + j] : 0.0;
-    Minv[(int64_t)i * ldm + j] = 0.0;
+    A[i * ld + j] = (i < wa && j < wa) ? gram[(int64_t)i * ldg + j] : 0.0;
   }
   for (int c = tid; c < w; c += blockDim.x) {
+    const double g = (c < wa) ? fmax(gram[(int64_t)c * ldg + c], 0.0) : 0.0;
+    gdiag[c] = g;
     const double lim = prenorm ? drop_tol * prenorm[c] : 0.0;
-    keep[c] = (c < wa) && (sqrt(fmax(gram[(int64_t)c * ldg + c], 0.0)) > lim) ? 1 : 0;
+    keep[c] = (c < wa) && (sqrt(g) > lim) ? 1 : 0;
   }
   __syncthreads();
-  // upper Cholesky R^T R = G on the kept columns, in place in R (row c holds Rsm[(c) * (w + 1) + (c..)])
+  // Right-looking Cholesky on the upper triangle.  At step c every thread reads the pivot
+  // d = A[c][c] (the Schur complement) and takes the same keep decision; a kept column then
+  // updates the trailing upper triangle A[i][j] -= A[c][i] A[c][j] / d, i, j > c.
   for (int c = 0; c < wa; ++c) {
-    if (keep[c]) {
-      if (tid == 0) {
-        double d = Rsm[(c) * (w + 1) + (c)];
-        for (int l = 0; l < c; ++l)
-          if (keep[l]) d -= Rsm[(l) * (w + 1) + (c)] * Rsm[(l) * (w + 1) + (c)];
-        const double lim2 = dep_tol * dep_tol * gram[(int64_t)c * ldg + c];
-        if (!(d > lim2) || !(d > 0.0)) {
-          keep[c] = 0;
-        } else {
-          Rsm[(c) * (w + 1) + (c)] = sqrt(d);
-        }
+    if (!keep[c]) continue;            // uniform: keep[] only changes below, after a barrier
+    const double d = A[c * ld + c];
+    const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
+    if (ok) {
+      const int L = wa - c - 1;
+      const double inv = 1.0 / d;
+      for (int e = tid; e < L * L; e += blockDim.x) {
+        const int i = c + 1 + e / L, j = c + 1 + e % L;
+        if (i <= j) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
       }
-      __syncthreads();
-      if (keep[c]) {
-        for (int j = c + 1 + tid; j < wa; j += blockDim.x) {
-          double v = Rsm[(c) * (w + 1) + (j)];
-          for (int l = 0; l < c; ++l)
-            if (keep[l]) v -= Rsm[(l) * (w + 1) + (c)] * Rsm[(l) * (w + 1) + (j)];
-          Rsm[(c) * (w + 1) + (j)] = v / Rsm[(c) * (w + 1) + (c)];
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    if (!ok && tid == 0) keep[c] = 0;
+    __syncthreads();
+  }
+  // Rout: row c of the factor for kept c (R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c]);
+  // a dropped column keeps an all-zero row and column, R[c][c] = 0 marking it for the row solve.
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int c = e / w, j = e % w;
+    double v = 0.0;
+    if (c < wa && j < wa && j >= c && keep[c] && keep[j]) {
+      const double rc = sqrt(A[c * ld + c]);
+      v = (j == c) ? rc : A[c * ld + j] / rc;
+    }
+    Rout[(int64_t)c * ldm + j] = v;
   }
   if (tid == 0) {
     int q = 0;
-    for (int c = 0; c < w; ++c) {
-      pos[c] = keep[c] ? q : -1;
-      q += keep[c];
-    }
-    wk_s = q;
+    for (int c = 0; c < wa; ++c) q += keep[c];
+    scal[slot] = (double)q;
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-wise solve Z R = X for the factor of k_block_chol: one thread per row, forward
+// substitution over the columns with R broadcast from LDS; the kept columns are written packed
+// to the left of out and the remaining columns are zero.
+// ------------------------------------------------------------------------------------------
+template <int WM>
+__global__ __launch_bounds__(256) void k_trsm_rows(int rows, const double* __restrict__ X, int ldx, int w,
+                                                   const double* __restrict__ R, int ldr, double* __restrict__ out,
+                                                   int ldo) {
+  extern __shared__ double Rs[];   // w x (w + 1)
+  const int ld = w + 1;
+  for (int e = threadIdx.x; e < w * w; e += blockDim.x) Rs[(e / w) * ld + e % w] = R[(int64_t)(e / w) * ldr + e % w];
   __syncthreads();
-  // Minv[:, pos[jj]] = column jj of R_kept^{-1}, by back substitution (one thread per column).
-  // Row c of Minv multiplies column c of the input block; dropped rows and columns stay zero.
-  for (int jj = tid; jj < wa; jj += blockDim.x) {
-    if (!keep[jj]) continue;
-    double* zc = Minv + pos[jj];
-    for (int i = jj; i >= 0; --i) {
-      if (!keep[i]) continue;
-      double v = (i == jj) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= jj; ++l)
-        if (keep[l]) v -= Rsm[(i) * (w + 1) + (l)] * zc[(int64_t)l * ldm];
-      zc[(int64_t)i * ldm] = v / Rsm[(i) * (w + 1) + (i)];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  double z[WM];
+#pragma unroll
+  for (int c = 0; c < WM; ++c) z[c] = (c < w) ? X[(int64_t)i * ldx + c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < WM; ++c) {
+    if (c < w) {
+      double v = z[c];
+#pragma unroll
+      for (int l = 0; l < c; ++l) v = fma(-z[l], Rs[l * ld + c], v);
+      const double rcc = Rs[c * ld + c];
+      z[c] = (rcc != 0.0) ? v / rcc : 0.0;
     }
   }
-  if (tid == 0) scal[slot] = (double)wk_s;
+  double* o = out + (int64_t)i * ldo;
+  int q = 0;
+#pragma unroll
+  for (int c = 0; c < WM; ++c) {
+    if (c < w && Rs[c * ld + c] != 0.0) o[q++] = z[c];
+  }
+  for (; q < w; ++q) o[q] = 0.0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -541,6 +660,40 @@ hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const i
   return hipGetLastError();
 }
 
+int tiled_row_tiles(int64_t m) { return (int)((m + kTR - 1) / kTR); }
+
+hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0) {
+  const int64_t work = (int64_t)rows * count;
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_unit, dim3(grid1(work)), dim3(256), 0, s, V, rows, ld, c0, count, row0);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
+                               const double* val, const double* Q, int ldq, int r, double* W, int ldw,
+                               double* partial, int64_t partial_cap) {
+  if (n == 0 || r == 0) return hipSuccess;
+  const int nt = tiled_row_tiles(m);
+  const int gx = (n + kTJ - 1) / kTJ, gy = (r + kTC - 1) / kTC;
+  int splits = std::max(1, std::min(nt, 512 / std::max(1, gx * gy)));
+  while (splits > 1 && (int64_t)splits * n * r > partial_cap) --splits;
+  const int tps = (nt + splits - 1) / splits;
+  splits = (nt + tps - 1) / tps;
+  if (splits == 1) {
+    hipLaunchKernelGGL(k_spmm_t_tiled, dim3(gx, gy, 1), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
+                       W, ldw, tps, (int64_t)0);
+    return hipGetLastError();
+  }
+  const int64_t stride = (int64_t)n * r;
+  hipLaunchKernelGGL(k_spmm_t_tiled, dim3(gx, gy, splits), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
+                     partial, r, tps, stride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_split_sum, dim3(grid1((int64_t)n * r)), dim3(256), 0, s, n, r, partial, splits, stride, r, W,
+                     ldw);
+  return hipGetLastError();
+}
+
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const double* A, int lda, const double* M, int ldm,
                          double* out, int ldo, int w, double alpha, double beta) {
   if (rows == 0 || w == 0) return hipSuccess;
@@ -553,7 +706,8 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const double* A, int lda, i
                             int nb, double* out, int ldo, double* partial, int64_t partial_cap) {
   if (na == 0 || nb == 0) return hipSuccess;
   const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
-  int splits = std::max(1, std::min(rows / 512, 1024 / std::max(1, gx * gy)));
+  // enough workgroups to fill the chip: about 512 in total, at least 32 rows per split
+  int splits = std::max(1, std::min(std::max(1, rows / 32), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
   splits = std::max(1, std::min(splits, std::max(1, rows)));
   const int rps = (rows + splits - 1) / splits;
@@ -588,7 +742,7 @@ hipError_t launch_sumsq_cols(hipStream_t s, int rows, const double* A, int lda, 
   hipLaunchKernelGGL(k_sumsq_cols, dim3(nb), dim3(256), 0, s, rows, A, lda, c0, w, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 1, 1, scal, slot);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
   return hipGetLastError();
 }
 
@@ -597,7 +751,7 @@ hipError_t launch_sumsq(hipStream_t s, int64_t len, const double* v, double* par
   hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, s, len, v, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nb, 1, 1, scal, slot);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
   return hipGetLastError();
 }
 
@@ -620,8 +774,30 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
     attr_set = true;
   }
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Minv, ldm, scal, slot,
-                     wk_slot_in);
+  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Minv, ldm,
+                     scal, slot, wk_slot_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rows(hipStream_t s, int rows, const double* X, int ldx, int w, const double* R, int ldr,
+                           double* out, int ldo) {
+  if (rows == 0 || w == 0) return hipSuccess;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_trsm_rows<kEigMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kEigMax * (kEigMax + 1) * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const size_t lds = (size_t)w * (w + 1) * sizeof(double);
+  const unsigned g = (unsigned)((rows + 255) / 256);
+  if (w <= 16) {
+    hipLaunchKernelGGL(k_trsm_rows<16>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+  } else if (w <= 64) {
+    hipLaunchKernelGGL(k_trsm_rows<64>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+  } else {
+    hipLaunchKernelGGL(k_trsm_rows<kEigMax>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+  }
   return hipGetLastError();
 }
 
@@ -637,7 +813,7 @@ hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, cons
 
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal,
                          int slot) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, partial, nblocks, stride, nq, scal, slot);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nblocks, stride, nq, scal, slot);
   return hipGetLastError();
 }
 

@@ -25,7 +25,10 @@ thread_local std::string g_init_err;
 constexpr double kDropTol = 1e-10;   // a projected column this small relative to its norm before lies in span(Q)
 constexpr double kDepTol = 1e-6;     // a Cholesky pivot this small relative to the column norm means dependence
 constexpr double kEigTol = 1e-13;    // Ritz residual relative to the largest Ritz value
-constexpr int kEigIters = 300;       // cap on subspace iterations per SVT iteration
+constexpr int kEigBatches = 60;      // cap on Rayleigh-Ritz batches per SVT iteration
+constexpr int kPowerSteps = 2;       // CholeskyQR steps per batch (two products with G each)
+constexpr double kEigDepTol = 1e-12; // eigen-block CholeskyQR drops only numerically dependent columns
+constexpr int kDirect = 32;          // basis widths up to this are diagonalised directly
 
 // scalar slots of the device readback buffer
 enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_RES2 = 4, S_YN2 = 5, S_SWEEPS = 6, S_NORMY = 7,
@@ -125,11 +128,21 @@ svt_status orthonormalize_block(Handle* h, int rows, double* X, double* X2, int 
   HIPCHK(launch_tn_narrow(s, rows, X, ld, wc, X, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
   HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1,
                            -1));
-  HIPCHK(launch_rowmul(s, rows, wc, X, ld, h->Minv, kEigMax, X2, ld, wc, 1.0, 0.0));
+  HIPCHK(launch_trsm_rows(s, rows, X, ld, wc, h->Minv, kEigMax, X2, ld));
   HIPCHK(launch_tn_narrow(s, rows, X2, ld, wc, X2, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
   HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2,
                            S_WK1));
-  HIPCHK(launch_rowmul(s, rows, wc, X2, ld, h->Minv, kEigMax, X, ld, wc, 1.0, 0.0));
+  HIPCHK(launch_trsm_rows(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
+  return SVT_OK;
+}
+
+// One CholeskyQR pass Out = In R^{-1} without the span rule (dependent columns still drop).
+svt_status chol_orth(Handle* h, int rows, const double* In, double* Out, int ld, int wc) {
+  hipStream_t s = h->stream;
+  HIPCHK(launch_tn_narrow(s, rows, In, ld, wc, In, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
+  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kEigDepTol, h->Minv, kEigMax, h->scal, S_WK2,
+                           -1));
+  HIPCHK(launch_trsm_rows(s, rows, In, ld, wc, h->Minv, kEigMax, Out, ld));
   return SVT_OK;
 }
 
@@ -206,7 +219,12 @@ svt_status r4svd_core(Handle* h, int it, int replay_blocks, svt_step_stats* st) 
     {
       const double r = h->r, nnz = (double)h->nnz;
       PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * 12.0 + 4.0 * (h->n + 1) + 8.0 * r * (double)(h->m + h->n), 2.0 * nnz * r);
-      CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
+      if (h->tstart) {
+        HIPCHK(launch_spmm_t_tiled(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, h->y, h->Q, h->r_cap, h->r,
+                                   h->W, h->r_cap, h->partial, h->partial_cap));
+      } else {
+        CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
+      }
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
@@ -270,11 +288,11 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
     PhaseTimer tm(h, SVT_PH_GRAM, 8.0 * (double)h->n * r + 8.0 * (double)r * r, (double)h->n * r * (r + 1.0));
     HIPCHK(launch_gram(s, (int)h->n, h->W, h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
   }
-  std::vector<double> theta(kEigMax), res(kEigMax);
+  std::vector<double> theta(2 * kEigMax), res(kEigMax);
   const double* S = nullptr;
   int k = 0;
   st->eig_iters = 0;
-  if (r <= kEigMax) {
+  if (r <= kDirect) {
     {
       PhaseTimer tm(h, SVT_PH_EIG);
       HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
@@ -282,71 +300,97 @@ svt_status projected_svd(Handle* h, svt_step_stats* st) {
     CHK(to_host(h, theta.data(), h->Eval, r));
     while (k < r && theta[k] > tau2) ++k;
     S = h->ES;
-    // keep the leading eigenvectors as the warm start of the block solver
-    const int keep = std::min(r, h->b_cap);
-    HIPCHK(launch_copy_cols(s, r, h->ES, kEigMax, h->EV, kEigMax, keep));
-    h->ev_valid = keep;
+    // keep the eigenvectors as the warm start of the block solver
+    HIPCHK(launch_copy_cols(s, r, h->ES, kEigMax, h->EV, kEigMax, r));
+    h->ev_valid = r;
     h->ev_rows = r;
     st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
   } else {
-    // warm-started block subspace iteration with Rayleigh-Ritz
-    int b = std::min(h->b_cap, std::max(32, ((2 * h->k + 16 + 15) / 16) * 16));
-    int valid = (h->ev_valid > 0 && h->ev_rows <= r) ? std::min(h->ev_valid, b) : 0;
-    if (valid > 0 && h->ev_rows < r) {
-      // new basis columns were appended: zero the new rows of the kept vectors
-      HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
-                              valid * sizeof(double), r - h->ev_rows, s));
-    }
+    // Warm-started orthogonal iteration on G in batches of kPowerSteps products, each batch
+    // closed by CholeskyQR2 and a Rayleigh-Ritz step on the whole block (b columns).
+    // Start block: the previous Ritz vectors (new basis rows zero), the unit vectors of the basis
+    // columns appended since then (where new energy enters), and Gaussian columns.
+    const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
+    const int newc = warm ? r - h->ev_rows : 0;
+    int b = std::min(std::min(h->b_cap, r), std::max(16, ((2 * std::max(h->k, 4) + 8 + 7) / 8) * 8));
+    int valid = warm ? std::min(h->ev_valid, b) : 0;
+    if (valid + newc + 4 > b) b = std::min(std::min(h->b_cap, r), valid + newc + 4);
+    valid = std::min(valid, b);
+    const int unit = std::min(newc, b - valid);
     {
       PhaseTimer tm(h, SVT_PH_EIG);
-      HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+      if (valid > 0 && h->ev_rows < r) {
+        // new basis columns were appended: zero the new rows of the kept vectors
+        HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
+                                valid * sizeof(double), r - h->ev_rows, s));
+      }
+      HIPCHK(launch_set_unit(s, h->EV, r, kEigMax, valid, unit, h->ev_rows));
+      HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid + unit, b, h->p.seed ^ 0x5A5A5A5Aull,
+                                (uint64_t)h->iter));
       CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
     }
     bool done = false;
-    int iters = 0;
+    int iters = 0, batches = 0, prev_k = -1;
     while (!done) {
-      if (iters >= kEigIters) {
+      if (batches >= kEigBatches) {
         st->flags |= SVT_F_EIG_INEXACT;
         break;
       }
-      ++iters;
+      ++batches;
       {
-      PhaseTimer tm(h, SVT_PH_EIG);
-      // power step: V <- orth(G V)
-      HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
-      CHK(orthonormalize_block(h, r, h->EZ, h->EZ2, kEigMax, b, nullptr));
-      // Rayleigh-Ritz on span(V): H = V^T G V, H = S Theta S^T, V <- V S, Z <- Z S
-      HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EZ, kEigMax, h->EZ2, kEigMax, b, 1.0, 0.0));
-      HIPCHK(launch_tn_narrow(s, r, h->EZ, kEigMax, b, h->EZ2, kEigMax, b, h->EH, kEigMax, h->partial, h->partial_cap));
-      HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
-      HIPCHK(launch_rowmul(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EV, kEigMax, b, 1.0, 0.0));   // V = V S
-      HIPCHK(launch_rowmul(s, r, b, h->EZ2, kEigMax, h->ES, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));  // Z = G V
-      HIPCHK(launch_ritz_residual(s, r, h->EZ, h->EV, kEigMax, b, h->Eval, h->partial, h->EZ3));
+        PhaseTimer tm(h, SVT_PH_EIG);
+        // each step multiplies by G twice before one CholeskyQR (the last step: CholeskyQR2)
+        for (int step = 0; step < kPowerSteps; ++step, iters += 2) {
+          HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b, 1.0, 0.0));
+          HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EZ3, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
+          if (step + 1 < kPowerSteps) {
+            CHK(chol_orth(h, r, h->EZ, h->EV, kEigMax, b));
+          } else {
+            CHK(chol_orth(h, r, h->EZ, h->EZ2, kEigMax, b));
+            CHK(chol_orth(h, r, h->EZ2, h->EV, kEigMax, b));
+          }
+        }
+        // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; Z <- (G V) S; residuals
+        HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
+        HIPCHK(launch_tn_narrow(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->EH, kEigMax, h->partial,
+                                h->partial_cap));
+        HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+        HIPCHK(launch_rowmul(s, r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b, 1.0, 0.0));
+        HIPCHK(launch_rowmul(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b, 1.0, 0.0));
+        std::swap(h->EV, h->EZ2);
+        HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
       }
-      CHK(to_host(h, theta.data(), h->Eval, b));
-      CHK(to_host(h, res.data(), h->EZ3, b));
+      CHK(to_host(h, theta.data(), h->Eval, 2 * kEigMax));
+      for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
       k = 0;
       while (k < b && theta[k] > tau2) ++k;
-      if (k >= b - 4) {
+      if (k + 4 > b && b < r) {
         if (b >= h->b_cap) {
           if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks (kmax)");
         } else {
-          const int nb = std::min(h->b_cap, b + 32);
-          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)iters));
+          const int nb = std::min(std::min(h->b_cap, r), b + 16);
+          PhaseTimer tm(h, SVT_PH_EIG);
+          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)batches));
           b = nb;
           CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
+          prev_k = -1;
           continue;
         }
       }
+      // Accept when the pairs above tau^2 and four guard pairs below it have converged and the
+      // count k agrees with the previous check (Ritz values rise monotonically under subspace
+      // iteration, so a missed eigenvalue above tau^2 would still be moving k).  A block that
+      // spans the whole basis (b == r) is exact after one Rayleigh-Ritz step.
+      // In the steady state the first check may also accept when k equals the previous SVT
+      // iteration's count, whose eigenvectors started this solve.
       const double lim = kEigTol * std::max(theta[0], 0.0);
-      done = true;
-      for (int c = 0; c < std::min(b, k + 1); ++c) {
-        const double tolc = (c < k) ? lim : 1e3 * lim;
-        if (!(res[c] <= tolc)) {
-          done = false;
-          break;
-        }
-      }
+      done = (b == r) || (k == prev_k) || (prev_k < 0 && warm && k == h->k);
+      for (int c = 0; done && c < k; ++c)
+        if (!(res[c] <= lim)) done = false;
+      // guard pairs: an eigenvalue lies within res of each Ritz value; it must sit below tau^2
+      for (int c = k; done && c < std::min(b, k + 4); ++c)
+        if (!(theta[c] + res[c] < tau2)) done = false;
+      prev_k = k;
     }
     st->eig_iters = iters;
     S = h->EV;
@@ -427,7 +471,8 @@ svt_status do_iteration(Handle* h, svt_step_stats* st) {
 }
 
 void release(Handle* h) {
-  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->a, h->y, h->y_next, h->x, h->Q, h->W,
+  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->a, h->y, h->y_next, h->x,
+                  h->Q, h->W,
                   h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2, h->EZ3,
                   h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->C, h->D, h->Sk, h->Utmp, h->partial, h->scal};
   for (void* b : bufs)
@@ -546,6 +591,22 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   }
   for (int64_t i = 0; i < m; ++i) rowptr[i + 1] += rowptr[i];
 
+  // Row-tile starts for the LDS-tiled Y^T Q when most tiles hold observed entries (at least 5% of
+  // the entries observed); very sparse patterns use the gather kernel instead.
+  const int ntiles = tiled_row_tiles(m);
+  std::vector<int32_t> tstart;
+  if ((double)nnz >= 0.05 * (double)m * (double)n && (int64_t)n * (ntiles + 1) <= ((int64_t)1 << 26)) {
+    tstart.resize((size_t)n * (ntiles + 1));
+    for (int64_t j = 0; j < n; ++j) {
+      int32_t p = colptr[j];
+      for (int t = 0; t <= ntiles; ++t) {
+        const int64_t lim = std::min<int64_t>((int64_t)t * 32, m);
+        while (p < colptr[j + 1] && rowidx[p] < lim) ++p;
+        tstart[(size_t)j * (ntiles + 1) + t] = p;
+      }
+    }
+  }
+
   h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
   h->w_cap = 64;
   h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
@@ -581,7 +642,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->EZ3, (size_t)h->r_cap * kEigMax));
   A(dalloc(&h->EH, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->ES, (size_t)kEigMax * kEigMax));
-  A(dalloc(&h->Eval, kEigMax));
+  A(dalloc(&h->Eval, 2 * kEigMax));
   A(dalloc(&h->Ut, (size_t)m * kEigMax));
   A(dalloc(&h->Vt, (size_t)n * kEigMax));
   A(dalloc(&h->Utmp, (size_t)std::max(m, n) * kEigMax));
@@ -590,6 +651,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->Sk, (size_t)h->r_cap * kEigMax));
   A(dalloc(&h->partial, (size_t)h->partial_cap));
   A(dalloc(&h->scal, kScalars));
+  if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
@@ -605,6 +667,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   up(h->colidx, colidx.data(), nnz * sizeof(int32_t));
   up(h->csr2csc, csr2csc.data(), nnz * sizeof(int32_t));
   up(h->a, a_csc.data(), nnz * sizeof(double));
+  if (!tstart.empty()) up(h->tstart, tstart.data(), tstart.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * sizeof(double), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {

@@ -31,6 +31,7 @@ struct Handle {
   int32_t *colptr = nullptr, *rowidx = nullptr;   // CSC (primary order of values)
   int32_t *rowptr = nullptr, *colidx = nullptr;   // CSR
   int32_t *csr2csc = nullptr;                     // CSR position -> CSC position
+  int32_t *tstart = nullptr;                      // row-tile starts per column (dense-ish patterns only)
   std::vector<int64_t> user2csc;                  // caller order -> CSC position (host)
 
   // values on Lambda (CSC order)
@@ -111,6 +112,16 @@ hipError_t launch_omega(hipStream_t s, double* om, int n, int c0, int w, int ld,
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
                            const double* val, const double* D, int ldd, double* out, int ldo, int w);
 
+// columns c0 .. c0+count-1 of a rows x ld block set to e_{row0}, e_{row0+1}, ...
+hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0);
+
+// LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
+// position of its first entry in each row tile (n x (tiled_row_tiles(m) + 1) int32)
+int tiled_row_tiles(int64_t m);
+hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
+                               const double* val, const double* Q, int ldq, int r, double* W, int ldw,
+                               double* partial, int64_t partial_cap);
+
 // out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w]
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const double* A, int lda, const double* M, int ldm,
                          double* out, int ldo, int w, double alpha, double beta);
@@ -132,10 +143,13 @@ hipError_t launch_sumsq(hipStream_t s, int64_t len, const double* v, double* par
 hipError_t launch_colnorms(hipStream_t s, int rows, const double* A, int lda, int w, double* gram_scratch,
                            double* partial, int64_t partial_cap, double* out);
 
-// orthonormalising transform of a block from its Gram (one workgroup): see kernels.hip
+// Cholesky factor R of a block's Gram with the column-drop rules (one workgroup): see kernels.hip
 hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
-                             double drop_tol, double dep_tol, double* Minv, int ldm, double* scal, int slot,
+                             double drop_tol, double dep_tol, double* Rout, int ldm, double* scal, int slot,
                              int wk_slot_in);
+// out = X[:, kept] R^{-1} row by row, kept columns packed left, the rest zero
+hipError_t launch_trsm_rows(hipStream_t s, int rows, const double* X, int ldx, int w, const double* R, int ldr,
+                           double* out, int ldo);
 
 // sampled product on Lambda (CSC order) with residual and dual update; per-block partial sums of
 // res^2 and y_next^2 land in partial[2 b], partial[2 b + 1]; returns the number of blocks
@@ -157,7 +171,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const double* src, int lds,
 // Jacobi eigen-decomposition of a b x b symmetric matrix (b <= kEigMax) in one workgroup.
 // Eigenvalues descending into eval, eigenvectors as columns of evec (row-major, ld = ldv).
 hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double* eval, double* evec, int ldv,
-                         double* scal, int slot);
+                         double* scal, int slot, int max_sweeps = 40);
 // residual column norms ||Z[:, c] - theta_c V[:, c]|| for c < b
 hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const double* V, int ld, int b,
                                 const double* theta, double* partial, double* out);

@@ -53,6 +53,7 @@ SHAPES = [
     (130, 110, 4, 0.35, 33, {"dt": 7}),          # ragged sizes, basis grows past one eigen block
     (64, 64, 2, 0.5, 34, {"t0": 5, "npow": 1}),   # power iterations
     (150, 40, 3, 0.6, 35, {"eps_thr0": 0.3}),     # tall, explicit threshold
+    (500, 400, 2, 0.04, 36, {"t0": 12}),          # 4% observed: gather path for Y^T Q
 ]
 
 
