@@ -66,39 +66,25 @@ def cpu_baseline(w, r, seed, budget_s=20.0):
                       f"blocks; {el:.1f} s wall on the host, BLAS threads={threads}, scipy sparse products single-threaded"}
 
 
-def time_to_tolerance(svt, W, stream, seed):
+def time_to_tolerance(svt, W, stream, seed, precision):
     import torch
     w = W.planted()
     h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, stream=stream, tau=w.tau, delta=w.delta, seed=seed, maxit=1000,
-                     tol=w.tol)
+                     tol=w.tol, precision=precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = h.iterate(1000)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    return {"workload": "planted 1000x1000 rank 10, 20% observed, tau=5 sqrt(mn), delta=1.2 mn/|Lambda|",
-            "tol": w.tol, "seconds": el, "iterations": st.iter, "converged": bool(st.stopped),
-            "rel_res": st.rel_res, "r_final": st.r, "k_final": st.k}
+    return {"seconds": el, "iterations": st.iter, "converged": bool(st.stopped), "rel_res": st.rel_res,
+            "r_final": st.r, "k_final": st.k}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the multi-GPU column "
-              f"sharding is a design, not part of this build)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def run_form(svt, w, stream, args, precision):
+    """Warm up, then time args.steps SVT iterations of one precision form with per-phase events."""
     import torch
-
-    import paper_1704_05528_amd as svt
-    import svt_workloads as W
-
-    svt.require_gpu()
-    torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
-    w = W.image()
     h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, stream=stream, tau=w.tau, delta=w.delta, seed=args.seed,
-                     maxit=args.warmup + args.steps + 1000)
+                     maxit=args.warmup + args.steps + 1000, precision=precision)
     if args.warmup > 0:
         h.iterate(args.warmup)
     torch.cuda.synchronize()
@@ -117,7 +103,7 @@ def main():
     h.profile(False)
     n_it = len(stats)
     r_vals = [s[0] for s in stats]
-
+    es = 4.0 if precision else 8.0
     # roofline of the dominant single-kernel phase
     kernels = {"spmm_t": "hbm", "sddmm": "hbm", "gram": "alu"}
     dom = max(kernels, key=lambda ph: prof[ph]["ms"])
@@ -137,21 +123,48 @@ def main():
                    "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None,
                    "TFLOP_s": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
               for ph, v in prof.items()}
+    return {"iters_per_s": n_it / el, "ms_per_step": 1e3 * el / max(n_it, 1), "steps": n_it,
+            "iterations_timed": [args.warmup + 1, args.warmup + n_it], "r_range": [min(r_vals), max(r_vals)],
+            "r_mean": float(sum(r_vals) / len(r_vals)), "k_last": stats[-1][1],
+            "growth_blocks": int(sum(s[2] for s in stats)), "eig_products": int(sum(s[3] for s in stats)),
+            "rel_res_last": stats[-1][4], "bytes_per_value": es, "roofline": roof, "phases": phases}
 
-    out = {"metric": METRIC, "value": n_it / el, "unit": "iters/s", "n_gpus": 1, "steps": n_it,
-           "warmup": args.warmup, "ms_per_step": 1e3 * el / max(n_it, 1), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the multi-GPU column "
+              f"sharding is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import paper_1704_05528_amd as svt
+    import svt_workloads as W
+    import torch
+
+    svt.require_gpu()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    w = W.image()
+    mixed = run_form(svt, w, stream, args, svt.SVT_MIXED)
+    fp64 = run_form(svt, w, stream, args, svt.SVT_FP64)
+    out = {"metric": METRIC, "value": mixed["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": mixed["steps"],
+           "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage / f64 Gram+eig (mixed form)",
+           "data": "synthetic",
            "config": {"workload": "image 1024x1024, 40 separable cosine patterns + N(0,0.01^2), 50% observed, "
-                                  "tau=||P_Lambda A||_F, delta=sqrt(mn/|Lambda|), FP64 form",
-                      "m": w.m, "n": w.n, "nnz": w.nnz, "iterations_timed": [args.warmup + 1, args.warmup + n_it],
-                      "r_range": [min(r_vals), max(r_vals)], "k_last": stats[-1][1],
-                      "growth_blocks": int(sum(s[2] for s in stats)),
-                      "eig_iters": int(sum(s[3] for s in stats)), "rel_res_last": stats[-1][4]},
-           "roofline": roof, "phases": phases}
+                                  "tau=||P_Lambda A||_F, delta=sqrt(mn/|Lambda|)",
+                      "m": w.m, "n": w.n, "nnz": w.nnz, "form": "mixed (float32 storage, float64 Gram/eig)"},
+           "roofline": mixed["roofline"],
+           "mixed": mixed, "fp64": fp64, "speedup_mixed_vs_fp64": mixed["iters_per_s"] / fp64["iters_per_s"]}
     if not args.no_ttt:
-        out["time_to_tol"] = time_to_tolerance(svt, W, stream, args.seed)
+        t_mixed = time_to_tolerance(svt, W, stream, args.seed, svt.SVT_MIXED)
+        t_fp64 = time_to_tolerance(svt, W, stream, args.seed, svt.SVT_FP64)
+        out["time_to_tol"] = {"workload": "planted 1000x1000 rank 10, 20% observed, tau=5 sqrt(mn), "
+                                          "delta=1.2 mn/|Lambda|, tol 1e-4",
+                              "mixed": t_mixed, "fp64": t_fp64,
+                              "speedup_mixed_vs_fp64": t_fp64["seconds"] / t_mixed["seconds"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, int(round(float(np.mean(r_vals)))), args.seed)
+        out["cpu_baseline"] = cpu_baseline(w, int(round(fp64["r_mean"])), args.seed)
+        out["cpu_baseline"]["gpu_fp64_speedup"] = fp64["iters_per_s"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 
 

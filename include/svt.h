@@ -57,7 +57,9 @@ typedef enum {
 /* Precision forms. */
 enum {
   SVT_FP64 = 0,  /* every stored value and every accumulation in float64 */
-  SVT_MIXED = 1  /* y, a, W, factors float32; basis Q bfloat16; Gram/Cholesky/eig float64 */
+  SVT_MIXED = 1  /* float32 storage of y, a, Q, W, sampled blocks and factors, float32 accumulation in
+                    the sparse products and the sampled update; float64 Gram matrices, Cholesky,
+                    eigen-solver and every norm and reduction */
 };
 
 /* Bits of svt_step_stats.flags. */

@@ -1,8 +1,12 @@
 // Streaming kernels of the SVT / R4SVD hot path for gfx950 (wave64).
 //
-// Every reduction is deterministic: per-workgroup partial sums in a fixed
-// butterfly order, then one workgroup adds the partials in index order.
-// No floating-point atomics are used anywhere.
+// Kernels that touch the iterate Y, the basis Q, the projection W = Y^T Q, sampled blocks
+// and the factors of X are templates over the storage type T: double in the FP64 form,
+// float in the mixed form.  Sparse products and the sampled product accumulate in T; Gram
+// matrices, norms and every reduction accumulate in double.
+//
+// Every reduction is deterministic: per-workgroup partial sums in a fixed butterfly order,
+// then one workgroup adds the partials in index order.  No floating-point atomics are used.
 #include "svt_internal.h"
 
 #include <algorithm>
@@ -17,7 +21,13 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum over a 256-thread workgroup; the result is valid in thread 0.
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.
 __device__ inline double block_sum(double v, double* lds) {
   v = wave_sum(v);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -65,8 +75,8 @@ __device__ inline void gaussian4(uint64_t j, uint64_t q, uint64_t blk, uint64_t 
 }
 
 // om[j, c] for rows j < n and block columns c0 <= c < c0 + w (c0 a multiple of 4), stored at om[j*ld + c - c0].
-__global__ void k_omega(double* __restrict__ om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
-                        uint64_t it) {
+template <class T>
+__global__ void k_omega(T* __restrict__ om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk, uint64_t it) {
   const int ng = (w + 3) / 4;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * ng) return;
@@ -75,10 +85,10 @@ __global__ void k_omega(double* __restrict__ om, int n, int c0, int w, int ld, u
   gaussian4((uint64_t)j, (uint64_t)(c0 / 4 + g), blk, it, seed, z);
 #pragma unroll
   for (int l = 0; l < 4; ++l)
-    if (4 * g + l < w) om[(int64_t)j * ld + 4 * g + l] = z[l];
+    if (4 * g + l < w) om[(int64_t)j * ld + 4 * g + l] = (T)z[l];
 }
 
-// Gaussian fill of columns [c0, c1) of a rows x ld block, rows >= valid_rows set to zero (warm starts).
+// Gaussian fill of columns [c0, c1) of a rows x ld block (eigensolver start vectors).
 __global__ void k_fill_random(double* __restrict__ V, int rows, int ld, int c0, int c1, uint64_t seed, uint64_t tag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = c1 - c0;
@@ -104,54 +114,52 @@ __global__ void k_set_unit(double* __restrict__ V, int rows, int ld, int c0, int
 // ------------------------------------------------------------------------------------------
 
 // Narrow blocks (w <= 16): lanes stride over the nonzeros, each keeps w partial sums.
-template <int WN>
+template <int WN, class T>
 __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
-                                                         const int32_t* __restrict__ vperm,
-                                                         const double* __restrict__ val,
-                                                         const double* __restrict__ D, int ldd,
-                                                         double* __restrict__ out, int ldo, int w) {
+                                                         const int32_t* __restrict__ vperm, const T* __restrict__ val,
+                                                         const T* __restrict__ D, int ldd, T* __restrict__ out,
+                                                         int ldo, int w) {
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= nrows) return;
-  double acc[WN];
+  T acc[WN];
 #pragma unroll
-  for (int c = 0; c < WN; ++c) acc[c] = 0.0;
+  for (int c = 0; c < WN; ++c) acc[c] = (T)0;
   const int p0 = ptr[row], p1 = ptr[row + 1];
   for (int p = p0 + lane; p < p1; p += kWave) {
-    const double v = val[vperm ? vperm[p] : p];
-    const double* d = D + (int64_t)idx[p] * ldd;
+    const T v = val[vperm ? vperm[p] : p];
+    const T* d = D + (int64_t)idx[p] * ldd;
 #pragma unroll
     for (int c = 0; c < WN; ++c)
       if (c < w) acc[c] = fma(v, d[c], acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < WN; ++c) {
-    const double s = wave_sum(acc[c]);
+    const T s = wave_sum(acc[c]);
     if (lane == 0 && c < w) out[(int64_t)row * ldo + c] = s;
   }
 }
 
 // Wide blocks: lanes over output columns (CPL per lane), nonzeros broadcast across the wave.
-template <int CPL>
+template <int CPL, class T>
 __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ idx,
-                                                       const int32_t* __restrict__ vperm,
-                                                       const double* __restrict__ val,
-                                                       const double* __restrict__ D, int ldd,
-                                                       double* __restrict__ out, int ldo, int w) {
+                                                       const int32_t* __restrict__ vperm, const T* __restrict__ val,
+                                                       const T* __restrict__ D, int ldd, T* __restrict__ out, int ldo,
+                                                       int w) {
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= nrows) return;
   const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
-  double acc[CPL];
+  T acc[CPL];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) acc[c] = 0.0;
+  for (int c = 0; c < CPL; ++c) acc[c] = (T)0;
   const int p0 = ptr[row], p1 = ptr[row + 1];
   for (int base = p0; base < p1; base += kWave) {
     const int p = base + lane;
     int my_i = 0;
-    double my_v = 0.0;
+    T my_v = (T)0;
     if (p < p1) {
       my_i = idx[p];
       my_v = val[vperm ? vperm[p] : p];
@@ -159,8 +167,8 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
     const int cnt = min(kWave, p1 - base);
     for (int t = 0; t < cnt; ++t) {
       const int ii = __shfl(my_i, t, kWave);
-      const double vv = __shfl(my_v, t, kWave);
-      const double* d = D + (int64_t)ii * ldd + c0;
+      const T vv = __shfl(my_v, t, kWave);
+      const T* d = D + (int64_t)ii * ldd + c0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c)
         if (c0 + c < w) acc[c] = fma(vv, d[c], acc[c]);
@@ -172,12 +180,96 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
 }
 
 // ------------------------------------------------------------------------------------------
-// Row-wise small product: out[i, g0:g0+16] = beta * out + alpha * A[i, 0:K] M[0:K, g0:g0+16].
-// One wave per row, lanes stride over K.  Used for X -= Q (Q^T X), X R^-1, Q C, W D, G V.
+// LDS-tiled W = Y^T Q for inputs where most RT x JB tiles of Y hold observed entries (image-
+// like sampling densities).  A workgroup owns JB columns of Y (rows of W) and CB columns of Q;
+// for each RT-row tile it scatters the tile's observed values into a zero-filled LDS tile,
+// stages Q[i0:i0+RT, c0:c0+CB], and accumulates 4 x 4 register blocks.  tstart[j*(nt+1)+t] is
+// the first CSC position of column j with row >= t*RT (built once from the fixed pattern).
+// Row tiles are split over blockIdx.z; split s writes its sum to out + s * split_stride.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const double* __restrict__ A, int lda,
-                                                const double* __restrict__ M, int ldm, double* __restrict__ out,
-                                                int ldo, int w, double alpha, double beta) {
+constexpr int kTR = 32, kTJ = 64, kTC = 64;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_t* __restrict__ rowidx,
+                                                      const int32_t* __restrict__ tstart, int nt,
+                                                      const T* __restrict__ val, const T* __restrict__ Q, int ldq,
+                                                      int r, T* __restrict__ out, int ldo, int tiles_per_split,
+                                                      int64_t split_stride) {
+  __shared__ T Ys[kTR][kTJ + 2];
+  __shared__ T Qs[kTR][kTC + 2];
+  const int tid = threadIdx.x;
+  const int j0 = blockIdx.x * kTJ, c0 = blockIdx.y * kTC;
+  const int tj = tid / 16, tc = tid % 16;
+  const int t_begin = blockIdx.z * tiles_per_split, t_end = min(nt, t_begin + tiles_per_split);
+  T acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = (T)0;
+  // scatter roles: 4 threads per column j of the tile
+  const int sj = tid / 4, ssub = tid % 4;
+  const int gj = j0 + sj;
+  for (int t = t_begin; t < t_end; ++t) {
+    const int i0 = t * kTR;
+    for (int e = tid; e < kTR * kTJ; e += 256) Ys[e / kTJ][e % kTJ] = (T)0;
+    for (int e = tid; e < kTR * kTC; e += 256) {
+      const int i = e / kTC, c = e % kTC;
+      Qs[i][c] = (i0 + i < m && c0 + c < r) ? Q[(int64_t)(i0 + i) * ldq + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    if (gj < n) {
+      const int p1 = tstart[(int64_t)gj * (nt + 1) + t + 1];
+      for (int p = tstart[(int64_t)gj * (nt + 1) + t] + ssub; p < p1; p += 4) Ys[rowidx[p] - i0][sj] = val[p];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = 0; i < kTR; ++i) {
+      T a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Ys[i][tj * 4 + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Qs[i][tc * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  T* o = out + blockIdx.z * split_stride;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + tj * 4 + u;
+    if (j >= n) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = c0 + tc * 4 + v;
+      if (c < r) o[(int64_t)j * ldo + c] = acc[u][v];
+    }
+  }
+}
+
+// W[j, c] = sum_s partial[s][j][c] in split order
+template <class T>
+__global__ void k_split_sum(int n, int r, const T* __restrict__ partial, int splits, int64_t split_stride, int ldp,
+                            T* __restrict__ W, int ldw) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * r) return;
+  const int j = (int)(t / r), c = (int)(t % r);
+  T v = (T)0;
+  for (int s = 0; s < splits; ++s) v += partial[s * split_stride + (int64_t)j * ldp + c];
+  W[(int64_t)j * ldw + c] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-wise small product: out[i, g0:g0+16] = beta * out + alpha * A[i, 0:K] M[0:K, g0:g0+16],
+// accumulated in double.  One wave per row, lanes stride over K.  Used for X -= Q (Q^T X),
+// Q C, W D, G V, V S.
+// ------------------------------------------------------------------------------------------
+template <class TA, class TM, class TO>
+__global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
+                                                const TM* __restrict__ M, int ldm, TO* __restrict__ out, int ldo,
+                                                int w, double alpha, double beta) {
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= rows) return;
@@ -185,30 +277,31 @@ __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const double* _
   double acc[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-  const double* a = A + (int64_t)row * lda;
+  const TA* a = A + (int64_t)row * lda;
   for (int c = lane; c < K; c += kWave) {
-    const double av = a[c];
-    const double* mr = M + (int64_t)c * ldm + g0;
+    const double av = (double)a[c];
+    const TM* mr = M + (int64_t)c * ldm + g0;
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      if (g0 + j < w) acc[j] = fma(av, mr[j], acc[j]);
+      if (g0 + j < w) acc[j] = fma(av, (double)mr[j], acc[j]);
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double s = wave_sum(acc[j]);
     if (lane == 0 && g0 + j < w) {
-      double* o = out + (int64_t)row * ldo + g0 + j;
-      *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * s;
+      TO* o = out + (int64_t)row * ldo + g0 + j;
+      *o = (TO)((beta == 0.0 ? 0.0 : beta * (double)*o) + alpha * s);
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// Tall-skinny A^T B with a narrow B (nb columns in groups of 16), split over rows.
-// partial[s][a][b] = sum_{i in split s} A[i, a] B[i, b]; then k_tn_finish sums the splits.
+// Tall-skinny A^T B with a narrow B (nb columns in groups of 16), split over rows, double
+// accumulation.  partial[s][a][b] = sum_{i in split s} A[i, a] B[i, b]; k_tn_finish sums.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tn_narrow(int rows, const double* __restrict__ A, int lda, int na,
-                                                   const double* __restrict__ B, int ldb, int nb,
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restrict__ A, int lda, int na,
+                                                   const TB* __restrict__ B, int ldb, int nb,
                                                    double* __restrict__ partial, int rows_per_split) {
   __shared__ double red[4][16][kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -221,17 +314,16 @@ __global__ __launch_bounds__(256) void k_tn_narrow(int rows, const double* __res
   for (int j = 0; j < 16; ++j) acc[j] = 0.0;
   if (a < na) {
     for (int i = i0 + wid; i < i1; i += 4) {
-      const double av = A[(int64_t)i * lda + a];
-      const double* br = B + (int64_t)i * ldb + g0;
+      const double av = (double)A[(int64_t)i * lda + a];
+      const TB* br = B + (int64_t)i * ldb + g0;
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        if (g0 + j < nb) acc[j] = fma(av, br[j], acc[j]);
+        if (g0 + j < nb) acc[j] = fma(av, (double)br[j], acc[j]);
     }
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j) red[wid][j][lane] = acc[j];
   __syncthreads();
-  // 4 waves -> one value per (a, j): thread t handles j = t / 64 * 4 .. +3 for its lane
   for (int e = threadIdx.x; e < 16 * kWave; e += blockDim.x) {
     const int j = e / kWave, l = e % kWave;
     const int aa = blockIdx.x * kWave + l;
@@ -253,18 +345,21 @@ __global__ void k_tn_finish(const double* __restrict__ partial, int splits, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// Gram G = A^T A (na x na) for a tall A: 64 x 64 output tiles of the upper triangle,
+// Gram G = A^T A (na x na, double) for a tall A: 64 x 64 output tiles of the upper triangle,
 // 16-row LDS stages, 4 x 4 outputs per thread, split over rows; k_gram_finish mirrors.
 // ------------------------------------------------------------------------------------------
 constexpr int kGT = 64, kGK = 16;
 
-__global__ __launch_bounds__(256) void k_gram_tiles(int rows, const double* __restrict__ A, int lda, int na,
-                                                    double* __restrict__ partial, int rows_per_split,
-                                                    int ntile) {
+template <class T>
+__global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
+                                                    double* __restrict__ partial, int rows_per_split, int ntile) {
   __shared__ double sa[kGK][kGT + 1], sb[kGK][kGT + 1];
   // map blockIdx.x to an upper-triangular tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
-  while (t >= ntile - ti) { t -= ntile - ti; ++ti; }
+  while (t >= ntile - ti) {
+    t -= ntile - ti;
+    ++ti;
+  }
   const int tj = ti + t;
   const int s = blockIdx.y;
   const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
@@ -279,8 +374,8 @@ __global__ __launch_bounds__(256) void k_gram_tiles(int rows, const double* __re
     for (int e = threadIdx.x; e < kGK * kGT; e += blockDim.x) {
       const int rr = e / kGT, cc = e % kGT;
       const int i = ib + rr;
-      sa[rr][cc] = (i < i1 && a0 + cc < na) ? A[(int64_t)i * lda + a0 + cc] : 0.0;
-      sb[rr][cc] = (i < i1 && b0 + cc < na) ? A[(int64_t)i * lda + b0 + cc] : 0.0;
+      sa[rr][cc] = (i < i1 && a0 + cc < na) ? (double)A[(int64_t)i * lda + a0 + cc] : 0.0;
+      sb[rr][cc] = (i < i1 && b0 + cc < na) ? (double)A[(int64_t)i * lda + b0 + cc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -321,34 +416,37 @@ __global__ void k_gram_finish(const double* __restrict__ partial, int splits, in
 }
 
 // ------------------------------------------------------------------------------------------
-// Reductions
+// Reductions (double accumulation)
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sumsq_cols(int rows, const double* __restrict__ A, int lda, int c0, int w,
+template <class T>
+__global__ __launch_bounds__(256) void k_sumsq_cols(int rows, const T* __restrict__ A, int lda, int c0, int w,
                                                     double* __restrict__ partial) {
   __shared__ double lds[4];
   double v = 0.0;
   const int64_t total = (int64_t)rows * w;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / w), c = (int)(e % w);
-    const double x = A[(int64_t)i * lda + c0 + c];
+    const double x = (double)A[(int64_t)i * lda + c0 + c];
     v = fma(x, x, v);
   }
   const double s = block_sum(v, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_sumsq(int64_t len, const double* __restrict__ x,
-                                               double* __restrict__ partial) {
+template <class T>
+__global__ __launch_bounds__(256) void k_sumsq(int64_t len, const T* __restrict__ x, double* __restrict__ partial) {
   __shared__ double lds[4];
   double v = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
-    v = fma(x[e], x[e], v);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+    const double xe = (double)x[e];
+    v = fma(xe, xe, v);
+  }
   const double s = block_sum(v, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// scal[slot + q] = sum_b partial[b * stride + q] for q < nq (nq <= 4): one workgroup, each thread
-// sums a fixed strided subset, then a fixed butterfly and wave order (deterministic).
+// scal[slot + q] = sum_b partial[b * stride + q] for q < nq: one workgroup, each thread sums a
+// fixed strided subset, then a fixed butterfly and wave order (deterministic).
 __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int nblocks, int stride, int nq,
                                                 double* scal, int slot) {
   __shared__ double lds[4];
@@ -360,98 +458,18 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ parti
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// LDS-tiled W = Y^T Q for inputs where most RT x JB tiles of Y hold observed entries (image-
-// like sampling densities).  A workgroup owns JB columns of Y (rows of W) and CB columns of Q;
-// for each RT-row tile it scatters the tile's observed values into a zero-filled LDS tile,
-// stages Q[i0:i0+RT, c0:c0+CB], and accumulates 4 x 4 register blocks.  tstart[j*(nt+1)+t] is
-// the first CSC position of column j with row >= t*RT (built once from the fixed pattern).
-// Row tiles are split over blockIdx.z; split s writes its sum to out + s * split_stride.
-// ------------------------------------------------------------------------------------------
-constexpr int kTR = 32, kTJ = 64, kTC = 64;
-
-__global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_t* __restrict__ rowidx,
-                                                      const int32_t* __restrict__ tstart, int nt,
-                                                      const double* __restrict__ val, const double* __restrict__ Q,
-                                                      int ldq, int r, double* __restrict__ out, int ldo,
-                                                      int tiles_per_split, int64_t split_stride) {
-  __shared__ double Ys[kTR][kTJ + 2];
-  __shared__ double Qs[kTR][kTC + 2];
-  const int tid = threadIdx.x;
-  const int j0 = blockIdx.x * kTJ, c0 = blockIdx.y * kTC;
-  const int tj = tid / 16, tc = tid % 16;
-  const int t_begin = blockIdx.z * tiles_per_split, t_end = min(nt, t_begin + tiles_per_split);
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  // scatter roles: 4 threads per column j of the tile
-  const int sj = tid / 4, ssub = tid % 4;
-  const int gj = j0 + sj;
-  for (int t = t_begin; t < t_end; ++t) {
-    const int i0 = t * kTR;
-    for (int e = tid; e < kTR * kTJ; e += 256) Ys[e / kTJ][e % kTJ] = 0.0;
-    for (int e = tid; e < kTR * kTC; e += 256) {
-      const int i = e / kTC, c = e % kTC;
-      Qs[i][c] = (i0 + i < m && c0 + c < r) ? Q[(int64_t)(i0 + i) * ldq + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (gj < n) {
-      const int p1 = tstart[(int64_t)gj * (nt + 1) + t + 1];
-      for (int p = tstart[(int64_t)gj * (nt + 1) + t] + ssub; p < p1; p += 4) Ys[rowidx[p] - i0][sj] = val[p];
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int i = 0; i < kTR; ++i) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = Ys[i][tj * 4 + u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Qs[i][tc * 4 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-  double* o = out + blockIdx.z * split_stride;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int j = j0 + tj * 4 + u;
-    if (j >= n) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int c = c0 + tc * 4 + v;
-      if (c < r) o[(int64_t)j * ldo + c] = acc[u][v];
-    }
-  }
-}
-
-// W[j, c] = sum_s partial[s][j][c] in split order
-__global__ void k_split_sum(int n, int r, const double* __restrict__ partial, int splits, int64_t split_stride,
-                            int ldp, double* __restrict__ W, int ldw) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * r) return;
-  const int j = (int)(t / r), c = (int)(t % r);
-  double v = 0.0;
-  for (int s = 0; s < splits; ++s) v += partial[s * split_stride + (int64_t)j * ldp + c];
-  W[(int64_t)j * ldw + c] = v;
-}
-
 __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < w) out[c] = sqrt(fmax(G[(int64_t)c * ldg + c], 0.0));
 }
 
 // ------------------------------------------------------------------------------------------
-// Orthonormalising transform of a block (CholeskyQR with column dropping), one workgroup.
+// Cholesky factor of a block's Gram (CholeskyQR with column dropping), one workgroup, double.
 // Input: the w x w Gram of the projected block and the column norms before projection.
 // A column c is dropped when its projected norm is at most drop_tol * prenorm[c] (it lies in
 // the span of the basis it was projected against; skipped when prenorm == nullptr), or when
 // its Cholesky pivot is at most dep_tol times its projected norm (it depends on the kept
-// columns before it; a Gram-based pivot cannot resolve dependence much below 1e-8).  The kept
+// columns before it; a Gram-based pivot cannot resolve dependence much below 1e-8).  The
 // factor R (upper, R^T R = Gram of the kept columns) goes to Rout for k_trsm_rows, which writes
 // X_new = X[:, kept] R^{-1}: wk orthonormal columns followed by zero columns.  If wk_in >= 0
 // only the first wk_in columns take part (second pass of CholeskyQR2 reads the count of the
@@ -459,11 +477,11 @@ __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int w,
                                                     const double* __restrict__ prenorm, double drop_tol,
-                                                    double dep_tol, double* __restrict__ Rout, int ldm,
-                                                    double* scal, int slot, int wk_slot_in) {
+                                                    double dep_tol, double* __restrict__ Rout, int ldm, double* scal,
+                                                    int slot, int wk_slot_in) {
   extern __shared__ double sm[];
   const int ld = w + 1;
-  double* A = sm;            // w x (w + 1): Gram, overwritten by the Schur complements / rows of R
+  double* A = sm;  // w x (w + 1): Gram, overwritten by the Schur complements / rows of R
   __shared__ int keep[kEigMax];
   __shared__ double gdiag[kEigMax];
   const int tid = threadIdx.x;
@@ -484,7 +502,7 @@ __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ g
   // d = A[c][c] (the Schur complement) and takes the same keep decision; a kept column then
   // updates the trailing upper triangle A[i][j] -= A[c][i] A[c][j] / d, i, j > c.
   for (int c = 0; c < wa; ++c) {
-    if (!keep[c]) continue;            // uniform: keep[] only changes below, after a barrier
+    if (!keep[c]) continue;  // uniform: keep[] only changes below, after a barrier
     const double d = A[c * ld + c];
     const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
     if (ok) {
@@ -519,14 +537,14 @@ __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ g
 
 // ------------------------------------------------------------------------------------------
 // Row-wise solve Z R = X for the factor of k_block_chol: one thread per row, forward
-// substitution over the columns with R broadcast from LDS; the kept columns are written packed
-// to the left of out and the remaining columns are zero.
+// substitution in double over the columns with R broadcast from LDS; the kept columns are
+// written packed to the left of out and the remaining columns are zero.
 // ------------------------------------------------------------------------------------------
-template <int WM>
-__global__ __launch_bounds__(256) void k_trsm_rows(int rows, const double* __restrict__ X, int ldx, int w,
-                                                   const double* __restrict__ R, int ldr, double* __restrict__ out,
+template <int WM, class T>
+__global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict__ X, int ldx, int w,
+                                                   const double* __restrict__ R, int ldr, T* __restrict__ out,
                                                    int ldo) {
-  extern __shared__ double Rs[];   // w x (w + 1)
+  extern __shared__ double Rs[];  // w x (w + 1)
   const int ld = w + 1;
   for (int e = threadIdx.x; e < w * w; e += blockDim.x) Rs[(e / w) * ld + e % w] = R[(int64_t)(e / w) * ldr + e % w];
   __syncthreads();
@@ -534,7 +552,7 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const double* __res
   if (i >= rows) return;
   double z[WM];
 #pragma unroll
-  for (int c = 0; c < WM; ++c) z[c] = (c < w) ? X[(int64_t)i * ldx + c] : 0.0;
+  for (int c = 0; c < WM; ++c) z[c] = (c < w) ? (double)X[(int64_t)i * ldx + c] : 0.0;
 #pragma unroll
   for (int c = 0; c < WM; ++c) {
     if (c < w) {
@@ -545,27 +563,28 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const double* __res
       z[c] = (rcc != 0.0) ? v / rcc : 0.0;
     }
   }
-  double* o = out + (int64_t)i * ldo;
+  T* o = out + (int64_t)i * ldo;
   int q = 0;
 #pragma unroll
   for (int c = 0; c < WM; ++c) {
-    if (c < w && Rs[c * ld + c] != 0.0) o[q++] = z[c];
+    if (c < w && Rs[c * ld + c] != 0.0) o[q++] = (T)z[c];
   }
-  for (; q < w; ++q) o[q] = 0.0;
+  for (; q < w; ++q) o[q] = (T)0;
 }
 
 // ------------------------------------------------------------------------------------------
 // Fused sampled product and dual update on Lambda (CSC order), Eq. 4 with X = Ut Vt^T:
 //   x = <Ut[i,:], Vt[j,:]>, res = a - x, y_next = y + delta res, sums of res^2 and y_next^2.
-// One wave per column j; Vt[j, :] staged in LDS.
+// One wave per column j; Vt[j, :] staged in LDS.  The dot product and the update run in T;
+// the two sums accumulate in double.
 // ------------------------------------------------------------------------------------------
+template <class T>
 __global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __restrict__ colptr,
-                                                      const int32_t* __restrict__ rowidx,
-                                                      const double* __restrict__ a, const double* __restrict__ y,
-                                                      double* __restrict__ y_next, double* __restrict__ x_out,
-                                                      const double* __restrict__ Ut, const double* __restrict__ Vt,
-                                                      int ld, int k, double delta, double* __restrict__ partial) {
-  __shared__ double vs[4][kEigMax];
+                                                      const int32_t* __restrict__ rowidx, const T* __restrict__ a,
+                                                      const T* __restrict__ y, T* __restrict__ y_next,
+                                                      const T* __restrict__ Ut, const T* __restrict__ Vt, int ld,
+                                                      int k, T delta, double* __restrict__ partial) {
+  __shared__ T vs[4][kEigMax];
   __shared__ double lds[4];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int j = blockIdx.x * 4 + wid;
@@ -577,15 +596,14 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __re
   if (j < n) {
     const int p0 = colptr[j], p1 = colptr[j + 1];
     for (int p = p0 + lane; p < p1; p += kWave) {
-      const double* u = Ut + (int64_t)rowidx[p] * ld;
-      double x = 0.0;
+      const T* u = Ut + (int64_t)rowidx[p] * ld;
+      T x = (T)0;
       for (int l = 0; l < k; ++l) x = fma(u[l], vs[wid][l], x);
-      const double res = a[p] - x;
-      const double yn = fma(delta, res, y[p]);
+      const T res = a[p] - x;
+      const T yn = fma(delta, res, y[p]);
       y_next[p] = yn;
-      if (x_out) x_out[p] = x;
-      s_res = fma(res, res, s_res);
-      s_y = fma(yn, yn, s_y);
+      s_res = fma((double)res, (double)res, s_res);
+      s_y = fma((double)yn, (double)yn, s_y);
     }
   }
   const double t0 = block_sum(s_res, lds);
@@ -596,29 +614,30 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __re
   }
 }
 
+template <class T>
 __global__ void k_sample(int64_t nq, const int32_t* __restrict__ qi, const int32_t* __restrict__ qj,
-                         const double* __restrict__ Ut, const double* __restrict__ Vt, int ld, int k,
-                         double* __restrict__ out) {
+                         const T* __restrict__ Ut, const T* __restrict__ Vt, int ld, int k, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq) return;
-  const double* u = Ut + (int64_t)qi[t] * ld;
-  const double* v = Vt + (int64_t)qj[t] * ld;
-  double x = 0.0;
+  const T* u = Ut + (int64_t)qi[t] * ld;
+  const T* v = Vt + (int64_t)qj[t] * ld;
+  T x = (T)0;
   for (int l = 0; l < k; ++l) x = fma(u[l], v[l], x);
-  out[t] = x;
+  out[t] = (double)x;
 }
 
-__global__ void k_scale_copy(int64_t len, const double* __restrict__ src, double alpha, double* __restrict__ dst) {
+template <class TS, class TD>
+__global__ void k_scale_copy(int64_t len, const TS* __restrict__ src, double alpha, TD* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < len) dst[t] = alpha * src[t];
+  if (t < len) dst[t] = (TD)(alpha * (double)src[t]);
 }
 
-__global__ void k_copy_cols(int rows, const double* __restrict__ src, int lds_, double* __restrict__ dst, int ldd,
-                            int w) {
+template <class TS, class TD>
+__global__ void k_copy_cols(int rows, const TS* __restrict__ src, int lds_, TD* __restrict__ dst, int ldd, int w) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)rows * w) return;
   const int i = (int)(t / w), c = (int)(t % w);
-  dst[(int64_t)i * ldd + c] = src[(int64_t)i * lds_ + c];
+  dst[(int64_t)i * ldd + c] = (TD)src[(int64_t)i * lds_ + c];
 }
 
 inline unsigned grid1(int64_t work, int per = 256) { return (unsigned)((work + per - 1) / per); }
@@ -628,11 +647,14 @@ inline unsigned grid1(int64_t work, int per = 256) { return (unsigned)((work + p
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-hipError_t launch_omega(hipStream_t s, double* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
+int tiled_row_tiles(int64_t m) { return (int)((m + kTR - 1) / kTR); }
+
+template <class T>
+hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
                         uint64_t it) {
   const int64_t work = (int64_t)n * ((w + 3) / 4);
   if (work == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_omega, dim3(grid1(work)), dim3(256), 0, s, om, n, c0, w, ld, seed, blk, it);
+  hipLaunchKernelGGL(k_omega<T>, dim3(grid1(work)), dim3(256), 0, s, om, n, c0, w, ld, seed, blk, it);
   return hipGetLastError();
 }
 
@@ -644,24 +666,6 @@ hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0
   return hipGetLastError();
 }
 
-hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const double* val, const double* D, int ldd, double* out, int ldo, int w) {
-  if (nrows == 0 || w == 0) return hipSuccess;
-  const unsigned gx = (unsigned)((nrows + 3) / 4);
-  if (w <= kNarrow) {
-    hipLaunchKernelGGL(k_seg_spmm_narrow<kNarrow>, dim3(gx), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
-                       out, ldo, w);
-  } else {
-    constexpr int CPL = 4;
-    const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
-    hipLaunchKernelGGL(k_seg_spmm_wide<CPL>, dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
-                       out, ldo, w);
-  }
-  return hipGetLastError();
-}
-
-int tiled_row_tiles(int64_t m) { return (int)((m + kTR - 1) / kTR); }
-
 hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0) {
   const int64_t work = (int64_t)rows * count;
   if (work <= 0) return hipSuccess;
@@ -669,9 +673,27 @@ hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, i
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w) {
+  if (nrows == 0 || w == 0) return hipSuccess;
+  const unsigned gx = (unsigned)((nrows + 3) / 4);
+  if (w <= kNarrow) {
+    hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, T>), dim3(gx), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D,
+                       ldd, out, ldo, w);
+  } else {
+    constexpr int CPL = 4;
+    const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
+    hipLaunchKernelGGL((k_seg_spmm_wide<CPL, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
+                       out, ldo, w);
+  }
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
-                               const double* val, const double* Q, int ldq, int r, double* W, int ldw,
-                               double* partial, int64_t partial_cap) {
+                               const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
+                               int64_t partial_cap) {
   if (n == 0 || r == 0) return hipSuccess;
   const int nt = tiled_row_tiles(m);
   const int gx = (n + kTJ - 1) / kTJ, gy = (r + kTC - 1) / kTC;
@@ -680,91 +702,97 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
   const int tps = (nt + splits - 1) / splits;
   splits = (nt + tps - 1) / tps;
   if (splits == 1) {
-    hipLaunchKernelGGL(k_spmm_t_tiled, dim3(gx, gy, 1), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
+    hipLaunchKernelGGL(k_spmm_t_tiled<T>, dim3(gx, gy, 1), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
                        W, ldw, tps, (int64_t)0);
     return hipGetLastError();
   }
+  T* part = reinterpret_cast<T*>(partial);
   const int64_t stride = (int64_t)n * r;
-  hipLaunchKernelGGL(k_spmm_t_tiled, dim3(gx, gy, splits), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
-                     partial, r, tps, stride);
+  hipLaunchKernelGGL(k_spmm_t_tiled<T>, dim3(gx, gy, splits), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq,
+                     r, part, r, tps, stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_split_sum, dim3(grid1((int64_t)n * r)), dim3(256), 0, s, n, r, partial, splits, stride, r, W,
+  hipLaunchKernelGGL(k_split_sum<T>, dim3(grid1((int64_t)n * r)), dim3(256), 0, s, n, r, part, splits, stride, r, W,
                      ldw);
   return hipGetLastError();
 }
 
-hipError_t launch_rowmul(hipStream_t s, int rows, int K, const double* A, int lda, const double* M, int ldm,
-                         double* out, int ldo, int w, double alpha, double beta) {
+template <class TA, class TM, class TO>
+hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
+                         int w, double alpha, double beta) {
   if (rows == 0 || w == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rowmul, dim3((rows + 3) / 4, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M, ldm, out,
-                     ldo, w, alpha, beta);
+  hipLaunchKernelGGL((k_rowmul<TA, TM, TO>), dim3((rows + 3) / 4, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M,
+                     ldm, out, ldo, w, alpha, beta);
   return hipGetLastError();
 }
 
-hipError_t launch_tn_narrow(hipStream_t s, int rows, const double* A, int lda, int na, const double* B, int ldb,
-                            int nb, double* out, int ldo, double* partial, int64_t partial_cap) {
+template <class TA, class TB>
+hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
+                            double* out, int ldo, double* partial, int64_t partial_cap) {
   if (na == 0 || nb == 0) return hipSuccess;
   const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
   // enough workgroups to fill the chip: about 512 in total, at least 32 rows per split
   int splits = std::max(1, std::min(std::max(1, rows / 32), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
-  splits = std::max(1, std::min(splits, std::max(1, rows)));
   const int rps = (rows + splits - 1) / splits;
-  hipLaunchKernelGGL(k_tn_narrow, dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb, partial,
-                     std::max(rps, 1));
+  hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
+                     partial, std::max(rps, 1));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tn_finish, dim3(grid1((int64_t)na * nb)), dim3(256), 0, s, partial, splits, na, nb, out, ldo);
   return hipGetLastError();
 }
 
-hipError_t launch_gram(hipStream_t s, int rows, const double* A, int lda, int na, double* G, int ldg,
-                       double* partial, int64_t partial_cap) {
+template <class T>
+hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
+                       int64_t partial_cap) {
   if (na == 0) return hipSuccess;
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
   int splits = std::max(1, std::min(512 / ntri, rows / 256));
   while (splits > 1 && (int64_t)splits * na * na > partial_cap) --splits;
   const int rps = (rows + splits - 1) / splits;
-  hipLaunchKernelGGL(k_gram_tiles, dim3(ntri, splits), dim3(256), 0, s, rows, A, lda, na, partial, std::max(rps, 1),
-                     nt);
+  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri, splits), dim3(256), 0, s, rows, A, lda, na, partial,
+                     std::max(rps, 1), nt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_finish, dim3(grid1((int64_t)na * na)), dim3(256), 0, s, partial, splits, na, G, ldg);
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq_cols(hipStream_t s, int rows, const double* A, int lda, int c0, int w, double* partial,
+template <class T>
+hipError_t launch_sumsq_cols(hipStream_t s, int rows, const T* A, int lda, int c0, int w, double* partial,
                              double* scal, int slot) {
   const int64_t total = (int64_t)rows * w;
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (total + 255) / 256));
-  hipLaunchKernelGGL(k_sumsq_cols, dim3(nb), dim3(256), 0, s, rows, A, lda, c0, w, partial);
+  hipLaunchKernelGGL(k_sumsq_cols<T>, dim3(nb), dim3(256), 0, s, rows, A, lda, c0, w, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(hipStream_t s, int64_t len, const double* v, double* partial, double* scal, int slot) {
+template <class T>
+hipError_t launch_sumsq(hipStream_t s, int64_t len, const T* v, double* partial, double* scal, int slot) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (len + 255) / 256));
-  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, s, len, v, partial);
+  hipLaunchKernelGGL(k_sumsq<T>, dim3(nb), dim3(256), 0, s, len, v, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
   return hipGetLastError();
 }
 
-hipError_t launch_colnorms(hipStream_t s, int rows, const double* A, int lda, int w, double* gram_scratch,
-                           double* partial, int64_t partial_cap, double* out) {
-  hipError_t e = launch_tn_narrow(s, rows, A, lda, w, A, lda, w, gram_scratch, w, partial, partial_cap);
+template <class T>
+hipError_t launch_colnorms(hipStream_t s, int rows, const T* A, int lda, int w, double* gram_scratch, double* partial,
+                           int64_t partial_cap, double* out) {
+  hipError_t e = launch_tn_narrow<T, T>(s, rows, A, lda, w, A, lda, w, gram_scratch, w, partial, partial_cap);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_sqrt, dim3(1), dim3(128), 0, s, gram_scratch, w, w, out);
   return hipGetLastError();
 }
 
 hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
-                             double drop_tol, double dep_tol, double* Minv, int ldm, double* scal, int slot,
+                             double drop_tol, double dep_tol, double* Rout, int ldm, double* scal, int slot,
                              int wk_slot_in) {
   static bool attr_set = false;
   if (!attr_set) {
@@ -774,40 +802,49 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
     attr_set = true;
   }
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Minv, ldm,
+  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Rout, ldm,
                      scal, slot, wk_slot_in);
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_rows(hipStream_t s, int rows, const double* X, int ldx, int w, const double* R, int ldr,
-                           double* out, int ldo) {
-  if (rows == 0 || w == 0) return hipSuccess;
+template <int WM, class T>
+hipError_t set_trsm_attr() {
   static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_trsm_rows<kEigMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kEigMax * (kEigMax + 1) * sizeof(double)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  if (attr_set) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_trsm_rows<WM, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(kEigMax * (kEigMax + 1) * sizeof(double)));
+  if (e == hipSuccess) attr_set = true;
+  return e;
+}
+
+template <class T>
+hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
+                            int ldo) {
+  if (rows == 0 || w == 0) return hipSuccess;
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
   const unsigned g = (unsigned)((rows + 255) / 256);
+  hipError_t e;
   if (w <= 16) {
-    hipLaunchKernelGGL(k_trsm_rows<16>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    if ((e = set_trsm_attr<16, T>()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_trsm_rows<16, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   } else if (w <= 64) {
-    hipLaunchKernelGGL(k_trsm_rows<64>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    if ((e = set_trsm_attr<64, T>()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_trsm_rows<64, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   } else {
-    hipLaunchKernelGGL(k_trsm_rows<kEigMax>, dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    if ((e = set_trsm_attr<kEigMax, T>()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_trsm_rows<kEigMax, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* a,
-                               const double* y, double* y_next, double* x_out, const double* Ut, const double* Vt,
-                               int ld, int k, double delta, double* partial, int* nblocks) {
+template <class T>
+hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* a,
+                               const T* y, T* y_next, const T* Ut, const T* Vt, int ld, int k, double delta,
+                               double* partial, int* nblocks) {
   const int nb = (n + 3) / 4;
   *nblocks = nb;
-  hipLaunchKernelGGL(k_sddmm_update, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, x_out, Ut, Vt, ld,
-                     k, delta, partial);
+  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, Ut, Vt, ld, k,
+                     (T)delta, partial);
   return hipGetLastError();
 }
 
@@ -817,24 +854,64 @@ hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int 
   return hipGetLastError();
 }
 
-hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const double* Ut,
-                         const double* Vt, int ld, int k, double* out) {
+template <class T>
+hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
+                         int ld, int k, double* out) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sample, dim3(grid1(nq)), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, out);
+  hipLaunchKernelGGL(k_sample<T>, dim3(grid1(nq)), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, out);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_copy(hipStream_t s, int64_t len, const double* src, double alpha, double* dst) {
+template <class TS, class TD>
+hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst) {
   if (len == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_copy, dim3(grid1(len)), dim3(256), 0, s, len, src, alpha, dst);
+  hipLaunchKernelGGL((k_scale_copy<TS, TD>), dim3(grid1(len)), dim3(256), 0, s, len, src, alpha, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_copy_cols(hipStream_t s, int rows, const double* src, int lds_, double* dst, int ldd, int w) {
+template <class TS, class TD>
+hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD* dst, int ldd, int w) {
   const int64_t work = (int64_t)rows * w;
   if (work == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_cols, dim3(grid1(work)), dim3(256), 0, s, rows, src, lds_, dst, ldd, w);
+  hipLaunchKernelGGL((k_copy_cols<TS, TD>), dim3(grid1(work)), dim3(256), 0, s, rows, src, lds_, dst, ldd, w);
   return hipGetLastError();
 }
+
+// explicit instantiations for the two storage types
+#define SVT_INST(T)                                                                                                   \
+  template hipError_t launch_omega<T>(hipStream_t, T*, int, int, int, int, uint64_t, uint64_t, uint64_t);             \
+  template hipError_t launch_seg_spmm<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*, const T*,  \
+                                         const T*, int, T*, int, int);                                                \
+  template hipError_t launch_spmm_t_tiled<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,         \
+                                             const T*, int, int, T*, int, double*, int64_t);                          \
+  template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \
+                                             double*, int64_t);                                                       \
+  template hipError_t launch_gram<T>(hipStream_t, int, const T*, int, int, double*, int, double*, int64_t);           \
+  template hipError_t launch_sumsq_cols<T>(hipStream_t, int, const T*, int, int, int, double*, double*, int);         \
+  template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \
+  template hipError_t launch_colnorms<T>(hipStream_t, int, const T*, int, int, double*, double*, int64_t, double*);   \
+  template hipError_t launch_trsm_rows<T>(hipStream_t, int, const T*, int, int, const double*, int, T*, int);         \
+  template hipError_t launch_sddmm_update<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, const T*,    \
+                                             T*, const T*, const T*, int, int, double, double*, int*);                \
+  template hipError_t launch_sample<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*, int, \
+                                       int, double*);                                                                 \
+  template hipError_t launch_scale_copy<T, T>(hipStream_t, int64_t, const T*, double, T*);                            \
+  template hipError_t launch_copy_cols<T, T>(hipStream_t, int, const T*, int, T*, int, int);
+
+SVT_INST(double)
+SVT_INST(float)
+#undef SVT_INST
+
+template hipError_t launch_rowmul<double, double, double>(hipStream_t, int, int, const double*, int, const double*,
+                                                          int, double*, int, int, double, double);
+template hipError_t launch_rowmul<float, double, float>(hipStream_t, int, int, const float*, int, const double*, int,
+                                                        float*, int, int, double, double);
+template hipError_t launch_rowmul<float, double, double>(hipStream_t, int, int, const float*, int, const double*, int,
+                                                         double*, int, int, double, double);
+template hipError_t launch_tn_narrow<float, double>(hipStream_t, int, const float*, int, int, const double*, int, int,
+                                                    double*, int, double*, int64_t);
+template hipError_t launch_copy_cols<float, double>(hipStream_t, int, const float*, int, double*, int, int);
+template hipError_t launch_copy_cols<double, float>(hipStream_t, int, const double*, int, float*, int, int);
+template hipError_t launch_scale_copy<double, float>(hipStream_t, int64_t, const double*, double, float*);
 
 }  // namespace svt

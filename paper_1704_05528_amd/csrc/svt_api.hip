@@ -1,16 +1,20 @@
 // Host control of the SVT / R4SVD hot path and the C-ABI of libsvt.
 //
-// The device kernels live in kernels.hip and eig.hip.  This file owns the handle,
-// the order in which the kernels run (Alg. 2-4 of Li & Yu), and the discrete
-// decisions the paper takes on scalars: the rank-revealing test eps > eps_threshold
-// (Alg. 3), the annealing test on the residual (Eq. 13-14) and the stop test (Alg. 4).
-// Each decision reads back a few float64 scalars produced by deterministic device
-// reductions.
+// The device kernels live in kernels.hip and eig.hip.  This file owns the handle, the order in
+// which the kernels run (Alg. 2-4 of Li & Yu), and the discrete decisions the paper takes on
+// scalars: the rank-revealing test eps > eps_threshold (Alg. 3), the annealing test on the
+// residual (Eq. 13-14) and the stop test (Alg. 4).  Each decision reads back a few float64
+// scalars produced by deterministic device reductions.
+//
+// The engine is a template over the storage type T of the iterate, the basis and the factors:
+// double for SVT_FP64, float for SVT_MIXED.  Gram matrices, the eigensolver and reductions are
+// double in both forms.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <type_traits>
 
 #include "svt_internal.h"
 
@@ -22,37 +26,39 @@ namespace {
 
 thread_local std::string g_init_err;
 
-constexpr double kDropTol = 1e-10;   // a projected column this small relative to its norm before lies in span(Q)
-constexpr double kDepTol = 1e-6;     // a Cholesky pivot this small relative to the column norm means dependence
-constexpr double kEigTol = 1e-13;    // Ritz residual relative to the largest Ritz value
-constexpr int kEigBatches = 60;      // cap on Rayleigh-Ritz batches per SVT iteration
-constexpr int kPowerSteps = 2;       // CholeskyQR steps per batch (two products with G each)
-constexpr double kEigDepTol = 1e-12; // eigen-block CholeskyQR drops only numerically dependent columns
-constexpr int kDirect = 32;          // basis widths up to this are diagonalised directly
+constexpr double kDropTol = 1e-10;    // a projected column this small relative to its norm before lies in span(Q)
+constexpr double kDepTol = 1e-6;      // a Cholesky pivot this small relative to the column norm means dependence
+constexpr double kEigTol = 1e-13;     // Ritz residual relative to the largest Ritz value
+constexpr int kEigBatches = 60;       // cap on Rayleigh-Ritz batches per SVT iteration
+constexpr int kPowerSteps = 2;        // CholeskyQR steps per batch (two products with G each)
+constexpr double kEigDepTol = 1e-12;  // eigen-block CholeskyQR drops only numerically dependent columns
+constexpr int kDirect = 32;           // basis widths up to this are diagonalised directly
 
 // scalar slots of the device readback buffer
 enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_RES2 = 4, S_YN2 = 5, S_SWEEPS = 6, S_NORMY = 7,
        S_A = 8, S_B = 9 };
 
-#define HIPCHK(expr)                                                                 \
-  do {                                                                               \
-    hipError_t e_ = (expr);                                                          \
-    if (e_ != hipSuccess) {                                                          \
-      h->err = std::string(#expr) + " failed: " + hipGetErrorString(e_);             \
-      return SVT_E_HIP;                                                              \
-    }                                                                                \
+#define HIPCHK(expr)                                                     \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) {                                              \
+      h->err = std::string(#expr) + " failed: " + hipGetErrorString(e_); \
+      return SVT_E_HIP;                                                  \
+    }                                                                    \
   } while (0)
 
-#define CHK(expr)                         \
-  do {                                    \
-    svt_status st_ = (expr);              \
-    if (st_ != SVT_OK) return st_;        \
+#define CHK(expr)                  \
+  do {                             \
+    svt_status st_ = (expr);       \
+    if (st_ != SVT_OK) return st_; \
   } while (0)
 
 svt_status fail(Handle* h, svt_status st, const std::string& msg) {
   h->err = msg;
   return st;
 }
+
+hipError_t dalloc_bytes(void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)); }
 
 template <class T>
 hipError_t dalloc(T** p, size_t count) {
@@ -111,370 +117,532 @@ svt_status readback(Handle* h, int count) {
   return SVT_OK;
 }
 
-svt_status to_host(Handle* h, double* dst, const double* src, size_t count) {
-  HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+template <class T>
+svt_status to_host(Handle* h, T* dst, const T* src, size_t count) {
+  HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   resolve_pending(h);
   return SVT_OK;
 }
 
-// ------------------------------------------------------------------------------------------
-// Block orthonormalisation (CholeskyQR2 with the column-drop rule) of X (m x wc, ld w_cap).
-// prenorm == nullptr: no drop rule (re-orthonormalisation inside power iterations).
-// The orthonormal columns are packed to the left of X; scal[S_WK2] holds their count.
-// ------------------------------------------------------------------------------------------
-svt_status orthonormalize_block(Handle* h, int rows, double* X, double* X2, int ld, int wc, const double* prenorm) {
-  hipStream_t s = h->stream;
-  HIPCHK(launch_tn_narrow(s, rows, X, ld, wc, X, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
-  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1,
-                           -1));
-  HIPCHK(launch_trsm_rows(s, rows, X, ld, wc, h->Minv, kEigMax, X2, ld));
-  HIPCHK(launch_tn_narrow(s, rows, X2, ld, wc, X2, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
-  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2,
-                           S_WK1));
-  HIPCHK(launch_trsm_rows(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
-  return SVT_OK;
-}
+// ==============================================================================================
+// The engine, templated on the storage type
+// ==============================================================================================
+template <class T>
+struct Engine {
+  Handle* h;
+  explicit Engine(Handle* hh) : h(hh) {}
 
-// One CholeskyQR pass Out = In R^{-1} without the span rule (dependent columns still drop).
-svt_status chol_orth(Handle* h, int rows, const double* In, double* Out, int ld, int wc) {
-  hipStream_t s = h->stream;
-  HIPCHK(launch_tn_narrow(s, rows, In, ld, wc, In, ld, wc, h->small, kEigMax, h->partial, h->partial_cap));
-  HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kEigDepTol, h->Minv, kEigMax, h->scal, S_WK2,
-                           -1));
-  HIPCHK(launch_trsm_rows(s, rows, In, ld, wc, h->Minv, kEigMax, Out, ld));
-  return SVT_OK;
-}
+  T* a() const { return (T*)h->a; }
+  T* y() const { return (T*)h->y; }
+  T* y_next() const { return (T*)h->y_next; }
+  T* Q() const { return (T*)h->Q; }
+  T* W() const { return (T*)h->W; }
+  T* X() const { return (T*)h->X; }
+  T* X2() const { return (T*)h->X2; }
+  T* Om() const { return (T*)h->Om; }
+  T* Ut() const { return (T*)h->Ut; }
+  T* Vt() const { return (T*)h->Vt; }
+  T* Utmp() const { return (T*)h->Utmp; }
+  static constexpr double es = (double)sizeof(T);
 
-// X = Y Om (CSR order, values through the CSR->CSC map)
-svt_status spmm_y(Handle* h, const double* Om, int ldo_in, double* X, int ldx, int w) {
-  HIPCHK(launch_seg_spmm(h->stream, (int)h->m, h->rowptr, h->colidx, h->csr2csc, h->y, Om, ldo_in, X, ldx, w));
-  return SVT_OK;
-}
-
-// out = Y^T D (CSC order)
-svt_status spmm_yt(Handle* h, const double* D, int ldd, double* out, int ldo, int w) {
-  HIPCHK(launch_seg_spmm(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, h->y, D, ldd, out, ldo, w));
-  return SVT_OK;
-}
-
-// ------------------------------------------------------------------------------------------
-// Append one sampled block of width w (Alg. 2 initial block when blk == 0, Alg. 3 growth
-// block otherwise): Omega from Philox, X = Y Omega, power iterations, projection against the
-// current basis (twice), CholeskyQR2, Q <- [Q, Q'], W <- [W, Y^T Q'], normB += ||Y^T Q'||^2.
-// Blocks wider than 64 columns are processed in 64-column chunks, each chunk orthogonalised
-// against the basis including the previous chunks (the same span as one wide block).
-// ------------------------------------------------------------------------------------------
-svt_status append_block(Handle* h, int it, int blk, int w, int* got, double* add) {
-  hipStream_t s = h->stream;
-  const int m = (int)h->m, n = (int)h->n;
-  const int ld = h->w_cap;
-  *got = 0;
-  *add = 0.0;
-  for (int c0 = 0; c0 < w; c0 += 64) {
-    const int wc = std::min(64, w - c0);
-    const int rq = h->r + *got;
-    {
-    PhaseTimer tm(h, SVT_PH_GROW);
-    HIPCHK(launch_omega(s, h->Om, n, c0, wc, ld, h->p.seed, (uint64_t)blk, (uint64_t)it));
-    CHK(spmm_y(h, h->Om, ld, h->X, ld, wc));
-    for (int pi = 0; pi < h->p.npow; ++pi) {
-      CHK(orthonormalize_block(h, m, h->X, h->X2, ld, wc, nullptr));
-      CHK(spmm_yt(h, h->X, ld, h->Om, ld, wc));
-      CHK(spmm_y(h, h->Om, ld, h->X, ld, wc));
-    }
-    HIPCHK(launch_colnorms(s, m, h->X, ld, wc, h->small, h->partial, h->partial_cap, h->prenorm));
-    if (rq > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        HIPCHK(launch_tn_narrow(s, m, h->Q, h->r_cap, rq, h->X, ld, wc, h->T, ld, h->partial, h->partial_cap));
-        HIPCHK(launch_rowmul(s, m, rq, h->Q, h->r_cap, h->T, ld, h->X, ld, wc, -1.0, 1.0));
-      }
-    }
-    CHK(orthonormalize_block(h, m, h->X, h->X2, ld, wc, h->prenorm));
-    HIPCHK(launch_copy_cols(s, m, h->X, ld, h->Q + rq, h->r_cap, wc));
-    CHK(spmm_yt(h, h->Q + rq, h->r_cap, h->W + rq, h->r_cap, wc));
-    HIPCHK(launch_sumsq_cols(s, n, h->W, h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
-    }
-    CHK(readback(h, S_NADD + 1));
-    const int kept = (int)h->hscal[S_WK2];
-    *got += kept;
-    *add += h->hscal[S_NADD];
+  // Block orthonormalisation (CholeskyQR2 with the column-drop rule) of X (rows x wc, ld).
+  // prenorm == nullptr: no span rule.  Orthonormal columns packed left; scal[S_WK2] = count.
+  template <class U>
+  svt_status orthonormalize_block(int rows, U* X, U* X2, int ld, int wc, const double* prenorm) {
+    hipStream_t s = h->stream;
+    HIPCHK((launch_tn_narrow<U, U>(s, rows, X, ld, wc, X, ld, wc, h->small, kEigMax, h->partial, h->partial_cap)));
+    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1,
+                             -1));
+    HIPCHK(launch_trsm_rows<U>(s, rows, X, ld, wc, h->Minv, kEigMax, X2, ld));
+    HIPCHK((launch_tn_narrow<U, U>(s, rows, X2, ld, wc, X2, ld, wc, h->small, kEigMax, h->partial, h->partial_cap)));
+    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2,
+                             S_WK1));
+    HIPCHK(launch_trsm_rows<U>(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
+    return SVT_OK;
   }
-  return SVT_OK;
-}
 
-// ------------------------------------------------------------------------------------------
-// R4SVD (Alg. 3; Alg. 2 for the first call): leaves Q[:, 0:r], W = Y^T Q, and st->eps.
-// ------------------------------------------------------------------------------------------
-svt_status r4svd_core(Handle* h, int it, int replay_blocks, svt_step_stats* st) {
-  double normB = 0.0;
-  if (h->r == 0) {
-    int got = 0;
-    double add = 0.0;
-    CHK(append_block(h, it, 0, h->p.t0, &got, &add));
-    if (got == 0) return fail(h, SVT_E_NUMERIC, "the first sampled block has no nonzero direction (Y = 0?)");
-    h->r = got;
-    normB = add;
-  } else {
-    {
-      const double r = h->r, nnz = (double)h->nnz;
-      PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * 12.0 + 4.0 * (h->n + 1) + 8.0 * r * (double)(h->m + h->n), 2.0 * nnz * r);
-      if (h->tstart) {
-        HIPCHK(launch_spmm_t_tiled(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, h->y, h->Q, h->r_cap, h->r,
-                                   h->W, h->r_cap, h->partial, h->partial_cap));
-      } else {
-        CHK(spmm_yt(h, h->Q, h->r_cap, h->W, h->r_cap, h->r));
+  // One CholeskyQR pass Out = In R^{-1} of an eigensolver block (only dependent columns drop).
+  svt_status chol_orth(int rows, const double* In, double* Out, int ld, int wc) {
+    hipStream_t s = h->stream;
+    HIPCHK((launch_tn_narrow<double, double>(s, rows, In, ld, wc, In, ld, wc, h->small, kEigMax, h->partial,
+                                             h->partial_cap)));
+    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kEigDepTol, h->Minv, kEigMax, h->scal, S_WK2,
+                             -1));
+    HIPCHK(launch_trsm_rows<double>(s, rows, In, ld, wc, h->Minv, kEigMax, Out, ld));
+    return SVT_OK;
+  }
+
+  // X = Y Om (CSR order, values through the CSR->CSC map)
+  svt_status spmm_y(const T* D, int ldd, T* out, int ldo, int w) {
+    HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->m, h->rowptr, h->colidx, h->csr2csc, y(), D, ldd, out, ldo, w));
+    return SVT_OK;
+  }
+
+  // out = Y^T D (CSC order)
+  svt_status spmm_yt(const T* D, int ldd, T* out, int ldo, int w) {
+    HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w));
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
+  // Append one sampled block of width w (Alg. 2 initial block when blk == 0, Alg. 3 growth
+  // block otherwise): Omega from Philox, X = Y Omega, power iterations, projection against the
+  // current basis (twice), CholeskyQR2, Q <- [Q, Q'], W <- [W, Y^T Q'], normB += ||Y^T Q'||^2.
+  // Blocks wider than 64 columns are processed in 64-column chunks, each chunk orthogonalised
+  // against the basis including the previous chunks (the same span as one wide block).
+  // ----------------------------------------------------------------------------------------
+  svt_status append_block(int it, int blk, int w, int* got, double* add) {
+    hipStream_t s = h->stream;
+    const int m = (int)h->m, n = (int)h->n;
+    const int ld = h->w_cap;
+    *got = 0;
+    *add = 0.0;
+    for (int c0 = 0; c0 < w; c0 += 64) {
+      const int wc = std::min(64, w - c0);
+      const int rq = h->r + *got;
+      {
+        PhaseTimer tm(h, SVT_PH_GROW);
+        HIPCHK(launch_omega<T>(s, Om(), n, c0, wc, ld, h->p.seed, (uint64_t)blk, (uint64_t)it));
+        CHK(spmm_y(Om(), ld, X(), ld, wc));
+        for (int pi = 0; pi < h->p.npow; ++pi) {
+          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, nullptr));
+          CHK(spmm_yt(X(), ld, Om(), ld, wc));
+          CHK(spmm_y(Om(), ld, X(), ld, wc));
+        }
+        HIPCHK(launch_colnorms<T>(s, m, X(), ld, wc, h->small, h->partial, h->partial_cap, h->prenorm));
+        if (rq > 0) {
+          for (int pass = 0; pass < 2; ++pass) {
+            HIPCHK((launch_tn_narrow<T, T>(s, m, Q(), h->r_cap, rq, X(), ld, wc, h->T, ld, h->partial,
+                                           h->partial_cap)));
+            HIPCHK((launch_rowmul<T, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0)));
+          }
+        }
+        CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm));
+        HIPCHK((launch_copy_cols<T, T>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
+        CHK(spmm_yt(Q() + rq, h->r_cap, W() + rq, h->r_cap, wc));
+        HIPCHK(launch_sumsq_cols<T>(s, n, W(), h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
       }
+      CHK(readback(h, S_NADD + 1));
+      const int kept = (int)h->hscal[S_WK2];
+      *got += kept;
+      *add += h->hscal[S_NADD];
+    }
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
+  // R4SVD (Alg. 3; Alg. 2 for the first call): leaves Q[:, 0:r], W = Y^T Q, and st->eps.
+  // ----------------------------------------------------------------------------------------
+  svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
+    double normB = 0.0;
+    if (h->r == 0) {
+      int got = 0;
+      double add = 0.0;
+      CHK(append_block(it, 0, h->p.t0, &got, &add));
+      if (got == 0) return fail(h, SVT_E_NUMERIC, "the first sampled block has no nonzero direction (Y = 0?)");
+      h->r = got;
+      normB = add;
+    } else {
+      {
+        const double r = h->r, nnz = (double)h->nnz;
+        PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * (es + 4.0) + 4.0 * (h->n + 1) + es * r * (double)(h->m + h->n),
+                      2.0 * nnz * r);
+        if (h->tstart) {
+          HIPCHK(launch_spmm_t_tiled<T>(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, y(), Q(), h->r_cap,
+                                        h->r, W(), h->r_cap, h->partial, h->partial_cap));
+        } else {
+          CHK(spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r));
+        }
+      }
+      {
+        PhaseTimer tm(h, SVT_PH_REDUCE);
+        HIPCHK(launch_sumsq_cols<T>(h->stream, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+      }
+      CHK(readback(h, S_NORMB + 1));
+      normB = h->hscal[S_NORMB];
+    }
+    const double normY = h->normY;
+    double eps = (normY - normB) / normY;
+    if (!std::isfinite(eps)) return fail(h, SVT_E_NUMERIC, "non-finite error percentage");
+    if (!h->eps_thr_set) {
+      h->eps_thr = h->p.eps_thr0 >= 0.0 ? h->p.eps_thr0 : 0.5 * (1.0 + eps);
+      h->eps_thr_set = true;
+    }
+    st->eps_thr = h->eps_thr;
+    st->grow_margin = std::numeric_limits<double>::infinity();
+    int blk = 0;
+    for (;;) {
+      const int room = std::min(h->p.dt, h->p.r_max - h->r);
+      bool grow;
+      if (replay_blocks >= 0) {
+        grow = blk < replay_blocks;
+      } else {
+        grow = eps > h->eps_thr;
+        if (h->eps_thr > 0.0) st->grow_margin = std::min(st->grow_margin, std::fabs(eps - h->eps_thr) / h->eps_thr);
+      }
+      if (!grow) break;
+      if (room <= 0) {
+        st->flags |= SVT_F_RMAX_HIT;
+        break;
+      }
+      ++blk;
+      int got = 0;
+      double add = 0.0;
+      CHK(append_block(it, blk, room, &got, &add));
+      if (got == 0) {
+        st->flags |= SVT_F_EXHAUSTED;
+        break;
+      }
+      h->r += got;
+      normB += add;
+      eps = (normY - normB) / normY;
+    }
+    st->blocks = blk;
+    st->eps = eps;
+    st->normY = normY;
+    st->normB = normB;
+    st->r = h->r;
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
+  // svd(B) through eig(W^T W): eigenpairs with sigma > tau, factor matrices Ut = Q C, Vt = W D.
+  // ----------------------------------------------------------------------------------------
+  svt_status projected_svd(svt_step_stats* st) {
+    hipStream_t s = h->stream;
+    const int r = h->r;
+    const double tau2 = h->p.tau * h->p.tau;
+    {
+      PhaseTimer tm(h, SVT_PH_GRAM, es * (double)h->n * r + 8.0 * (double)r * r, (double)h->n * r * (r + 1.0));
+      HIPCHK(launch_gram<T>(s, (int)h->n, W(), h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
+    }
+    std::vector<double> theta(2 * kEigMax), res(kEigMax);
+    const double* S = nullptr;
+    int k = 0;
+    st->eig_iters = 0;
+    if (r <= kDirect) {
+      {
+        PhaseTimer tm(h, SVT_PH_EIG);
+        HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+      }
+      CHK(to_host<double>(h, theta.data(), h->Eval, r));
+      while (k < r && theta[k] > tau2) ++k;
+      S = h->ES;
+      // keep the eigenvectors as the warm start of the block solver
+      HIPCHK((launch_copy_cols<double, double>(s, r, h->ES, kEigMax, h->EV, kEigMax, r)));
+      h->ev_valid = r;
+      h->ev_rows = r;
+      st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
+    } else {
+      // Warm-started orthogonal iteration on G in batches of kPowerSteps CholeskyQR steps (two
+      // products with G each), each batch closed by CholeskyQR2 and a Rayleigh-Ritz step on the
+      // whole block.  Start block: the previous Ritz vectors (new basis rows zero), the unit
+      // vectors of the basis columns appended since then (where new energy enters), Gaussians.
+      const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
+      const int newc = warm ? r - h->ev_rows : 0;
+      int b = std::min(std::min(h->b_cap, r), std::max(16, ((2 * std::max(h->k, 4) + 8 + 7) / 8) * 8));
+      int valid = warm ? std::min(h->ev_valid, b) : 0;
+      if (valid + newc + 4 > b) b = std::min(std::min(h->b_cap, r), valid + newc + 4);
+      valid = std::min(valid, b);
+      const int unit = std::min(newc, b - valid);
+      {
+        PhaseTimer tm(h, SVT_PH_EIG);
+        if (valid > 0 && h->ev_rows < r) {
+          // new basis columns were appended: zero the new rows of the kept vectors
+          HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
+                                  valid * sizeof(double), r - h->ev_rows, s));
+        }
+        HIPCHK(launch_set_unit(s, h->EV, r, kEigMax, valid, unit, h->ev_rows));
+        HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid + unit, b, h->p.seed ^ 0x5A5A5A5Aull,
+                                  (uint64_t)h->iter));
+        CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
+      }
+      bool done = false;
+      int iters = 0, batches = 0, prev_k = -1;
+      while (!done) {
+        if (batches >= kEigBatches) {
+          st->flags |= SVT_F_EIG_INEXACT;
+          break;
+        }
+        ++batches;
+        {
+          PhaseTimer tm(h, SVT_PH_EIG);
+          for (int step = 0; step < kPowerSteps; ++step, iters += 2) {
+            HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
+                                                          1.0, 0.0)));
+            HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EZ3, kEigMax, h->EZ, kEigMax, b,
+                                                          1.0, 0.0)));
+            if (step + 1 < kPowerSteps) {
+              CHK(chol_orth(r, h->EZ, h->EV, kEigMax, b));
+            } else {
+              CHK(chol_orth(r, h->EZ, h->EZ2, kEigMax, b));
+              CHK(chol_orth(r, h->EZ2, h->EV, kEigMax, b));
+            }
+          }
+          // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; Z <- (G V) S; residuals
+          HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
+                                                        1.0, 0.0)));
+          HIPCHK((launch_tn_narrow<double, double>(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->EH, kEigMax,
+                                                   h->partial, h->partial_cap)));
+          HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+          HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b,
+                                                        1.0, 0.0)));
+          HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b,
+                                                        1.0, 0.0)));
+          std::swap(h->EV, h->EZ2);
+          HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
+        }
+        CHK(to_host<double>(h, theta.data(), h->Eval, 2 * kEigMax));
+        for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
+        k = 0;
+        while (k < b && theta[k] > tau2) ++k;
+        if (k + 4 > b && b < r) {
+          if (b >= h->b_cap) {
+            if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks");
+          } else {
+            const int nb = std::min(std::min(h->b_cap, r), b + 16);
+            PhaseTimer tm(h, SVT_PH_EIG);
+            HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)batches));
+            b = nb;
+            CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
+            prev_k = -1;
+            continue;
+          }
+        }
+        // Accept when the pairs above tau^2 have converged, four guard pairs below it have Ritz
+        // intervals below tau^2, and the count k agrees with the previous check (Ritz values rise
+        // monotonically under subspace iteration, so a missed eigenvalue above tau^2 would still be
+        // moving k).  In the steady state the first check may also accept when k equals the
+        // previous SVT iteration's count, whose eigenvectors started this solve.  A block that
+        // spans the whole basis (b == r) is exact after one Rayleigh-Ritz step.
+        const double lim = kEigTol * std::max(theta[0], 0.0);
+        done = (b == r) || (k == prev_k) || (prev_k < 0 && warm && k == h->k);
+        for (int c = 0; done && c < k; ++c)
+          if (!(res[c] <= lim)) done = false;
+        for (int c = k; done && c < std::min(b, k + 4); ++c)
+          if (!(theta[c] + res[c] < tau2)) done = false;
+        prev_k = k;
+      }
+      st->eig_iters = iters;
+      S = h->EV;
+      h->ev_valid = b;
+      h->ev_rows = r;
+      st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
+    }
+    if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
+    h->k = k;
+    h->sigma_k.assign(theta.begin(), theta.begin() + k);
+    for (auto& v : h->sigma_k) v = std::sqrt(v);
+    st->k = k;
+    st->sigmak = k > 0 ? h->sigma_k[k - 1] : 0.0;
+    if (k > 0) {
+      PhaseTimer tm(h, SVT_PH_FACTORS, es * (double)(h->m + h->n) * (r + k) + 16.0 * r * k,
+                    2.0 * (double)(h->m + h->n) * r * k);
+      HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
+      HIPCHK((launch_copy_cols<double, double>(s, r, S, kEigMax, h->Sk, kEigMax, k)));
+      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, kEigMax, Ut(), kEigMax, k, 1.0,
+                                          0.0)));
+      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, kEigMax, Vt(), kEigMax, k, 1.0,
+                                          0.0)));
+    }
+    h->have_factors = true;
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
+  // One iteration of Alg. 4 (reading: X^(i) on Lambda, residual, annealing, stop, update).
+  // ----------------------------------------------------------------------------------------
+  svt_status iteration(svt_step_stats* st) {
+    std::memset(st, 0, sizeof(*st));
+    const int it = h->iter + 1;
+    st->iter = it;
+    int rb = -1, ra = -1;
+    if (h->replay_pos < h->replay_blocks.size()) {
+      rb = h->replay_blocks[h->replay_pos];
+      ra = h->replay_anneal[h->replay_pos];
+      ++h->replay_pos;
+    }
+    CHK(r4svd_core(it, rb, st));
+    CHK(projected_svd(st));
+    int nbl = 0;
+    {
+      const double nnz = (double)h->nnz, k = h->k;
+      PhaseTimer tm(h, SVT_PH_SDDMM, nnz * (3.0 * es + 4.0) + 4.0 * (h->n + 1) + es * k * (double)(h->m + h->n),
+                    nnz * (2.0 * k + 3.0));
+      HIPCHK(launch_sddmm_update<T>(h->stream, (int)h->n, h->colptr, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
+                                    kEigMax, h->k, h->p.delta, h->partial, &nbl));
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
-      HIPCHK(launch_sumsq_cols(h->stream, (int)h->n, h->W, h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+      HIPCHK(launch_finish(h->stream, h->partial, nbl, 2, 2, h->scal, S_RES2));
     }
-    CHK(readback(h, S_NORMB + 1));
-    normB = h->hscal[S_NORMB];
-  }
-  const double normY = h->normY;
-  double eps = (normY - normB) / normY;
-  if (!std::isfinite(eps)) return fail(h, SVT_E_NUMERIC, "non-finite error percentage");
-  if (!h->eps_thr_set) {
-    h->eps_thr = h->p.eps_thr0 >= 0.0 ? h->p.eps_thr0 : 0.5 * (1.0 + eps);
-    h->eps_thr_set = true;
-  }
-  st->eps_thr = h->eps_thr;
-  st->grow_margin = std::numeric_limits<double>::infinity();
-  int blk = 0;
-  for (;;) {
-    const int room = std::min(h->p.dt, h->p.r_max - h->r);
-    bool grow;
-    if (replay_blocks >= 0) {
-      grow = blk < replay_blocks;
+    CHK(readback(h, S_YN2 + 1));
+    const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
+    const double rel = std::sqrt(res2) / h->norm_a;
+    if (!std::isfinite(rel) || !std::isfinite(yn2)) return fail(h, SVT_E_NUMERIC, "non-finite residual");
+    st->rel_res = rel;
+    const double target = h->eps_min * (1.0 - h->p.eta);
+    st->anneal_margin =
+        std::isfinite(h->eps_min) ? (rel - target) / h->eps_min : -std::numeric_limits<double>::infinity();
+    const bool annealed = (ra >= 0) ? (ra != 0) : !(rel < target);
+    if (annealed) {
+      h->eps_thr *= h->p.beta;
+      st->flags |= SVT_F_ANNEALED;
     } else {
-      grow = eps > h->eps_thr;
-      if (h->eps_thr > 0.0) st->grow_margin = std::min(st->grow_margin, std::fabs(eps - h->eps_thr) / h->eps_thr);
+      h->eps_min = rel;
     }
-    if (!grow) break;
-    if (room <= 0) {
-      st->flags |= SVT_F_RMAX_HIT;
-      break;
+    st->annealed = annealed ? 1 : 0;
+    h->iter = it;
+    if (rel < h->p.tol) {
+      st->stopped = 1;
+      st->flags |= SVT_F_CONVERGED;
+      h->converged = true;
+      return SVT_OK;
     }
-    ++blk;
-    int got = 0;
-    double add = 0.0;
-    CHK(append_block(h, it, blk, room, &got, &add));
-    if (got == 0) {
-      st->flags |= SVT_F_EXHAUSTED;
-      break;
-    }
-    h->r += got;
-    normB += add;
-    eps = (normY - normB) / normY;
-  }
-  st->blocks = blk;
-  st->eps = eps;
-  st->normY = normY;
-  st->normB = normB;
-  st->r = h->r;
-  return SVT_OK;
-}
-
-// ------------------------------------------------------------------------------------------
-// svd(B) through eig(W^T W): eigenpairs with sigma > tau, factor matrices Ut = Q C, Vt = W D.
-// ------------------------------------------------------------------------------------------
-svt_status projected_svd(Handle* h, svt_step_stats* st) {
-  hipStream_t s = h->stream;
-  const int r = h->r;
-  const double tau2 = h->p.tau * h->p.tau;
-  {
-    PhaseTimer tm(h, SVT_PH_GRAM, 8.0 * (double)h->n * r + 8.0 * (double)r * r, (double)h->n * r * (r + 1.0));
-    HIPCHK(launch_gram(s, (int)h->n, h->W, h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
-  }
-  std::vector<double> theta(2 * kEigMax), res(kEigMax);
-  const double* S = nullptr;
-  int k = 0;
-  st->eig_iters = 0;
-  if (r <= kDirect) {
-    {
-      PhaseTimer tm(h, SVT_PH_EIG);
-      HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
-    }
-    CHK(to_host(h, theta.data(), h->Eval, r));
-    while (k < r && theta[k] > tau2) ++k;
-    S = h->ES;
-    // keep the eigenvectors as the warm start of the block solver
-    HIPCHK(launch_copy_cols(s, r, h->ES, kEigMax, h->EV, kEigMax, r));
-    h->ev_valid = r;
-    h->ev_rows = r;
-    st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
-  } else {
-    // Warm-started orthogonal iteration on G in batches of kPowerSteps products, each batch
-    // closed by CholeskyQR2 and a Rayleigh-Ritz step on the whole block (b columns).
-    // Start block: the previous Ritz vectors (new basis rows zero), the unit vectors of the basis
-    // columns appended since then (where new energy enters), and Gaussian columns.
-    const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
-    const int newc = warm ? r - h->ev_rows : 0;
-    int b = std::min(std::min(h->b_cap, r), std::max(16, ((2 * std::max(h->k, 4) + 8 + 7) / 8) * 8));
-    int valid = warm ? std::min(h->ev_valid, b) : 0;
-    if (valid + newc + 4 > b) b = std::min(std::min(h->b_cap, r), valid + newc + 4);
-    valid = std::min(valid, b);
-    const int unit = std::min(newc, b - valid);
-    {
-      PhaseTimer tm(h, SVT_PH_EIG);
-      if (valid > 0 && h->ev_rows < r) {
-        // new basis columns were appended: zero the new rows of the kept vectors
-        HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
-                                valid * sizeof(double), r - h->ev_rows, s));
-      }
-      HIPCHK(launch_set_unit(s, h->EV, r, kEigMax, valid, unit, h->ev_rows));
-      HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid + unit, b, h->p.seed ^ 0x5A5A5A5Aull,
-                                (uint64_t)h->iter));
-      CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
-    }
-    bool done = false;
-    int iters = 0, batches = 0, prev_k = -1;
-    while (!done) {
-      if (batches >= kEigBatches) {
-        st->flags |= SVT_F_EIG_INEXACT;
-        break;
-      }
-      ++batches;
-      {
-        PhaseTimer tm(h, SVT_PH_EIG);
-        // each step multiplies by G twice before one CholeskyQR (the last step: CholeskyQR2)
-        for (int step = 0; step < kPowerSteps; ++step, iters += 2) {
-          HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b, 1.0, 0.0));
-          HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EZ3, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
-          if (step + 1 < kPowerSteps) {
-            CHK(chol_orth(h, r, h->EZ, h->EV, kEigMax, b));
-          } else {
-            CHK(chol_orth(h, r, h->EZ, h->EZ2, kEigMax, b));
-            CHK(chol_orth(h, r, h->EZ2, h->EV, kEigMax, b));
-          }
-        }
-        // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; Z <- (G V) S; residuals
-        HIPCHK(launch_rowmul(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b, 1.0, 0.0));
-        HIPCHK(launch_tn_narrow(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->EH, kEigMax, h->partial,
-                                h->partial_cap));
-        HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
-        HIPCHK(launch_rowmul(s, r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b, 1.0, 0.0));
-        HIPCHK(launch_rowmul(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b, 1.0, 0.0));
-        std::swap(h->EV, h->EZ2);
-        HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
-      }
-      CHK(to_host(h, theta.data(), h->Eval, 2 * kEigMax));
-      for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
-      k = 0;
-      while (k < b && theta[k] > tau2) ++k;
-      if (k + 4 > b && b < r) {
-        if (b >= h->b_cap) {
-          if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks (kmax)");
-        } else {
-          const int nb = std::min(std::min(h->b_cap, r), b + 16);
-          PhaseTimer tm(h, SVT_PH_EIG);
-          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)batches));
-          b = nb;
-          CHK(orthonormalize_block(h, r, h->EV, h->EZ2, kEigMax, b, nullptr));
-          prev_k = -1;
-          continue;
-        }
-      }
-      // Accept when the pairs above tau^2 and four guard pairs below it have converged and the
-      // count k agrees with the previous check (Ritz values rise monotonically under subspace
-      // iteration, so a missed eigenvalue above tau^2 would still be moving k).  A block that
-      // spans the whole basis (b == r) is exact after one Rayleigh-Ritz step.
-      // In the steady state the first check may also accept when k equals the previous SVT
-      // iteration's count, whose eigenvectors started this solve.
-      const double lim = kEigTol * std::max(theta[0], 0.0);
-      done = (b == r) || (k == prev_k) || (prev_k < 0 && warm && k == h->k);
-      for (int c = 0; done && c < k; ++c)
-        if (!(res[c] <= lim)) done = false;
-      // guard pairs: an eigenvalue lies within res of each Ritz value; it must sit below tau^2
-      for (int c = k; done && c < std::min(b, k + 4); ++c)
-        if (!(theta[c] + res[c] < tau2)) done = false;
-      prev_k = k;
-    }
-    st->eig_iters = iters;
-    S = h->EV;
-    h->ev_valid = b;
-    h->ev_rows = r;
-    st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
-  }
-  if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
-  h->k = k;
-  h->sigma_k.assign(theta.begin(), theta.begin() + k);
-  for (auto& v : h->sigma_k) v = std::sqrt(v);
-  st->k = k;
-  st->sigmak = k > 0 ? h->sigma_k[k - 1] : 0.0;
-  if (k > 0) {
-    PhaseTimer tm(h, SVT_PH_FACTORS, 8.0 * (double)(h->m + h->n) * (r + k) + 16.0 * r * k,
-                  2.0 * (double)(h->m + h->n) * r * k);
-    HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
-    HIPCHK(launch_copy_cols(s, r, S, kEigMax, h->Sk, kEigMax, k));
-    HIPCHK(launch_rowmul(s, (int)h->m, r, h->Q, h->r_cap, h->C, kEigMax, h->Ut, kEigMax, k, 1.0, 0.0));
-    HIPCHK(launch_rowmul(s, (int)h->n, r, h->W, h->r_cap, h->D, kEigMax, h->Vt, kEigMax, k, 1.0, 0.0));
-  }
-  h->have_factors = true;
-  return SVT_OK;
-}
-
-// ------------------------------------------------------------------------------------------
-// One iteration of Alg. 4 (reading: X^(i) on Lambda, residual, annealing, stop, update).
-// ------------------------------------------------------------------------------------------
-svt_status do_iteration(Handle* h, svt_step_stats* st) {
-  std::memset(st, 0, sizeof(*st));
-  const int it = h->iter + 1;
-  st->iter = it;
-  int rb = -1, ra = -1;
-  if (h->replay_pos < h->replay_blocks.size()) {
-    rb = h->replay_blocks[h->replay_pos];
-    ra = h->replay_anneal[h->replay_pos];
-    ++h->replay_pos;
-  }
-  CHK(r4svd_core(h, it, rb, st));
-  CHK(projected_svd(h, st));
-  int nbl = 0;
-  {
-    const double nnz = (double)h->nnz, k = h->k;
-    PhaseTimer tm(h, SVT_PH_SDDMM, nnz * 28.0 + 4.0 * (h->n + 1) + 8.0 * k * (double)(h->m + h->n),
-                  nnz * (2.0 * k + 3.0));
-    HIPCHK(launch_sddmm_update(h->stream, (int)h->n, h->colptr, h->rowidx, h->a, h->y, h->y_next, nullptr, h->Ut,
-                               h->Vt, kEigMax, h->k, h->p.delta, h->partial, &nbl));
-  }
-  {
-    PhaseTimer tm(h, SVT_PH_REDUCE);
-    HIPCHK(launch_finish(h->stream, h->partial, nbl, 2, 2, h->scal, S_RES2));
-  }
-  CHK(readback(h, S_YN2 + 1));
-  const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
-  const double rel = std::sqrt(res2) / h->norm_a;
-  if (!std::isfinite(rel) || !std::isfinite(yn2)) return fail(h, SVT_E_NUMERIC, "non-finite residual");
-  st->rel_res = rel;
-  const double target = h->eps_min * (1.0 - h->p.eta);
-  st->anneal_margin = std::isfinite(h->eps_min) ? (rel - target) / h->eps_min : -std::numeric_limits<double>::infinity();
-  const bool annealed = (ra >= 0) ? (ra != 0) : !(rel < target);
-  if (annealed) {
-    h->eps_thr *= h->p.beta;
-    st->flags |= SVT_F_ANNEALED;
-  } else {
-    h->eps_min = rel;
-  }
-  st->annealed = annealed ? 1 : 0;
-  h->iter = it;
-  if (rel < h->p.tol) {
-    st->stopped = 1;
-    st->flags |= SVT_F_CONVERGED;
-    h->converged = true;
+    std::swap(h->y, h->y_next);
+    h->normY = yn2;
     return SVT_OK;
   }
-  std::swap(h->y, h->y_next);
-  h->normY = yn2;
-  return SVT_OK;
+
+  // R4SVD + factors on the current Y, leaving the iteration state as it was.
+  svt_status operator_only(svt_step_stats* st) {
+    std::memset(st, 0, sizeof(*st));
+    const int r_save = h->r;
+    const bool thr_set = h->eps_thr_set;
+    const double thr = h->eps_thr;
+    st->iter = h->iter + 1;
+    svt_status s1 = r4svd_core(h->iter + 1, -1, st);
+    if (s1 == SVT_OK) s1 = projected_svd(st);
+    h->r = r_save;
+    h->eps_thr_set = thr_set;
+    h->eps_thr = thr;
+    if (h->ev_rows > h->r) h->ev_valid = 0;
+    return s1;
+  }
+
+  // ||P_Lambda A||_2 by power iteration on (P_Lambda A)^T (P_Lambda A) (kicking, Alg. 4 init).
+  svt_status spectral_norm(double* out) {
+    hipStream_t s = h->stream;
+    const int m = (int)h->m, n = (int)h->n;
+    T* v = Utmp();  // n-vector (Utmp holds max(m, n) * kEigMax values)
+    T* u = X2();    // m-vector (X2 holds m * w_cap values)
+    HIPCHK(launch_fill_random(s, h->EV, n, 1, 0, 1, h->p.seed ^ 0x3C3C3C3Cull, 7));
+    HIPCHK((launch_copy_cols<double, T>(s, n, h->EV, 1, v, 1, 1)));
+    HIPCHK(launch_sumsq<T>(s, n, v, h->partial, h->scal, S_B));
+    CHK(readback(h, S_B + 1));
+    HIPCHK((launch_scale_copy<T, T>(s, n, v, 1.0 / std::sqrt(h->hscal[S_B]), v)));
+    double sig = 0.0, sig_prev = 0.0;
+    for (int itp = 0; itp < 5000; ++itp) {
+      HIPCHK(launch_seg_spmm<T>(s, m, h->rowptr, h->colidx, h->csr2csc, a(), v, 1, u, 1, 1));
+      HIPCHK(launch_seg_spmm<T>(s, n, h->colptr, h->rowidx, nullptr, a(), u, 1, v, 1, 1));
+      HIPCHK(launch_sumsq<T>(s, m, u, h->partial, h->scal, S_A));
+      HIPCHK(launch_sumsq<T>(s, n, v, h->partial + 2048, h->scal, S_B));
+      CHK(readback(h, S_B + 1));
+      sig = std::sqrt(h->hscal[S_A]);  // ||A v|| with ||v|| = 1
+      const double nv = std::sqrt(h->hscal[S_B]);
+      if (!(nv > 0.0)) break;
+      HIPCHK((launch_scale_copy<T, T>(s, n, v, 1.0 / nv, v)));
+      if (itp > 3 && std::fabs(sig - sig_prev) <= 1e-15 * sig) break;
+      sig_prev = sig;
+    }
+    *out = sig;
+    return SVT_OK;
+  }
+
+  // upload host float64 values on Lambda (caller order) as T in CSC order
+  svt_status upload_lambda(T* dst, const double* src_user) {
+    std::vector<T> buf(h->nnz);
+    for (int64_t u = 0; u < h->nnz; ++u) buf[h->user2csc[u]] = (T)src_user[u];
+    HIPCHK(hipMemcpyAsync(dst, buf.data(), h->nnz * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SVT_OK;
+  }
+
+  svt_status download_lambda(double* dst_user, const T* src) {
+    std::vector<T> buf(h->nnz);
+    CHK(to_host<T>(h, buf.data(), src, h->nnz));
+    for (int64_t u = 0; u < h->nnz; ++u) dst_user[u] = (double)buf[h->user2csc[u]];
+    return SVT_OK;
+  }
+
+  svt_status set_basis(const double* Qh, int r) {
+    std::vector<T> buf((size_t)h->m * r);
+    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (T)Qh[i];
+    HIPCHK(hipMemcpy2DAsync(Q(), h->r_cap * sizeof(T), buf.data(), r * sizeof(T), r * sizeof(T), h->m,
+                            hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SVT_OK;
+  }
+
+  svt_status get_basis(double* Qh, int qcap) {
+    std::vector<T> buf((size_t)h->m * h->r);
+    HIPCHK(hipMemcpy2DAsync(buf.data(), h->r * sizeof(T), Q(), h->r_cap * sizeof(T), h->r * sizeof(T), h->m,
+                            hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < h->m; ++i)
+      for (int c = 0; c < h->r; ++c) Qh[i * qcap + c] = (double)buf[(size_t)i * h->r + c];
+    return SVT_OK;
+  }
+
+  svt_status factors(int kk, int kcap, double* U, double* V) {
+    std::vector<T> buf;
+    if (U) {
+      HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, kEigMax, Utmp(), kEigMax,
+                                          kk, 1.0, 0.0)));
+      buf.resize((size_t)h->m * kEigMax);
+      CHK(to_host<T>(h, buf.data(), Utmp(), buf.size()));
+      for (int64_t i = 0; i < h->m; ++i)
+        for (int c = 0; c < kk; ++c) U[i * kcap + c] = (double)buf[i * kEigMax + c];
+    }
+    if (V) {
+      buf.resize((size_t)h->n * kEigMax);
+      CHK(to_host<T>(h, buf.data(), Vt(), buf.size()));
+      for (int64_t j = 0; j < h->n; ++j)
+        for (int c = 0; c < kk; ++c) V[j * kcap + c] = (double)buf[j * kEigMax + c];
+    }
+    return SVT_OK;
+  }
+
+  svt_status sample(int64_t nq, const int32_t* di, const int32_t* dj, double* dx) {
+    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), kEigMax, h->k, dx));
+    return SVT_OK;
+  }
+
+  svt_status sumsq_y(double* out) {
+    HIPCHK(launch_sumsq<T>(h->stream, h->nnz, y(), h->partial, h->scal, S_NORMY));
+    CHK(readback(h, S_NORMY + 1));
+    *out = h->hscal[S_NORMY];
+    return SVT_OK;
+  }
+
+  svt_status kick() {
+    HIPCHK((launch_scale_copy<T, T>(h->stream, h->nnz, a(), (double)h->k0 * h->p.delta, y())));
+    return sumsq_y(&h->normY);
+  }
+
+  svt_status norm_of_a(double* out) {
+    HIPCHK(launch_sumsq<T>(h->stream, h->nnz, a(), h->partial, h->scal, S_A));
+    CHK(readback(h, S_A + 1));
+    *out = std::sqrt(h->hscal[S_A]);
+    return SVT_OK;
+  }
+};
+
+template <class F>
+svt_status dispatch(Handle* h, F&& f) {
+  if (h->p.precision == SVT_MIXED) {
+    Engine<float> e(h);
+    return f(e);
+  }
+  Engine<double> e(h);
+  return f(e);
 }
 
 void release(Handle* h) {
-  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->a, h->y, h->y_next, h->x,
-                  h->Q, h->W,
-                  h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2, h->EZ3,
-                  h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->C, h->D, h->Sk, h->Utmp, h->partial, h->scal};
+  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->a, h->y, h->y_next,
+                  h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2,
+                  h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
@@ -544,7 +712,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.npow < 0) return bad("npow must be non-negative");
   if (p.kmax <= 0) p.kmax = 64;
   if (p.kmax > kEigMax) return bad("kmax must not exceed 96");
-  if (p.precision != SVT_FP64) return bad("precision form not available");
+  if (p.precision != SVT_FP64 && p.precision != SVT_MIXED) return bad("unknown precision form");
   const int64_t mn = std::min(m, n);
   if (p.t0 <= 0) p.t0 = (int32_t)std::max<int64_t>(1, (int64_t)std::floor(0.05 * (double)mn));
   p.r_max = (p.r_max <= 0) ? (int32_t)m : (int32_t)std::min<int64_t>(p.r_max, m);
@@ -571,12 +739,10 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   (void)hipGetDevice(&h->device);
   h->user2csc.resize(nnz);
   std::vector<int32_t> colptr(n + 1, 0), rowidx(nnz), rowptr(m + 1, 0), colidx(nnz), csr2csc(nnz);
-  std::vector<double> a_csc(nnz);
   for (int64_t q = 0; q < nnz; ++q) {
     const int64_t u = order[q];
     h->user2csc[u] = q;
     rowidx[q] = rows[u];
-    a_csc[q] = vals[u];
     colptr[cols[u] + 1]++;
   }
   for (int64_t j = 0; j < n; ++j) colptr[j + 1] += colptr[j];
@@ -598,11 +764,11 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if ((double)nnz >= 0.05 * (double)m * (double)n && (int64_t)n * (ntiles + 1) <= ((int64_t)1 << 26)) {
     tstart.resize((size_t)n * (ntiles + 1));
     for (int64_t j = 0; j < n; ++j) {
-      int32_t p = colptr[j];
+      int32_t pp = colptr[j];
       for (int t = 0; t <= ntiles; ++t) {
         const int64_t lim = std::min<int64_t>((int64_t)t * 32, m);
-        while (p < colptr[j + 1] && rowidx[p] < lim) ++p;
-        tstart[(size_t)j * (ntiles + 1) + t] = p;
+        while (pp < colptr[j + 1] && rowidx[pp] < lim) ++pp;
+        tstart[(size_t)j * (ntiles + 1) + t] = pp;
       }
     }
   }
@@ -612,6 +778,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
   h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
   h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
+  const size_t es = (p.precision == SVT_MIXED) ? sizeof(float) : sizeof(double);
+  const size_t mx = (size_t)std::max(m, n);
 
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) {
@@ -622,30 +790,29 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->rowptr, m + 1));
   A(dalloc(&h->colidx, nnz));
   A(dalloc(&h->csr2csc, nnz));
-  A(dalloc(&h->a, nnz));
-  A(dalloc(&h->y, nnz));
-  A(dalloc(&h->y_next, nnz));
-  A(dalloc(&h->x, nnz));
-  A(dalloc(&h->Q, (size_t)m * h->r_cap));
-  A(dalloc(&h->W, (size_t)n * h->r_cap));
-  A(dalloc(&h->X, (size_t)m * h->w_cap));
-  A(dalloc(&h->X2, (size_t)m * h->w_cap));
-  A(dalloc(&h->Om, (size_t)std::max(m, n) * h->w_cap));
+  A(dalloc_bytes(&h->a, nnz * es));
+  A(dalloc_bytes(&h->y, nnz * es));
+  A(dalloc_bytes(&h->y_next, nnz * es));
+  A(dalloc_bytes(&h->Q, (size_t)m * h->r_cap * es));
+  A(dalloc_bytes(&h->W, (size_t)n * h->r_cap * es));
+  A(dalloc_bytes(&h->X, (size_t)m * h->w_cap * es));
+  A(dalloc_bytes(&h->X2, (size_t)m * h->w_cap * es));
+  A(dalloc_bytes(&h->Om, mx * h->w_cap * es));
+  A(dalloc_bytes(&h->Ut, (size_t)m * kEigMax * es));
+  A(dalloc_bytes(&h->Vt, (size_t)n * kEigMax * es));
+  A(dalloc_bytes(&h->Utmp, mx * kEigMax * es));
   A(dalloc(&h->T, (size_t)h->r_cap * h->w_cap));
   A(dalloc(&h->G, (size_t)h->r_cap * h->r_cap));
   A(dalloc(&h->small, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->Minv, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->prenorm, kEigMax));
-  A(dalloc(&h->EV, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EV, std::max<size_t>((size_t)h->r_cap * kEigMax, mx)));
   A(dalloc(&h->EZ, (size_t)h->r_cap * kEigMax));
-  A(dalloc(&h->EZ2, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->EZ2, std::max<size_t>((size_t)h->r_cap * kEigMax, mx)));
   A(dalloc(&h->EZ3, (size_t)h->r_cap * kEigMax));
   A(dalloc(&h->EH, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->ES, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->Eval, 2 * kEigMax));
-  A(dalloc(&h->Ut, (size_t)m * kEigMax));
-  A(dalloc(&h->Vt, (size_t)n * kEigMax));
-  A(dalloc(&h->Utmp, (size_t)std::max(m, n) * kEigMax));
   A(dalloc(&h->C, (size_t)h->r_cap * kEigMax));
   A(dalloc(&h->D, (size_t)h->r_cap * kEigMax));
   A(dalloc(&h->Sk, (size_t)h->r_cap * kEigMax));
@@ -666,9 +833,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   up(h->rowptr, rowptr.data(), (m + 1) * sizeof(int32_t));
   up(h->colidx, colidx.data(), nnz * sizeof(int32_t));
   up(h->csr2csc, csr2csc.data(), nnz * sizeof(int32_t));
-  up(h->a, a_csc.data(), nnz * sizeof(double));
   if (!tstart.empty()) up(h->tstart, tstart.data(), tstart.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * sizeof(double), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * es, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     g_init_err = std::string("upload failed: ") + hipGetErrorString(e);
@@ -676,74 +842,26 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     return SVT_E_HIP;
   }
 
-  // ||P_Lambda A||_F and the kicking count (Alg. 4 initialisation)
-  svt_status st = SVT_OK;
-  auto finish_fail = [&](svt_status s2) {
+  // values, ||P_Lambda A||_F, the kicking count and Y^(0) (Alg. 4 initialisation)
+  svt_status st = dispatch(h, [&](auto& eng) -> svt_status {
+    using TT = std::remove_pointer_t<decltype(eng.a())>;
+    CHK(eng.upload_lambda((TT*)h->a, vals));
+    CHK(eng.norm_of_a(&h->norm_a));
+    if (!(h->norm_a > 0.0)) return fail(h, SVT_E_NUMERIC, "P_Lambda(A) is zero");
+    if (h->p.k0 < 0) {
+      double sig = 0.0;
+      CHK(eng.spectral_norm(&sig));
+      h->k0 = (int32_t)std::ceil(h->p.tau / (h->p.delta * sig));
+    } else {
+      h->k0 = h->p.k0;
+    }
+    return eng.kick();
+  });
+  if (st != SVT_OK) {
     g_init_err = h->err;
     svt_destroy(h);
-    return s2;
-  };
-  if ((e = launch_sumsq(h->stream, nnz, h->a, h->partial, h->scal, S_A)) != hipSuccess) {
-    h->err = hipGetErrorString(e);
-    return finish_fail(SVT_E_HIP);
+    return st;
   }
-  if ((st = readback(h, S_A + 1)) != SVT_OK) return finish_fail(st);
-  h->norm_a = std::sqrt(h->hscal[S_A]);
-  if (!(h->norm_a > 0.0)) {
-    h->err = "P_Lambda(A) is zero";
-    return finish_fail(SVT_E_NUMERIC);
-  }
-  if (p.k0 < 0) {
-    // ||P_Lambda A||_2 by power iteration on (P_Lambda A)^T (P_Lambda A)
-    double* v = h->Utmp;  // n-vector (Utmp holds max(m, n) * kEigMax doubles)
-    double* u = h->X2;    // m-vector (X2 holds m * w_cap doubles)
-    if ((e = launch_fill_random(h->stream, h->Om, (int)n, 1, 0, 1, p.seed ^ 0x3C3C3C3Cull, 7)) != hipSuccess ||
-        (e = launch_scale_copy(h->stream, n, h->Om, 1.0, v)) != hipSuccess) {
-      h->err = hipGetErrorString(e);
-      return finish_fail(SVT_E_HIP);
-    }
-    double sig_prev = 0.0, sig = 0.0, vnorm2 = 0.0;
-    if ((e = launch_sumsq(h->stream, n, v, h->partial, h->scal, S_B)) != hipSuccess) {
-      h->err = hipGetErrorString(e);
-      return finish_fail(SVT_E_HIP);
-    }
-    if ((st = readback(h, S_B + 1)) != SVT_OK) return finish_fail(st);
-    vnorm2 = h->hscal[S_B];
-    if ((e = launch_scale_copy(h->stream, n, v, 1.0 / std::sqrt(vnorm2), v)) != hipSuccess) {
-      h->err = hipGetErrorString(e);
-      return finish_fail(SVT_E_HIP);
-    }
-    for (int itp = 0; itp < 5000; ++itp) {
-      e = launch_seg_spmm(h->stream, (int)m, h->rowptr, h->colidx, h->csr2csc, h->a, v, 1, u, 1, 1);
-      if (e == hipSuccess) e = launch_seg_spmm(h->stream, (int)n, h->colptr, h->rowidx, nullptr, h->a, u, 1, v, 1, 1);
-      if (e == hipSuccess) e = launch_sumsq(h->stream, m, u, h->partial, h->scal, S_A);
-      if (e == hipSuccess) e = launch_sumsq(h->stream, n, v, h->partial + 2048, h->scal, S_B);
-      if (e != hipSuccess) {
-        h->err = hipGetErrorString(e);
-        return finish_fail(SVT_E_HIP);
-      }
-      if ((st = readback(h, S_B + 1)) != SVT_OK) return finish_fail(st);
-      sig = std::sqrt(h->hscal[S_A]);          // ||A v|| with ||v|| = 1
-      const double nv = std::sqrt(h->hscal[S_B]);
-      if (!(nv > 0.0)) break;
-      if ((e = launch_scale_copy(h->stream, n, v, 1.0 / nv, v)) != hipSuccess) {
-        h->err = hipGetErrorString(e);
-        return finish_fail(SVT_E_HIP);
-      }
-      if (itp > 3 && std::fabs(sig - sig_prev) <= 1e-15 * sig) break;
-      sig_prev = sig;
-    }
-    h->k0 = (int32_t)std::ceil(p.tau / (p.delta * sig));
-  } else {
-    h->k0 = p.k0;
-  }
-  if ((e = launch_scale_copy(h->stream, nnz, h->a, (double)h->k0 * p.delta, h->y)) != hipSuccess ||
-      (e = launch_sumsq(h->stream, nnz, h->y, h->partial, h->scal, S_NORMY)) != hipSuccess) {
-    h->err = hipGetErrorString(e);
-    return finish_fail(SVT_E_HIP);
-  }
-  if ((st = readback(h, S_NORMY + 1)) != SVT_OK) return finish_fail(st);
-  h->normY = h->hscal[S_NORMY];
   h->r = 0;
   h->iter = 0;
   h->eps_thr_set = false;
@@ -756,18 +874,7 @@ svt_status r4svd_step(svt_handle* h, svt_step_stats* st) {
   if (!h) return SVT_E_INVALID_ARG;
   svt_step_stats local;
   if (!st) st = &local;
-  std::memset(st, 0, sizeof(*st));
-  const int r_save = h->r;
-  const bool thr_set = h->eps_thr_set;
-  const double thr = h->eps_thr;
-  st->iter = h->iter + 1;
-  svt_status s1 = r4svd_core(h, h->iter + 1, -1, st);
-  if (s1 == SVT_OK) s1 = projected_svd(h, st);
-  h->r = r_save;
-  h->eps_thr_set = thr_set;
-  h->eps_thr = thr;
-  if (h->ev_rows > h->r) h->ev_valid = 0;
-  return s1;
+  return dispatch(h, [&](auto& eng) { return eng.operator_only(st); });
 }
 
 svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
@@ -776,17 +883,20 @@ svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
   if (h->converged) return fail(h, SVT_E_STATE, "the iteration has already converged");
   svt_step_stats st;
   std::memset(&st, 0, sizeof(st));
-  for (int s = 0; s < max_steps; ++s) {
-    if (h->iter >= h->p.maxit) {
-      st.flags |= SVT_F_MAXIT;
-      break;
+  svt_status status = dispatch(h, [&](auto& eng) -> svt_status {
+    for (int s = 0; s < max_steps; ++s) {
+      if (h->iter >= h->p.maxit) {
+        st.flags |= SVT_F_MAXIT;
+        break;
+      }
+      CHK(eng.iteration(&st));
+      if (h->iter >= h->p.maxit && !st.stopped) st.flags |= SVT_F_MAXIT;
+      if (st.stopped) break;
     }
-    CHK(do_iteration(h, &st));
-    if (h->iter >= h->p.maxit && !st.stopped) st.flags |= SVT_F_MAXIT;
-    if (st.stopped) break;
-  }
+    return SVT_OK;
+  });
   if (last) *last = st;
-  return SVT_OK;
+  return status;
 }
 
 svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V) {
@@ -797,21 +907,7 @@ svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, doubl
   if (kk == 0) return SVT_OK;
   if (s)
     for (int c = 0; c < kk; ++c) s[c] = h->sigma_k[c] - h->p.tau;
-  std::vector<double> buf;
-  if (U) {
-    HIPCHK(launch_rowmul(h->stream, (int)h->m, h->r, h->Q, h->r_cap, h->Sk, kEigMax, h->Utmp, kEigMax, kk, 1.0, 0.0));
-    buf.resize((size_t)h->m * kEigMax);
-    CHK(to_host(h, buf.data(), h->Utmp, buf.size()));
-    for (int64_t i = 0; i < h->m; ++i)
-      for (int c = 0; c < kk; ++c) U[i * kcap + c] = buf[i * kEigMax + c];
-  }
-  if (V) {
-    buf.resize((size_t)h->n * kEigMax);
-    CHK(to_host(h, buf.data(), h->Vt, buf.size()));
-    for (int64_t j = 0; j < h->n; ++j)
-      for (int c = 0; c < kk; ++c) V[j * kcap + c] = buf[j * kEigMax + c];
-  }
-  return SVT_OK;
+  return dispatch(h, [&](auto& eng) { return eng.factors(kk, kcap, U, V); });
 }
 
 svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out) {
@@ -819,7 +915,8 @@ svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_
   if (nq < 0 || (nq > 0 && (!qi || !qj || !x_out))) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   for (int64_t l = 0; l < nq; ++l)
-    if (qi[l] < 0 || qi[l] >= h->m || qj[l] < 0 || qj[l] >= h->n) return fail(h, SVT_E_INVALID_ARG, "query out of range");
+    if (qi[l] < 0 || qi[l] >= h->m || qj[l] < 0 || qj[l] >= h->n)
+      return fail(h, SVT_E_INVALID_ARG, "query out of range");
   if (nq == 0) return SVT_OK;
   int32_t *di = nullptr, *dj = nullptr;
   double* dx = nullptr;
@@ -828,30 +925,28 @@ svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_
   HIPCHK(dalloc(&dx, nq));
   hipError_t e = hipMemcpyAsync(di, qi, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(dj, qj, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = launch_sample(h->stream, nq, di, dj, h->Ut, h->Vt, kEigMax, h->k, dx);
-  if (e == hipSuccess) e = hipMemcpyAsync(x_out, dx, nq * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  svt_status st = SVT_OK;
+  if (e == hipSuccess) st = dispatch(h, [&](auto& eng) { return eng.sample(nq, di, dj, dx); });
+  if (e == hipSuccess && st == SVT_OK) e = hipMemcpyAsync(x_out, dx, nq * sizeof(double), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   (void)hipFree(di);
   (void)hipFree(dj);
   (void)hipFree(dx);
   HIPCHK(e);
-  return SVT_OK;
+  return st;
 }
 
 svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,
                          double* eps_min, int32_t* iter) {
   if (!h) return SVT_E_INVALID_ARG;
-  if (y) {
-    std::vector<double> buf(h->nnz);
-    CHK(to_host(h, buf.data(), h->y, h->nnz));
-    for (int64_t u = 0; u < h->nnz; ++u) y[u] = buf[h->user2csc[u]];
-  }
-  if (Q && h->r > 0) {
-    if (qcap < h->r) return fail(h, SVT_E_INVALID_ARG, "qcap smaller than r");
-    HIPCHK(hipMemcpy2DAsync(Q, qcap * sizeof(double), h->Q, h->r_cap * sizeof(double), h->r * sizeof(double), h->m,
-                            hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-  }
+  if (Q && h->r > 0 && qcap < h->r) return fail(h, SVT_E_INVALID_ARG, "qcap smaller than r");
+  svt_status st = dispatch(h, [&](auto& eng) -> svt_status {
+    using TT = std::remove_pointer_t<decltype(eng.a())>;
+    if (y) CHK(eng.download_lambda(y, (const TT*)h->y));
+    if (Q && h->r > 0) CHK(eng.get_basis(Q, qcap));
+    return SVT_OK;
+  });
+  if (st != SVT_OK) return st;
   if (r) *r = h->r;
   if (eps_thr) *eps_thr = h->eps_thr_set ? h->eps_thr : std::numeric_limits<double>::quiet_NaN();
   if (eps_min) *eps_min = h->eps_min;
@@ -865,15 +960,13 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   if (!y) return fail(h, SVT_E_INVALID_ARG, "y is NULL");
   if (r < 0 || r > h->p.r_max || (r > 0 && !Q)) return fail(h, SVT_E_INVALID_ARG, "bad basis width");
   if (iter < 0) return fail(h, SVT_E_INVALID_ARG, "iter must be non-negative");
-  std::vector<double> buf(h->nnz);
-  for (int64_t u = 0; u < h->nnz; ++u) buf[h->user2csc[u]] = y[u];
-  HIPCHK(hipMemcpyAsync(h->y, buf.data(), h->nnz * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  if (r > 0)
-    HIPCHK(hipMemcpy2DAsync(h->Q, h->r_cap * sizeof(double), Q, r * sizeof(double), r * sizeof(double), h->m,
-                            hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_sumsq(h->stream, h->nnz, h->y, h->partial, h->scal, S_NORMY));
-  CHK(readback(h, S_NORMY + 1));
-  h->normY = h->hscal[S_NORMY];
+  svt_status st = dispatch(h, [&](auto& eng) -> svt_status {
+    using TT = std::remove_pointer_t<decltype(eng.a())>;
+    CHK(eng.upload_lambda((TT*)h->y, y));
+    if (r > 0) CHK(eng.set_basis(Q, r));
+    return eng.sumsq_y(&h->normY);
+  });
+  if (st != SVT_OK) return st;
   h->r = r;
   h->eps_thr_set = !std::isnan(eps_thr);
   h->eps_thr = h->eps_thr_set ? eps_thr : 0.0;

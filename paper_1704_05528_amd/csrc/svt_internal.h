@@ -11,65 +11,68 @@
 
 namespace svt {
 
-constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kBlock = 256;        // threads per workgroup for streaming kernels
-constexpr int kEigMax = 96;        // largest Rayleigh-Ritz block the in-LDS Jacobi solver holds
-constexpr int kNarrow = 16;        // widest block handled by the lanes-over-nonzeros SpMM
-constexpr int kScalars = 64;       // doubles in the device->host readback buffer
+constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
+constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
+constexpr int kScalars = 64;  // doubles in the device->host readback buffer
 
-// Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.
+// Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
+// marked (T) hold the storage type of the precision form: double (SVT_FP64) or float
+// (SVT_MIXED); the Gram matrices, the eigensolver and all reductions are double in both.
 struct Handle {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t m = 0, n = 0, nnz = 0;
   svt_params p{};
-  int32_t r_cap = 0;      // columns allocated for Q and W (>= r_max)
-  int32_t w_cap = 0;      // columns allocated for a sampled block (>= max(t0, dt))
-  int32_t b_cap = 0;      // columns of the eigensolver block (kEigMax)
+  int32_t r_cap = 0;  // columns allocated for Q and W (>= r_max + 64)
+  int32_t w_cap = 0;  // columns of a sampled block chunk (64)
+  int32_t b_cap = 0;  // columns of the eigensolver block
 
   // sparsity structure
-  int32_t *colptr = nullptr, *rowidx = nullptr;   // CSC (primary order of values)
-  int32_t *rowptr = nullptr, *colidx = nullptr;   // CSR
-  int32_t *csr2csc = nullptr;                     // CSR position -> CSC position
-  int32_t *tstart = nullptr;                      // row-tile starts per column (dense-ish patterns only)
-  std::vector<int64_t> user2csc;                  // caller order -> CSC position (host)
+  int32_t *colptr = nullptr, *rowidx = nullptr;  // CSC (primary order of values)
+  int32_t *rowptr = nullptr, *colidx = nullptr;  // CSR
+  int32_t *csr2csc = nullptr;                    // CSR position -> CSC position
+  int32_t *tstart = nullptr;                     // row-tile starts per column (dense-ish patterns only)
+  std::vector<int64_t> user2csc;                 // caller order -> CSC position (host)
 
-  // values on Lambda (CSC order)
-  double *a = nullptr, *y = nullptr, *y_next = nullptr, *x = nullptr;
+  // values on Lambda, CSC order (T)
+  void *a = nullptr, *y = nullptr, *y_next = nullptr;
 
-  // basis and projections
-  double *Q = nullptr;    // m x r_cap
-  double *W = nullptr;    // n x r_cap, W = Y^T Q = B^T
-  double *X = nullptr;    // m x w_cap sampled block
-  double *X2 = nullptr;   // m x w_cap scratch block
-  double *Om = nullptr;   // n x w_cap Gaussian block, also Y^T X scratch for power iterations
-  double *T = nullptr;    // r_cap x w_cap projection coefficients Q^T X
-  double *G = nullptr;    // r_cap x r_cap Gram W^T W
-  double *small = nullptr;  // w_cap x w_cap Gram / factor scratch
-  double *Minv = nullptr;   // w_cap x w_cap orthonormalising transform
-  double *prenorm = nullptr;  // w_cap column norms before projection
+  // basis, projections, sampled blocks (T)
+  void* Q = nullptr;   // m x r_cap
+  void* W = nullptr;   // n x r_cap, W = Y^T Q = B^T
+  void* X = nullptr;   // m x w_cap sampled block
+  void* X2 = nullptr;  // m x w_cap scratch block
+  void* Om = nullptr;  // max(m, n) x w_cap Gaussian block, also Y^T X in power iterations
+  // double
+  double* T = nullptr;        // r_cap x w_cap projection coefficients Q^T X
+  double* G = nullptr;        // r_cap x r_cap Gram W^T W
+  double* small = nullptr;    // kEigMax x kEigMax block Gram
+  double* Minv = nullptr;     // kEigMax x kEigMax block Cholesky factor
+  double* prenorm = nullptr;  // column norms before projection
 
-  // eigensolver
+  // eigensolver (double)
   double *EV = nullptr, *EZ = nullptr, *EZ2 = nullptr, *EZ3 = nullptr;  // r_cap x kEigMax blocks
-  double *EH = nullptr, *ES = nullptr;                  // b_cap x b_cap Rayleigh quotient and its eigvecs
-  double *Eval = nullptr;                               // b_cap eigenvalues (descending)
-  int32_t ev_valid = 0;   // columns of EV that hold Ritz vectors of the previous iteration
-  int32_t ev_rows = 0;    // basis width those vectors refer to
+  double *EH = nullptr, *ES = nullptr;                                   // kEigMax x kEigMax
+  double* Eval = nullptr;  // eigenvalues (descending) followed by Ritz residual norms
+  int32_t ev_valid = 0;    // columns of EV that hold Ritz vectors of the previous iteration
+  int32_t ev_rows = 0;     // basis width those vectors refer to
 
   // factors of X = Ut Vt^T
-  double *Ut = nullptr;   // m x kEigMax, Q U_K diag(sigma - tau)
-  double *Vt = nullptr;   // n x kEigMax, W U_K diag(1 / sigma)
-  double *C = nullptr;    // r_cap x kEigMax
-  double *D = nullptr;    // r_cap x kEigMax
-  double *Sk = nullptr;   // r_cap x kEigMax, eigenvectors of the Gram for sigma > tau
-  double *Utmp = nullptr; // max(m, n) x kEigMax scratch
+  void* Ut = nullptr;      // (T) m x kEigMax, Q S_K diag(sigma - tau)
+  void* Vt = nullptr;      // (T) n x kEigMax, W S_K diag(1 / sigma)
+  void* Utmp = nullptr;    // (T) max(m, n) x kEigMax scratch
+  double* C = nullptr;     // r_cap x kEigMax
+  double* D = nullptr;     // r_cap x kEigMax
+  double* Sk = nullptr;    // r_cap x kEigMax, eigenvectors of the Gram for sigma > tau
   int32_t k = 0;
-  std::vector<double> sigma_k;   // host copy of the k singular values above tau
+  std::vector<double> sigma_k;  // host copy of the k singular values above tau
 
   // reductions
-  double *partial = nullptr;  int64_t partial_cap = 0;
-  double *scal = nullptr;     // device scalars
-  double *hscal = nullptr;    // pinned host mirror
+  double* partial = nullptr;
+  int64_t partial_cap = 0;
+  double* scal = nullptr;   // device scalars
+  double* hscal = nullptr;  // pinned host mirror
 
   // iteration state (host)
   int32_t r = 0;
@@ -102,71 +105,87 @@ struct Handle {
 };
 
 // ---------------------------------------------------------------------------------------------
-// kernel launchers (kernels.hip)
+// kernel launchers (kernels.hip); T is double or float
 // ---------------------------------------------------------------------------------------------
 // columns c0 .. c0+w-1 (c0 a multiple of 4) of the Omega block (it, blk), stored from column 0 of om
-hipError_t launch_omega(hipStream_t s, double* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk,
-                        uint64_t it);
+template <class T>
+hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk, uint64_t it);
 
 // out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w]
+template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const double* val, const double* D, int ldd, double* out, int ldo, int w);
-
-// columns c0 .. c0+count-1 of a rows x ld block set to e_{row0}, e_{row0+1}, ...
-hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0);
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w);
 
 // LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
 // position of its first entry in each row tile (n x (tiled_row_tiles(m) + 1) int32)
 int tiled_row_tiles(int64_t m);
+template <class T>
 hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
-                               const double* val, const double* Q, int ldq, int r, double* W, int ldw,
-                               double* partial, int64_t partial_cap);
+                               const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
+                               int64_t partial_cap);
 
-// out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w]
-hipError_t launch_rowmul(hipStream_t s, int rows, int K, const double* A, int lda, const double* M, int ldm,
-                         double* out, int ldo, int w, double alpha, double beta);
+// out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w] (double accumulation)
+template <class TA, class TM, class TO>
+hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
+                         int w, double alpha, double beta);
 
-// partial Gram blocks: out[a, b] = sum_i A[i, a] B[i, b], a < na (any), b < nb (<= 64)
-hipError_t launch_tn_narrow(hipStream_t s, int rows, const double* A, int lda, int na, const double* B, int ldb,
-                            int nb, double* out, int ldo, double* partial, int64_t partial_cap);
+// out[a, b] = sum_i A[i, a] B[i, b] in double, a < na (any), b < nb (<= kEigMax)
+template <class TA, class TB>
+hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
+                            double* out, int ldo, double* partial, int64_t partial_cap);
 
-// Gram G = A^T A for A rows x na (na up to r_cap), full symmetric output
-hipError_t launch_gram(hipStream_t s, int rows, const double* A, int lda, int na, double* G, int ldg,
-                       double* partial, int64_t partial_cap);
+// Gram G = A^T A in double for A rows x na (na up to r_cap), full symmetric output
+template <class T>
+hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
+                       int64_t partial_cap);
 
 // scal[slot] = sum of squares over the columns c0..c0+w-1 of a rows x ld matrix
-hipError_t launch_sumsq_cols(hipStream_t s, int rows, const double* A, int lda, int c0, int w, double* partial,
+template <class T>
+hipError_t launch_sumsq_cols(hipStream_t s, int rows, const T* A, int lda, int c0, int w, double* partial,
                              double* scal, int slot);
 // scal[slot] = sum v[i]^2
-hipError_t launch_sumsq(hipStream_t s, int64_t len, const double* v, double* partial, double* scal, int slot);
+template <class T>
+hipError_t launch_sumsq(hipStream_t s, int64_t len, const T* v, double* partial, double* scal, int slot);
 // out[c] = ||A[:, c]||_2 for c < w (w <= 64), via the w x w Gram in gram_scratch
-hipError_t launch_colnorms(hipStream_t s, int rows, const double* A, int lda, int w, double* gram_scratch,
-                           double* partial, int64_t partial_cap, double* out);
+template <class T>
+hipError_t launch_colnorms(hipStream_t s, int rows, const T* A, int lda, int w, double* gram_scratch, double* partial,
+                           int64_t partial_cap, double* out);
 
 // Cholesky factor R of a block's Gram with the column-drop rules (one workgroup): see kernels.hip
 hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
                              double drop_tol, double dep_tol, double* Rout, int ldm, double* scal, int slot,
                              int wk_slot_in);
 // out = X[:, kept] R^{-1} row by row, kept columns packed left, the rest zero
-hipError_t launch_trsm_rows(hipStream_t s, int rows, const double* X, int ldx, int w, const double* R, int ldr,
-                           double* out, int ldo);
+template <class T>
+hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
+                            int ldo);
 
 // sampled product on Lambda (CSC order) with residual and dual update; per-block partial sums of
-// res^2 and y_next^2 land in partial[2 b], partial[2 b + 1]; returns the number of blocks
-hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* a,
-                               const double* y, double* y_next, double* x_out, const double* Ut, const double* Vt,
-                               int ld, int k, double delta, double* partial, int* nblocks);
+// res^2 and y_next^2 land in partial[2 b], partial[2 b + 1]; *nblocks receives the block count
+template <class T>
+hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* a,
+                               const T* y, T* y_next, const T* Ut, const T* Vt, int ld, int k, double delta,
+                               double* partial, int* nblocks);
 // scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
 // X on arbitrary entries
-hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const double* Ut,
-                         const double* Vt, int ld, int k, double* out);
+template <class T>
+hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
+                         int ld, int k, double* out);
 
-hipError_t launch_scale_copy(hipStream_t s, int64_t len, const double* src, double alpha, double* dst);
-hipError_t launch_copy_cols(hipStream_t s, int rows, const double* src, int lds, double* dst, int ldd, int w);
+template <class TS, class TD>
+hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst);
+template <class TS, class TD>
+hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds, TD* dst, int ldd, int w);
+
+// columns c0 .. c0+count-1 of a rows x ld block set to e_{row0}, e_{row0+1}, ...
+hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0);
+// fill columns c0..c1-1 of a rows x ld block with Philox Gaussians
+hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0, int c1, uint64_t seed,
+                              uint64_t tag);
 
 // ---------------------------------------------------------------------------------------------
-// eigensolver (eig.hip)
+// eigensolver (eig.hip), double
 // ---------------------------------------------------------------------------------------------
 // Jacobi eigen-decomposition of a b x b symmetric matrix (b <= kEigMax) in one workgroup.
 // Eigenvalues descending into eval, eigenvectors as columns of evec (row-major, ld = ldv).
@@ -178,8 +197,5 @@ hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const 
 // factor matrices C = S[:, :k] diag(sigma - tau), D = S[:, :k] diag(1/sigma) from eigenpairs of the Gram
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds, const double* theta,
                                 double tau, double* C, double* D, int ldc);
-// fill columns c0..c1-1 of an r x ld block with Philox Gaussians (rows >= r zero)
-hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0, int c1, uint64_t seed,
-                              uint64_t tag);
 
 }  // namespace svt

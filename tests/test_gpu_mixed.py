@@ -1,0 +1,86 @@
+"""GPU parity of the mixed form (float32 storage and sparse accumulation, float64 Gram / Cholesky /
+eigen-solver / norms) against the emulated-precision oracle, and its error against the FP64 oracle.
+
+Bars: against the emulated oracle, values within 2e-5 relative (float32 accumulation-order noise,
+about sqrt(row length) x 6e-8, amplified by the conditioning of the step); against the FP64
+oracle the same step stays within 1e-4 relative; integers (r, k, blocks) exact.
+"""
+import numpy as np
+import pytest
+
+import svt_workloads as W
+from oracle import Params, Problem, State, initial_state, svt_run, svt_step
+from oracle.mixed import f32, svt_step_mixed
+
+pytestmark = pytest.mark.gpu
+
+TOL_EMU = 2e-5
+TOL_FP64 = 1e-4
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _state_after(prob, p, steps):
+    state, k0 = initial_state(prob, p)
+    for _ in range(steps):
+        state, _ = svt_step(prob, p, state)
+    return state, k0
+
+
+@pytest.mark.parametrize("m,n,rank,frac,seed,steps", [(90, 70, 3, 0.4, 61, 6), (130, 110, 4, 0.35, 62, 14),
+                                                      (200, 150, 3, 0.3, 63, 25)])
+def test_mixed_step_against_emulated_and_fp64_oracle(gpu_lib, m, n, rank, frac, seed, steps):
+    w = W.tiny_dense(m, n, rank, frac, seed=seed)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=seed)
+    s64, k0 = _state_after(prob, p, steps)
+    st32 = State(it=s64.it, y=f32(s64.y), Q=f32(s64.Q), eps_thr=s64.eps_thr, eps_min=s64.eps_min)
+    nxt_emu, info_emu = svt_step_mixed(prob, p, st32)
+    _, info_64 = svt_step(prob, p, st32)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, seed=seed,
+                         precision=gpu_lib.SVT_MIXED)
+    h.set_state(st32.y, st32.Q, st32.eps_thr, st32.eps_min, st32.it)
+    st = h.iterate(1)
+    x = h.sample(w.rows, w.cols)
+    assert st.r == info_emu.r and st.k == info_emu.k and st.blocks == info_emu.blocks
+    assert rel_err(x, info_emu.x) <= TOL_EMU, rel_err(x, info_emu.x)
+    assert abs(st.rel_res - info_emu.rel) <= TOL_EMU * info_emu.rel
+    assert abs(st.eps - info_emu.eps) <= 1e-6
+    assert rel_err(h.get_state()["y"], nxt_emu.y) <= TOL_EMU
+    # stated error of the mixed form against the FP64 step from the same state
+    assert rel_err(x, info_64.x) <= TOL_FP64
+    assert abs(st.rel_res - info_64.rel) <= TOL_FP64 * info_64.rel
+
+
+def test_mixed_free_run_with_replay_tracks_fp64(gpu_lib):
+    """30 iterations of the mixed form with the FP64 oracle's decisions replayed: the residual
+    trajectory stays within 1e-4 relative of the FP64 one."""
+    w = W.tiny_dense(120, 100, 3, 0.4, seed=64)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=3, maxit=30)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, seed=3, maxit=30,
+                         precision=gpu_lib.SVT_MIXED)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    worst = 0.0
+    for info in infos:
+        st = h.iterate(1)
+        assert st.r == info.r and st.k == info.k
+        worst = max(worst, abs(st.rel_res - info.rel) / info.rel)
+    assert worst <= TOL_FP64, worst
+
+
+def test_mixed_planted_reaches_tolerance(gpu_lib):
+    """The mixed form reaches relative residual 1e-4 on a planted problem (float32 storage is far
+    below the tolerance)."""
+    w = W.tiny_dense(150, 150, 3, 0.4, seed=65)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=1, maxit=800,
+                         precision=gpu_lib.SVT_MIXED)
+    st = h.iterate(800)
+    assert st.stopped and st.rel_res < 1e-4
+    k, s, U, V = h.factors()
+    X = (U * s) @ V.T
+    assert np.linalg.norm(X - w.A) / np.linalg.norm(w.A) < 2e-3

@@ -324,3 +324,27 @@ def test_replay_forces_decisions():
     for a, b in zip(infos, infos2):
         assert a.blocks == b.blocks and a.annealed == b.annealed
         np.testing.assert_array_equal(a.x, b.x)
+
+
+# ---------------------------------------------------------------------------- emulated reduced precision
+
+def test_mixed_oracle_rounds_at_storage_points_and_tracks_fp64():
+    """The emulated mixed form keeps Y, x and the residual float32-representable and stays within
+    float32 error of the FP64 step from the same state (same decisions)."""
+    from oracle.mixed import f32, svt_step_mixed
+    w = W.tiny_dense(70, 60, 3, 0.45, seed=19)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=4)
+    state, _ = initial_state(prob, p)
+    for _ in range(5):
+        state, _ = svt_step(prob, p, state)
+    st32 = State(it=state.it, y=f32(state.y), Q=f32(state.Q), eps_thr=state.eps_thr, eps_min=state.eps_min)
+    new32, i32 = svt_step_mixed(prob, p, st32)
+    new64, i64 = svt_step(prob, p, st32)
+    assert np.array_equal(new32.y, f32(new32.y)) and np.array_equal(i32.x, f32(i32.x))
+    assert i32.r == i64.r and i32.k == i64.k
+    assert np.abs(i32.x - i64.x).max() <= 1e-5 * np.abs(i64.x).max()
+    assert abs(i32.rel - i64.rel) <= 1e-5 * i64.rel
+    assert np.abs(new32.y - new64.y).max() <= 1e-5 * np.abs(new64.y).max()
+    # and the float32 rounding is really applied: the two forms are not bit-identical
+    assert np.abs(i32.x - i64.x).max() > 0
