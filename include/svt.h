@@ -164,14 +164,24 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
  * growth blocks and annealed[l] (0/1).  len = 0 clears the replay. */
 svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* annealed, int32_t len);
 
-/* Derivative of a held-out loss through T unrolled iterations of Alg. 4
- * (frozen-basis convention: every discrete decision and every basis Q_i of
- * the forward run is held fixed).  Runs T iterations from Y^(0), with Y
- * checkpointed every ckpt iterations and recomputed during the reverse sweep,
- * then back-propagates gx_h = dL/dX on the held-out set H (nh entries).
- * Outputs: dtau, ddelta (scalars) and da (nnz, caller order) = dL/dA on
- * Lambda.  The forward run restarts from the initial state; the handle's
- * state afterwards is that after T iterations. */
+/* Derivative of a held-out loss through the first T unrolled iterations of
+ * Alg. 4 (Eq. 4 with the kicking start), in the frozen-basis convention: the
+ * kicking count, every growth and annealing decision and every basis Q_i of
+ * the forward run are held fixed, so iteration i is the map
+ * Y_i -> X_i = Q_i D_tau(Q_i^T Y_i) (Eq. 5) followed by the dual update.
+ * The handle must have run at least T iterations since svt_init (svt_iterate,
+ * no svt_set_state since), in the FP64 form, with bases of at most 96 columns
+ * over those T iterations.  The Y_i are recomputed from Y_1 = k0 delta P(A),
+ * checkpointed every ckpt iterations (ckpt <= 0: about sqrt(T)); device
+ * memory of (T / ckpt + ckpt) nnz doubles plus a few m x 288 and n x 288
+ * blocks is allocated for the call and released before it returns.
+ * Input: gx_h[l] = dL/dX_T(hi[l], hj[l]) on the held-out set H (nh entries,
+ * repeats add up; nh = 0 gives zero gradients).
+ * Outputs: *dtau, *ddelta, and da (nnz, caller order) = dL/dA on Lambda.
+ * The iteration state of the handle is left unchanged.
+ * Errors: SVT_E_INVALID_ARG (T <= 0, NULL outputs, H index out of range),
+ * SVT_E_STATE (fewer than T recorded iterations, state replaced, mixed form),
+ * SVT_E_LIMIT (a basis wider than 96 columns). */
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
                     const double* gx_h, double* dtau, double* ddelta, double* da);
 

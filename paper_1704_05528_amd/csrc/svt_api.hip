@@ -36,7 +36,7 @@ constexpr int kDirect = 32;           // basis widths up to this are diagonalise
 
 // scalar slots of the device readback buffer
 enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_RES2 = 4, S_YN2 = 5, S_SWEEPS = 6, S_NORMY = 7,
-       S_A = 8, S_B = 9 };
+       S_A = 8, S_B = 9, S_TBAR = 10, S_DOT = 11 };
 
 #define HIPCHK(expr)                                                     \
   do {                                                                   \
@@ -464,6 +464,7 @@ struct Engine {
       ++h->replay_pos;
     }
     CHK(r4svd_core(it, rb, st));
+    h->hist_r.push_back(h->r);
     CHK(projected_svd(st));
     int nbl = 0;
     {
@@ -637,6 +638,194 @@ svt_status dispatch(Handle* h, F&& f) {
   }
   Engine<double> e(h);
   return f(e);
+}
+
+// ==============================================================================================
+// Reverse sweep through T unrolled iterations of Alg. 4 (frozen-basis convention), FP64 form.
+//
+// Iteration i (0-based) maps Y_i to X_i = Q_i D_tau(Q_i^T Y_i), Q_i the first hist_r[i] columns
+// of the append-only basis, then Y_{i+1} = Y_i + delta P(A - X_i) (Eq. 4); Y_0 = k0 delta P(A).
+// The Y_i are recomputed from checkpoints; per iteration the Gram of W_i = Y_i^T Q_i is
+// diagonalised in full (one-workgroup Jacobi), and the adjoint of the thresholding map becomes
+// one sampled product L R^T on Lambda whose small coefficient block comes from adjoint.hip.
+// ==============================================================================================
+struct GradArena {
+  hipStream_t s;
+  std::vector<void*> bufs;
+  explicit GradArena(hipStream_t st) : s(st) {}
+  ~GradArena() {
+    (void)hipStreamSynchronize(s);
+    for (void* b : bufs) (void)hipFree(b);
+  }
+  template <class T>
+  hipError_t get(T** p, size_t count) {
+    hipError_t e = dalloc(p, count);
+    if (e == hipSuccess) bufs.push_back((void*)*p);
+    return e;
+  }
+};
+
+svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, const int32_t* hj, const double* gx,
+                     double* dtau, double* ddelta, double* da) {
+  Engine<double> eng(h);
+  const hipStream_t s = h->stream;
+  const int m = (int)h->m, n = (int)h->n;
+  const int64_t nnz = h->nnz;
+  const double tau = h->p.tau, delta = h->p.delta, tau2 = tau * tau;
+  constexpr int kW = 3 * kEigMax;  // widest factor pair of the sampled adjoint: 2 k + r
+  if (ckpt <= 0) ckpt = (int)std::ceil(std::sqrt((double)T));
+  ckpt = std::min(ckpt, T);
+  const int nseg = (T + ckpt - 1) / ckpt;
+
+  // H in CSC order (stable counting sort by column; repeated entries add up in the product)
+  std::vector<int32_t> hcp(n + 1, 0), hri(std::max<int64_t>(nh, 1));
+  std::vector<double> hv(std::max<int64_t>(nh, 1));
+  for (int64_t l = 0; l < nh; ++l) hcp[hj[l] + 1]++;
+  for (int j = 0; j < n; ++j) hcp[j + 1] += hcp[j];
+  {
+    std::vector<int32_t> pos(hcp.begin(), hcp.end() - 1);
+    for (int64_t l = 0; l < nh; ++l) {
+      const int32_t q = pos[hj[l]]++;
+      hri[q] = hi[l];
+      hv[q] = gx[l];
+    }
+  }
+
+  GradArena ar(s);
+  int32_t *d_hcp = nullptr, *d_hri = nullptr;
+  double *d_hv = nullptr, *ycp = nullptr, *yseg = nullptr, *ybar = nullptr, *abar = nullptr, *res = nullptr;
+  double *xb = nullptr, *tmp = nullptr, *Wb = nullptr, *F = nullptr, *R = nullptr, *L = nullptr, *Cm = nullptr;
+  double *Z1 = nullptr, *Z2 = nullptr, *scr = nullptr, *U = nullptr, *th = nullptr, *Cc = nullptr, *Dc = nullptr;
+  double *Ut = nullptr, *Vt = nullptr;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  A(ar.get(&d_hcp, n + 1));
+  A(ar.get(&d_hri, hri.size()));
+  A(ar.get(&d_hv, hv.size()));
+  A(ar.get(&ycp, (size_t)nseg * nnz));
+  A(ar.get(&yseg, (size_t)ckpt * nnz));
+  for (double** p : {&ybar, &abar, &res, &xb, &tmp}) A(ar.get(p, nnz));
+  A(ar.get(&Wb, (size_t)n * kEigMax));
+  A(ar.get(&F, (size_t)n * kEigMax));
+  A(ar.get(&Vt, (size_t)n * kEigMax));
+  A(ar.get(&Ut, (size_t)m * kEigMax));
+  A(ar.get(&R, (size_t)n * kW));
+  A(ar.get(&L, (size_t)m * kW));
+  A(ar.get(&Cm, (size_t)kEigMax * kW));
+  for (double** p : {&Z1, &Z2, &scr, &U, &Cc, &Dc}) A(ar.get(p, (size_t)kEigMax * kEigMax));
+  A(ar.get(&th, 2 * kEigMax));
+  if (e != hipSuccess)
+    return fail(h, e == hipErrorOutOfMemory ? SVT_E_OOM : SVT_E_HIP,
+                std::string("svt_grad: device allocation failed: ") + hipGetErrorString(e));
+  HIPCHK(hipMemcpyAsync(d_hcp, hcp.data(), hcp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_hri, hri.data(), hri.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_hv, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+
+  const double* Q = eng.Q();
+  const double* a = eng.a();
+  const int ldq = h->r_cap;
+  std::vector<double> theta(kEigMax);
+
+  // Frozen map of iteration i on yi: W_i, eigenpairs (U, th) of G = W_i^T W_i, k, and the
+  // factors Ut = Q_i U_K diag(s - tau), Vt = W_i U_K diag(1/s) = V_K.  Returns k.
+  auto frozen_map = [&](const double* yi, int ri, int* kout) -> svt_status {
+    HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, yi, Q, ldq, Wb, kEigMax, ri));
+    HIPCHK(launch_gram<double>(s, n, Wb, kEigMax, ri, h->G, h->r_cap, h->partial, h->partial_cap));
+    HIPCHK(launch_jacobi(s, h->G, h->r_cap, ri, th, U, kEigMax, h->scal, S_SWEEPS));
+    CHK(to_host<double>(h, theta.data(), th, ri));
+    int k = 0;
+    while (k < ri && theta[k] > tau2) ++k;
+    if (k > 0) {
+      HIPCHK(launch_factor_coeffs(s, ri, k, U, kEigMax, th, tau, Cc, Dc, kEigMax));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cc, kEigMax, Ut, kEigMax, k, 1.0, 0.0)));
+      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, Wb, kEigMax, Dc, kEigMax, Vt, kEigMax, k, 1.0, 0.0)));
+    }
+    *kout = k;
+    return SVT_OK;
+  };
+  // X_i on Lambda, the residual P(A - X_i) and Y_{i+1} (ynext may alias tmp when unused)
+  auto dual_step = [&](const double* yi, int k, double* rs, double* ynext) -> svt_status {
+    HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, Ut, kEigMax, Vt, kEigMax, k, xb));
+    HIPCHK(launch_dual_update(s, nnz, a, xb, yi, delta, rs, ynext));
+    return SVT_OK;
+  };
+
+  // forward pass: Y_0 and the checkpoints Y_{c ckpt}
+  HIPCHK((launch_scale_copy<double, double>(s, nnz, a, (double)h->k0 * delta, ycp)));
+  for (int sg = 1; sg < nseg; ++sg) {
+    HIPCHK(hipMemcpyAsync(yseg, ycp + (size_t)(sg - 1) * nnz, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int i = (sg - 1) * ckpt; i < sg * ckpt; ++i) {
+      int k = 0;
+      CHK(frozen_map(yseg, h->hist_r[i], &k));
+      double* dst = (i + 1 == sg * ckpt) ? ycp + (size_t)sg * nnz : yseg;
+      CHK(dual_step(yseg, k, res, tmp));
+      HIPCHK(hipMemcpyAsync(dst, tmp, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+
+  // reverse sweep, one segment at a time
+  double t_bar = 0.0, d_bar = 0.0;
+  HIPCHK(hipMemsetAsync(abar, 0, nnz * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(ybar, 0, nnz * sizeof(double), s));
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int s0 = sg * ckpt, s1 = std::min(T, s0 + ckpt);
+    HIPCHK(hipMemcpyAsync(yseg, ycp + (size_t)sg * nnz, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int i = s0; i + 1 < s1; ++i) {
+      int k = 0;
+      CHK(frozen_map(yseg + (size_t)(i - s0) * nnz, h->hist_r[i], &k));
+      CHK(dual_step(yseg + (size_t)(i - s0) * nnz, k, res, yseg + (size_t)(i + 1 - s0) * nnz));
+    }
+    for (int i = s1 - 1; i >= s0; --i) {
+      const double* yi = yseg + (size_t)(i - s0) * nnz;
+      const int ri = h->hist_r[i];
+      int k = 0;
+      CHK(frozen_map(yi, ri, &k));
+      if (i < T - 1) {
+        // Y_{i+1} = Y_i + delta P(A - X_i): contributions to abar and dbar, cotangent of X_i
+        CHK(dual_step(yi, k, res, tmp));
+        HIPCHK(launch_axpby(s, nnz, delta, ybar, 1.0, abar));
+        HIPCHK(launch_dot(s, nnz, ybar, res, h->partial, h->scal, S_DOT));
+        CHK(readback(h, S_DOT + 1));
+        d_bar += h->hscal[S_DOT];
+        if (k == 0) continue;
+        HIPCHK((launch_scale_copy<double, double>(s, nnz, ybar, -delta, tmp)));
+        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, kEigMax, ri));
+      } else {
+        if (k == 0 || nh == 0) continue;
+        HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, kEigMax, ri));
+      }
+      // F = Xbar^T Q_i = Bbar^T; Z1 = Bbar V_K, Z2 = Bbar W_i, R = [F U_K | V_K | W_i]
+      const int wl = 2 * k + ri;
+      HIPCHK((launch_tn_narrow<double, double>(s, n, F, kEigMax, ri, Vt, kEigMax, k, Z1, kEigMax, h->partial,
+                                               h->partial_cap)));
+      HIPCHK((launch_tn_narrow<double, double>(s, n, F, kEigMax, ri, Wb, kEigMax, ri, Z2, kEigMax, h->partial,
+                                               h->partial_cap)));
+      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, F, kEigMax, U, kEigMax, R, kW, k, 1.0, 0.0)));
+      HIPCHK((launch_copy_cols<double, double>(s, n, Vt, kEigMax, R + k, kW, k)));
+      HIPCHK((launch_copy_cols<double, double>(s, n, Wb, kEigMax, R + 2 * k, kW, ri)));
+      hipError_t ec = launch_adjoint_coeffs(s, ri, k, U, kEigMax, th, Z1, kEigMax, Z2, kEigMax, tau, Cm, kW, scr,
+                                            h->scal, S_TBAR);
+      if (ec == hipErrorInvalidValue)
+        return fail(h, SVT_E_LIMIT, "svt_grad: r * k too large for the one-workgroup adjoint coefficients");
+      HIPCHK(ec);
+      HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cm, kW, L, kW, wl, 1.0, 0.0)));
+      HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, L, kW, R, kW, wl, tmp));
+      HIPCHK(launch_axpby(s, nnz, 1.0, tmp, 1.0, ybar));
+      CHK(readback(h, S_TBAR + 1));
+      t_bar += h->hscal[S_TBAR];
+    }
+  }
+  // Y_0 = k0 delta P(A)
+  HIPCHK(launch_axpby(s, nnz, (double)h->k0 * delta, ybar, 1.0, abar));
+  HIPCHK(launch_dot(s, nnz, ybar, a, h->partial, h->scal, S_DOT));
+  CHK(readback(h, S_DOT + 1));
+  d_bar += (double)h->k0 * h->hscal[S_DOT];
+  CHK(eng.download_lambda(da, abar));
+  *dtau = t_bar;
+  *ddelta = d_bar;
+  return SVT_OK;
 }
 
 void release(Handle* h) {
@@ -977,6 +1166,8 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   h->ev_valid = 0;
   h->ev_rows = 0;
   h->k = 0;
+  h->hist_ok = false;
+  h->hist_r.clear();
   return SVT_OK;
 }
 
@@ -1018,9 +1209,22 @@ svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* fl
 
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
                     const double* gx_h, double* dtau, double* ddelta, double* da) {
-  (void)T; (void)ckpt; (void)nh; (void)hi; (void)hj; (void)gx_h; (void)dtau; (void)ddelta; (void)da;
   if (!h) return SVT_E_INVALID_ARG;
-  return fail(h, SVT_E_STATE, "svt_grad is not available in this build");
+  if (T <= 0) return fail(h, SVT_E_INVALID_ARG, "T must be positive");
+  if (!dtau || !ddelta || !da) return fail(h, SVT_E_INVALID_ARG, "NULL output pointer");
+  if (nh < 0 || (nh > 0 && (!hi || !hj || !gx_h))) return fail(h, SVT_E_INVALID_ARG, "bad held-out arrays");
+  if (nh >= ((int64_t)1 << 31)) return fail(h, SVT_E_INVALID_ARG, "nh must be below 2^31");
+  for (int64_t l = 0; l < nh; ++l) {
+    if (hi[l] < 0 || hi[l] >= h->m || hj[l] < 0 || hj[l] >= h->n)
+      return fail(h, SVT_E_INVALID_ARG, "held-out index out of range");
+    if (!std::isfinite(gx_h[l])) return fail(h, SVT_E_INVALID_ARG, "non-finite held-out cotangent");
+  }
+  if (h->p.precision != SVT_FP64) return fail(h, SVT_E_STATE, "svt_grad needs the FP64 form");
+  if (!h->hist_ok || (int64_t)h->hist_r.size() < T)
+    return fail(h, SVT_E_STATE, "svt_grad needs T iterations run by svt_iterate since svt_init");
+  for (int i = 0; i < T; ++i)
+    if (h->hist_r[i] > kEigMax) return fail(h, SVT_E_LIMIT, "svt_grad supports bases of at most 96 columns");
+  return grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, dtau, ddelta, da);
 }
 
 }  // extern "C"

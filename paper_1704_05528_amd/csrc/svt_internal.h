@@ -87,6 +87,10 @@ struct Handle {
   bool have_factors = false;
   std::vector<int32_t> replay_blocks, replay_anneal;
   size_t replay_pos = 0;
+  // basis width used by every iteration since svt_init (the basis only grows, so the basis of
+  // iteration i is the first hist_r[i] columns of Q); svt_set_state invalidates it
+  std::vector<int32_t> hist_r;
+  bool hist_ok = true;
 
   // instrumentation: hipEvent pairs per phase, resolved at the next host synchronisation
   struct Pending {
@@ -197,5 +201,26 @@ hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const 
 // factor matrices C = S[:, :k] diag(sigma - tau), D = S[:, :k] diag(1/sigma) from eigenpairs of the Gram
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds, const double* theta,
                                 double tau, double* C, double* D, int ldc);
+
+// ---------------------------------------------------------------------------------------------
+// reverse sweep (adjoint.hip), double
+// ---------------------------------------------------------------------------------------------
+// Cmat = [U_K diag(f/s) | U_K Gamma + U_N Kappa | U_K Beta^T U^T] (r x (2k + r)) and scal[slot] =
+// tau_bar for one unrolled iteration; U, theta: full eigen-decomposition of G (r <= kEigMax),
+// Z1 = Bbar V_K (r x k), Z2 = Bbar B^T (r x r); scratch r x r
+hipError_t launch_adjoint_coeffs(hipStream_t s, int r, int k, const double* U, int ldu, const double* theta,
+                                 const double* Z1, int ldz1, const double* Z2, int ldz2, double tau, double* Cmat,
+                                 int ldc, double* scratch, double* scal, int slot);
+// out[p] = <L[row(p), 0:w], R[col(p), 0:w]> on Lambda (CSC order)
+hipError_t launch_lambda_dot(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* L,
+                             int ldl, const double* R, int ldr, int w, double* out);
+// res = a - x, y_next = y + delta res
+hipError_t launch_dual_update(hipStream_t s, int64_t nnz, const double* a, const double* x, const double* y,
+                              double delta, double* res, double* y_next);
+// dst = alpha x + beta dst
+hipError_t launch_axpby(hipStream_t s, int64_t len, double alpha, const double* x, double beta, double* dst);
+// scal[slot] = <x, y> (deterministic)
+hipError_t launch_dot(hipStream_t s, int64_t len, const double* x, const double* y, double* partial, double* scal,
+                      int slot);
 
 }  // namespace svt
