@@ -18,71 +18,93 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Newton-Raphson refinement (two steps each, quadratic convergence from the hardware estimates)
+// of the reciprocal and of the reciprocal square root.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+
+constexpr int kHalfMax = kEigMax / 2;
+
 // Cyclic Jacobi (Golub & Van Loan, sym.schur2 rotations) with round-robin ordering: in each
 // round the bb/2 disjoint pairs rotate at once.  With J block-diagonal over the pairs, every
 // 2 x 2 block (P, R) of J^T A J depends only on the same block of A, so one pass over the
 // blocks applies the round (rows and columns together), and V <- V J in the same pass.
-// A and V live in LDS.  Sweeps stop when the off-diagonal mass is below 1e-30 of the total
-// squared Frobenius norm, or after max_sweeps.
+// A and V live in LDS.  A pair rotates when |a_pq| exceeds 1e-15 of the largest diagonal entry
+// (absolute accuracy, which is what the top eigenpairs need); a sweep without any rotation
+// ends the iteration.  The rotating threads all sit in wave 0, so one ballot decides whether a
+// round rotates at all.  Each thread gathers the operands of its blocks before updating them
+// (its blocks never overlap), so one round costs two LDS round trips per thread.
 __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, int ldh, int b,
                                                 double* __restrict__ eval, double* __restrict__ evec, int ldv,
                                                 double* scal, int slot, int max_sweeps) {
+  constexpr int CA = 3, CV = 5;  // blocks of A and row pairs of V per thread and chunk
   extern __shared__ double sm[];
   const int bb = b + (b & 1);
   const int ld = bb + 1;
+  const int half = bb / 2;
+  const float inv_half = 1.0f / (float)half;
   double* A = sm;
   double* V = sm + bb * ld;
-  __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
-  __shared__ int pp[kEigMax / 2], qq[kEigMax / 2];
-  __shared__ double red[8];
-  __shared__ int perm[kEigMax];
+  __shared__ double cs[kHalfMax], sn[kHalfMax];
+  __shared__ int pp[kHalfMax], qq[kHalfMax];
+  __shared__ double red[4];
+  __shared__ int flag[2];
+  __shared__ int rank_of[kEigMax];
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wid = tid / kWave;
-  const int half = bb / 2;
 
   for (int e = tid; e < bb * bb; e += blockDim.x) {
-    const int i = e / bb, j = e % bb;
+    const int i = e / bb, j = e - (e / bb) * bb;
     A[i * ld + j] = (i < b && j < b) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
     V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-
-  // A rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|) (the relative test of Demmel and
-  // Veselic for positive semidefinite matrices) or when |a_pq| is below 1e-19 of the largest
-  // diagonal entry (irrelevant at working precision); a sweep without any rotation ends it.
-  __shared__ int rotated;
-  __shared__ double dmax_s;
-  if (tid == 0) {
-    double d = 0.0;
-    for (int i = 0; i < b; ++i) d = fmax(d, fabs(A[i * ld + i]));
-    dmax_s = d;
-  }
+  double dm = 0.0;
+  for (int i = tid; i < b; i += blockDim.x) dm = fmax(dm, fabs(A[i * ld + i]));
+  dm = fmax(dm, __shfl_xor(dm, 32, kWave));
+  dm = fmax(dm, __shfl_xor(dm, 16, kWave));
+  dm = fmax(dm, __shfl_xor(dm, 8, kWave));
+  dm = fmax(dm, __shfl_xor(dm, 4, kWave));
+  dm = fmax(dm, __shfl_xor(dm, 2, kWave));
+  dm = fmax(dm, __shfl_xor(dm, 1, kWave));
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = dm;
   __syncthreads();
-  const double dmax = dmax_s;
+  const double tol = 1e-15 * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const int nb1 = bb - 1;
+  const int totA = half * half, totV = bb * half;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < bb - 1; ++round) {
+    int sweep_any = 0;
+    for (int round = 0; round < nb1; ++round) {
+      int mine = 0;
       if (tid < half) {
+        // round-robin pairing: slot 0 fixed, the others rotate by one position per round
         const int t = tid;
-        const int pa = (t == 0) ? 0 : 1 + ((t - 1 + round) % (bb - 1));
-        const int pb = 1 + ((bb - 2 - t + round) % (bb - 1));
+        int x = t - 1 + round;
+        x = (x >= nb1) ? x - nb1 : x;
+        int y = bb - 2 - t + round;
+        y = (y >= nb1) ? y - nb1 : y;
+        const int pa = (t == 0) ? 0 : 1 + x;
+        const int pb = 1 + y;
         const int p = min(pa, pb), q = max(pa, pb);
-        const double apq = A[p * ld + q];
+        const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(A[p * ld + p] * A[q * ld + q])) &&
-            fabs(apq) > 1e-19 * dmax) {
-          rotated = 1;
-          const double app = A[p * ld + p], aqq = A[q * ld + q];
-          const double th = (aqq - app) / (2.0 * apq);
-          double tt;
-          if (fabs(th) > 1e150) {
-            tt = 0.5 / th;
-          } else {
-            tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          }
-          c = 1.0 / sqrt(1.0 + tt * tt);
+        if (fabs(apq) > tol) {
+          mine = 1;
+          // tangent of the smaller rotation angle that annihilates a_pq
+          const double dd = aqq - app;
+          const double den = fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq));
+          const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq * rcp_nr(den);
+          c = rsq_nr(fma(tt, tt, 1.0));
           s = tt * c;
         }
         cs[t] = c;
@@ -90,54 +112,103 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
         pp[t] = p;
         qq[t] = q;
       }
-      __syncthreads();
-      // blocks (P, R): rows p1, q1 rotate by pair P, columns p2, q2 by pair R
-      for (int e = tid; e < half * half; e += blockDim.x) {
-        const int P = e / half, R = e % half;
-        const int p1 = pp[P], q1 = qq[P], p2 = pp[R], q2 = qq[R];
-        const double c1 = cs[P], s1 = sn[P], c2 = cs[R], s2 = sn[R];
-        const double a00 = A[p1 * ld + p2], a01 = A[p1 * ld + q2];
-        const double a10 = A[q1 * ld + p2], a11 = A[q1 * ld + q2];
-        const double r00 = c1 * a00 - s1 * a10, r01 = c1 * a01 - s1 * a11;
-        const double r10 = s1 * a00 + c1 * a10, r11 = s1 * a01 + c1 * a11;
-        A[p1 * ld + p2] = c2 * r00 - s2 * r01;
-        A[p1 * ld + q2] = s2 * r00 + c2 * r01;
-        A[q1 * ld + p2] = c2 * r10 - s2 * r11;
-        A[q1 * ld + q2] = s2 * r10 + c2 * r11;
+      if (tid < kWave) {
+        const unsigned long long bal = __ballot(mine);
+        if (tid == 0) flag[round & 1] = (bal != 0ull);
       }
-      for (int e = tid; e < bb * half; e += blockDim.x) {
-        const int i = e / half, R = e % half;
-        const int p = pp[R], q = qq[R];
-        const double c = cs[R], s = sn[R];
-        const double vp = V[i * ld + p], vq = V[i * ld + q];
-        V[i * ld + p] = c * vp - s * vq;
-        V[i * ld + q] = s * vp + c * vq;
+      __syncthreads();
+      if (!flag[round & 1]) continue;  // uniform: nothing rotates, nothing to update this round
+      sweep_any = 1;
+      for (int base = 0; base < totA; base += CA * 256) {
+        double a0[CA], a1[CA], a2[CA], a3[CA], c1v[CA], s1v[CA], c2v[CA], s2v[CA];
+        int o0[CA], o1[CA], o2[CA], o3[CA];
+        bool ok[CA];
+#pragma unroll
+        for (int j = 0; j < CA; ++j) {
+          const int e = base + tid + j * 256;
+          ok[j] = e < totA;
+          // e = P * half + R (exact in float for e < 96 * 48)
+          const int P = ok[j] ? (int)((float)e * inv_half + 0.5f * inv_half) : 0;
+          const int R = ok[j] ? e - P * half : 0;
+          const int p1 = pp[P], q1 = qq[P], p2 = pp[R], q2 = qq[R];
+          c1v[j] = cs[P];
+          s1v[j] = sn[P];
+          c2v[j] = cs[R];
+          s2v[j] = sn[R];
+          o0[j] = p1 * ld + p2;
+          o1[j] = p1 * ld + q2;
+          o2[j] = q1 * ld + p2;
+          o3[j] = q1 * ld + q2;
+        }
+#pragma unroll
+        for (int j = 0; j < CA; ++j)
+          if (ok[j]) {
+            a0[j] = A[o0[j]];
+            a1[j] = A[o1[j]];
+            a2[j] = A[o2[j]];
+            a3[j] = A[o3[j]];
+          }
+#pragma unroll
+        for (int j = 0; j < CA; ++j)
+          if (ok[j]) {
+            const double c1 = c1v[j], s1 = s1v[j], c2 = c2v[j], s2 = s2v[j];
+            const double r00 = c1 * a0[j] - s1 * a2[j], r01 = c1 * a1[j] - s1 * a3[j];
+            const double r10 = s1 * a0[j] + c1 * a2[j], r11 = s1 * a1[j] + c1 * a3[j];
+            A[o0[j]] = c2 * r00 - s2 * r01;
+            A[o1[j]] = s2 * r00 + c2 * r01;
+            A[o2[j]] = c2 * r10 - s2 * r11;
+            A[o3[j]] = s2 * r10 + c2 * r11;
+          }
+      }
+      for (int base = 0; base < totV; base += CV * 256) {
+        double v0[CV], v1[CV], cv[CV], sv[CV];
+        int ov0[CV], ov1[CV];
+        bool ok[CV];
+#pragma unroll
+        for (int j = 0; j < CV; ++j) {
+          const int e = base + tid + j * 256;
+          ok[j] = e < totV;
+          const int i = ok[j] ? (int)((float)e * inv_half + 0.5f * inv_half) : 0;
+          const int R = ok[j] ? e - i * half : 0;
+          cv[j] = cs[R];
+          sv[j] = sn[R];
+          ov0[j] = i * ld + pp[R];
+          ov1[j] = i * ld + qq[R];
+        }
+#pragma unroll
+        for (int j = 0; j < CV; ++j)
+          if (ok[j]) {
+            v0[j] = V[ov0[j]];
+            v1[j] = V[ov1[j]];
+          }
+#pragma unroll
+        for (int j = 0; j < CV; ++j)
+          if (ok[j]) {
+            V[ov0[j]] = cv[j] * v0[j] - sv[j] * v1[j];
+            V[ov1[j]] = sv[j] * v0[j] + cv[j] * v1[j];
+          }
       }
       __syncthreads();
     }
-    const int any = rotated;
-    __syncthreads();   // every thread has read the flag before thread 0 clears it again
-    if (!any) break;
+    if (!sweep_any) break;
   }
 
-  // sort eigenvalues descending (the padding index of odd b has eigenvalue 0 and is excluded)
-  if (tid == 0) {
-    for (int i = 0; i < b; ++i) perm[i] = i;
-    for (int i = 0; i < b; ++i) {
-      int best = i;
-      for (int j = i + 1; j < b; ++j)
-        if (A[perm[j] * ld + perm[j]] > A[perm[best] * ld + perm[best]]) best = j;
-      const int t = perm[i];
-      perm[i] = perm[best];
-      perm[best] = t;
+  // descending order by a parallel rank count (ties by index); the padding index of odd b is excluded
+  for (int i = tid; i < b; i += blockDim.x) {
+    const double di = A[i * ld + i];
+    int rk = 0;
+    for (int j = 0; j < b; ++j) {
+      const double dj = A[j * ld + j];
+      rk += (dj > di) || (dj == di && j < i);
     }
-    scal[slot] = (double)sweep;
+    rank_of[rk] = i;
   }
   __syncthreads();
-  for (int i = tid; i < b; i += blockDim.x) eval[i] = A[perm[i] * ld + perm[i]];
+  if (tid == 0) scal[slot] = (double)sweep;
+  for (int c = tid; c < b; c += blockDim.x) eval[c] = A[rank_of[c] * ld + rank_of[c]];
   for (int e = tid; e < b * b; e += blockDim.x) {
-    const int i = e / b, c = e % b;
-    evec[(int64_t)i * ldv + c] = V[i * ld + perm[c]];
+    const int i = e / b, c = e - (e / b) * b;
+    evec[(int64_t)i * ldv + c] = V[i * ld + rank_of[c]];
   }
 }
 

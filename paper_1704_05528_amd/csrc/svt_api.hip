@@ -29,8 +29,8 @@ thread_local std::string g_init_err;
 constexpr double kDropTol = 1e-10;    // a projected column this small relative to its norm before lies in span(Q)
 constexpr double kDepTol = 1e-6;      // a Cholesky pivot this small relative to the column norm means dependence
 constexpr double kEigTol = 1e-13;     // Ritz residual relative to the largest Ritz value
-constexpr int kEigBatches = 60;       // cap on Rayleigh-Ritz batches per SVT iteration
-constexpr int kPowerSteps = 2;        // CholeskyQR steps per batch (two products with G each)
+constexpr int kEigMaxProducts = 240;  // cap on products with G per SVT iteration
+constexpr int kEigMaxPred = 32;       // cap on the predicted number of products before a Rayleigh-Ritz test
 constexpr double kEigDepTol = 1e-12;  // eigen-block CholeskyQR drops only numerically dependent columns
 constexpr int kDirect = 32;           // basis widths up to this are diagonalised directly
 
@@ -335,17 +335,15 @@ struct Engine {
       h->ev_rows = r;
       st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
     } else {
-      // Warm-started orthogonal iteration on G in batches of kPowerSteps CholeskyQR steps (two
-      // products with G each), each batch closed by CholeskyQR2 and a Rayleigh-Ritz step on the
-      // whole block.  Start block: the previous Ritz vectors (new basis rows zero), the unit
-      // vectors of the basis columns appended since then (where new energy enters), Gaussians.
+      // Warm-started subspace iteration on G.  Start block: the previous iteration's Ritz vectors
+      // (rows of basis columns appended since then set to zero) and Gaussian columns.  Products
+      // with G come in pairs, each pair followed by one CholeskyQR pass (the last pass before a
+      // Rayleigh-Ritz step twice); a Rayleigh-Ritz step and the convergence test follow once the
+      // predicted number of products is done.  The prediction is the count the previous SVT
+      // iteration needed, lowered by one when its first test already passed.
       const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
-      const int newc = warm ? r - h->ev_rows : 0;
       int b = std::min(std::min(h->b_cap, r), std::max(16, ((2 * std::max(h->k, 4) + 8 + 7) / 8) * 8));
-      int valid = warm ? std::min(h->ev_valid, b) : 0;
-      if (valid + newc + 4 > b) b = std::min(std::min(h->b_cap, r), valid + newc + 4);
-      valid = std::min(valid, b);
-      const int unit = std::min(newc, b - valid);
+      int valid = warm ? std::max(0, std::min(h->ev_valid, b - 4)) : 0;
       {
         PhaseTimer tm(h, SVT_PH_EIG);
         if (valid > 0 && h->ev_rows < r) {
@@ -353,34 +351,46 @@ struct Engine {
           HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
                                   valid * sizeof(double), r - h->ev_rows, s));
         }
-        HIPCHK(launch_set_unit(s, h->EV, r, kEigMax, valid, unit, h->ev_rows));
-        HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid + unit, b, h->p.seed ^ 0x5A5A5A5Aull,
-                                  (uint64_t)h->iter));
+        HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
         CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
       }
-      bool done = false;
-      int iters = 0, batches = 0, prev_k = -1;
+      bool done = false, have_gv = false;
+      int powers = 0, tests = 0, prev_k = -1;
+      int target = std::max(2, h->eig_pred);
       while (!done) {
-        if (batches >= kEigBatches) {
+        if (powers >= kEigMaxProducts) {
           st->flags |= SVT_F_EIG_INEXACT;
           break;
         }
-        ++batches;
         {
           PhaseTimer tm(h, SVT_PH_EIG);
-          for (int step = 0; step < kPowerSteps; ++step, iters += 2) {
-            HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
-                                                          1.0, 0.0)));
-            HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EZ3, kEigMax, h->EZ, kEigMax, b,
-                                                          1.0, 0.0)));
-            if (step + 1 < kPowerSteps) {
-              CHK(chol_orth(r, h->EZ, h->EV, kEigMax, b));
+          while (powers < target) {
+            const int step = (target - powers >= 2) ? 2 : 1;
+            const bool last = powers + step >= target;
+            // Z = G^step V (a product left by the previous Rayleigh-Ritz step counts as the first)
+            const double* z = nullptr;
+            if (have_gv) {
+              z = h->EZ3;
+              have_gv = false;
             } else {
-              CHK(chol_orth(r, h->EZ, h->EZ2, kEigMax, b));
-              CHK(chol_orth(r, h->EZ2, h->EV, kEigMax, b));
+              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
+                                                            1.0, 0.0)));
+              z = h->EZ3;
             }
+            if (step == 2) {
+              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEigMax, h->EZ, kEigMax, b,
+                                                            1.0, 0.0)));
+              z = h->EZ;
+            }
+            if (last) {
+              CHK(chol_orth(r, z, h->EZ2, kEigMax, b));
+              CHK(chol_orth(r, h->EZ2, h->EV, kEigMax, b));
+            } else {
+              CHK(chol_orth(r, z, h->EV, kEigMax, b));
+            }
+            powers += step;
           }
-          // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; Z <- (G V) S; residuals
+          // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; G V <- (G V) S; residual norms
           HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
                                                         1.0, 0.0)));
           HIPCHK((launch_tn_narrow<double, double>(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->EH, kEigMax,
@@ -392,7 +402,9 @@ struct Engine {
                                                         1.0, 0.0)));
           std::swap(h->EV, h->EZ2);
           HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
+          have_gv = true;
         }
+        ++tests;
         CHK(to_host<double>(h, theta.data(), h->Eval, 2 * kEigMax));
         for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
         k = 0;
@@ -401,21 +413,24 @@ struct Engine {
           if (b >= h->b_cap) {
             if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks");
           } else {
+            // widen the block with Gaussian columns and continue from the enlarged block
             const int nb = std::min(std::min(h->b_cap, r), b + 16);
             PhaseTimer tm(h, SVT_PH_EIG);
-            HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)batches));
+            HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
             b = nb;
             CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
+            have_gv = false;
             prev_k = -1;
+            target = powers + 2;
             continue;
           }
         }
         // Accept when the pairs above tau^2 have converged, four guard pairs below it have Ritz
-        // intervals below tau^2, and the count k agrees with the previous check (Ritz values rise
+        // intervals below tau^2, and the count k agrees with the previous test (Ritz values rise
         // monotonically under subspace iteration, so a missed eigenvalue above tau^2 would still be
-        // moving k).  In the steady state the first check may also accept when k equals the
-        // previous SVT iteration's count, whose eigenvectors started this solve.  A block that
-        // spans the whole basis (b == r) is exact after one Rayleigh-Ritz step.
+        // moving k).  The first test may also accept when k equals the previous SVT iteration's
+        // count, whose eigenvectors started this solve.  A block that spans the whole basis
+        // (b == r) is exact after one Rayleigh-Ritz step.
         const double lim = kEigTol * std::max(theta[0], 0.0);
         done = (b == r) || (k == prev_k) || (prev_k < 0 && warm && k == h->k);
         for (int c = 0; done && c < k; ++c)
@@ -423,7 +438,10 @@ struct Engine {
         for (int c = k; done && c < std::min(b, k + 4); ++c)
           if (!(theta[c] + res[c] < tau2)) done = false;
         prev_k = k;
+        if (!done) target = powers + 2;
       }
+      h->eig_pred = std::min(kEigMaxPred, std::max(2, tests == 1 ? powers - 1 : powers));
+      const int iters = powers + tests;
       st->eig_iters = iters;
       S = h->EV;
       h->ev_valid = b;
