@@ -44,9 +44,9 @@ constexpr int kHalfMax = kEigMax / 2;
 // ends the iteration.  The rotating threads all sit in wave 0, so one ballot decides whether a
 // round rotates at all.  Each thread gathers the operands of its blocks before updating them
 // (its blocks never overlap), so one round costs two LDS round trips per thread.
-__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, int ldh, int b,
-                                                double* __restrict__ eval, double* __restrict__ evec, int ldv,
-                                                double* scal, int slot, int max_sweeps) {
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, int ldh, int splits, int64_t sstride,
+                                                int b, double* __restrict__ eval, double* __restrict__ evec,
+                                                int ldv, double* scal, int slot, int max_sweeps) {
   constexpr int CA = 3, CV = 5;  // blocks of A and row pairs of V per thread and chunk
   extern __shared__ double sm[];
   const int bb = b + (b & 1);
@@ -62,9 +62,16 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
   __shared__ int rank_of[kEigMax];
   const int tid = threadIdx.x;
 
+  // H is the sum of `splits` matrices sstride apart (partial products, added in split order)
   for (int e = tid; e < bb * bb; e += blockDim.x) {
     const int i = e / bb, j = e - (e / bb) * bb;
-    A[i * ld + j] = (i < b && j < b) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+    double hij = 0.0, hji = 0.0;
+    if (i < b && j < b)
+      for (int sp = 0; sp < splits; ++sp) {
+        hij += H[sp * sstride + (int64_t)i * ldh + j];
+        hji += H[sp * sstride + (int64_t)j * ldh + i];
+      }
+    A[i * ld + j] = 0.5 * (hij + hji);
     V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -246,7 +253,8 @@ __global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int 
 }  // namespace
 
 hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double* eval, double* evec, int ldv,
-                         double* scal, int slot, int max_sweeps) {
+                         double* scal, int slot, int max_sweeps, int splits, int64_t sstride) {
+  if (b <= 0 || b > kEigMax || splits <= 0) return hipErrorInvalidValue;
   const int bb = b + (b & 1);
   const size_t lds = (size_t)2 * bb * (bb + 1) * sizeof(double);
   static bool attr_set = false;
@@ -256,7 +264,8 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, H, ldh, b, eval, evec, ldv, scal, slot, max_sweeps);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, H, ldh, splits, sstride, b, eval, evec, ldv, scal, slot,
+                     max_sweeps);
   return hipGetLastError();
 }
 

@@ -475,10 +475,10 @@ __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double
 // only the first wk_in columns take part (second pass of CholeskyQR2 reads the count of the
 // first pass from scal[wk_slot_in]).  scal[slot] = wk.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int w,
-                                                    const double* __restrict__ prenorm, double drop_tol,
-                                                    double dep_tol, double* __restrict__ Rout, int ldm, double* scal,
-                                                    int slot, int wk_slot_in) {
+__global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int splits,
+                                                    int64_t sstride, int w, const double* __restrict__ prenorm,
+                                                    double drop_tol, double dep_tol, double* __restrict__ Rout,
+                                                    int ldm, double* scal, int slot, int wk_slot_in) {
   extern __shared__ double sm[];
   const int ld = w + 1;
   double* A = sm;  // w x (w + 1): Gram, overwritten by the Schur complements / rows of R
@@ -487,12 +487,17 @@ __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ g
   const int tid = threadIdx.x;
   int wa = w;
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
+  // the Gram is the sum of `splits` partial Grams (sstride apart), added in split order
   for (int e = tid; e < w * w; e += blockDim.x) {
     const int i = e / w, j = e % w;
-    A[i * ld + j] = (i < wa && j < wa) ? gram[(int64_t)i * ldg + j] : 0.0;
+    double v = 0.0;
+    if (i < wa && j < wa)
+      for (int sp = 0; sp < splits; ++sp) v += gram[sp * sstride + (int64_t)i * ldg + j];
+    A[i * ld + j] = v;
   }
+  __syncthreads();
   for (int c = tid; c < w; c += blockDim.x) {
-    const double g = (c < wa) ? fmax(gram[(int64_t)c * ldg + c], 0.0) : 0.0;
+    const double g = (c < wa) ? fmax(A[c * ld + c], 0.0) : 0.0;
     gdiag[c] = g;
     const double lim = prenorm ? drop_tol * prenorm[c] : 0.0;
     keep[c] = (c < wa) && (sqrt(g) > lim) ? 1 : 0;
@@ -791,9 +796,25 @@ hipError_t launch_colnorms(hipStream_t s, int rows, const T* A, int lda, int w, 
   return hipGetLastError();
 }
 
+template <class TA, class TB>
+hipError_t launch_tn_partial(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
+                             double* partial, int64_t partial_cap, int* splits_out) {
+  *splits_out = 0;
+  if (na == 0 || nb == 0) return hipSuccess;
+  const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
+  int splits = std::max(1, std::min(std::max(1, rows / 32), 512 / std::max(1, gx * gy)));
+  while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
+  const int rps = (rows + splits - 1) / splits;
+  hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
+                     partial, std::max(rps, 1));
+  *splits_out = splits;
+  return hipGetLastError();
+}
+
 hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
                              double drop_tol, double dep_tol, double* Rout, int ldm, double* scal, int slot,
-                             int wk_slot_in) {
+                             int wk_slot_in, int splits, int64_t sstride) {
+  if (splits <= 0) return hipErrorInvalidValue;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_block_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -802,8 +823,8 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
     attr_set = true;
   }
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, w, prenorm, drop_tol, dep_tol, Rout, ldm,
-                     scal, slot, wk_slot_in);
+  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, splits, sstride, w, prenorm, drop_tol,
+                     dep_tol, Rout, ldm, scal, slot, wk_slot_in);
   return hipGetLastError();
 }
 
@@ -886,6 +907,8 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
                                              const T*, int, int, T*, int, double*, int64_t);                          \
   template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \
                                              double*, int64_t);                                                       \
+  template hipError_t launch_tn_partial<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*,      \
+                                              int64_t, int*);                                                         \
   template hipError_t launch_gram<T>(hipStream_t, int, const T*, int, int, double*, int, double*, int64_t);           \
   template hipError_t launch_sumsq_cols<T>(hipStream_t, int, const T*, int, int, int, double*, double*, int);         \
   template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \

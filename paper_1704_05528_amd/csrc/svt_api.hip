@@ -151,13 +151,15 @@ struct Engine {
   template <class U>
   svt_status orthonormalize_block(int rows, U* X, U* X2, int ld, int wc, const double* prenorm) {
     hipStream_t s = h->stream;
-    HIPCHK((launch_tn_narrow<U, U>(s, rows, X, ld, wc, X, ld, wc, h->small, kEigMax, h->partial, h->partial_cap)));
-    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1,
-                             -1));
+    const int64_t ss = (int64_t)wc * wc;  // stride of the split partial Grams
+    int sp = 0;
+    HIPCHK((launch_tn_partial<U, U>(s, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap, &sp)));
+    HIPCHK(launch_block_chol(s, h->partial, wc, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1, -1,
+                             sp, ss));
     HIPCHK(launch_trsm_rows<U>(s, rows, X, ld, wc, h->Minv, kEigMax, X2, ld));
-    HIPCHK((launch_tn_narrow<U, U>(s, rows, X2, ld, wc, X2, ld, wc, h->small, kEigMax, h->partial, h->partial_cap)));
-    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2,
-                             S_WK1));
+    HIPCHK((launch_tn_partial<U, U>(s, rows, X2, ld, wc, X2, ld, wc, h->partial, h->partial_cap, &sp)));
+    HIPCHK(launch_block_chol(s, h->partial, wc, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2, S_WK1,
+                             sp, ss));
     HIPCHK(launch_trsm_rows<U>(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
     return SVT_OK;
   }
@@ -165,10 +167,10 @@ struct Engine {
   // One CholeskyQR pass Out = In R^{-1} of an eigensolver block (only dependent columns drop).
   svt_status chol_orth(int rows, const double* In, double* Out, int ld, int wc) {
     hipStream_t s = h->stream;
-    HIPCHK((launch_tn_narrow<double, double>(s, rows, In, ld, wc, In, ld, wc, h->small, kEigMax, h->partial,
-                                             h->partial_cap)));
-    HIPCHK(launch_block_chol(s, h->small, kEigMax, wc, nullptr, 0.0, kEigDepTol, h->Minv, kEigMax, h->scal, S_WK2,
-                             -1));
+    int sp = 0;
+    HIPCHK((launch_tn_partial<double, double>(s, rows, In, ld, wc, In, ld, wc, h->partial, h->partial_cap, &sp)));
+    HIPCHK(launch_block_chol(s, h->partial, wc, wc, nullptr, 0.0, kEigDepTol, h->Minv, kEigMax, h->scal, S_WK2, -1,
+                             sp, (int64_t)wc * wc));
     HIPCHK(launch_trsm_rows<double>(s, rows, In, ld, wc, h->Minv, kEigMax, Out, ld));
     return SVT_OK;
   }
@@ -351,8 +353,9 @@ struct Engine {
           HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
                                   valid * sizeof(double), r - h->ev_rows, s));
         }
+        // the Ritz columns are orthonormal and the Gaussian ones well conditioned: the CholeskyQR
+        // after the first products orthonormalises the block
         HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
-        CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
       }
       bool done = false, have_gv = false;
       int powers = 0, tests = 0, prev_k = -1;
@@ -393,9 +396,11 @@ struct Engine {
           // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; G V <- (G V) S; residual norms
           HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
                                                         1.0, 0.0)));
-          HIPCHK((launch_tn_narrow<double, double>(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->EH, kEigMax,
-                                                   h->partial, h->partial_cap)));
-          HIPCHK(launch_jacobi(s, h->EH, kEigMax, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+          int sp = 0;
+          HIPCHK((launch_tn_partial<double, double>(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->partial,
+                                                    h->partial_cap, &sp)));
+          HIPCHK(launch_jacobi(s, h->partial, b, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS, 40, sp,
+                               (int64_t)b * b));
           HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b,
                                                         1.0, 0.0)));
           HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b,

@@ -157,9 +157,15 @@ hipError_t launch_colnorms(hipStream_t s, int rows, const T* A, int lda, int w, 
                            int64_t partial_cap, double* out);
 
 // Cholesky factor R of a block's Gram with the column-drop rules (one workgroup): see kernels.hip
+// The Gram may be given as the sum of `splits` partial Grams sstride doubles apart.
 hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, const double* prenorm,
                              double drop_tol, double dep_tol, double* Rout, int ldm, double* scal, int slot,
-                             int wk_slot_in);
+                             int wk_slot_in, int splits = 1, int64_t sstride = 0);
+// partial[s][a][b] of A^T B split over rows, without the final sum; *splits_out receives the split
+// count (the consumer adds the splits, stride na * nb)
+template <class TA, class TB>
+hipError_t launch_tn_partial(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
+                             double* partial, int64_t partial_cap, int* splits_out);
 // out = X[:, kept] R^{-1} row by row, kept columns packed left, the rest zero
 template <class T>
 hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
@@ -194,8 +200,9 @@ hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0
 // ---------------------------------------------------------------------------------------------
 // Jacobi eigen-decomposition of a b x b symmetric matrix (b <= kEigMax) in one workgroup.
 // Eigenvalues descending into eval, eigenvectors as columns of evec (row-major, ld = ldv).
+// H may be given as the sum of `splits` matrices sstride doubles apart (split partial products).
 hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double* eval, double* evec, int ldv,
-                         double* scal, int slot, int max_sweeps = 40);
+                         double* scal, int slot, int max_sweeps = 40, int splits = 1, int64_t sstride = 0);
 // residual column norms ||Z[:, c] - theta_c V[:, c]|| for c < b
 hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const double* V, int ld, int b,
                                 const double* theta, double* partial, double* out);
