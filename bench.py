@@ -109,7 +109,7 @@ def run_form(svt, w, stream, args, precision):
     r_vals = [s[0] for s in stats]
     es = 4.0 if precision else 8.0
     # roofline of the dominant single-kernel phase
-    kernels = {"spmm_t": "hbm", "sddmm": "hbm", "gram": "alu"}
+    kernels = {"spmm_t": "hbm", "sddmm": "hbm", "gram": "mfma"}
     dom = max(kernels, key=lambda ph: prof[ph]["ms"])
     pd = prof[dom]
     if kernels[dom] == "hbm":
@@ -118,7 +118,7 @@ def run_form(svt, w, stream, args, precision):
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     else:
         achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFS, "traffic": None}
     roof.update({"kernel": dom, "launches": pd["launches"], "avg_launch_us": 1e3 * pd["ms"] / max(pd["launches"], 1),
                  "bytes_per_launch": pd["bytes"] / max(pd["launches"], 1),

@@ -262,74 +262,145 @@ __global__ void k_split_sum(int n, int r, const T* __restrict__ partial, int spl
 }
 
 // ------------------------------------------------------------------------------------------
-// Row-wise small product: out[i, g0:g0+16] = beta * out + alpha * A[i, 0:K] M[0:K, g0:g0+16],
-// accumulated in double.  One wave per row, lanes stride over K.  Used for X -= Q (Q^T X),
-// Q C, W D, G V, V S.
+// FP64 matrix cores.  v_mfma_f64_16x16x4f64 (one wave) takes the A operand (16 x 4) as
+// A[l % 16][l / 16] in lane l, the B operand (4 x 16) as B[l / 16][l % 16], and accumulates the
+// 16 x 16 result with rows (l / 16) + 4 v, v = 0..3, of column l % 16 in lane l.  Operands of
+// float storage are widened to double on load.
+// ------------------------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kUnroll = 8;  // k-steps whose operands are loaded before their products issue
+
+__device__ inline dbl4 mfma_f64_16x16x4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Sum the accumulators of the four waves of a workgroup in wave order (deterministic); the
+// result is valid in wave 0.
+__device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  if (wv > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv - 1][lane][v] = acc[v];
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = ((acc[v] + red[0][lane][v]) + red[1][lane][v]) + red[2][lane][v];
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Row-times-matrix product out[i, :] = beta out[i, :] + alpha A[i, 0:K] M[0:K, :] on the FP64
+// matrix cores: one 16 x 16 output tile per workgroup, the four waves take contiguous quarters
+// of the K steps and their accumulators are added in LDS.  Used for Q C, W D, G V, V S and the
+// projections X - Q (Q^T X).
 // ------------------------------------------------------------------------------------------
 template <class TA, class TM, class TO>
 __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
                                                 const TM* __restrict__ M, int ldm, TO* __restrict__ out, int ldo,
                                                 int w, double alpha, double beta) {
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (row >= rows) return;
-  const int g0 = blockIdx.y * 16;
-  double acc[16];
+  __shared__ double red[3][kWave][4];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int ia = i0 + (lane & 15), jb = j0 + (lane & 15), kl = lane >> 4;
+  const bool rowok = ia < rows, colok = jb < w;
+  // out-of-range operands are loaded from a clamped, valid address and replaced by zero
+  const TA* arow = A + (int64_t)min(ia, rows - 1) * lda;
+  const TM* mcol = M + min(jb, w - 1);
+  const int steps = (K + 3) / 4;
+  const int per = (steps + 3) / 4;
+  const int s0 = wv * per, s1 = min(steps, s0 + per);
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int st = s0;
+  for (; st + kUnroll <= s1; st += kUnroll) {
+    double a[kUnroll], b[kUnroll];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-  const TA* a = A + (int64_t)row * lda;
-  for (int c = lane; c < K; c += kWave) {
-    const double av = (double)a[c];
-    const TM* mr = M + (int64_t)c * ldm + g0;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = (st + u) * 4 + kl;
+      const int kc = min(k, K - 1);
+      const double av = (double)arow[kc], bv = (double)mcol[(int64_t)kc * ldm];
+      a[u] = (rowok && k < K) ? av : 0.0;
+      b[u] = (colok && k < K) ? bv : 0.0;
+    }
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (g0 + j < w) acc[j] = fma(av, (double)mr[j], acc[j]);
+    for (int u = 0; u < kUnroll; u += 2) {
+      acc0 = mfma_f64_16x16x4(a[u], b[u], acc0);
+      acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
+    }
   }
+  for (; st < s1; ++st) {
+    const int k = st * 4 + kl;
+    const int kc = min(k, K - 1);
+    const double av = (double)arow[kc], bv = (double)mcol[(int64_t)kc * ldm];
+    acc0 = mfma_f64_16x16x4((rowok && k < K) ? av : 0.0, (colok && k < K) ? bv : 0.0, acc0);
+  }
+  dbl4 acc = acc0 + acc1;
+  acc = reduce_waves(acc, red);
+  if (wv == 0) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const double s = wave_sum(acc[j]);
-    if (lane == 0 && g0 + j < w) {
-      TO* o = out + (int64_t)row * ldo + g0 + j;
-      *o = (TO)((beta == 0.0 ? 0.0 : beta * (double)*o) + alpha * s);
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + (lane >> 4) + 4 * v, col = j0 + (lane & 15);
+      if (row < rows && col < w) {
+        TO* o = out + (int64_t)row * ldo + col;
+        *o = (TO)((beta == 0.0 ? 0.0 : beta * (double)*o) + alpha * acc[v]);
+      }
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// Tall-skinny A^T B with a narrow B (nb columns in groups of 16), split over rows, double
-// accumulation.  partial[s][a][b] = sum_{i in split s} A[i, a] B[i, b]; k_tn_finish sums.
+// Tall-skinny A^T B on the FP64 matrix cores, split over rows: workgroup (x, y, s) computes the
+// 16 x 16 tile (a0, b0) of partial[s] = sum_{i in split s} A[i, :]^T B[i, :]; the four waves take
+// contiguous quarters of the split's rows.  k_tn_finish (or the consumer) adds the splits.
 // ------------------------------------------------------------------------------------------
 template <class TA, class TB>
 __global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restrict__ A, int lda, int na,
                                                    const TB* __restrict__ B, int ldb, int nb,
                                                    double* __restrict__ partial, int rows_per_split) {
-  __shared__ double red[4][16][kWave];
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int a = blockIdx.x * kWave + lane;
-  const int g0 = blockIdx.y * 16;
-  const int s = blockIdx.z;
+  __shared__ double red[3][kWave][4];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16, s = blockIdx.z;
   const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
-  double acc[16];
+  const int aa = a0 + (lane & 15), bb = b0 + (lane & 15), kl = lane >> 4;
+  const bool aok = aa < na, bok = bb < nb;
+  const TA* acol = A + min(aa, na - 1);
+  const TB* bcol = B + min(bb, nb - 1);
+  const int steps = (max(i1 - i0, 0) + 3) / 4;
+  const int per = (steps + 3) / 4;
+  const int s0 = wv * per, s1 = min(steps, s0 + per);
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int st = s0;
+  for (; st + kUnroll <= s1; st += kUnroll) {
+    double a[kUnroll], b[kUnroll];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-  if (a < na) {
-    for (int i = i0 + wid; i < i1; i += 4) {
-      const double av = (double)A[(int64_t)i * lda + a];
-      const TB* br = B + (int64_t)i * ldb + g0;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int row = i0 + (st + u) * 4 + kl;
+      const int rc = min(row, i1 - 1);
+      const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * ldb];
+      a[u] = (row < i1 && aok) ? av : 0.0;
+      b[u] = (row < i1 && bok) ? bv : 0.0;
+    }
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (g0 + j < nb) acc[j] = fma(av, (double)br[j], acc[j]);
+    for (int u = 0; u < kUnroll; u += 2) {
+      acc0 = mfma_f64_16x16x4(a[u], b[u], acc0);
+      acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
   }
+  for (; st < s1; ++st) {
+    const int row = i0 + st * 4 + kl;
+    const int rc = min(row, i1 - 1);
+    const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * ldb];
+    acc0 = mfma_f64_16x16x4((row < i1 && aok) ? av : 0.0, (row < i1 && bok) ? bv : 0.0, acc0);
+  }
+  dbl4 acc = acc0 + acc1;
+  acc = reduce_waves(acc, red);
+  if (wv == 0) {
+    double* P = partial + (int64_t)s * na * nb;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) red[wid][j][lane] = acc[j];
-  __syncthreads();
-  for (int e = threadIdx.x; e < 16 * kWave; e += blockDim.x) {
-    const int j = e / kWave, l = e % kWave;
-    const int aa = blockIdx.x * kWave + l;
-    if (aa < na && g0 + j < nb) {
-      const double v = ((red[0][j][l] + red[1][j][l]) + red[2][j][l]) + red[3][j][l];
-      partial[((int64_t)s * na + aa) * nb + g0 + j] = v;
+    for (int v = 0; v < 4; ++v) {
+      const int ra = a0 + (lane >> 4) + 4 * v, cb = b0 + (lane & 15);
+      if (ra < na && cb < nb) P[(int64_t)ra * nb + cb] = acc[v];
     }
   }
 }
@@ -345,15 +416,15 @@ __global__ void k_tn_finish(const double* __restrict__ partial, int splits, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// Gram G = A^T A (na x na, double) for a tall A: 64 x 64 output tiles of the upper triangle,
-// 16-row LDS stages, 4 x 4 outputs per thread, split over rows; k_gram_finish mirrors.
+// Gram G = A^T A (na x na, double) for a tall A on the FP64 matrix cores: one 32 x 32 tile of the
+// upper triangle per workgroup (one 16 x 16 quarter per wave) over all rows, written to both
+// triangles; no partial sums.
 // ------------------------------------------------------------------------------------------
-constexpr int kGT = 64, kGK = 16;
+constexpr int kGT = 32;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
-                                                    double* __restrict__ partial, int rows_per_split, int ntile) {
-  __shared__ double sa[kGK][kGT + 1], sb[kGK][kGT + 1];
+                                                    double* __restrict__ G, int ldg, int ntile) {
   // map blockIdx.x to an upper-triangular tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
   while (t >= ntile - ti) {
@@ -361,58 +432,46 @@ __global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restric
     ++ti;
   }
   const int tj = ti + t;
-  const int s = blockIdx.y;
-  const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 16 x 16 threads, 4 x 4 outputs each
-  double acc[4][4];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int a0 = ti * kGT + (wv >> 1) * 16, b0 = tj * kGT + (wv & 1) * 16;
+  const int aa = a0 + (lane & 15), bb = b0 + (lane & 15), kl = lane >> 4;
+  const bool aok = aa < na, bok = bb < na;
+  const T* acol = A + min(aa, na - 1);
+  const T* bcol = A + min(bb, na - 1);
+  const int steps = (rows + 3) / 4;
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int st = 0;
+  for (; st + kUnroll <= steps; st += kUnroll) {
+    double a[kUnroll], b[kUnroll];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  const int a0 = ti * kGT, b0 = tj * kGT;
-  for (int ib = i0; ib < i1; ib += kGK) {
-    for (int e = threadIdx.x; e < kGK * kGT; e += blockDim.x) {
-      const int rr = e / kGT, cc = e % kGT;
-      const int i = ib + rr;
-      sa[rr][cc] = (i < i1 && a0 + cc < na) ? (double)A[(int64_t)i * lda + a0 + cc] : 0.0;
-      sb[rr][cc] = (i < i1 && b0 + cc < na) ? (double)A[(int64_t)i * lda + b0 + cc] : 0.0;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int row = (st + u) * 4 + kl;
+      const int rc = min(row, rows - 1);
+      const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * lda];
+      a[u] = (row < rows && aok) ? av : 0.0;
+      b[u] = (row < rows && bok) ? bv : 0.0;
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kGK; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = sa[kk][ty * 4 + u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sb[kk][tx * 4 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    for (int u = 0; u < kUnroll; u += 2) {
+      acc0 = mfma_f64_16x16x4(a[u], b[u], acc0);
+      acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
-    __syncthreads();
   }
-  double* P = partial + (int64_t)s * na * na;
+  for (; st < steps; ++st) {
+    const int row = st * 4 + kl;
+    const int rc = min(row, rows - 1);
+    const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * lda];
+    acc0 = mfma_f64_16x16x4((row < rows && aok) ? av : 0.0, (row < rows && bok) ? bv : 0.0, acc0);
+  }
+  const dbl4 acc = acc0 + acc1;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = a0 + ty * 4 + u, b = b0 + tx * 4 + v;
-      if (a < na && b < na) P[(int64_t)a * na + b] = acc[u][v];
+  for (int v = 0; v < 4; ++v) {
+    const int ra = a0 + (lane >> 4) + 4 * v, cb = b0 + (lane & 15);
+    if (ra < na && cb < na) {
+      G[(int64_t)ra * ldg + cb] = acc[v];
+      if (ti != tj) G[(int64_t)cb * ldg + ra] = acc[v];
     }
-}
-
-__global__ void k_gram_finish(const double* __restrict__ partial, int splits, int na, double* __restrict__ G,
-                              int ldg) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)na * na) return;
-  const int a = (int)(t / na), b = (int)(t % na);
-  const int ta = a / kGT, tb = b / kGT;
-  // tiles below the diagonal were not computed: read the transposed element
-  const int64_t src = (ta <= tb) ? (int64_t)a * na + b : (int64_t)b * na + a;
-  double v = 0.0;
-  for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * na * na + src];
-  G[(int64_t)a * ldg + b] = v;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -726,7 +785,7 @@ template <class TA, class TM, class TO>
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
                          int w, double alpha, double beta) {
   if (rows == 0 || w == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rowmul<TA, TM, TO>), dim3((rows + 3) / 4, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M,
+  hipLaunchKernelGGL((k_rowmul<TA, TM, TO>), dim3((rows + 15) / 16, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M,
                      ldm, out, ldo, w, alpha, beta);
   return hipGetLastError();
 }
@@ -735,9 +794,9 @@ template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
                             double* out, int ldo, double* partial, int64_t partial_cap) {
   if (na == 0 || nb == 0) return hipSuccess;
-  const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
-  // enough workgroups to fill the chip: about 512 in total, at least 32 rows per split
-  int splits = std::max(1, std::min(std::max(1, rows / 32), 512 / std::max(1, gx * gy)));
+  const int gx = (na + 15) / 16, gy = (nb + 15) / 16;
+  // enough workgroups to fill the chip: about 512 in total, at least 64 rows per split
+  int splits = std::max(1, std::min(std::max(1, rows / 64), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
   const int rps = (rows + splits - 1) / splits;
   hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
@@ -751,17 +810,12 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
 template <class T>
 hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
                        int64_t partial_cap) {
+  (void)partial;
+  (void)partial_cap;
   if (na == 0) return hipSuccess;
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
-  int splits = std::max(1, std::min(512 / ntri, rows / 256));
-  while (splits > 1 && (int64_t)splits * na * na > partial_cap) --splits;
-  const int rps = (rows + splits - 1) / splits;
-  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri, splits), dim3(256), 0, s, rows, A, lda, na, partial,
-                     std::max(rps, 1), nt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gram_finish, dim3(grid1((int64_t)na * na)), dim3(256), 0, s, partial, splits, na, G, ldg);
+  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(256), 0, s, rows, A, lda, na, G, ldg, nt);
   return hipGetLastError();
 }
 
@@ -801,8 +855,8 @@ hipError_t launch_tn_partial(hipStream_t s, int rows, const TA* A, int lda, int 
                              double* partial, int64_t partial_cap, int* splits_out) {
   *splits_out = 0;
   if (na == 0 || nb == 0) return hipSuccess;
-  const int gx = (na + kWave - 1) / kWave, gy = (nb + 15) / 16;
-  int splits = std::max(1, std::min(std::max(1, rows / 32), 512 / std::max(1, gx * gy)));
+  const int gx = (na + 15) / 16, gy = (nb + 15) / 16;
+  int splits = std::max(1, std::min(std::max(1, rows / 64), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
   const int rps = (rows + splits - 1) / splits;
   hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
