@@ -98,10 +98,26 @@ class Params:
     r_max: int = 0              # [S19] <= 0: m (an orthonormal basis in R^m holds at most m columns)
     seed: int = 0               # Omega stream key
     k0: int = -1                # < 0: kicking count computed from ||P_Lambda A||_2
+    # Variants of the operator (all default to Alg. 4 with R4SVD):
+    #   mode "r4svd": recycle the previous left singular vectors (Alg. 3);
+    #   mode "r3svd": no recycling, Alg. 2 from a fresh t-block in every SVT iteration;
+    #   mode "rsvd":  fixed-rank randomized SVD (Alg. 1) with `rank` + `oversample` samples and the
+    #                 `rank` leading singular triplets thresholded.
+    mode: str = "r4svd"
+    recycle_extra: int = -1     # >= 0: recycle only the leading k + recycle_extra left singular vectors
+    rank: int = 0               # rank of the "rsvd" mode
+    oversample: int = 10        # oversampling p of the "rsvd" mode
+    mae_tol: float = 0.0        # > 0: also stop when the sample MAE on Lambda falls below it (Eq. 15, Sec. 3)
 
     def resolved(self, m, n):
+        if self.mode not in ("r4svd", "r3svd", "rsvd"):
+            raise ValueError(f"unknown mode {self.mode!r}")
+        if self.mode == "rsvd" and self.rank <= 0:
+            raise ValueError("the rsvd mode needs rank > 0")
         t0 = self.t0 if self.t0 > 0 else max(1, int(math.floor(0.05 * min(m, n))))
         r_max = min(self.r_max, m) if self.r_max > 0 else m
+        if self.mode == "rsvd":
+            t0 = self.rank + max(self.oversample, 0)
         return replace(self, t0=min(t0, r_max), r_max=r_max)
 
 
@@ -131,6 +147,7 @@ class StepInfo:
     sigma: np.ndarray = None     # all singular values of B
     x: np.ndarray = None         # X^(i) on Lambda
     rel: float = 0.0             # ||P_Lambda(A - X)||_F / ||P_Lambda A||_F   (S10)
+    mae: float = 0.0             # sample MAE (1/|Lambda|) sum |A - X| on Lambda (Sec. 3)
     annealed: bool = False
     anneal_margin: float = 0.0   # (rel - eps_min (1 - eta)) / eps_min before the update
     stopped: bool = False
@@ -196,7 +213,7 @@ def r4svd(Y, normY, Q, eps_thr, p, it, replay_blocks=None, info=None):
     info.eps_thr_used = eps_thr
     info.eps_hist.append(eps)
     blk = 0
-    while True:
+    while p.mode != "rsvd":              # Alg. 1 takes one sample of fixed width, no growth
         r = Q.shape[1]
         room = min(p.dt, p.r_max - r)
         if replay_blocks is not None:
@@ -248,7 +265,8 @@ def svt_step(prob, p, state, replay=None):
     info = StepInfo(it=it)
     Y = prob.sparse(state.y)
     normY = float(state.y @ state.y)
-    Q, W, normB, eps, eps_thr = r4svd(Y, normY, state.Q, state.eps_thr, p, it,
+    Q0 = state.Q if p.mode == "r4svd" else None   # R3SVD / RSVD start every iteration from a fresh sample
+    Q, W, normB, eps, eps_thr = r4svd(Y, normY, Q0, state.eps_thr, p, it,
                                       replay_blocks=None if replay is None else replay[0], info=info)
     info.r, info.eps, info.normY, info.normB, info.Q, info.W = Q.shape[1], eps, normY, normB, Q, W
 
@@ -256,6 +274,8 @@ def svt_step(prob, p, state, replay=None):
     # the full one keeps all r columns so that the whole basis is recycled (reading S8).
     U_B, s, VBt = np.linalg.svd(W.T, full_matrices=W.shape[1] > W.shape[0])
     K = np.flatnonzero(s > p.tau)                  # reading S16
+    if p.mode == "rsvd":
+        K = K[K < p.rank]                          # Alg. 1 keeps the `rank` leading triplets
     info.sigma, info.k = s, int(K.size)
     U_L = Q @ U_B
     info.U, info.s_minus_tau, info.V = U_L[:, K], s[K] - p.tau, VBt[K].T
@@ -267,6 +287,7 @@ def svt_step(prob, p, state, replay=None):
     res = prob.a - x
     rel = float(np.linalg.norm(res)) / prob.norm_a
     info.x, info.rel = x, rel
+    info.mae = float(np.mean(np.abs(res)))
 
     # Annealing (Eq. 14): a residual that does not decrease tightens the threshold.
     eps_min = state.eps_min
@@ -279,8 +300,10 @@ def svt_step(prob, p, state, replay=None):
         eps_min = rel
     info.annealed = annealed
 
-    new = State(it=it, y=state.y.copy(), Q=U_L, eps_thr=eps_thr, eps_min=eps_min)  # recycle U_L (all r columns, S8)
-    if rel < p.tol:
+    # recycle U_L: all r columns (S8), or the leading k + recycle_extra (truncated recycling)
+    keep = U_L.shape[1] if p.recycle_extra < 0 else min(U_L.shape[1], info.k + p.recycle_extra)
+    new = State(it=it, y=state.y.copy(), Q=U_L[:, :keep] if keep > 0 else None, eps_thr=eps_thr, eps_min=eps_min)
+    if rel < p.tol or (p.mae_tol > 0 and info.mae < p.mae_tol):
         info.stopped = True
         return new, info
     new.y = state.y + p.delta * res                # Eq. 4, dual update on Lambda
