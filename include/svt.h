@@ -62,6 +62,14 @@ enum {
                     eigen-solver and every norm and reduction */
 };
 
+/* Operator variants (svt_params.mode). */
+enum {
+  SVT_MODE_R4SVD = 0, /* Alg. 3: recycle the previous left singular vectors (Sec. 2.4), default */
+  SVT_MODE_R3SVD = 1, /* Alg. 2 from a fresh t-block in every SVT iteration (no recycling, Sec. 2.2) */
+  SVT_MODE_RSVD = 2   /* Alg. 1: fixed-rank randomized SVD with rank + oversample Gaussian samples,
+                         no growth, the `rank` leading singular triplets thresholded (Sec. 2.1) */
+};
+
 /* Bits of svt_step_stats.flags. */
 enum {
   SVT_F_CONVERGED = 1, /* relative residual fell below tol; Y was not updated */
@@ -91,6 +99,13 @@ typedef struct {
   uint64_t seed;   /* key of the Philox4x64-10 Omega stream */
   int32_t precision; /* SVT_FP64 or SVT_MIXED */
   int32_t kmax;    /* most singular values above tau the eigensolver tracks; <= 0 => 64 (max 96) */
+  int32_t mode;    /* SVT_MODE_R4SVD (default), SVT_MODE_R3SVD or SVT_MODE_RSVD */
+  int32_t recycle_extra; /* R4SVD: < 0 recycles all r columns (default); e >= 0 recycles only the
+                            k + e leading left singular vectors of B */
+  int32_t rank;    /* SVT_MODE_RSVD: the fixed rank (> 0) */
+  int32_t oversample; /* SVT_MODE_RSVD: oversampling p >= 0 (default 10) */
+  double mae_tol;  /* > 0: also stop when the sample MAE (1/|Lambda|) sum |A - X| on Lambda falls
+                      below mae_tol (the stop rule of Sec. 3); <= 0: unused */
 } svt_params;
 
 /* Per-iteration report. */
@@ -112,6 +127,7 @@ typedef struct {
   double sigmak;     /* smallest singular value above tau (0 if k = 0) */
   double grow_margin;   /* min over growth tests of |eps - eps_thr| / eps_thr */
   double anneal_margin; /* (rel - eps_min (1 - eta)) / eps_min before the update */
+  double mae;           /* sample MAE (1/|Lambda|) sum |A - X| on Lambda (Sec. 3) */
 } svt_step_stats;
 
 /* Fill *p with defaults (tau and delta are set to 0 and must be given). */
@@ -146,6 +162,11 @@ svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, doubl
 
 /* X of the last iteration sampled on nq arbitrary entries (qi[l], qj[l]). */
 svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out);
+
+/* Mean absolute error of the last X against reference values ref on nq entries (qi[l], qj[l]):
+ * *mae = (1/nq) sum_l |ref[l] - X(qi[l], qj[l])|, the MAE of Eq. 15 restricted to the given entries
+ * (all m n entries for the overall error, a held-out set for a test error).  nq >= 1. */
+svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref, double* mae);
 
 /* Current state: y (nnz, caller order), basis Q (m x r row-major; pass
  * qcap >= r columns, or NULL), r, eps_threshold (NaN before the first

@@ -7,13 +7,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SVT_OK = 0
 SVT_E_INVALID_ARG, SVT_E_OOM, SVT_E_HIP, SVT_E_NUMERIC, SVT_E_STATE, SVT_E_LIMIT = -1, -2, -3, -4, -5, -6
 SVT_FP64, SVT_MIXED = 0, 1
+SVT_MODE_R4SVD, SVT_MODE_R3SVD, SVT_MODE_RSVD = 0, 1, 2
 SVT_F_CONVERGED, SVT_F_MAXIT, SVT_F_RMAX_HIT, SVT_F_EXHAUSTED, SVT_F_ANNEALED, SVT_F_EIG_INEXACT = 1, 2, 4, 8, 16, 32
 
 _STATUS = {0: "SVT_OK", -1: "SVT_E_INVALID_ARG", -2: "SVT_E_OOM", -3: "SVT_E_HIP", -4: "SVT_E_NUMERIC",
            -5: "SVT_E_STATE", -6: "SVT_E_LIMIT"}
 
 # Names of every symbol include/svt.h declares (checked by the CPU tests).
-EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample",
+EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample", "svt_mae",
            "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_read",
            "svt_last_error", "svt_destroy"]
 PHASES = ["spmm_t", "grow", "gram", "eig", "factors", "sddmm", "reduce"]
@@ -29,7 +30,9 @@ class Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("delta", C.c_double), ("tol", C.c_double), ("beta", C.c_double),
                 ("eta", C.c_double), ("eps_thr0", C.c_double), ("maxit", C.c_int32), ("t0", C.c_int32),
                 ("dt", C.c_int32), ("npow", C.c_int32), ("r_max", C.c_int32), ("k0", C.c_int32),
-                ("seed", C.c_uint64), ("precision", C.c_int32), ("kmax", C.c_int32)]
+                ("seed", C.c_uint64), ("precision", C.c_int32), ("kmax", C.c_int32), ("mode", C.c_int32),
+                ("recycle_extra", C.c_int32), ("rank", C.c_int32), ("oversample", C.c_int32),
+                ("mae_tol", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -37,7 +40,7 @@ class StepStats(C.Structure):
                 ("annealed", C.c_int32), ("stopped", C.c_int32), ("flags", C.c_int32), ("eig_iters", C.c_int32),
                 ("eps", C.c_double), ("eps_thr", C.c_double), ("rel_res", C.c_double), ("normY", C.c_double),
                 ("normB", C.c_double), ("sigma1", C.c_double), ("sigmak", C.c_double),
-                ("grow_margin", C.c_double), ("anneal_margin", C.c_double)]
+                ("grow_margin", C.c_double), ("anneal_margin", C.c_double), ("mae", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,6 +75,7 @@ def load():
     L.svt_iterate.argtypes = [_vp, C.c_int32, _P(StepStats)]
     L.svt_factors.argtypes = [_vp, C.c_int32, _i32p, _f64p, _f64p, _f64p]
     L.svt_sample.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p]
+    L.svt_mae.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p, _f64p]
     L.svt_get_state.argtypes = [_vp, _f64p, _f64p, C.c_int32, _i32p, _f64p, _f64p, _i32p]
     L.svt_set_state.argtypes = [_vp, _f64p, _f64p, C.c_int32, C.c_double, C.c_double, C.c_int32]
     L.svt_set_replay.argtypes = [_vp, _i32p, _i32p, C.c_int32]
@@ -82,7 +86,7 @@ def load():
     L.svt_last_error.restype = C.c_char_p
     L.svt_destroy.argtypes = [_vp]
     L.svt_destroy.restype = None
-    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample", "svt_get_state",
+    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample", "svt_mae", "svt_get_state",
                  "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L

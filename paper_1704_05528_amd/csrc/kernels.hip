@@ -652,7 +652,7 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __re
   __shared__ double lds[4];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int j = blockIdx.x * 4 + wid;
-  double s_res = 0.0, s_y = 0.0;
+  double s_res = 0.0, s_y = 0.0, s_abs = 0.0;
   if (j < n) {
     for (int l = lane; l < k; l += kWave) vs[wid][l] = Vt[(int64_t)j * ld + l];
   }
@@ -668,14 +668,28 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __re
       y_next[p] = yn;
       s_res = fma((double)res, (double)res, s_res);
       s_y = fma((double)yn, (double)yn, s_y);
+      s_abs += fabs((double)res);
     }
   }
   const double t0 = block_sum(s_res, lds);
   const double t1 = block_sum(s_y, lds);
+  const double t2 = block_sum(s_abs, lds);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = t0;
-    partial[2 * blockIdx.x + 1] = t1;
+    partial[3 * blockIdx.x] = t0;
+    partial[3 * blockIdx.x + 1] = t1;
+    partial[3 * blockIdx.x + 2] = t2;
   }
+}
+
+// partial[b] = sum over this block's entries of |ref - x| (double), grid-stride
+__global__ __launch_bounds__(256) void k_absdiff(int64_t len, const double* __restrict__ x,
+                                                 const double* __restrict__ ref, double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
+    v += fabs(ref[e] - x[e]);
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 template <class T>
@@ -921,6 +935,15 @@ hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, cons
   hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, Ut, Vt, ld, k,
                      (T)delta, partial);
   return hipGetLastError();
+}
+
+hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const double* ref, double* partial,
+                              double* scal, int slot) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (len + 255) / 256));
+  hipLaunchKernelGGL(k_absdiff, dim3(nb), dim3(256), 0, s, len, x, ref, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish(s, partial, nb, 1, 1, scal, slot);
 }
 
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal,

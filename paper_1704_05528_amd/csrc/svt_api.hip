@@ -35,8 +35,8 @@ constexpr double kEigDepTol = 1e-12;  // eigen-block CholeskyQR drops only numer
 constexpr int kDirect = 32;           // basis widths up to this are diagonalised directly
 
 // scalar slots of the device readback buffer
-enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_RES2 = 4, S_YN2 = 5, S_SWEEPS = 6, S_NORMY = 7,
-       S_A = 8, S_B = 9, S_TBAR = 10, S_DOT = 11 };
+enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_SWEEPS = 6, S_NORMY = 7, S_A = 8, S_B = 9, S_TBAR = 10,
+       S_DOT = 11, S_RES2 = 12, S_YN2 = 13, S_ABS = 14, S_MAE = 15 };
 
 #define HIPCHK(expr)                                                     \
   do {                                                                   \
@@ -274,7 +274,7 @@ struct Engine {
     st->eps_thr = h->eps_thr;
     st->grow_margin = std::numeric_limits<double>::infinity();
     int blk = 0;
-    for (;;) {
+    while (h->p.mode != SVT_MODE_RSVD) {  // Alg. 1 draws one sample of fixed width, no growth
       const int room = std::min(h->p.dt, h->p.r_max - h->r);
       bool grow;
       if (replay_blocks >= 0) {
@@ -357,6 +357,8 @@ struct Engine {
         // after the first products orthonormalises the block
         HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
       }
+      // truncated recycling keeps the k + e leading Ritz vectors, which then must converge too
+      const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
       bool done = false, have_gv = false;
       int powers = 0, tests = 0, prev_k = -1;
       int target = std::max(2, h->eig_pred);
@@ -414,9 +416,11 @@ struct Engine {
         for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
         k = 0;
         while (k < b && theta[k] > tau2) ++k;
-        if (k + 4 > b && b < r) {
+        const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
+        if (nconv + 4 > b && b < r) {
           if (b >= h->b_cap) {
             if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks");
+            if (nconv > b) return fail(h, SVT_E_LIMIT, "truncated recycling keeps more vectors than the eigensolver tracks");
           } else {
             // widen the block with Gaussian columns and continue from the enlarged block
             const int nb = std::min(std::min(h->b_cap, r), b + 16);
@@ -438,10 +442,16 @@ struct Engine {
         // (b == r) is exact after one Rayleigh-Ritz step.
         const double lim = kEigTol * std::max(theta[0], 0.0);
         done = (b == r) || (k == prev_k) || (prev_k < 0 && warm && k == h->k);
-        for (int c = 0; done && c < k; ++c)
+        for (int c = 0; done && c < nconv; ++c)
           if (!(res[c] <= lim)) done = false;
         for (int c = k; done && c < std::min(b, k + 4); ++c)
           if (!(theta[c] + res[c] < tau2)) done = false;
+        if (nconv > k && nconv < r) {
+          // the kept Ritz vectors span the leading invariant subspace: four guard pairs below it
+          const double floor_kept = theta[nconv - 1] - res[nconv - 1];
+          for (int c = nconv; done && c < std::min(b, nconv + 4); ++c)
+            if (!(theta[c] + res[c] < floor_kept)) done = false;
+        }
         prev_k = k;
         if (!done) target = powers + 2;
       }
@@ -453,6 +463,7 @@ struct Engine {
       h->ev_rows = r;
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
     }
+    if (h->p.mode == SVT_MODE_RSVD) k = std::min(k, h->p.rank);  // Alg. 1 keeps `rank` leading triplets
     if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
     h->k = k;
     h->sigma_k.assign(theta.begin(), theta.begin() + k);
@@ -474,6 +485,31 @@ struct Engine {
   }
 
   // ----------------------------------------------------------------------------------------
+  // Truncated recycling: keep the k + e leading left singular vectors U_L = Q U_B of this
+  // iteration as the next basis (Q <- Q S[:, :keep]); the factors keep their meaning because the
+  // first k new columns are U_L[:, K].
+  // ----------------------------------------------------------------------------------------
+  svt_status recycle_truncated() {
+    if (h->p.mode != SVT_MODE_R4SVD || h->p.recycle_extra < 0) return SVT_OK;
+    const int r = h->r, keep = std::min(r, h->k + h->p.recycle_extra);
+    if (keep >= r) return SVT_OK;
+    hipStream_t s = h->stream;
+    h->hist_ok = false;
+    if (keep > 0) {
+      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->EV, kEigMax, Utmp(), kEigMax, keep, 1.0,
+                                          0.0)));
+      HIPCHK((launch_copy_cols<T, T>(s, (int)h->m, Utmp(), kEigMax, Q(), h->r_cap, keep)));
+      // in the new basis the Ritz vectors are unit vectors
+      HIPCHK(launch_set_unit(s, h->EV, keep, kEigMax, 0, keep, 0));
+      if (h->k > 0) HIPCHK(launch_set_unit(s, h->Sk, keep, kEigMax, 0, h->k, 0));
+    }
+    h->r = keep;
+    h->ev_valid = keep;
+    h->ev_rows = keep;
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
   // One iteration of Alg. 4 (reading: X^(i) on Lambda, residual, annealing, stop, update).
   // ----------------------------------------------------------------------------------------
   svt_status iteration(svt_step_stats* st) {
@@ -485,6 +521,13 @@ struct Engine {
       rb = h->replay_blocks[h->replay_pos];
       ra = h->replay_anneal[h->replay_pos];
       ++h->replay_pos;
+    }
+    if (h->p.mode != SVT_MODE_R4SVD) {
+      // R3SVD / RSVD: a fresh sample in every iteration, nothing recycled
+      h->r = 0;
+      h->ev_valid = 0;
+      h->ev_rows = 0;
+      h->hist_ok = false;
     }
     CHK(r4svd_core(it, rb, st));
     h->hist_r.push_back(h->r);
@@ -499,13 +542,15 @@ struct Engine {
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
-      HIPCHK(launch_finish(h->stream, h->partial, nbl, 2, 2, h->scal, S_RES2));
+      HIPCHK(launch_finish(h->stream, h->partial, nbl, 3, 3, h->scal, S_RES2));
     }
-    CHK(readback(h, S_YN2 + 1));
+    CHK(recycle_truncated());
+    CHK(readback(h, S_ABS + 1));
     const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
     const double rel = std::sqrt(res2) / h->norm_a;
     if (!std::isfinite(rel) || !std::isfinite(yn2)) return fail(h, SVT_E_NUMERIC, "non-finite residual");
     st->rel_res = rel;
+    st->mae = h->hscal[S_ABS] / (double)h->nnz;
     const double target = h->eps_min * (1.0 - h->p.eta);
     st->anneal_margin =
         std::isfinite(h->eps_min) ? (rel - target) / h->eps_min : -std::numeric_limits<double>::infinity();
@@ -518,7 +563,7 @@ struct Engine {
     }
     st->annealed = annealed ? 1 : 0;
     h->iter = it;
-    if (rel < h->p.tol) {
+    if (rel < h->p.tol || (h->p.mae_tol > 0.0 && st->mae < h->p.mae_tol)) {
       st->stopped = 1;
       st->flags |= SVT_F_CONVERGED;
       h->converged = true;
@@ -536,6 +581,10 @@ struct Engine {
     const bool thr_set = h->eps_thr_set;
     const double thr = h->eps_thr;
     st->iter = h->iter + 1;
+    if (h->p.mode != SVT_MODE_R4SVD) {
+      h->r = 0;  // R3SVD / RSVD start from a fresh sample (the basis buffer is scratch in these modes)
+      h->ev_valid = 0;
+    }
     svt_status s1 = r4svd_core(h->iter + 1, -1, st);
     if (s1 == SVT_OK) s1 = projected_svd(st);
     h->r = r_save;
@@ -888,6 +937,11 @@ void svt_default_params(svt_params* p) {
   p->seed = 0;
   p->precision = SVT_FP64;
   p->kmax = 0;
+  p->mode = SVT_MODE_R4SVD;
+  p->recycle_extra = -1;
+  p->rank = 0;
+  p->oversample = 10;
+  p->mae_tol = 0.0;
 }
 
 const char* svt_last_error(const svt_handle* h) { return h ? h->err.c_str() : g_init_err.c_str(); }
@@ -925,8 +979,13 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.kmax <= 0) p.kmax = 64;
   if (p.kmax > kEigMax) return bad("kmax must not exceed 96");
   if (p.precision != SVT_FP64 && p.precision != SVT_MIXED) return bad("unknown precision form");
+  if (p.mode != SVT_MODE_R4SVD && p.mode != SVT_MODE_R3SVD && p.mode != SVT_MODE_RSVD) return bad("unknown mode");
+  if (p.mode == SVT_MODE_RSVD && p.rank <= 0) return bad("the RSVD mode needs rank > 0");
+  if (p.mode == SVT_MODE_RSVD && p.oversample < 0) return bad("oversample must be non-negative");
+  if (std::isnan(p.mae_tol)) return bad("mae_tol is NaN");
   const int64_t mn = std::min(m, n);
   if (p.t0 <= 0) p.t0 = (int32_t)std::max<int64_t>(1, (int64_t)std::floor(0.05 * (double)mn));
+  if (p.mode == SVT_MODE_RSVD) p.t0 = (int32_t)std::min<int64_t>((int64_t)p.rank + p.oversample, 1 << 30);
   p.r_max = (p.r_max <= 0) ? (int32_t)m : (int32_t)std::min<int64_t>(p.r_max, m);
   p.t0 = std::min(p.t0, p.r_max);
 
@@ -1146,6 +1205,34 @@ svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_
   (void)hipFree(dx);
   HIPCHK(e);
   return st;
+}
+
+svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref, double* mae) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (nq <= 0 || !qi || !qj || !ref || !mae) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
+  if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
+  for (int64_t l = 0; l < nq; ++l) {
+    if (qi[l] < 0 || qi[l] >= h->m || qj[l] < 0 || qj[l] >= h->n)
+      return fail(h, SVT_E_INVALID_ARG, "query out of range");
+    if (!std::isfinite(ref[l])) return fail(h, SVT_E_INVALID_ARG, "non-finite reference value");
+  }
+  GradArena ar(h->stream);
+  int32_t *di = nullptr, *dj = nullptr;
+  double *dx = nullptr, *dr = nullptr;
+  hipError_t e = ar.get(&di, nq);
+  if (e == hipSuccess) e = ar.get(&dj, nq);
+  if (e == hipSuccess) e = ar.get(&dx, nq);
+  if (e == hipSuccess) e = ar.get(&dr, nq);
+  if (e != hipSuccess)
+    return fail(h, e == hipErrorOutOfMemory ? SVT_E_OOM : SVT_E_HIP, std::string("svt_mae: ") + hipGetErrorString(e));
+  HIPCHK(hipMemcpyAsync(di, qi, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(dj, qj, nq * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(dr, ref, nq * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  CHK(dispatch(h, [&](auto& eng) { return eng.sample(nq, di, dj, dx); }));
+  HIPCHK(launch_absdiff_sum(h->stream, nq, dx, dr, h->partial, h->scal, S_MAE));
+  CHK(readback(h, S_MAE + 1));
+  *mae = h->hscal[S_MAE] / (double)nq;
+  return SVT_OK;
 }
 
 svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,

@@ -172,13 +172,17 @@ hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w,
                             int ldo);
 
 // sampled product on Lambda (CSC order) with residual and dual update; per-block partial sums of
-// res^2 and y_next^2 land in partial[2 b], partial[2 b + 1]; *nblocks receives the block count
+// res^2, y_next^2 and |res| land in partial[3 b], partial[3 b + 1], partial[3 b + 2]; *nblocks
+// receives the block count
 template <class T>
 hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* a,
                                const T* y, T* y_next, const T* Ut, const T* Vt, int ld, int k, double delta,
                                double* partial, int* nblocks);
 // scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
+// scal[slot] = sum |ref - x| over len entries (deterministic)
+hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const double* ref, double* partial,
+                              double* scal, int slot);
 // X on arbitrary entries
 template <class T>
 hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,

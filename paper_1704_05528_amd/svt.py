@@ -102,6 +102,15 @@ class SVT:
         check(load().svt_sample(self._h, qi.size, ip, jp, out.ctypes.data_as(_f64p)), self._h)
         return out
 
+    def mae(self, qi, qj, ref):
+        """Mean |ref - X| over the entries (qi, qj) (the MAE of Eq. 15 on those entries)."""
+        qi, ip = _i32(qi)
+        qj, jp = _i32(qj)
+        ref, rp = _f64(ref)
+        out = C.c_double()
+        check(load().svt_mae(self._h, qi.size, ip, jp, rp, C.byref(out)), self._h)
+        return out.value
+
     def get_state(self):
         L = load()
         r = C.c_int32()

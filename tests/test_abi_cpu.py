@@ -35,15 +35,16 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # svt_params: 6 doubles, 6 int32, uint64, 2 int32 (+ tail padding)
-    assert C.sizeof(_capi.Params) == 6 * 8 + 6 * 4 + 8 + 2 * 4
-    assert C.sizeof(_capi.StepStats) == 8 * 4 + 9 * 8
+    # svt_params: 6 doubles, 6 int32, uint64, 6 int32, double
+    assert C.sizeof(_capi.Params) == 6 * 8 + 6 * 4 + 8 + 6 * 4 + 8
+    assert C.sizeof(_capi.StepStats) == 8 * 4 + 10 * 8
 
 
 def test_default_params():
     p = svt.default_params()
     assert p.tol == 1e-4 and p.beta == 0.95 and p.dt == 10 and p.maxit == 500
     assert p.k0 == -1 and p.eps_thr0 < 0 and p.precision == svt.SVT_FP64 and p.t0 == 0
+    assert p.mode == svt.SVT_MODE_R4SVD and p.recycle_extra == -1 and p.oversample == 10 and p.mae_tol == 0.0
 
 
 def _init(m, n, rows, cols, vals, **kw):

@@ -1,0 +1,125 @@
+"""GPU parity of the operator variants against the FP64 oracle: R3SVD in every iteration, the
+fixed-rank RSVD mode (Alg. 1), truncated recycling, and the sample MAE with its stop rule.
+
+Bar (FP64 form): x on Lambda, rel and MAE within 1e-10 relative; r, k, growth blocks and
+decisions exact (decisions replayed from the oracle so that rounding-level ties cannot split
+the trajectories).
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import svt_workloads as W
+from oracle import Params, Problem, svt_run
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+MODES = {"r4svd": 0, "r3svd": 1, "rsvd": 2}
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _run_both(svt, w, p, steps):
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = replace(p, maxit=steps)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    kw = dict(tau=p.tau, delta=p.delta, seed=p.seed, maxit=steps, k0=k0, t0=p.t0, dt=p.dt, tol=p.tol,
+              mode=MODES[p.mode], recycle_extra=p.recycle_extra, rank=p.rank, oversample=p.oversample,
+              mae_tol=p.mae_tol, npow=p.npow)
+    h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, **kw)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    out = []
+    for info in infos:
+        st = h.iterate(1)
+        out.append((st, h.sample(w.rows, w.cols)))
+    return infos, out, h
+
+
+def _compare(infos, out, ctx):
+    for info, (st, x) in zip(infos, out):
+        c = (ctx, info.it)
+        assert st.r == info.r, (c, "r", st.r, info.r)
+        assert st.k == info.k, (c, "k", st.k, info.k)
+        assert st.blocks == info.blocks, (c, "blocks")
+        assert bool(st.stopped) == bool(info.stopped), (c, "stopped")
+        assert rel_err(x, info.x) <= TOL, (c, "x", rel_err(x, info.x))
+        assert abs(st.rel_res - info.rel) <= TOL * info.rel, (c, "rel")
+        assert abs(st.mae - info.mae) <= TOL * info.mae, (c, "mae", st.mae, info.mae)
+
+
+@pytest.mark.parametrize("m,n,seed,extra", [(90, 70, 91, {}), (130, 110, 92, {"dt": 7}), (64, 64, 93, {"npow": 1})])
+def test_r3svd_every_iteration(gpu_lib, m, n, seed, extra):
+    w = W.tiny_dense(m, n, 3, 0.4, seed=seed)
+    p = Params(tau=w.tau, delta=w.delta, seed=seed, mode="r3svd", **extra)
+    infos, out, _ = _run_both(gpu_lib, w, p, 15)
+    _compare(infos, out, ("r3svd", m, n))
+
+
+@pytest.mark.parametrize("m,n,rank,over,seed", [(80, 60, 3, 5, 94), (120, 90, 6, 10, 95), (100, 100, 20, 30, 96)])
+def test_rsvd_fixed_rank(gpu_lib, m, n, rank, over, seed):
+    w = W.tiny_dense(m, n, 4, 0.5, seed=seed)
+    p = Params(tau=w.tau, delta=w.delta, seed=seed, mode="rsvd", rank=rank, oversample=over)
+    infos, out, _ = _run_both(gpu_lib, w, p, 12)
+    _compare(infos, out, ("rsvd", m, n, rank))
+    assert all(i.k <= rank for i in infos)
+
+
+@pytest.mark.parametrize("m,n,seed,extra,e", [
+    (60, 45, 97, {"t0": 6, "dt": 4}, 2),       # bases up to 32 columns: direct eigen-decomposition
+    (200, 160, 98, {"t0": 40, "dt": 10}, 3),   # wider bases: block eigensolver with the kept vectors converged
+    (90, 70, 99, {}, 0),
+])
+def test_truncated_recycling(gpu_lib, m, n, seed, extra, e):
+    w = W.tiny_dense(m, n, 3, 0.4, seed=seed)
+    p = Params(tau=w.tau, delta=w.delta, seed=seed, recycle_extra=e, **extra)
+    infos, out, h = _run_both(gpu_lib, w, p, 12)
+    _compare(infos, out, ("trunc", m, n, e))
+    s = h.get_state()
+    assert s["r"] == min(infos[-1].r, infos[-1].k + e) or infos[-1].stopped
+
+
+def test_mae_stop_rule(gpu_lib):
+    w = W.tiny_dense(70, 60, 3, 0.5, seed=100)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=100, tol=0.0, maxit=30)
+    _, ref_infos, _ = svt_run(prob, p, keep_infos=True)
+    target = ref_infos[9].mae * 1.000001
+    infos, out, _ = _run_both(gpu_lib, w, replace(p, mae_tol=target), 30)
+    assert len(infos) == next(i for i, inf in enumerate(ref_infos) if inf.mae < target) + 1
+    _compare(infos, out, "mae")
+    assert out[-1][0].stopped
+
+
+def test_svt_mae_matches_definition(gpu_lib):
+    """svt_mae is (1/nq) sum |ref - X| over the given entries (Eq. 15 on those entries)."""
+    w = W.tiny_dense(80, 70, 3, 0.4, seed=101)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=101)
+    h.iterate(8)
+    rows, cols = np.divmod(np.arange(w.m * w.n), w.n)
+    x = h.sample(rows, cols)
+    ref = w.A[rows, cols]
+    assert abs(h.mae(rows, cols, ref) - np.mean(np.abs(ref - x))) <= 1e-12 * np.mean(np.abs(ref))
+    sel = np.arange(0, rows.size, 7)
+    assert abs(h.mae(rows[sel], cols[sel], ref[sel]) - np.mean(np.abs(ref[sel] - x[sel]))) <= 1e-12 * np.mean(np.abs(ref))
+
+
+def test_modes_in_the_mixed_form(gpu_lib):
+    """The variants run in the float32-storage form and track the FP64 oracle to the mixed bar."""
+    w = W.tiny_dense(90, 70, 3, 0.4, seed=102)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    for mode, kw in (("r3svd", {}), ("rsvd", {"rank": 4, "oversample": 6}), ("r4svd", {"recycle_extra": 2})):
+        p = Params(tau=w.tau, delta=w.delta, seed=102, mode=mode, maxit=6, **kw)
+        _, infos, k0 = svt_run(prob, p, keep_infos=True)
+        h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=102, k0=k0, maxit=6,
+                             precision=gpu_lib.SVT_MIXED, mode=MODES[mode], rank=p.rank, oversample=p.oversample,
+                             recycle_extra=p.recycle_extra)
+        h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+        for info in infos:
+            st = h.iterate(1)
+            assert st.k == info.k, (mode, info.it)
+            assert rel_err(h.sample(w.rows, w.cols), info.x) <= 1e-4, (mode, info.it)
