@@ -7,11 +7,17 @@ workload: a 1024 x 1024 matrix of 40 separable smooth patterns plus noise,
 50% of the pixels observed, tau = ||P_Lambda A||_F, delta = sqrt(mn / |Lambda|).
 Inputs are synthetic and seeded; they are resident on the GPU before timing.
 
-Prints one JSON line with iterations/s over the timed steps, the roofline of
-the dominant kernel (device time from hipEvents recorded on the library's
-stream during the timed steps), the time to relative residual 1e-4 on the
-planted 1000 x 1000 rank-10 problem, and the FP64 CPU oracle timed on a
-bounded sample on the host.
+Prints one JSON line with:
+  * iterations/s over the timed steps for the float32-storage form (the value)
+    and the FP64 form, with per-phase device time from hipEvents recorded on
+    the library's stream;
+  * the roofline of the dominant single-kernel phase;
+  * the sample MAE and the MAE of Eq. 15 over all pixels (0..255 scale);
+  * the time to relative residual 1e-4 on the planted 1000 x 1000 rank-10
+    problem for five Omega seeds (median and range), both forms;
+  * the recycling ablation: per-iteration cost of R4SVD, R3SVD from a fresh
+    t-block every iteration, and the fixed-rank randomized SVD of Alg. 1;
+  * the FP64 CPU oracle timed on a bounded sample on the host.
 """
 import argparse
 import json
@@ -24,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFS = 78.6
+FP64_PEAK_TFS = 78.6    # FP64 vector FMA and FP64 matrix cores (dense)
+FP32_PEAK_TFS = 157.3   # FP32 vector FMA
 
 METRIC = "SVT iters/sec + time-to-rel-residual 1e-4 (BF16/FP32 form vs FP64 plain)"
 
@@ -38,10 +45,20 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance run")
     ap.add_argument("--forms", default="mixed,fp64", help="precision forms to time (comma list of mixed, fp64)")
+    ap.add_argument("--ttt-seeds", default="11,12,13,14,15",
+                    help="Omega seeds of the time-to-tolerance runs (median and range are reported)")
+    ap.add_argument("--ablation-steps", type=int, default=30,
+                    help="SVT iterations per operator variant in the recycling ablation (0 skips it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size reference kernel for "
                          "hardware traffic counters)")
     return ap.parse_args()
+
+
+def divmod_all(m, n):
+    import numpy as np
+    i, j = np.divmod(np.arange(m * n, dtype=np.int64), n)
+    return i.astype(np.int32), j.astype(np.int32)
 
 
 def cpu_baseline(w, r, seed, budget_s=20.0):
@@ -84,6 +101,41 @@ def time_to_tolerance(svt, W, stream, seed, precision):
             "r_final": st.r, "k_final": st.k}
 
 
+def ttt_seeds(svt, W, stream, seeds, precision):
+    runs = [time_to_tolerance(svt, W, stream, sd, precision) for sd in seeds]
+    secs = sorted(r["seconds"] for r in runs)
+    its = sorted(r["iterations"] for r in runs)
+    return {"seeds": list(seeds), "median_seconds": secs[len(secs) // 2], "min_seconds": secs[0],
+            "max_seconds": secs[-1], "median_iterations": its[len(its) // 2], "min_iterations": its[0],
+            "max_iterations": its[-1], "all_converged": all(r["converged"] for r in runs), "runs": runs}
+
+
+def ablation(svt, w, stream, steps, seed):
+    """Per-iteration cost and progress of the operator variants over the same first SVT iterations
+    (FP64 form): R4SVD (recycling, Alg. 3), R3SVD from a fresh t-block every iteration (Alg. 2), and
+    the fixed-rank randomized SVD of Alg. 1 (rank 40 + 10 oversampling)."""
+    import torch
+    out = {}
+    variants = [("r4svd", dict(mode=svt.SVT_MODE_R4SVD)), ("r3svd", dict(mode=svt.SVT_MODE_R3SVD)),
+                ("rsvd_rank40_p10", dict(mode=svt.SVT_MODE_RSVD, rank=40, oversample=10))]
+    for name, kw in variants:
+        h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, stream=stream, tau=w.tau, delta=w.delta, seed=seed,
+                         maxit=steps + 1, tol=0.0, precision=svt.SVT_FP64, **kw)
+        rs, blocks = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = h.iterate(1)
+            rs.append(st.r)
+            blocks += st.blocks
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"iterations": steps, "seconds": el, "ms_per_iter": 1e3 * el / steps, "r_mean": sum(rs) / steps,
+                     "r_last": rs[-1], "growth_blocks": blocks, "rel_res_last": st.rel_res, "mae_last": st.mae}
+        h.close()
+    return out
+
+
 def run_form(svt, w, stream, args, precision):
     """Warm up, then time args.steps SVT iterations of one precision form with per-phase events."""
     import torch
@@ -98,28 +150,39 @@ def run_form(svt, w, stream, args, precision):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = h.iterate(1)
-        stats.append((st.r, st.k, st.blocks, st.eig_iters, st.rel_res))
+        stats.append((st.r, st.k, st.blocks, st.eig_iters, st.rel_res, st.mae))
         if st.stopped:
             break
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = h.profile_read()
     h.profile(False)
+    # recovery quality after the timed steps on the 0..255 scale of the paper's images (Sec. 3):
+    # the sample MAE on Lambda and the MAE of Eq. 15 over all m n pixels
+    all_i, all_j = divmod_all(w.m, w.n)
+    quality = {"sample_mae_255": 255.0 * stats[-1][5], "overall_mae_255": 255.0 * h.mae(all_i, all_j, w.A.ravel())}
     n_it = len(stats)
     r_vals = [s[0] for s in stats]
     es = 4.0 if precision else 8.0
-    # roofline of the dominant single-kernel phase
-    kernels = {"spmm_t": "hbm", "sddmm": "hbm", "gram": "mfma"}
-    dom = max(kernels, key=lambda ph: prof[ph]["ms"])
+    # Roofline of the dominant single-kernel phase.  Its bound is the resource whose peak time for
+    # the phase's algorithmic work is larger: HBM bytes, or flops on the unit the kernel uses (FP64
+    # matrix cores for the Gram; plain FP32 or FP64 vector FMA for the sparse products).
+    compute_unit = {"spmm_t": "alu", "sddmm": "alu", "gram": "mfma"}
+    alu_peak = FP32_PEAK_TFS if precision else FP64_PEAK_TFS
+    dom = max(compute_unit, key=lambda ph: prof[ph]["ms"])
     pd = prof[dom]
-    if kernels[dom] == "hbm":
+    unit = compute_unit[dom]
+    cpeak = FP64_PEAK_TFS if unit == "mfma" else alu_peak
+    t_hbm = pd["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_cmp = pd["flops"] / (cpeak * 1e12)
+    if t_hbm >= t_cmp:
         achieved = pd["bytes"] / (pd["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     else:
         achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFS, "traffic": None}
+        roof = {"bound": unit, "achieved": achieved, "peak": cpeak, "unit": "TFLOP/s",
+                "frac": achieved / cpeak, "traffic": None}
     roof.update({"kernel": dom, "launches": pd["launches"], "avg_launch_us": 1e3 * pd["ms"] / max(pd["launches"], 1),
                  "bytes_per_launch": pd["bytes"] / max(pd["launches"], 1),
                  "flops_per_launch": pd["flops"] / max(pd["launches"], 1)})
@@ -131,7 +194,7 @@ def run_form(svt, w, stream, args, precision):
             "iterations_timed": [args.warmup + 1, args.warmup + n_it], "r_range": [min(r_vals), max(r_vals)],
             "r_mean": float(sum(r_vals) / len(r_vals)), "k_last": stats[-1][1],
             "growth_blocks": int(sum(s[2] for s in stats)), "eig_products": int(sum(s[3] for s in stats)),
-            "rel_res_last": stats[-1][4], "bytes_per_value": es, "roofline": roof, "phases": phases}
+            "rel_res_last": stats[-1][4], "bytes_per_value": es, "quality": quality, "roofline": roof, "phases": phases}
 
 
 def main():
@@ -174,12 +237,16 @@ def main():
         out["speedup_mixed_vs_fp64"] = res["mixed"]["iters_per_s"] / res["fp64"]["iters_per_s"]
     fp64 = res.get("fp64")
     if not args.no_ttt:
-        t_mixed = time_to_tolerance(svt, W, stream, args.seed, svt.SVT_MIXED)
-        t_fp64 = time_to_tolerance(svt, W, stream, args.seed, svt.SVT_FP64)
+        seeds = [int(x) for x in args.ttt_seeds.split(",") if x.strip()]
+        t_mixed = ttt_seeds(svt, W, stream, seeds, svt.SVT_MIXED)
+        t_fp64 = ttt_seeds(svt, W, stream, seeds, svt.SVT_FP64)
         out["time_to_tol"] = {"workload": "planted 1000x1000 rank 10, 20% observed, tau=5 sqrt(mn), "
                                           "delta=1.2 mn/|Lambda|, tol 1e-4",
                               "mixed": t_mixed, "fp64": t_fp64,
-                              "speedup_mixed_vs_fp64": t_fp64["seconds"] / t_mixed["seconds"]}
+                              "speedup_mixed_vs_fp64_median": t_fp64["median_seconds"] / t_mixed["median_seconds"]}
+    if args.ablation_steps > 0:
+        out["recycling_ablation"] = {"workload": "image 1024x1024 (as above), first iterations from Y^(0), FP64",
+                                     **ablation(svt, w, stream, args.ablation_steps, args.seed)}
     if not args.no_cpu:
         r_mean = (fp64 or head)["r_mean"]
         out["cpu_baseline"] = cpu_baseline(w, int(round(r_mean)), args.seed)
