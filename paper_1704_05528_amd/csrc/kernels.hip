@@ -911,17 +911,22 @@ hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w,
                             int ldo) {
   if (rows == 0 || w == 0) return hipSuccess;
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
-  const unsigned g = (unsigned)((rows + 255) / 256);
+  // one row per thread in 64-thread workgroups: a few hundred rows still occupy many CUs
+  constexpr int kTB = 64;
+  const unsigned g = (unsigned)((rows + kTB - 1) / kTB);
   hipError_t e;
   if (w <= 16) {
     if ((e = set_trsm_attr<16, T>()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_trsm_rows<16, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    hipLaunchKernelGGL((k_trsm_rows<16, T>), dim3(g), dim3(kTB), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+  } else if (w <= 32) {
+    if ((e = set_trsm_attr<32, T>()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_trsm_rows<32, T>), dim3(g), dim3(kTB), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   } else if (w <= 64) {
     if ((e = set_trsm_attr<64, T>()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_trsm_rows<64, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    hipLaunchKernelGGL((k_trsm_rows<64, T>), dim3(g), dim3(kTB), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   } else {
     if ((e = set_trsm_attr<kEigMax, T>()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_trsm_rows<kEigMax, T>), dim3(g), dim3(256), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
+    hipLaunchKernelGGL((k_trsm_rows<kEigMax, T>), dim3(g), dim3(kTB), lds, s, rows, X, ldx, w, R, ldr, out, ldo);
   }
   return hipGetLastError();
 }

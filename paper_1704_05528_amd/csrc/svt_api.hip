@@ -455,7 +455,19 @@ struct Engine {
         prev_k = k;
         if (!done) target = powers + 2;
       }
-      h->eig_pred = std::min(kEigMaxPred, std::max(2, tests == 1 ? powers - 1 : powers));
+      // a failed first test costs a Rayleigh-Ritz step and a readback, far more than one product:
+      // keep the count after a first-test pass, and probe one lower only after four in a row
+      if (tests == 1) {
+        if (++h->eig_pass_streak >= 4) {
+          h->eig_pred = std::max(2, powers - 1);
+          h->eig_pass_streak = 0;
+        } else {
+          h->eig_pred = std::max(2, powers);
+        }
+      } else {
+        h->eig_pred = std::min(kEigMaxPred, powers);
+        h->eig_pass_streak = 0;
+      }
       const int iters = powers + tests;
       st->eig_iters = iters;
       S = h->EV;

@@ -58,6 +58,7 @@ struct Handle {
   int32_t ev_valid = 0;    // columns of EV that hold Ritz vectors of the previous iteration
   int32_t ev_rows = 0;     // basis width those vectors refer to
   int32_t eig_pred = 6;    // products with G before the first Rayleigh-Ritz test (adapted each iteration)
+  int32_t eig_pass_streak = 0;  // consecutive iterations whose first test passed
 
   // factors of X = Ut Vt^T
   void* Ut = nullptr;      // (T) m x kEigMax, Q S_K diag(sigma - tau)

@@ -250,3 +250,31 @@ def test_image_workload_wide_basis_step(gpu_lib):
     h.set_state(y, Q, 0.2, 0.05, 7)
     st = h.iterate(1)
     _compare_step(st, info, h, w, "image")
+
+
+def test_image_workload_bench_configuration(gpu_lib):
+    """The benchmark's own configuration: image workload from Y^(0) with Omega seed 11 through the
+    warm-up into the timed window (45 iterations, basis 51 -> ~300 columns), every step against
+    the oracle (decisions replayed)."""
+    w = W.image()
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=11, maxit=45)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=11, maxit=45)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        _compare_step(h.iterate(1), info, h, w, ("image", info.it))
+
+
+def test_ratings_workload_first_iterations(gpu_lib):
+    """Recommendation shape (6040 x 3706, 900,188 power-law training entries, 4% observed: the
+    gather kernels), tau and delta by the rule of Sec. 3, r_max = 1024: first 6 iterations,
+    including a round of growth blocks, against the oracle."""
+    w = W.ratings()
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=11, maxit=6, r_max=1024)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=11, maxit=6, r_max=1024)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        _compare_step(h.iterate(1), info, h, w, ("ratings", info.it))
