@@ -141,20 +141,47 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
   }
 }
 
-// Wide blocks: lanes over output columns (CPL per lane), nonzeros broadcast across the wave.
-template <int CPL, class T>
+// Wide blocks: lanes over output columns (CPL = 4 per lane), nonzeros broadcast across the wave.
+// Four nonzeros' rows of D are loaded before their products issue; with VEC the four columns of a
+// lane come as one 16-byte (float) or two 16-byte (double) loads (ldd % 4 == 0, D 16-byte aligned).
+template <int CPL, bool VEC, class T>
 __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ vperm, const T* __restrict__ val,
                                                        const T* __restrict__ D, int ldd, T* __restrict__ out, int ldo,
                                                        int w) {
+  static_assert(CPL == 4, "four columns per lane");
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= nrows) return;
   const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
+  const bool vec = VEC && (c0 + CPL <= w);
   T acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = (T)0;
+  auto load4 = [&](int ii, T (&d)[CPL]) {
+    const T* src = D + (int64_t)ii * ldd + c0;
+    if (vec) {
+      if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 v = *reinterpret_cast<const f4*>(src);
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+      } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 v0 = reinterpret_cast<const d2*>(src)[0], v1 = reinterpret_cast<const d2*>(src)[1];
+        d[0] = v0.x;
+        d[1] = v0.y;
+        d[2] = v1.x;
+        d[3] = v1.y;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) d[c] = (c0 + c < w) ? src[c] : (T)0;
+    }
+  };
   const int p0 = ptr[row], p1 = ptr[row + 1];
   for (int base = p0; base < p1; base += kWave) {
     const int p = base + lane;
@@ -165,13 +192,31 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
       my_v = val[vperm ? vperm[p] : p];
     }
     const int cnt = min(kWave, p1 - base);
-    for (int t = 0; t < cnt; ++t) {
-      const int ii = __shfl(my_i, t, kWave);
-      const T vv = __shfl(my_v, t, kWave);
-      const T* d = D + (int64_t)ii * ldd + c0;
+    int t = 0;
+    for (; t + 4 <= cnt; t += 4) {
+      T d0[CPL], d1[CPL], d2[CPL], d3[CPL];
+      const int i0 = __shfl(my_i, t, kWave), i1 = __shfl(my_i, t + 1, kWave);
+      const int i2 = __shfl(my_i, t + 2, kWave), i3 = __shfl(my_i, t + 3, kWave);
+      load4(i0, d0);
+      load4(i1, d1);
+      load4(i2, d2);
+      load4(i3, d3);
+      const T v0 = __shfl(my_v, t, kWave), v1 = __shfl(my_v, t + 1, kWave);
+      const T v2 = __shfl(my_v, t + 2, kWave), v3 = __shfl(my_v, t + 3, kWave);
 #pragma unroll
-      for (int c = 0; c < CPL; ++c)
-        if (c0 + c < w) acc[c] = fma(vv, d[c], acc[c]);
+      for (int c = 0; c < CPL; ++c) {
+        acc[c] = fma(v0, d0[c], acc[c]);
+        acc[c] = fma(v1, d1[c], acc[c]);
+        acc[c] = fma(v2, d2[c], acc[c]);
+        acc[c] = fma(v3, d3[c], acc[c]);
+      }
+    }
+    for (; t < cnt; ++t) {
+      T d0[CPL];
+      load4(__shfl(my_i, t, kWave), d0);
+      const T v0 = __shfl(my_v, t, kWave);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c] = fma(v0, d0[c], acc[c]);
     }
   }
 #pragma unroll
@@ -636,40 +681,91 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict
   for (; q < w; ++q) o[q] = (T)0;
 }
 
+// 16-byte vectors of the storage type and their dot product, element by element in order
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+__device__ inline float dot16(Vec16<float>::type a, Vec16<float>::type b, float x) {
+  x = fmaf(a.x, b.x, x);
+  x = fmaf(a.y, b.y, x);
+  x = fmaf(a.z, b.z, x);
+  return fmaf(a.w, b.w, x);
+}
+__device__ inline double dot16(Vec16<double>::type a, Vec16<double>::type b, double x) {
+  x = fma(a.x, b.x, x);
+  return fma(a.y, b.y, x);
+}
+
 // ------------------------------------------------------------------------------------------
 // Fused sampled product and dual update on Lambda (CSC order), Eq. 4 with X = Ut Vt^T:
-//   x = <Ut[i,:], Vt[j,:]>, res = a - x, y_next = y + delta res, sums of res^2 and y_next^2.
-// One wave per column j; Vt[j, :] staged in LDS.  The dot product and the update run in T;
-// the two sums accumulate in double.
+//   x = <Ut[i,:], Vt[j,:]>, res = a - x, y_next = y + delta res, sums of res^2, y_next^2, |res|.
+// Work comes in chunks of at most kSddmmChunk consecutive CSC positions of one column (the chunk
+// table is built once at set-up), one wave per chunk, so power-law columns do not serialise on
+// one wave.  Vt[j, :] is staged in LDS.  The dot product and the update run in T; the sums
+// accumulate in double.
 // ------------------------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_sddmm_update(int n, const int32_t* __restrict__ colptr,
+__global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t* __restrict__ cstart,
+                                                      const int32_t* __restrict__ ccol,
                                                       const int32_t* __restrict__ rowidx, const T* __restrict__ a,
                                                       const T* __restrict__ y, T* __restrict__ y_next,
                                                       const T* __restrict__ Ut, const T* __restrict__ Vt, int ld,
                                                       int k, T delta, double* __restrict__ partial) {
-  __shared__ T vs[4][kEigMax];
+  using V = typename Vec16<T>::type;  // 16-byte vector of T
+  constexpr int E = Vec16<T>::n;
+  __shared__ __align__(16) T vs[4][kEigMax];
   __shared__ double lds[4];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int j = blockIdx.x * 4 + wid;
+  const int c = blockIdx.x * 4 + wid;
+  const int kv = (k + E - 1) / E;  // 16-byte vectors per factor row (ld is a multiple of E)
   double s_res = 0.0, s_y = 0.0, s_abs = 0.0;
-  if (j < n) {
-    for (int l = lane; l < k; l += kWave) vs[wid][l] = Vt[(int64_t)j * ld + l];
+  int p0 = 0, p1 = 0;
+  if (c < nchunks) {
+    p0 = cstart[c];
+    p1 = cstart[c + 1];
+    const int j = ccol[c];
+    // Vt[j, :k] and zeros up to the vector boundary (the factor buffers are zero-initialised, so
+    // the padded products are exact zeros)
+    for (int l = lane; l < kv * E; l += kWave) vs[wid][l] = (l < k) ? Vt[(int64_t)j * ld + l] : (T)0;
   }
   __syncthreads();
-  if (j < n) {
-    const int p0 = colptr[j], p1 = colptr[j + 1];
-    for (int p = p0 + lane; p < p1; p += kWave) {
-      const T* u = Ut + (int64_t)rowidx[p] * ld;
-      T x = (T)0;
-      for (int l = 0; l < k; ++l) x = fma(u[l], vs[wid][l], x);
-      const T res = a[p] - x;
-      const T yn = fma(delta, res, y[p]);
-      y_next[p] = yn;
-      s_res = fma((double)res, (double)res, s_res);
-      s_y = fma((double)yn, (double)yn, s_y);
-      s_abs += fabs((double)res);
+  const V* vv = reinterpret_cast<const V*>(vs[wid]);
+  auto update = [&](int p, T x) {
+    const T res = a[p] - x;
+    const T yn = fma(delta, res, y[p]);
+    y_next[p] = yn;
+    s_res = fma((double)res, (double)res, s_res);
+    s_y = fma((double)yn, (double)yn, s_y);
+    s_abs += fabs((double)res);
+  };
+  // two entries per lane and step: both factor rows are in flight before the products
+  int p = p0 + lane;
+  for (; p + kWave < p1; p += 2 * kWave) {
+    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p] * ld);
+    const V* u1 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p + kWave] * ld);
+    T x0 = (T)0, x1 = (T)0;
+    for (int l = 0; l < kv; ++l) {
+      const V a0 = u0[l], a1 = u1[l], b = vv[l];
+      x0 = dot16(a0, b, x0);
+      x1 = dot16(a1, b, x1);
     }
+    update(p, x0);
+    update(p + kWave, x1);
+  }
+  if (p < p1) {
+    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p] * ld);
+    T x0 = (T)0;
+    for (int l = 0; l < kv; ++l) x0 = dot16(u0[l], vv[l], x0);
+    update(p, x0);
   }
   const double t0 = block_sum(s_res, lds);
   const double t1 = block_sum(s_y, lds);
@@ -762,8 +858,13 @@ hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const i
   } else {
     constexpr int CPL = 4;
     const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
-    hipLaunchKernelGGL((k_seg_spmm_wide<CPL, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D, ldd,
-                       out, ldo, w);
+    const bool vec = (ldd % CPL == 0) && ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
+    if (vec)
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D,
+                         ldd, out, ldo, w);
+    else
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, false, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val,
+                         D, ldd, out, ldo, w);
   }
   return hipGetLastError();
 }
@@ -932,13 +1033,13 @@ hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w,
 }
 
 template <class T>
-hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* a,
-                               const T* y, T* y_next, const T* Ut, const T* Vt, int ld, int k, double delta,
-                               double* partial, int* nblocks) {
-  const int nb = (n + 3) / 4;
+hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
+                               const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
+                               int ld, int k, double delta, double* partial, int* nblocks) {
+  const int nb = std::max(1, (nchunks + 3) / 4);
   *nblocks = nb;
-  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), 0, s, n, colptr, rowidx, a, y, y_next, Ut, Vt, ld, k,
-                     (T)delta, partial);
+  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), 0, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut,
+                     Vt, ld, k, (T)delta, partial);
   return hipGetLastError();
 }
 
@@ -996,8 +1097,9 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
   template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \
   template hipError_t launch_colnorms<T>(hipStream_t, int, const T*, int, int, double*, double*, int64_t, double*);   \
   template hipError_t launch_trsm_rows<T>(hipStream_t, int, const T*, int, int, const double*, int, T*, int);         \
-  template hipError_t launch_sddmm_update<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, const T*,    \
-                                             T*, const T*, const T*, int, int, double, double*, int*);                \
+  template hipError_t launch_sddmm_update<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*,       \
+                                             const T*, const T*, T*, const T*, const T*, int, int, double, double*,   \
+                                             int*);                                                                   \
   template hipError_t launch_sample<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*, int, \
                                        int, double*);                                                                 \
   template hipError_t launch_scale_copy<T, T>(hipStream_t, int64_t, const T*, double, T*);                            \

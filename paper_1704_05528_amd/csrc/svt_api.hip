@@ -549,8 +549,8 @@ struct Engine {
       const double nnz = (double)h->nnz, k = h->k;
       PhaseTimer tm(h, SVT_PH_SDDMM, nnz * (3.0 * es + 4.0) + 4.0 * (h->n + 1) + es * k * (double)(h->m + h->n),
                     nnz * (2.0 * k + 3.0));
-      HIPCHK(launch_sddmm_update<T>(h->stream, (int)h->n, h->colptr, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
-                                    kEigMax, h->k, h->p.delta, h->partial, &nbl));
+      HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(),
+                                    Vt(), kEigMax, h->k, h->p.delta, h->partial, &nbl));
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
@@ -913,7 +913,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
 }
 
 void release(Handle* h) {
-  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->a, h->y, h->y_next,
+  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->cstart, h->ccol, h->a, h->y,
+                  h->y_next,
                   h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2,
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal};
   for (void* b : bufs)
@@ -1056,11 +1057,21 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     }
   }
 
+  // chunks of at most kSddmmChunk consecutive CSC positions within one column (fused update)
+  std::vector<int32_t> cstart, ccol;
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; q += kSddmmChunk) {
+      cstart.push_back((int32_t)q);
+      ccol.push_back((int32_t)j);
+    }
+  cstart.push_back((int32_t)nnz);
+
   h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
   h->w_cap = 64;
   h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
   h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
   h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
+  h->partial_cap = std::max<int64_t>(h->partial_cap, 3 * ((int64_t)ccol.size() / 4 + 2));  // fused-update sums
   const size_t es = (p.precision == SVT_MIXED) ? sizeof(float) : sizeof(double);
   const size_t mx = (size_t)std::max(m, n);
 
@@ -1102,6 +1113,9 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->partial, (size_t)h->partial_cap));
   A(dalloc(&h->scal, kScalars));
   if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
+  h->nchunks = (int32_t)ccol.size();
+  A(dalloc(&h->cstart, cstart.size()));
+  A(dalloc(&h->ccol, std::max<size_t>(ccol.size(), 1)));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
@@ -1117,7 +1131,13 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   up(h->colidx, colidx.data(), nnz * sizeof(int32_t));
   up(h->csr2csc, csr2csc.data(), nnz * sizeof(int32_t));
   if (!tstart.empty()) up(h->tstart, tstart.data(), tstart.size() * sizeof(int32_t));
+  up(h->cstart, cstart.data(), cstart.size() * sizeof(int32_t));
+  if (!ccol.empty()) up(h->ccol, ccol.data(), ccol.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * es, h->stream);
+  // factor buffers start at zero: the fused update reads whole 16-byte vectors of a factor row and
+  // multiplies the columns beyond k by zeros, which then must be finite
+  if (e == hipSuccess) e = hipMemsetAsync(h->Ut, 0, (size_t)m * kEigMax * es, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->Vt, 0, (size_t)n * kEigMax * es, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     g_init_err = std::string("upload failed: ") + hipGetErrorString(e);

@@ -15,6 +15,7 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
 constexpr int kScalars = 64;  // doubles in the device->host readback buffer
+constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
 // Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
 // marked (T) hold the storage type of the precision form: double (SVT_FP64) or float
@@ -33,6 +34,8 @@ struct Handle {
   int32_t *rowptr = nullptr, *colidx = nullptr;  // CSR
   int32_t *csr2csc = nullptr;                    // CSR position -> CSC position
   int32_t *tstart = nullptr;                     // row-tile starts per column (dense-ish patterns only)
+  int32_t *cstart = nullptr, *ccol = nullptr;    // load-balanced chunks of the CSC order (fused update)
+  int32_t nchunks = 0;
   std::vector<int64_t> user2csc;                 // caller order -> CSC position (host)
 
   // values on Lambda, CSC order (T)
@@ -172,13 +175,14 @@ template <class T>
 hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
                             int ldo);
 
-// sampled product on Lambda (CSC order) with residual and dual update; per-block partial sums of
-// res^2, y_next^2 and |res| land in partial[3 b], partial[3 b + 1], partial[3 b + 2]; *nblocks
-// receives the block count
+// sampled product on Lambda (CSC order) with residual and dual update, one wave per chunk of at
+// most kSddmmChunk positions of one column (chunk c = [cstart[c], cstart[c+1]) in column ccol[c]);
+// per-block partial sums of res^2, y_next^2 and |res| land in partial[3 b], partial[3 b + 1],
+// partial[3 b + 2]; *nblocks receives the block count
 template <class T>
-hipError_t launch_sddmm_update(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* a,
-                               const T* y, T* y_next, const T* Ut, const T* Vt, int ld, int k, double delta,
-                               double* partial, int* nblocks);
+hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
+                               const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
+                               int ld, int k, double delta, double* partial, int* nblocks);
 // scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
 // scal[slot] = sum |ref - x| over len entries (deterministic)

@@ -158,19 +158,44 @@ def _round_bf16(x):
     return f.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _alias_table(w):
+    """Vose's alias method for drawing index i with probability w_i / sum(w) in O(1) per draw."""
+    k = w.size
+    prob = w * (k / w.sum())
+    alias = np.zeros(k, dtype=np.int64)
+    small = [i for i in range(k) if prob[i] < 1.0]
+    large = [i for i in range(k) if prob[i] >= 1.0]
+    prob = prob.tolist()
+    while small and large:
+        s_, l_ = small.pop(), large.pop()
+        alias[s_] = l_
+        prob[l_] = prob[l_] + prob[s_] - 1.0
+        (small if prob[l_] < 1.0 else large).append(l_)
+    for i in small + large:
+        prob[i] = 1.0
+    return np.asarray(prob), alias
+
+
+def _alias_draw(rng, table, size):
+    prob, alias = table
+    i = rng.integers(0, prob.size, size=size)
+    return np.where(rng.random(size) < prob[i], i, alias[i])
+
+
 def large_sparse(m=100_000, n=50_000, rank=20, total=20_000_000, zipf=1.1, noise=0.1, seed=5, tol=1e-3):
     """Large sparse: planted rank-20 Gaussian factors plus N(0, noise^2), Chung-Lu pattern with
     power-law row/column weights, exactly `total` unique entries, values rounded to BF16."""
     rng = np.random.default_rng(seed)
     wr = (np.arange(1, m + 1, dtype=np.float64) ** -zipf)[rng.permutation(m)]
     wc = (np.arange(1, n + 1, dtype=np.float64) ** -zipf)[rng.permutation(n)]
-    pr, pc = wr / wr.sum(), wc / wc.sum()
+    tr, tc = _alias_table(wr), _alias_table(wc)
     lin = np.empty(0, dtype=np.int64)
     while lin.size < total:
-        need = int((total - lin.size) * 1.3) + 1000
-        r = rng.choice(m, size=need, p=pr)
-        c = rng.choice(n, size=need, p=pc)
-        lin = np.unique(np.concatenate([lin, r.astype(np.int64) * n + c]))
+        # heavy rows and columns saturate, so late draws are mostly repeats: draw in large batches
+        need = int((total - lin.size) * 1.3) + total // 4
+        r = _alias_draw(rng, tr, need)       # row i with probability wr_i / sum wr (Chung-Lu)
+        c = _alias_draw(rng, tc, need)
+        lin = np.unique(np.concatenate([lin, r * n + c]))
     lin = np.sort(rng.choice(lin, size=total, replace=False))
     rows, cols = (lin // n).astype(np.int32), (lin % n).astype(np.int32)
     M = rng.standard_normal((m, rank))
