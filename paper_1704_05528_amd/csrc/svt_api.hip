@@ -344,7 +344,7 @@ struct Engine {
       // predicted number of products is done.  The prediction is the count the previous SVT
       // iteration needed, lowered by one when its first test already passed.
       const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
-      int b = std::min(std::min(h->b_cap, r), std::max(16, ((2 * std::max(h->k, 4) + 8 + 7) / 8) * 8));
+      int b = std::min(std::min(h->b_cap, r), std::max(12, 2 * std::max(h->k, 4) + 4));
       int valid = warm ? std::max(0, std::min(h->ev_valid, b - 4)) : 0;
       {
         PhaseTimer tm(h, SVT_PH_EIG);
@@ -359,7 +359,7 @@ struct Engine {
       }
       // truncated recycling keeps the k + e leading Ritz vectors, which then must converge too
       const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
-      bool done = false, have_gv = false;
+      bool done = false, have_gv = false, have_g2 = false;
       int powers = 0, tests = 0, prev_k = -1;
       int target = std::max(2, h->eig_pred);
       while (!done) {
@@ -372,20 +372,31 @@ struct Engine {
           while (powers < target) {
             const int step = (target - powers >= 2) ? 2 : 1;
             const bool last = powers + step >= target;
-            // Z = G^step V (a product left by the previous Rayleigh-Ritz step counts as the first)
+            // Z = G^step V.  A product G V left by the previous Rayleigh-Ritz step counts as the first;
+            // otherwise a double step is one product with G^2, formed once per SVT iteration (the
+            // subspace iteration only needs the dominant invariant subspace, which G^2 shares).
             const double* z = nullptr;
             if (have_gv) {
               z = h->EZ3;
               have_gv = false;
+              if (step == 2) {
+                HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEigMax, h->EZ, kEigMax, b,
+                                                              1.0, 0.0)));
+                z = h->EZ;
+              }
+            } else if (step == 2) {
+              if (!have_g2) {
+                HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap,
+                                                              r, 1.0, 0.0)));
+                have_g2 = true;
+              }
+              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G2, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
+                                                            1.0, 0.0)));
+              z = h->EZ;
             } else {
               HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
                                                             1.0, 0.0)));
               z = h->EZ3;
-            }
-            if (step == 2) {
-              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEigMax, h->EZ, kEigMax, b,
-                                                            1.0, 0.0)));
-              z = h->EZ;
             }
             if (last) {
               CHK(chol_orth(r, z, h->EZ2, kEigMax, b));
@@ -915,7 +926,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
 void release(Handle* h) {
   void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->cstart, h->ccol, h->a, h->y,
                   h->y_next,
-                  h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->small, h->Minv, h->prenorm, h->EV, h->EZ, h->EZ2,
+                  h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->G2, h->small, h->Minv, h->prenorm, h->EV, h->EZ,
+                  h->EZ2,
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -1097,6 +1109,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc_bytes(&h->Utmp, mx * kEigMax * es));
   A(dalloc(&h->T, (size_t)h->r_cap * h->w_cap));
   A(dalloc(&h->G, (size_t)h->r_cap * h->r_cap));
+  A(dalloc(&h->G2, (size_t)h->r_cap * h->r_cap));
   A(dalloc(&h->small, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->Minv, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->prenorm, kEigMax));

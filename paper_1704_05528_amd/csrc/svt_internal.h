@@ -50,6 +50,7 @@ struct Handle {
   // double
   double* T = nullptr;        // r_cap x w_cap projection coefficients Q^T X
   double* G = nullptr;        // r_cap x r_cap Gram W^T W
+  double* G2 = nullptr;       // r_cap x r_cap, G^2 for the double steps of the block eigensolver
   double* small = nullptr;    // kEigMax x kEigMax block Gram
   double* Minv = nullptr;     // kEigMax x kEigMax block Cholesky factor
   double* prenorm = nullptr;  // column norms before projection
