@@ -176,7 +176,10 @@ def run_form(svt, w, stream, args, precision, **extra):
     # Roofline of the dominant single-kernel phase.  Its bound is the resource whose peak time for
     # the phase's algorithmic work is larger: HBM bytes, or flops on the unit the kernel uses (FP64
     # matrix cores for the Gram; plain FP32 or FP64 vector FMA for the sparse products).
-    compute_unit = {"spmm_t": "alu", "sddmm": "alu", "gram": "mfma"}
+    # W = Y^T Q runs on the matrix cores with a dense copy of Y when at least a quarter of the
+    # entries are observed (the library's rule), else on the vector units
+    dense_y = 4 * w.nnz >= w.m * w.n
+    compute_unit = {"spmm_t": "mfma" if dense_y else "alu", "sddmm": "alu", "gram": "mfma"}
     alu_peak = FP32_PEAK_TFS if precision else FP64_PEAK_TFS
     dom = max(compute_unit, key=lambda ph: prof[ph]["ms"])
     pd = prof[dom]

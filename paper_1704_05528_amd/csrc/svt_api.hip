@@ -181,8 +181,14 @@ struct Engine {
     return SVT_OK;
   }
 
-  // out = Y^T D (CSC order)
+  // out = Y^T D: a matrix-core product with the dense copy of Y when at least a quarter of the
+  // entries are observed and D has 32 columns or more (the copy is refreshed at the start of
+  // every R4SVD call), else the CSC gather kernel
   svt_status spmm_yt(const T* D, int ldd, T* out, int ldo, int w) {
+    if (h->yT && w >= 32) {  // narrow blocks stay on the sparse kernel (too few output tiles)
+      HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo));
+      return SVT_OK;
+    }
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w));
     return SVT_OK;
   }
@@ -238,6 +244,10 @@ struct Engine {
   // ----------------------------------------------------------------------------------------
   svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
     double normB = 0.0;
+    if (h->yT) {
+      PhaseTimer tm(h, SVT_PH_SPMM_T, (double)h->nnz * (2.0 * es + 4.0) + 4.0 * (h->n + 1));
+      HIPCHK(launch_scatter_dense_t<T>(h->stream, (int)h->n, h->colptr, h->rowidx, y(), (T*)h->yT, h->m));
+    }
     if (h->r == 0) {
       int got = 0;
       double add = 0.0;
@@ -250,7 +260,9 @@ struct Engine {
         const double r = h->r, nnz = (double)h->nnz;
         PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * (es + 4.0) + 4.0 * (h->n + 1) + es * r * (double)(h->m + h->n),
                       2.0 * nnz * r);
-        if (h->tstart) {
+        if (h->yT && h->r >= 32) {
+          CHK(spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r));
+        } else if (h->tstart) {
           HIPCHK(launch_spmm_t_tiled<T>(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, y(), Q(), h->r_cap,
                                         h->r, W(), h->r_cap, h->partial, h->partial_cap));
         } else {
@@ -924,7 +936,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
 }
 
 void release(Handle* h) {
-  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->cstart, h->ccol, h->a, h->y,
+  void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->cstart, h->ccol, h->yT, h->a,
+                  h->y,
                   h->y_next,
                   h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->G2, h->small, h->Minv, h->prenorm, h->EV, h->EZ,
                   h->EZ2,
@@ -1055,9 +1068,12 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
 
   // Row-tile starts for the LDS-tiled Y^T Q when most tiles hold observed entries (at least 5% of
   // the entries observed); very sparse patterns use the gather kernel instead.
+  // dense transposed copy of Y for the matrix-core products when at least a quarter of the
+  // entries are observed (it then costs at most four times the values on Lambda)
+  const bool dense_y = 4 * nnz >= m * n && m * n <= ((int64_t)1 << 28);
   const int ntiles = tiled_row_tiles(m);
   std::vector<int32_t> tstart;
-  if ((double)nnz >= 0.05 * (double)m * (double)n && (int64_t)n * (ntiles + 1) <= ((int64_t)1 << 26)) {
+  if (!dense_y && (double)nnz >= 0.05 * (double)m * (double)n && (int64_t)n * (ntiles + 1) <= ((int64_t)1 << 26)) {
     tstart.resize((size_t)n * (ntiles + 1));
     for (int64_t j = 0; j < n; ++j) {
       int32_t pp = colptr[j];
@@ -1126,6 +1142,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->partial, (size_t)h->partial_cap));
   A(dalloc(&h->scal, kScalars));
   if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
+  if (dense_y) A(dalloc_bytes(&h->yT, (size_t)m * n * es));
   h->nchunks = (int32_t)ccol.size();
   A(dalloc(&h->cstart, cstart.size()));
   A(dalloc(&h->ccol, std::max<size_t>(ccol.size(), 1)));
@@ -1147,6 +1164,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   up(h->cstart, cstart.data(), cstart.size() * sizeof(int32_t));
   if (!ccol.empty()) up(h->ccol, ccol.data(), ccol.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * es, h->stream);
+  if (e == hipSuccess && h->yT) e = hipMemsetAsync(h->yT, 0, (size_t)m * n * es, h->stream);
   // factor buffers start at zero: the fused update reads whole 16-byte vectors of a factor row and
   // multiplies the columns beyond k by zeros, which then must be finite
   if (e == hipSuccess) e = hipMemsetAsync(h->Ut, 0, (size_t)m * kEigMax * es, h->stream);

@@ -35,6 +35,7 @@ struct Handle {
   int32_t *csr2csc = nullptr;                    // CSR position -> CSC position
   int32_t *tstart = nullptr;                     // row-tile starts per column (dense-ish patterns only)
   int32_t *cstart = nullptr, *ccol = nullptr;    // load-balanced chunks of the CSC order (fused update)
+  void* yT = nullptr;  // (T) n x m dense transposed copy of Y (zeros off Lambda) when >= 25% is observed
   int32_t nchunks = 0;
   std::vector<int64_t> user2csc;                 // caller order -> CSC position (host)
 
@@ -144,6 +145,13 @@ template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
                             double* out, int ldo, double* partial, int64_t partial_cap);
 
+// dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation)
+template <class T>
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc);
+// yT[j * ldy + i] = y(i, j) on Lambda (the other entries of yT are left untouched)
+template <class T>
+hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* y, T* yT,
+                                  int64_t ldy);
 // Gram G = A^T A in double for A rows x na (na up to r_cap), full symmetric output
 template <class T>
 hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
