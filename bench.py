@@ -8,10 +8,11 @@ workload: a 1024 x 1024 matrix of 40 separable smooth patterns plus noise,
 Inputs are synthetic and seeded; they are resident on the GPU before timing.
 
 Prints one JSON line with:
-  * iterations/s over the timed steps for the float32-storage form (the value)
-    and the FP64 form, with per-phase device time from hipEvents recorded on
-    the library's stream;
-  * the roofline of the dominant single-kernel phase;
+  * iterations/s over the timed steps (one library call) for the float32-storage
+    form (the value) and the FP64 form;
+  * the roofline of the dominant single-kernel phase, from hipEvents recorded on
+    the library's stream around those phases inside the timed region;
+  * a per-phase breakdown of every phase over the following iterations (untimed);
   * the sample MAE and the MAE of Eq. 15 over all pixels (0..255 scale);
   * the time to relative residual 1e-4 on the planted 1000 x 1000 rank-10
     problem for five Omega seeds (median and range), both forms;
@@ -34,6 +35,8 @@ FP64_PEAK_TFS = 78.6    # FP64 vector FMA and FP64 matrix cores (dense)
 FP32_PEAK_TFS = 157.3   # FP32 vector FMA
 
 METRIC = "SVT iters/sec + time-to-rel-residual 1e-4 (BF16/FP32 form vs FP64 plain)"
+# single-kernel phases whose device time is recorded inside the timed region
+ROOF_PHASES = ["spmm_t", "gram", "sddmm", "densify"]
 
 
 def parse():
@@ -53,6 +56,8 @@ def parse():
                          "r_max 4096, timed for a few iterations per form")
     ap.add_argument("--ablation-steps", type=int, default=30,
                     help="SVT iterations per operator variant in the recycling ablation (0 skips it)")
+    ap.add_argument("--breakdown-steps", type=int, default=10,
+                    help="iterations after the timed ones with every phase timed (per-phase breakdown)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size reference kernel for "
                          "hardware traffic counters)")
@@ -125,15 +130,13 @@ def ablation(svt, w, stream, steps, seed):
     for name, kw in variants:
         h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, stream=stream, tau=w.tau, delta=w.delta, seed=seed,
                          maxit=steps + 1, tol=0.0, precision=svt.SVT_FP64, **kw)
-        rs, blocks = [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            st = h.iterate(1)
-            rs.append(st.r)
-            blocks += st.blocks
+        st = h.iterate(steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        hist = h.history()
+        rs, blocks = [x.r for x in hist], sum(x.blocks for x in hist)
         out[name] = {"iterations": steps, "seconds": el, "ms_per_iter": 1e3 * el / steps, "r_mean": sum(rs) / steps,
                      "r_last": rs[-1], "growth_blocks": blocks, "rel_res_last": st.rel_res, "mae_last": st.mae}
         h.close()
@@ -144,22 +147,29 @@ def run_form(svt, w, stream, args, precision, **extra):
     """Warm up, then time args.steps SVT iterations of one precision form with per-phase events."""
     import torch
     h = svt.svt_init(w.m, w.n, w.rows, w.cols, w.a, stream=stream, tau=w.tau, delta=w.delta, seed=args.seed,
-                     maxit=args.warmup + args.steps + 1000, precision=precision, **extra)
+                     maxit=args.warmup + args.steps + args.breakdown_steps + 1000, precision=precision, **extra)
     if args.warmup > 0:
         h.iterate(args.warmup)
     torch.cuda.synchronize()
-    h.profile(True)
-    stats = []
+    # Timed region: hipEvents only around the single-kernel phases that compete for the roofline
+    # (each event is a marker the GPU processes between kernels, so timing every phase would
+    # slow the iteration being measured).
+    h.profile(True, phases=ROOF_PHASES)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = h.iterate(1)
-        stats.append((st.r, st.k, st.blocks, st.eig_iters, st.rel_res, st.mae))
-        if st.stopped:
-            break
+    h.iterate(args.steps)  # one library call; it stops early only at convergence
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    stats = [(st.r, st.k, st.blocks, st.eig_iters, st.rel_res, st.mae) for st in h.history(first=args.warmup)]
     prof = h.profile_read()
+    # Per-phase breakdown of every phase over the next few iterations (not timed).
+    breakdown, n_bd = {}, 0
+    if args.breakdown_steps > 0 and not h.history()[-1].stopped:
+        h.profile(True)
+        n0 = len(h.history())
+        h.iterate(args.breakdown_steps)
+        breakdown = h.profile_read()
+        n_bd = len(h.history()) - n0
     h.profile(False)
     if w.A is not None:
         # recovery quality after the timed steps on the 0..255 scale of the paper's images (Sec. 3):
@@ -174,17 +184,19 @@ def run_form(svt, w, stream, args, precision, **extra):
     r_vals = [s[0] for s in stats]
     es = 4.0 if precision else 8.0
     # Roofline of the dominant single-kernel phase.  Its bound is the resource whose peak time for
-    # the phase's algorithmic work is larger: HBM bytes, or flops on the unit the kernel uses (FP64
-    # matrix cores for the Gram; plain FP32 or FP64 vector FMA for the sparse products).
-    # W = Y^T Q runs on the matrix cores with a dense copy of Y when at least a quarter of the
-    # entries are observed (the library's rule), else on the vector units
+    # the phase's algorithmic work is larger: HBM bytes, or flops on the unit the kernel uses.  The
+    # Gram runs on the FP64 matrix cores in both forms.  W = Y^T Q runs on the matrix cores in the
+    # storage precision (FP32 in the mixed form, FP64 in the FP64 form) with a dense copy of Y when
+    # at least a quarter of the entries are observed (the library's rule), else on the vector units;
+    # its algorithmic flops are 2 nnz r either way.  The scatter that refreshes the dense copy is a
+    # phase of its own (pure data movement).
     dense_y = 4 * w.nnz >= w.m * w.n
-    compute_unit = {"spmm_t": "mfma" if dense_y else "alu", "sddmm": "alu", "gram": "mfma"}
-    alu_peak = FP32_PEAK_TFS if precision else FP64_PEAK_TFS
-    dom = max(compute_unit, key=lambda ph: prof[ph]["ms"])
+    store_peak = FP32_PEAK_TFS if precision else FP64_PEAK_TFS
+    units = {"spmm_t": ("mfma" if dense_y else "alu", store_peak), "sddmm": ("alu", store_peak),
+             "gram": ("mfma", FP64_PEAK_TFS), "densify": ("alu", store_peak)}
+    dom = max(units, key=lambda ph: prof[ph]["ms"])
     pd = prof[dom]
-    unit = compute_unit[dom]
-    cpeak = FP64_PEAK_TFS if unit == "mfma" else alu_peak
+    unit, cpeak = units[dom]
     t_hbm = pd["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_cmp = pd["flops"] / (cpeak * 1e12)
     if t_hbm >= t_cmp:
@@ -198,15 +210,19 @@ def run_form(svt, w, stream, args, precision, **extra):
     roof.update({"kernel": dom, "launches": pd["launches"], "avg_launch_us": 1e3 * pd["ms"] / max(pd["launches"], 1),
                  "bytes_per_launch": pd["bytes"] / max(pd["launches"], 1),
                  "flops_per_launch": pd["flops"] / max(pd["launches"], 1)})
-    phases = {ph: {"ms_per_step": v["ms"] / max(n_it, 1), "launches": v["launches"],
+    phases = {ph: {"ms_per_step": v["ms"] / max(n_bd, 1), "launches": v["launches"],
                    "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None,
                    "TFLOP_s": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
-              for ph, v in prof.items()}
+              for ph, v in breakdown.items()}
+    timed_phases = {ph: {"ms_per_step": prof[ph]["ms"] / max(n_it, 1), "launches": prof[ph]["launches"]}
+                    for ph in ROOF_PHASES}
     return {"iters_per_s": n_it / el, "ms_per_step": 1e3 * el / max(n_it, 1), "steps": n_it,
             "iterations_timed": [args.warmup + 1, args.warmup + n_it], "r_range": [min(r_vals), max(r_vals)],
             "r_mean": float(sum(r_vals) / len(r_vals)), "k_last": stats[-1][1],
             "growth_blocks": int(sum(s[2] for s in stats)), "eig_products": int(sum(s[3] for s in stats)),
-            "rel_res_last": stats[-1][4], "bytes_per_value": es, "quality": quality, "roofline": roof, "phases": phases}
+            "rel_res_last": stats[-1][4], "bytes_per_value": es, "quality": quality, "roofline": roof,
+            "timed_phases": timed_phases, "phases": phases,
+            "phases_iterations": [args.warmup + n_it + 1, args.warmup + n_it + n_bd]}
 
 
 def main():

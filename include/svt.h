@@ -155,6 +155,13 @@ svt_status r4svd_step(svt_handle* h, svt_step_stats* st);
  * Returns SVT_E_STATE if the run had already converged. */
 svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last);
 
+/* Reports of the iterations run by svt_iterate on this handle, oldest first (iteration i of the
+ * run is record i - 1; replacing the state with svt_set_state does not clear them).  *total
+ * (may be NULL) receives the number of records; out[0 .. count) receives records first ..
+ * first + count - 1 that exist.  Host memory only; no device work.
+ * Errors: SVT_E_INVALID_ARG (first < 0, count < 0, out == NULL with count > 0). */
+svt_status svt_history(const svt_handle* h, int64_t first, int64_t count, svt_step_stats* out, int64_t* total);
+
 /* Thresholded factors of the last X = U diag(s) V^T (s = sigma - tau > 0):
  * k receives their count; U (m x kcap), V (n x kcap) row-major and s (kcap)
  * receive min(k, kcap) columns.  Any output pointer may be NULL. */
@@ -209,19 +216,26 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
 /* Instrumentation.  Phases of one iteration whose device time can be measured with hipEvents
  * recorded on the handle's stream around the launches of that phase. */
 enum {
-  SVT_PH_SPMM_T = 0,  /* W = Y^T Q on the recycled basis (one sparse-times-dense kernel) */
+  SVT_PH_SPMM_T = 0,  /* W = Y^T Q on the recycled basis (one kernel: sparse, or dense on the copy of Y) */
   SVT_PH_GROW = 1,    /* growth blocks: Omega, Y Omega, projections, CholeskyQR2, Y^T Q' */
   SVT_PH_GRAM = 2,    /* G = W^T W */
   SVT_PH_EIG = 3,     /* eigenpairs of G above tau^2 (Jacobi / block subspace iteration) */
   SVT_PH_FACTORS = 4, /* Ut = Q C, Vt = W D */
   SVT_PH_SDDMM = 5,   /* fused sampled product, residual and dual update (one kernel) */
   SVT_PH_REDUCE = 6,  /* norms and their deterministic final sums */
-  SVT_PH_COUNT = 7
+  SVT_PH_DENSIFY = 7, /* scatter of y into the dense transposed copy of Y (dense path only) */
+  SVT_PH_COUNT = 8
 };
 
-/* enable = 1 resets the counters and starts recording; enable = 0 stops.  Recording adds two
- * hipEventRecord calls per measured launch. */
+/* enable = 1 resets the counters and starts recording every phase; enable = 0 stops.  Recording
+ * adds two hipEventRecord calls per measured phase instance, each a marker the GPU processes
+ * between kernels (a few microseconds): record only the phases of interest with
+ * svt_profile_phases when the iteration rate is measured at the same time. */
 svt_status svt_profile(svt_handle* h, int32_t enable);
+
+/* Reset the counters and record only the phases whose bit (1u << SVT_PH_*) is set in mask;
+ * mask = 0 stops recording.  Errors: SVT_E_INVALID_ARG (bits above SVT_PH_COUNT). */
+svt_status svt_profile_phases(svt_handle* h, uint32_t mask);
 
 /* Per phase (arrays of SVT_PH_COUNT entries, any may be NULL): device milliseconds, algorithmic
  * bytes moved (each operand counted once per launch), algorithmic flops, number of launches. */

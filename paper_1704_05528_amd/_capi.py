@@ -14,10 +14,10 @@ _STATUS = {0: "SVT_OK", -1: "SVT_E_INVALID_ARG", -2: "SVT_E_OOM", -3: "SVT_E_HIP
            -5: "SVT_E_STATE", -6: "SVT_E_LIMIT"}
 
 # Names of every symbol include/svt.h declares (checked by the CPU tests).
-EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample", "svt_mae",
-           "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_read",
-           "svt_last_error", "svt_destroy"]
-PHASES = ["spmm_t", "grow", "gram", "eig", "factors", "sddmm", "reduce"]
+EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample",
+           "svt_mae", "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile",
+           "svt_profile_phases", "svt_profile_read", "svt_last_error", "svt_destroy"]
+PHASES = ["spmm_t", "grow", "gram", "eig", "factors", "sddmm", "reduce", "densify"]
 
 
 class SVTError(RuntimeError):
@@ -73,6 +73,7 @@ def load():
     L.svt_init.argtypes = [_P(_vp), C.c_int64, C.c_int64, C.c_int64, _i32p, _i32p, _f64p, _P(Params), _vp]
     L.r4svd_step.argtypes = [_vp, _P(StepStats)]
     L.svt_iterate.argtypes = [_vp, C.c_int32, _P(StepStats)]
+    L.svt_history.argtypes = [_vp, C.c_int64, C.c_int64, _P(StepStats), _P(C.c_int64)]
     L.svt_factors.argtypes = [_vp, C.c_int32, _i32p, _f64p, _f64p, _f64p]
     L.svt_sample.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p]
     L.svt_mae.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p, _f64p]
@@ -81,13 +82,15 @@ def load():
     L.svt_set_replay.argtypes = [_vp, _i32p, _i32p, C.c_int32]
     L.svt_grad.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
     L.svt_profile.argtypes = [_vp, C.c_int32]
+    L.svt_profile_phases.argtypes = [_vp, C.c_uint32]
     L.svt_profile_read.argtypes = [_vp, _f64p, _f64p, _f64p, _P(C.c_int64)]
     L.svt_last_error.argtypes = [_vp]
     L.svt_last_error.restype = C.c_char_p
     L.svt_destroy.argtypes = [_vp]
     L.svt_destroy.restype = None
-    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_factors", "svt_sample", "svt_mae", "svt_get_state",
-                 "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_read"]:
+    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample", "svt_mae", "svt_get_state",
+                 "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_phases",
+                 "svt_profile_read"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

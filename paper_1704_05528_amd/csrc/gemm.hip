@@ -1,0 +1,190 @@
+// Dense products on the matrix cores for the dense path of W = Y^T Q: when at least a quarter
+// of the entries are observed, Y is kept as a dense transposed copy (zeros off Lambda) and
+// Y^T Q becomes a plain dense product.  W is the transpose of the projection B of the sampled
+// basis (Alg. 1, Sec. 2.1), formed on the SVT iterate in Alg. 2-4.
+#include "svt_internal.h"
+
+namespace svt {
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// C = A B (row-major; A M x K, B K x N) in the storage precision: v_mfma_f32_16x16x4f32 for
+// float (float accumulation), v_mfma_f64_16x16x4f64 for double.  Both take the A operand as
+// A[l % 16][l / 16] and the B operand as B[l / 16][l % 16] in lane l; the f32 result holds rows
+// 4 (l / 16) + v, the f64 result rows (l / 16) + 4 v, v = 0..3, of column l % 16.
+//
+// A workgroup owns one 64 x 32 tile of C and is KG groups of four waves; group g takes the
+// 32-wide K chunks g, g + KG, g + 2 KG, ... (each wave 16 rows x 32 columns, two matrix
+// instructions per k-step sharing the A operand), staging its chunk in its own LDS area and
+// loading its next chunk into registers while the current one is consumed.  The groups'
+// accumulators are added in group order at the end (deterministic).  Splitting K inside the
+// workgroup keeps KG times more loads in flight per tile than one group alone: at the sizes of
+// the basis (a few hundred columns) there are fewer tiles than compute units, and one group
+// per tile would leave every CU waiting on memory latency.
+//
+// Tiles are numbered row-block major and dealt to the eight XCDs in contiguous ranges (the
+// hardware deals consecutive workgroups round-robin over the XCDs), so the workgroups that
+// share a row block of A share one L2.
+// ------------------------------------------------------------------------------------------
+constexpr int kGM = 64, kGN = 32, kGK = 32;
+constexpr int kXcd = 8;
+
+template <class T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <>
+struct Mfma16<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// K groups per workgroup: 4 for float (1024 threads), 2 for double (512 threads); about 50 KB of
+// LDS either way
+template <class T>
+constexpr int gemm_kgroups() {
+  return sizeof(T) == 4 ? 4 : 2;
+}
+
+// Tile of workgroup id when `total` tiles are dealt round-robin over the XCDs: XCD x receives the
+// contiguous range of tiles starting at x * (total / 8) + min(x, total % 8).
+__device__ inline int xcd_tile(int id, int total) {
+  const int x = id % kXcd, slot = id / kXcd, per = total / kXcd, rem = total % kXcd;
+  return x * per + min(x, rem) + slot;
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A, int lda,
+                                                  const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
+                                                  int tiles_n) {
+  using MM = Mfma16<T>;
+  constexpr int KG = gemm_kgroups<T>();
+  constexpr int kAS = kGM * (kGK + 1), kBS = kGK * (kGN + 1);
+  static_assert((KG - 1) * 8 * 256 <= KG * (kAS + kBS), "the reduction area must fit in the staging area");
+  __shared__ T smem[KG * (kAS + kBS)];
+  const int tid = threadIdx.x & 255, kg = threadIdx.x >> 8, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int m0 = (tile / tiles_n) * kGM, n0 = (tile % tiles_n) * kGN;
+  T* As = smem + kg * (kAS + kBS);  // [kGM][kGK + 1]
+  T* Bs = As + kAS;                  // [kGK][kGN + 1]
+  // global -> register staging: A chunk 64 x 32 (8 per thread), B chunk 32 x 32 (4 per thread)
+  T ra[8], rb[4];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + u * 256, i = e / kGK, kk = e % kGK;
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[u] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + u * 256, kk = e / kGN, j = e % kGN;
+      const int gk = k0 + kk, gj = n0 + j;
+      rb[u] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : (T)0;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + u * 256;
+      As[(e / kGK) * (kGK + 1) + e % kGK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + u * 256;
+      Bs[(e / kGN) * (kGN + 1) + e % kGN] = rb[u];
+    }
+  };
+  typename MM::acc_t acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) acc[t] = typename MM::acc_t{0, 0, 0, 0};
+  const int ar = wv * 16 + (lane & 15), kl = lane >> 4, bc = lane & 15;
+  const int nchunk = (K + kGK - 1) / kGK, rounds = (nchunk + KG - 1) / KG;
+  int c = kg;
+  if (c < nchunk) load_chunk(c * kGK);
+  for (int rd = 0; rd < rounds; ++rd, c += KG) {  // rounds is uniform over the workgroup
+    __syncthreads();  // the previous chunk has been consumed
+    if (c < nchunk) store_chunk();
+    __syncthreads();
+    if (c + KG < nchunk) load_chunk((c + KG) * kGK);
+    if (c < nchunk) {
+#pragma unroll
+      for (int ks = 0; ks < kGK / 4; ++ks) {
+        const T a = As[ar * (kGK + 1) + ks * 4 + kl];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t] = MM::mma(a, Bs[(ks * 4 + kl) * (kGN + 1) + 16 * t + bc], acc[t]);
+      }
+    }
+  }
+  // add the groups' accumulators in group order; the staging area is reused
+  __syncthreads();
+  if (kg > 0) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) smem[((kg - 1) * 8 + t * 4 + v) * 256 + tid] = acc[t][v];
+  }
+  __syncthreads();
+  if (kg > 0) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = m0 + wv * 16 + MM::row(lane, v);
+    if (row >= M) continue;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int col = n0 + 16 * t + bc;
+      T sum = acc[t][v];
+#pragma unroll
+      for (int g = 1; g < KG; ++g) sum += smem[((g - 1) * 8 + t * 4 + v) * 256 + tid];
+      if (col < N) C[(int64_t)row * ldc + col] = sum;
+    }
+  }
+}
+
+// yT[j * ldy + i] = y at CSC position p = (i, j): the dense transposed copy of Y on Lambda (the
+// entries outside Lambda stay zero from set-up); one wave per column
+template <class T>
+__global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* __restrict__ colptr,
+                                                         const int32_t* __restrict__ rowidx, const T* __restrict__ y,
+                                                         T* __restrict__ yT, int64_t ldy) {
+  const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (j >= n) return;
+  for (int p = colptr[j] + lane; p < colptr[j + 1]; p += kWave) yT[(int64_t)j * ldy + rowidx[p]] = y[p];
+}
+
+}  // namespace
+
+template <class T>
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc) {
+  if (M == 0 || N == 0) return hipSuccess;
+  if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
+  const int tm = (M + kGM - 1) / kGM, tn = (N + kGN - 1) / kGN;
+  hipLaunchKernelGGL(k_gemm_nn<T>, dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
+                     tn);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* y, T* yT,
+                                  int64_t ldy) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_dense_t<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, colptr, rowidx, y, yT, ldy);
+  return hipGetLastError();
+}
+
+#define SVT_GEMM_INST(T)                                                                                       \
+  template hipError_t launch_gemm_nn<T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int);   \
+  template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*, \
+                                                int64_t);
+
+SVT_GEMM_INST(double)
+SVT_GEMM_INST(float)
+
+}  // namespace svt

@@ -395,111 +395,6 @@ __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __res
 }
 
 // ------------------------------------------------------------------------------------------
-// Dense C = A B (row-major; A M x K, B K x N) on the matrix cores in the storage precision:
-// v_mfma_f32_16x16x4f32 for float (float accumulation), v_mfma_f64_16x16x4f64 for double.
-// Both take the A operand as A[l % 16][l / 16] and the B operand as B[l / 16][l % 16] in lane l;
-// the f32 result holds rows 4 (l / 16) + v, the f64 result rows (l / 16) + 4 v, v = 0..3, of
-// column l % 16.  A workgroup computes a 64 x 32 tile (each wave 16 rows x 32 columns, two
-// matrix instructions per k-step sharing the A operand); K advances in chunks of 32 staged in
-// LDS, the next chunk being loaded into registers while the current one is consumed.  Used for
-// W = Y^T Q (and the growth blocks' Y^T Q') on a dense copy of Y when most entries are observed.
-// ------------------------------------------------------------------------------------------
-constexpr int kGM = 64, kGN = 32, kGK = 32;
-
-template <class T>
-struct Mfma16;
-template <>
-struct Mfma16<float> {
-  typedef float acc_t __attribute__((ext_vector_type(4)));
-  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-template <>
-struct Mfma16<double> {
-  typedef double acc_t __attribute__((ext_vector_type(4)));
-  __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-
-template <class T>
-__global__ __launch_bounds__(256) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A, int lda,
-                                                 const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc) {
-  using MM = Mfma16<T>;
-  __shared__ T As[kGM][kGK + 1];
-  __shared__ T Bs[kGK][kGN + 1];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int m0 = blockIdx.x * kGM, n0 = blockIdx.y * kGN;
-  // global -> register staging: A chunk 64 x 32 (8 per thread), B chunk 32 x 32 (4 per thread)
-  T ra[8], rb[4];
-  auto load_chunk = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = tid + u * 256, i = e / kGK, kk = e % kGK;
-      const int gi = m0 + i, gk = k0 + kk;
-      ra[u] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + u * 256, kk = e / kGN, j = e % kGN;
-      const int gk = k0 + kk, gj = n0 + j;
-      rb[u] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : (T)0;
-    }
-  };
-  auto store_chunk = [&]() {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = tid + u * 256;
-      As[e / kGK][e % kGK] = ra[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + u * 256;
-      Bs[e / kGN][e % kGN] = rb[u];
-    }
-  };
-  // each wave: 16 rows x 32 columns, two accumulators sharing the A operand
-  typename MM::acc_t acc[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) acc[t] = typename MM::acc_t{0, 0, 0, 0};
-  const int ar = wv * 16 + (lane & 15), kl = lane >> 4, bc = lane & 15;
-  load_chunk(0);
-  for (int k0 = 0; k0 < K; k0 += kGK) {
-    __syncthreads();  // the previous chunk has been consumed
-    store_chunk();
-    __syncthreads();
-    if (k0 + kGK < K) load_chunk(k0 + kGK);
-#pragma unroll
-    for (int ks = 0; ks < kGK / 4; ++ks) {
-      const T a = As[ar][ks * 4 + kl];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) acc[t] = MM::mma(a, Bs[ks * 4 + kl][16 * t + bc], acc[t]);
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = m0 + wv * 16 + MM::row(lane, v);
-    if (row >= M) continue;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = n0 + 16 * t + bc;
-      if (col < N) C[(int64_t)row * ldc + col] = acc[t][v];
-    }
-  }
-}
-
-// yT[j * ldy + i] = y at CSC position p = (i, j): the dense transposed copy of Y on Lambda (the
-// entries outside Lambda stay zero from set-up); one wave per column
-template <class T>
-__global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* __restrict__ colptr,
-                                                         const int32_t* __restrict__ rowidx, const T* __restrict__ y,
-                                                         T* __restrict__ yT, int64_t ldy) {
-  const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (j >= n) return;
-  for (int p = colptr[j] + lane; p < colptr[j + 1]; p += kWave) yT[(int64_t)j * ldy + rowidx[p]] = y[p];
-}
-
-// ------------------------------------------------------------------------------------------
 // Tall-skinny A^T B on the FP64 matrix cores, split over rows: workgroup (x, y, s) computes the
 // 16 x 16 tile (a0, b0) of partial[s] = sum_{i in split s} A[i, :]^T B[i, :]; the four waves take
 // contiguous quarters of the split's rows.  k_tn_finish (or the consumer) adds the splits.
@@ -567,14 +462,18 @@ __global__ void k_tn_finish(const double* __restrict__ partial, int splits, int 
 
 // ------------------------------------------------------------------------------------------
 // Gram G = A^T A (na x na, double) for a tall A on the FP64 matrix cores: one 32 x 32 tile of the
-// upper triangle per workgroup (one 16 x 16 quarter per wave) over all rows, written to both
-// triangles; no partial sums.
+// upper triangle per workgroup, written to both triangles; no partial sums.  The workgroup is
+// four groups of four waves: wave q of a group takes the 16 x 16 quarter q of the tile, group g
+// the g-th contiguous quarter of the rows, and the groups' accumulators are added in group order
+// in LDS (deterministic).  With a few hundred columns there are fewer tiles than compute units;
+// the row split keeps four times more loads in flight per tile.
 // ------------------------------------------------------------------------------------------
 constexpr int kGT = 32;
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
-                                                    double* __restrict__ G, int ldg, int ntile) {
+__global__ __launch_bounds__(1024) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
+                                                     double* __restrict__ G, int ldg, int ntile) {
+  __shared__ double red[3][4][kWave][4];
   // map blockIdx.x to an upper-triangular tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
   while (t >= ntile - ti) {
@@ -582,16 +481,18 @@ __global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restric
     ++ti;
   }
   const int tj = ti + t;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int a0 = ti * kGT + (wv >> 1) * 16, b0 = tj * kGT + (wv & 1) * 16;
+  const int lane = threadIdx.x & (kWave - 1), wq = (threadIdx.x / kWave) & 3, grp = threadIdx.x / (4 * kWave);
+  const int a0 = ti * kGT + (wq >> 1) * 16, b0 = tj * kGT + (wq & 1) * 16;
   const int aa = a0 + (lane & 15), bb = b0 + (lane & 15), kl = lane >> 4;
   const bool aok = aa < na, bok = bb < na;
   const T* acol = A + min(aa, na - 1);
   const T* bcol = A + min(bb, na - 1);
   const int steps = (rows + 3) / 4;
+  const int per = (steps + 3) / 4;
+  const int s0 = grp * per, s1 = min(steps, s0 + per);
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int st = 0;
-  for (; st + kUnroll <= steps; st += kUnroll) {
+  int st = s0;
+  for (; st + kUnroll <= s1; st += kUnroll) {
     double a[kUnroll], b[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -607,19 +508,26 @@ __global__ __launch_bounds__(256) void k_gram_tiles(int rows, const T* __restric
       acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
   }
-  for (; st < steps; ++st) {
+  for (; st < s1; ++st) {
     const int row = st * 4 + kl;
     const int rc = min(row, rows - 1);
     const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * lda];
     acc0 = mfma_f64_16x16x4((row < rows && aok) ? av : 0.0, (row < rows && bok) ? bv : 0.0, acc0);
   }
-  const dbl4 acc = acc0 + acc1;
+  dbl4 acc = acc0 + acc1;
+  if (grp > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[grp - 1][wq][lane][v] = acc[v];
+  }
+  __syncthreads();
+  if (grp > 0) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
+    const double sum = ((acc[v] + red[0][wq][lane][v]) + red[1][wq][lane][v]) + red[2][wq][lane][v];
     const int ra = a0 + (lane >> 4) + 4 * v, cb = b0 + (lane & 15);
     if (ra < na && cb < na) {
-      G[(int64_t)ra * ldg + cb] = acc[v];
-      if (ti != tj) G[(int64_t)cb * ldg + ra] = acc[v];
+      G[(int64_t)ra * ldg + cb] = sum;
+      if (ti != tj) G[(int64_t)cb * ldg + ra] = sum;
     }
   }
 }
@@ -1028,22 +936,6 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
 }
 
 template <class T>
-hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc) {
-  if (M == 0 || N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_nn<T>, dim3((M + kGM - 1) / kGM, (N + kGN - 1) / kGN), dim3(256), 0, s, M, N, K, A, lda, B,
-                     ldb, C, ldc);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* y, T* yT,
-                                  int64_t ldy) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_dense_t<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, colptr, rowidx, y, yT, ldy);
-  return hipGetLastError();
-}
-
-template <class T>
 hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
                        int64_t partial_cap) {
   (void)partial;
@@ -1051,7 +943,7 @@ hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, dou
   if (na == 0) return hipSuccess;
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(256), 0, s, rows, A, lda, na, G, ldg, nt);
+  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(1024), 0, s, rows, A, lda, na, G, ldg, nt);
   return hipGetLastError();
 }
 
@@ -1214,9 +1106,6 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
   template hipError_t launch_tn_partial<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*,      \
                                               int64_t, int*);                                                         \
   template hipError_t launch_gram<T>(hipStream_t, int, const T*, int, int, double*, int, double*, int64_t);           \
-  template hipError_t launch_gemm_nn<T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int);          \
-  template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*,       \
-                                                int64_t);                                                             \
   template hipError_t launch_sumsq_cols<T>(hipStream_t, int, const T*, int, int, int, double*, double*, int);         \
   template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \
   template hipError_t launch_colnorms<T>(hipStream_t, int, const T*, int, int, double*, double*, int64_t, double*);   \

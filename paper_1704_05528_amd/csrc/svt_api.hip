@@ -84,7 +84,7 @@ struct PhaseTimer {
   int ph;
   hipEvent_t e0 = nullptr;
   PhaseTimer(Handle* hh, int phase, double bytes = 0.0, double flops = 0.0) : h(hh), ph(phase) {
-    if (!h->prof) return;
+    if (!((h->prof_mask >> ph) & 1u)) return;
     e0 = pool_event(h);
     if (e0) (void)hipEventRecord(e0, h->stream);
     h->ph_bytes[ph] += bytes;
@@ -92,13 +92,18 @@ struct PhaseTimer {
     h->ph_launch[ph] += 1;
   }
   ~PhaseTimer() {
-    if (!h->prof || !e0) return;
+    if (!e0) return;
     hipEvent_t e1 = pool_event(h);
     if (!e1) return;
     (void)hipEventRecord(e1, h->stream);
     h->pending.push_back({ph, e0, e1});
   }
 };
+
+// Event pairs wait unresolved until svt_profile_read (or until kMaxPending have piled up), so the
+// host does no event queries inside the iteration's synchronisation points.
+constexpr size_t kMaxPending = 4096;
+constexpr size_t kEventPrealloc = 2 * kMaxPending;
 
 void resolve_pending(Handle* h) {
   for (auto& p : h->pending) {
@@ -110,18 +115,43 @@ void resolve_pending(Handle* h) {
   h->pending.clear();
 }
 
+// Wait for the handle's stream at a host decision point.  The iteration waits for a handful of
+// scalars several times per step; a blocking wait would put the thread to sleep and add the
+// wake-up latency to every one of them, so the host spins on a timing-free event instead.
+svt_status wait_stream(Handle* h) {
+  if (!h->sync_ev) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SVT_OK;
+  }
+  HIPCHK(hipEventRecord(h->sync_ev, h->stream));
+  for (;;) {
+    const hipError_t e = hipEventQuery(h->sync_ev);
+    if (e == hipSuccess) return SVT_OK;
+    if (e != hipErrorNotReady) HIPCHK(e);
+  }
+}
+
 svt_status readback(Handle* h, int count) {
   HIPCHK(hipMemcpyAsync(h->hscal, h->scal, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  resolve_pending(h);
+  CHK(wait_stream(h));
+  if (h->pending.size() >= kMaxPending) resolve_pending(h);
   return SVT_OK;
 }
 
+// Device -> host copy and wait.  Small copies go through the pinned staging area: a copy into
+// pageable memory is staged by the runtime and costs far more than the transfer.
 template <class T>
 svt_status to_host(Handle* h, T* dst, const T* src, size_t count) {
-  HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  resolve_pending(h);
+  const size_t bytes = count * sizeof(T);
+  if (h->hstage && bytes <= kStageDoubles * sizeof(double)) {
+    HIPCHK(hipMemcpyAsync(h->hstage, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    CHK(wait_stream(h));
+    std::memcpy(dst, h->hstage, bytes);
+  } else {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (h->pending.size() >= kMaxPending) resolve_pending(h);
   return SVT_OK;
 }
 
@@ -245,7 +275,7 @@ struct Engine {
   svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
     double normB = 0.0;
     if (h->yT) {
-      PhaseTimer tm(h, SVT_PH_SPMM_T, (double)h->nnz * (2.0 * es + 4.0) + 4.0 * (h->n + 1));
+      PhaseTimer tm(h, SVT_PH_DENSIFY, (double)h->nnz * (2.0 * es + 4.0) + 4.0 * (h->n + 1));
       HIPCHK(launch_scatter_dense_t<T>(h->stream, (int)h->n, h->colptr, h->rowidx, y(), (T*)h->yT, h->m));
     }
     if (h->r == 0) {
@@ -945,11 +975,13 @@ void release(Handle* h) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->hstage) (void)hipHostFree(h->hstage);
   for (auto& p : h->pending) {
     h->event_pool.push_back(p.e0);
     h->event_pool.push_back(p.e1);
   }
   for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+  if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
 }
 
 }  // namespace
@@ -1147,6 +1179,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->cstart, cstart.size()));
   A(dalloc(&h->ccol, std::max<size_t>(ccol.size(), 1)));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->hstage, kStageDoubles * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     svt_destroy(h);
@@ -1225,12 +1259,22 @@ svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
       }
       CHK(eng.iteration(&st));
       if (h->iter >= h->p.maxit && !st.stopped) st.flags |= SVT_F_MAXIT;
+      h->history.push_back(st);
       if (st.stopped) break;
     }
     return SVT_OK;
   });
   if (last) *last = st;
   return status;
+}
+
+svt_status svt_history(const svt_handle* h, int64_t first, int64_t count, svt_step_stats* out, int64_t* total) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (first < 0 || count < 0 || (count > 0 && !out)) return SVT_E_INVALID_ARG;
+  const int64_t n = (int64_t)h->history.size();
+  if (total) *total = n;
+  for (int64_t i = 0; i < count && first + i < n; ++i) out[i] = h->history[(size_t)(first + i)];
+  return SVT_OK;
 }
 
 svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V) {
@@ -1353,18 +1397,29 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
   return SVT_OK;
 }
 
-svt_status svt_profile(svt_handle* h, int32_t enable) {
+svt_status svt_profile_phases(svt_handle* h, uint32_t mask) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (mask >> SVT_PH_COUNT) return fail(h, SVT_E_INVALID_ARG, "phase mask has bits above SVT_PH_COUNT");
   HIPCHK(hipStreamSynchronize(h->stream));
   resolve_pending(h);
-  if (enable) {
+  if (mask) {
     for (int i = 0; i < SVT_PH_COUNT; ++i) {
       h->ph_ms[i] = h->ph_bytes[i] = h->ph_flops[i] = 0.0;
       h->ph_launch[i] = 0;
     }
+    // create the events up front: none is created inside the measured iterations
+    while (h->event_pool.size() < kEventPrealloc) {
+      hipEvent_t e = nullptr;
+      HIPCHK(hipEventCreate(&e));
+      h->event_pool.push_back(e);
+    }
   }
-  h->prof = enable != 0;
+  h->prof_mask = mask;
   return SVT_OK;
+}
+
+svt_status svt_profile(svt_handle* h, int32_t enable) {
+  return svt_profile_phases(h, enable ? (1u << SVT_PH_COUNT) - 1u : 0u);
 }
 
 svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* flops, int64_t* launches) {

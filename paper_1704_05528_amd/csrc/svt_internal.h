@@ -15,6 +15,7 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
 constexpr int kScalars = 64;  // doubles in the device->host readback buffer
+constexpr int kStageDoubles = 4096;  // pinned staging doubles for small device->host copies
 constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
 // Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
@@ -80,6 +81,8 @@ struct Handle {
   int64_t partial_cap = 0;
   double* scal = nullptr;   // device scalars
   double* hscal = nullptr;  // pinned host mirror
+  double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks
+  hipEvent_t sync_ev = nullptr;  // timing-free event the host spins on at decision points
 
   // iteration state (host)
   int32_t r = 0;
@@ -104,7 +107,8 @@ struct Handle {
     int ph;
     hipEvent_t e0, e1;
   };
-  bool prof = false;
+  uint32_t prof_mask = 0;  // phases recorded by the phase timers (bit 1 << SVT_PH_*)
+  std::vector<svt_step_stats> history;  // reports of the iterations run by svt_iterate
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   double ph_ms[SVT_PH_COUNT] = {};

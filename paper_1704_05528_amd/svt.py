@@ -81,6 +81,18 @@ class SVT:
         check(load().svt_iterate(self._h, int(max_steps), C.byref(st)), self._h)
         return st
 
+    def history(self, first=0, count=None):
+        """Reports of the iterations run by iterate() on this handle, oldest first."""
+        L = load()
+        total = C.c_int64()
+        check(L.svt_history(self._h, 0, 0, None, C.byref(total)), self._h)
+        n = max(0, total.value - int(first)) if count is None else int(count)
+        if n <= 0:
+            return []
+        arr = (StepStats * n)()
+        check(L.svt_history(self._h, int(first), n, arr, None), self._h)
+        return list(arr[:max(0, min(n, total.value - int(first)))])
+
     # -- outputs --------------------------------------------------------------------------------
     def factors(self, kcap=None):
         L = load()
@@ -138,8 +150,17 @@ class SVT:
         a, ap = _i32(annealed)
         check(load().svt_set_replay(self._h, bp, ap, int(b.size)), self._h)
 
-    def profile(self, enable=True):
-        check(load().svt_profile(self._h, 1 if enable else 0), self._h)
+    def profile(self, enable=True, phases=None):
+        """Start (reset) or stop the per-phase device timers; `phases` limits them to the named
+        phases (names from PHASES), which keeps the event markers out of the other phases."""
+        if phases is None or not enable:
+            check(load().svt_profile(self._h, 1 if enable else 0), self._h)
+            return
+        from ._capi import PHASES
+        mask = 0
+        for ph in phases:
+            mask |= 1 << PHASES.index(ph)
+        check(load().svt_profile_phases(self._h, mask), self._h)
 
     def profile_read(self):
         """{phase: dict(ms, bytes, flops, launches)} accumulated since profile(True)."""

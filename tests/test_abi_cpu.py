@@ -87,4 +87,5 @@ def test_null_handles_are_rejected():
     assert L.svt_iterate(None, 1, None) == _capi.SVT_E_INVALID_ARG
     assert L.r4svd_step(None, None) == _capi.SVT_E_INVALID_ARG
     assert L.svt_grad(None, 1, 1, 0, None, None, None, None, None, None) == _capi.SVT_E_INVALID_ARG
+    assert L.svt_history(None, 0, 0, None, None) == _capi.SVT_E_INVALID_ARG
     L.svt_destroy(None)

@@ -123,3 +123,32 @@ def test_modes_in_the_mixed_form(gpu_lib):
             st = h.iterate(1)
             assert st.k == info.k, (mode, info.it)
             assert rel_err(h.sample(w.rows, w.cols), info.x) <= 1e-4, (mode, info.it)
+
+
+def test_history_keeps_every_iteration_report(gpu_lib):
+    """svt_history returns the reports of single steps and of one multi-step call, oldest first,
+    identical between the two (the iteration is deterministic); r and k agree with the oracle."""
+    w = W.tiny_dense(80, 60, 3, 0.4, seed=95)
+    p = Params(tau=w.tau, delta=w.delta, seed=95, maxit=4)
+    _, infos, k0 = svt_run(Problem(w.m, w.n, w.rows, w.cols, w.a), p, keep_infos=True)
+    kw = dict(tau=p.tau, delta=p.delta, seed=p.seed, maxit=4, k0=k0)
+    blocks, anneal = [i.blocks for i in infos], [int(i.annealed) for i in infos]
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, **kw)
+    h.set_replay(blocks, anneal)
+    steps = [h.iterate(1) for _ in infos]
+    hist = h.history()
+    assert [s.iter for s in hist] == [1, 2, 3, 4]
+    for rec, st, info in zip(hist, steps, infos):
+        assert (rec.r, rec.k, rec.blocks, rec.flags) == (st.r, st.k, st.blocks, st.flags)
+        assert rec.rel_res == st.rel_res and rec.normB == st.normB
+        assert (rec.r, rec.k) == (info.r, info.k)
+    assert h.history(first=2)[0].iter == 3
+    assert h.history(first=10) == []
+    h2 = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, **kw)
+    h2.set_replay(blocks, anneal)
+    last = h2.iterate(4)
+    hist2 = h2.history()
+    assert last.iter == 4 and len(hist2) == 4
+    for a, b in zip(hist, hist2):
+        assert (a.iter, a.r, a.k, a.blocks) == (b.iter, b.r, b.k, b.blocks)
+        assert a.rel_res == b.rel_res
