@@ -237,6 +237,20 @@ svt_status svt_profile(svt_handle* h, int32_t enable);
  * mask = 0 stops recording.  Errors: SVT_E_INVALID_ARG (bits above SVT_PH_COUNT). */
 svt_status svt_profile_phases(svt_handle* h, uint32_t mask);
 
+/* Benchmark support: `reps` back-to-back launches of the kernel of one single-kernel phase
+ * (SVT_PH_SPMM_T, SVT_PH_GRAM, SVT_PH_SDDMM or SVT_PH_DENSIFY) on the operands the last iteration
+ * left, between two hipEvents on the handle's stream.  Events around launches inside the
+ * iteration also count the time the GPU waits for the host to enqueue the kernel after a host
+ * decision point; here the launches queue behind each other, so the per-launch time is the
+ * kernel's own plus the dispatch gap between consecutive kernels.
+ * Outputs: *ms = device milliseconds per launch; *bytes, *flops (may be NULL) = algorithmic work
+ * of one launch (as svt_profile_read counts it).  The replayed kernels rewrite only buffers that
+ * every iteration rewrites before reading them (W, G, the dense copy of Y, the next Y and the
+ * partial sums), so the iteration state is unchanged.
+ * Errors: SVT_E_INVALID_ARG (another phase, reps < 1, ms == NULL), SVT_E_STATE (no iteration
+ * run yet, or the phase has no kernel in this problem). */
+svt_status svt_time_phase(svt_handle* h, int32_t phase, int32_t reps, double* ms, double* bytes, double* flops);
+
 /* Per phase (arrays of SVT_PH_COUNT entries, any may be NULL): device milliseconds, algorithmic
  * bytes moved (each operand counted once per launch), algorithmic flops, number of launches. */
 svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* flops, int64_t* launches);

@@ -461,19 +461,19 @@ __global__ void k_tn_finish(const double* __restrict__ partial, int splits, int 
 }
 
 // ------------------------------------------------------------------------------------------
-// Gram G = A^T A (na x na, double) for a tall A on the FP64 matrix cores: one 32 x 32 tile of the
-// upper triangle per workgroup, written to both triangles; no partial sums.  The workgroup is
-// four groups of four waves: wave q of a group takes the 16 x 16 quarter q of the tile, group g
-// the g-th contiguous quarter of the rows, and the groups' accumulators are added in group order
-// in LDS (deterministic).  With a few hundred columns there are fewer tiles than compute units;
-// the row split keeps four times more loads in flight per tile.
+// Gram G = A^T A (na x na, double) for a tall A on the FP64 matrix cores: one 16 x 16 tile of the
+// upper triangle per workgroup, written to both triangles; no partial sums.  The workgroup's 16
+// waves take contiguous sixteenths of the rows, and their accumulators are added in wave order
+// in LDS (deterministic).  With a few hundred columns there are a few hundred tiles: small tiles
+// spread them over every CU, and the row split keeps sixteen streams of loads in flight per tile.
 // ------------------------------------------------------------------------------------------
-constexpr int kGT = 32;
+constexpr int kGT = 16;
+constexpr int kGramWaves = 16;
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
-                                                     double* __restrict__ G, int ldg, int ntile) {
-  __shared__ double red[3][4][kWave][4];
+__global__ __launch_bounds__(kGramWaves * kWave) void k_gram_tiles(int rows, const T* __restrict__ A, int lda, int na,
+                                                                   double* __restrict__ G, int ldg, int ntile) {
+  __shared__ double red[kGramWaves - 1][4][kWave];
   // map blockIdx.x to an upper-triangular tile pair (ti <= tj)
   int t = blockIdx.x, ti = 0;
   while (t >= ntile - ti) {
@@ -481,26 +481,26 @@ __global__ __launch_bounds__(1024) void k_gram_tiles(int rows, const T* __restri
     ++ti;
   }
   const int tj = ti + t;
-  const int lane = threadIdx.x & (kWave - 1), wq = (threadIdx.x / kWave) & 3, grp = threadIdx.x / (4 * kWave);
-  const int a0 = ti * kGT + (wq >> 1) * 16, b0 = tj * kGT + (wq & 1) * 16;
+  const int lane = threadIdx.x & (kWave - 1), grp = threadIdx.x / kWave;
+  const int a0 = ti * kGT, b0 = tj * kGT;
   const int aa = a0 + (lane & 15), bb = b0 + (lane & 15), kl = lane >> 4;
   const bool aok = aa < na, bok = bb < na;
   const T* acol = A + min(aa, na - 1);
   const T* bcol = A + min(bb, na - 1);
   const int steps = (rows + 3) / 4;
-  const int per = (steps + 3) / 4;
+  const int per = (steps + kGramWaves - 1) / kGramWaves;
   const int s0 = grp * per, s1 = min(steps, s0 + per);
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int st = s0;
-  for (; st + kUnroll <= s1; st += kUnroll) {
+  for (int st = s0; st < s1; st += kUnroll) {
     double a[kUnroll], b[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int row = (st + u) * 4 + kl;
+      const bool ok = (st + u < s1) && (row < rows);
       const int rc = min(row, rows - 1);
       const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * lda];
-      a[u] = (row < rows && aok) ? av : 0.0;
-      b[u] = (row < rows && bok) ? bv : 0.0;
+      a[u] = (ok && aok) ? av : 0.0;
+      b[u] = (ok && bok) ? bv : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; u += 2) {
@@ -508,22 +508,17 @@ __global__ __launch_bounds__(1024) void k_gram_tiles(int rows, const T* __restri
       acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
   }
-  for (; st < s1; ++st) {
-    const int row = st * 4 + kl;
-    const int rc = min(row, rows - 1);
-    const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * lda];
-    acc0 = mfma_f64_16x16x4((row < rows && aok) ? av : 0.0, (row < rows && bok) ? bv : 0.0, acc0);
-  }
   dbl4 acc = acc0 + acc1;
   if (grp > 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[grp - 1][wq][lane][v] = acc[v];
+    for (int v = 0; v < 4; ++v) red[grp - 1][v][lane] = acc[v];
   }
   __syncthreads();
   if (grp > 0) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double sum = ((acc[v] + red[0][wq][lane][v]) + red[1][wq][lane][v]) + red[2][wq][lane][v];
+    double sum = acc[v];
+    for (int g = 0; g < kGramWaves - 1; ++g) sum += red[g][v][lane];
     const int ra = a0 + (lane >> 4) + 4 * v, cb = b0 + (lane & 15);
     if (ra < na && cb < na) {
       G[(int64_t)ra * ldg + cb] = sum;
@@ -943,7 +938,7 @@ hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, dou
   if (na == 0) return hipSuccess;
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(1024), 0, s, rows, A, lda, na, G, ldg, nt);
+  hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(kGramWaves * kWave), 0, s, rows, A, lda, na, G, ldg, nt);
   return hipGetLastError();
 }
 

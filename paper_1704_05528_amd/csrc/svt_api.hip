@@ -68,6 +68,11 @@ hipError_t dalloc(T** p, size_t count) {
 // ------------------------------------------------------------------------------------------
 // Instrumentation: an event pair around the launches of one phase, resolved after a sync.
 // ------------------------------------------------------------------------------------------
+// Phase-timer events only time: without the system-scope fence, recording one costs no cache
+// writeback and invalidation, which would both slow the following kernel and add to the
+// measured interval.
+constexpr unsigned kTimerEventFlags = hipEventDisableSystemFence;
+
 hipEvent_t pool_event(Handle* h) {
   if (!h->event_pool.empty()) {
     hipEvent_t e = h->event_pool.back();
@@ -75,7 +80,7 @@ hipEvent_t pool_event(Handle* h) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, kTimerEventFlags) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -270,13 +275,93 @@ struct Engine {
   }
 
   // ----------------------------------------------------------------------------------------
+  // The single-kernel phases (each one launcher call) and their algorithmic work per launch:
+  // every operand counted once (values, indices, dense factors), flops of the definition.
+  // ----------------------------------------------------------------------------------------
+  // yT <- y on Lambda (dense path)
+  svt_status run_densify() {
+    HIPCHK(launch_scatter_dense_t<T>(h->stream, (int)h->n, h->colptr, h->rowidx, y(), (T*)h->yT, h->m));
+    return SVT_OK;
+  }
+  // W = Y^T Q[:, 0:r]
+  svt_status run_spmm_t() {
+    if (h->yT && h->r >= 32) return spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r);
+    if (h->tstart) {
+      HIPCHK(launch_spmm_t_tiled<T>(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, y(), Q(), h->r_cap, h->r,
+                                    W(), h->r_cap, h->partial, h->partial_cap));
+      return SVT_OK;
+    }
+    return spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r);
+  }
+  // G = W^T W
+  svt_status run_gram() {
+    HIPCHK(launch_gram<T>(h->stream, (int)h->n, W(), h->r_cap, h->r, h->G, h->r_cap, h->partial, h->partial_cap));
+    return SVT_OK;
+  }
+  // y_next = y + delta P_Lambda(A - Ut Vt^T), with the residual sums in partial
+  svt_status run_sddmm(int* nbl) {
+    HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
+                                  kEigMax, h->k, h->p.delta, h->partial, nbl));
+    return SVT_OK;
+  }
+  double work_bytes(int ph) const {
+    const double nnz = (double)h->nnz, r = h->r, k = h->k, m = (double)h->m, n = (double)h->n;
+    switch (ph) {
+      case SVT_PH_DENSIFY: return nnz * (2.0 * es + 4.0) + 4.0 * (n + 1);
+      case SVT_PH_SPMM_T: return nnz * (es + 4.0) + 4.0 * (n + 1) + es * r * (m + n);
+      case SVT_PH_GRAM: return es * n * r + 8.0 * r * r;
+      case SVT_PH_SDDMM: return nnz * (3.0 * es + 4.0) + 4.0 * (n + 1) + es * k * (m + n);
+      default: return 0.0;
+    }
+  }
+  double work_flops(int ph) const {
+    const double nnz = (double)h->nnz, r = h->r, k = h->k, n = (double)h->n;
+    switch (ph) {
+      case SVT_PH_SPMM_T: return 2.0 * nnz * r;
+      case SVT_PH_GRAM: return n * r * (r + 1.0);
+      case SVT_PH_SDDMM: return nnz * (2.0 * k + 3.0);
+      default: return 0.0;
+    }
+  }
+
+  // Benchmark support: `reps` back-to-back launches of one single-kernel phase on the current
+  // operands between two events (no host work or markers between the launches).
+  svt_status replay_phase(int ph, int reps, double* ms) {
+    if (ph == SVT_PH_DENSIFY && !h->yT) return fail(h, SVT_E_STATE, "no dense copy of Y in this problem");
+    if ((ph == SVT_PH_SPMM_T || ph == SVT_PH_GRAM) && h->r <= 0) return fail(h, SVT_E_STATE, "empty basis");
+    hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
+    if (!e0 || !e1) return fail(h, SVT_E_HIP, "event creation failed");
+    svt_status stt = SVT_OK;
+    hipError_t he = hipEventRecord(e0, h->stream);
+    for (int i = 0; he == hipSuccess && stt == SVT_OK && i < reps; ++i) {
+      int nbl = 0;
+      switch (ph) {
+        case SVT_PH_DENSIFY: stt = run_densify(); break;
+        case SVT_PH_SPMM_T: stt = run_spmm_t(); break;
+        case SVT_PH_GRAM: stt = run_gram(); break;
+        default: stt = run_sddmm(&nbl); break;
+      }
+    }
+    if (he == hipSuccess) he = hipEventRecord(e1, h->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float el = 0.f;
+    if (he == hipSuccess && stt == SVT_OK) he = hipEventElapsedTime(&el, e0, e1);
+    h->event_pool.push_back(e0);
+    h->event_pool.push_back(e1);
+    CHK(stt);
+    HIPCHK(he);
+    *ms = (double)el / reps;
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
   // R4SVD (Alg. 3; Alg. 2 for the first call): leaves Q[:, 0:r], W = Y^T Q, and st->eps.
   // ----------------------------------------------------------------------------------------
   svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
     double normB = 0.0;
     if (h->yT) {
-      PhaseTimer tm(h, SVT_PH_DENSIFY, (double)h->nnz * (2.0 * es + 4.0) + 4.0 * (h->n + 1));
-      HIPCHK(launch_scatter_dense_t<T>(h->stream, (int)h->n, h->colptr, h->rowidx, y(), (T*)h->yT, h->m));
+      PhaseTimer tm(h, SVT_PH_DENSIFY, work_bytes(SVT_PH_DENSIFY));
+      CHK(run_densify());
     }
     if (h->r == 0) {
       int got = 0;
@@ -287,17 +372,8 @@ struct Engine {
       normB = add;
     } else {
       {
-        const double r = h->r, nnz = (double)h->nnz;
-        PhaseTimer tm(h, SVT_PH_SPMM_T, nnz * (es + 4.0) + 4.0 * (h->n + 1) + es * r * (double)(h->m + h->n),
-                      2.0 * nnz * r);
-        if (h->yT && h->r >= 32) {
-          CHK(spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r));
-        } else if (h->tstart) {
-          HIPCHK(launch_spmm_t_tiled<T>(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, y(), Q(), h->r_cap,
-                                        h->r, W(), h->r_cap, h->partial, h->partial_cap));
-        } else {
-          CHK(spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r));
-        }
+        PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
+        CHK(run_spmm_t());
       }
       {
         PhaseTimer tm(h, SVT_PH_REDUCE);
@@ -358,8 +434,8 @@ struct Engine {
     const int r = h->r;
     const double tau2 = h->p.tau * h->p.tau;
     {
-      PhaseTimer tm(h, SVT_PH_GRAM, es * (double)h->n * r + 8.0 * (double)r * r, (double)h->n * r * (r + 1.0));
-      HIPCHK(launch_gram<T>(s, (int)h->n, W(), h->r_cap, r, h->G, h->r_cap, h->partial, h->partial_cap));
+      PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
+      CHK(run_gram());
     }
     std::vector<double> theta(2 * kEigMax), res(kEigMax);
     const double* S = nullptr;
@@ -599,11 +675,8 @@ struct Engine {
     CHK(projected_svd(st));
     int nbl = 0;
     {
-      const double nnz = (double)h->nnz, k = h->k;
-      PhaseTimer tm(h, SVT_PH_SDDMM, nnz * (3.0 * es + 4.0) + 4.0 * (h->n + 1) + es * k * (double)(h->m + h->n),
-                    nnz * (2.0 * k + 3.0));
-      HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(),
-                                    Vt(), kEigMax, h->k, h->p.delta, h->partial, &nbl));
+      PhaseTimer tm(h, SVT_PH_SDDMM, work_bytes(SVT_PH_SDDMM), work_flops(SVT_PH_SDDMM));
+      CHK(run_sddmm(&nbl));
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
@@ -1410,12 +1483,26 @@ svt_status svt_profile_phases(svt_handle* h, uint32_t mask) {
     // create the events up front: none is created inside the measured iterations
     while (h->event_pool.size() < kEventPrealloc) {
       hipEvent_t e = nullptr;
-      HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventCreateWithFlags(&e, kTimerEventFlags));
       h->event_pool.push_back(e);
     }
   }
   h->prof_mask = mask;
   return SVT_OK;
+}
+
+svt_status svt_time_phase(svt_handle* h, int32_t phase, int32_t reps, double* ms, double* bytes, double* flops) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (phase != SVT_PH_SPMM_T && phase != SVT_PH_GRAM && phase != SVT_PH_SDDMM && phase != SVT_PH_DENSIFY)
+    return fail(h, SVT_E_INVALID_ARG, "svt_time_phase times single-kernel phases only");
+  if (reps < 1 || !ms) return fail(h, SVT_E_INVALID_ARG, "reps must be positive and ms non-NULL");
+  if (!h->have_factors) return fail(h, SVT_E_STATE, "no iteration has run yet");
+  return dispatch(h, [&](auto& eng) -> svt_status {
+    CHK(eng.replay_phase(phase, reps, ms));
+    if (bytes) *bytes = eng.work_bytes(phase);
+    if (flops) *flops = eng.work_flops(phase);
+    return SVT_OK;
+  });
 }
 
 svt_status svt_profile(svt_handle* h, int32_t enable) {

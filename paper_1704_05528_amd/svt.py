@@ -173,6 +173,15 @@ class SVT:
         return {ph: dict(ms=float(ms[i]), bytes=float(by[i]), flops=float(fl[i]), launches=int(ln[i]))
                 for i, ph in enumerate(PHASES)}
 
+    def time_phase(self, phase, reps=50):
+        """(ms per launch, algorithmic bytes, flops) of `reps` back-to-back launches of a single-kernel
+        phase ("spmm_t", "gram", "sddmm" or "densify") on the last iteration's operands."""
+        from ._capi import PHASES
+        ms, by, fl = C.c_double(), C.c_double(), C.c_double()
+        check(load().svt_time_phase(self._h, PHASES.index(phase), int(reps), C.byref(ms), C.byref(by), C.byref(fl)),
+              self._h)
+        return ms.value, by.value, fl.value
+
     def grad(self, T, ckpt, hi, hj, gx_h):
         hi, ip = _i32(hi)
         hj, jp = _i32(hj)

@@ -38,3 +38,51 @@ def test_phase_mask_rejects_unknown_bits(gpu_lib):
     L = capi.load()
     assert L.svt_profile_phases(h._h, 1 << 20) == capi.SVT_E_INVALID_ARG
     assert L.svt_profile_phases(h._h, 0) == capi.SVT_OK
+
+
+def test_time_phase_replays_without_changing_the_iteration(gpu_lib):
+    """Back-to-back replays of the single-kernel phases report positive per-launch times and the
+    phase timers' work counts, and leave the iteration bitwise unchanged."""
+    a, b = _handle(gpu_lib, seed=23), _handle(gpu_lib, seed=23)
+    a.iterate(3)
+    b.iterate(3)
+    b.profile(True, phases=["spmm_t", "gram", "sddmm", "densify"])
+    b.iterate(1)
+    counted = b.profile_read()
+    b.profile(False)
+    a.iterate(1)
+    grew = b.history()[-1].blocks > 0  # W = Y^T Q ran on the basis before this iteration's growth
+    for ph in ("spmm_t", "gram", "sddmm", "densify"):
+        ms, by, fl = a.time_phase(ph, reps=5)
+        assert ms > 0.0, ph
+        if ph == "spmm_t" and grew:
+            r = b.history()[-1].r
+            assert fl == 2.0 * a.nnz * r
+        else:
+            assert by == counted[ph]["bytes"] and fl == counted[ph]["flops"], ph
+    sa, sb = a.iterate(2), b.iterate(2)
+    assert (sa.r, sa.k, sa.blocks) == (sb.r, sb.k, sb.blocks)
+    assert sa.rel_res == sb.rel_res and sa.normB == sb.normB
+    assert (a.sample([0, 5, 7], [1, 2, 3]) == b.sample([0, 5, 7], [1, 2, 3])).all()
+
+
+def test_time_phase_rejects_bad_requests(gpu_lib):
+    from paper_1704_05528_amd import SVTError
+    import paper_1704_05528_amd._capi as capi
+    h = _handle(gpu_lib, seed=24)
+    with pytest.raises(SVTError) as e:
+        h.time_phase("gram")  # no iteration yet
+    assert e.value.status == capi.SVT_E_STATE
+    h.iterate(1)
+    with pytest.raises(SVTError) as e:
+        h.time_phase("eig")  # not a single-kernel phase
+    assert e.value.status == capi.SVT_E_INVALID_ARG
+    with pytest.raises(SVTError) as e:
+        h.time_phase("gram", reps=0)
+    assert e.value.status == capi.SVT_E_INVALID_ARG
+    w = W.tiny_dense(120, 90, 4, 0.15, seed=25)  # sparse enough to have no dense copy of Y
+    s = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=25, maxit=5)
+    s.iterate(1)
+    with pytest.raises(SVTError) as e:
+        s.time_phase("densify")
+    assert e.value.status == capi.SVT_E_STATE
