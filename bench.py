@@ -67,6 +67,26 @@ def parse():
     return ap.parse_args()
 
 
+def committed_traffic(phase, form, workload, r):
+    """HBM bytes per launch of the roofline kernel from a committed counter summary
+    (profiles/*_traffic.json), or None.  A summary counts only while the kernel source it was
+    taken with is unchanged (SHA-256) and it describes this phase, form, workload and basis width."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+            with open(os.path.join(ROOT, t["source"]), "rb") as f:
+                sha = hashlib.sha256(f.read()).hexdigest()
+        except (OSError, ValueError, KeyError):
+            continue
+        if (sha == t.get("source_sha256") and t.get("phase") == phase and t.get("form") == form
+                and t.get("workload") == workload and t.get("r") == r):
+            return float(t["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def divmod_all(m, n):
     import numpy as np
     i, j = np.divmod(np.arange(m * n, dtype=np.int64), n)
@@ -230,6 +250,11 @@ def run_form(svt, w, stream, args, precision, **extra):
         achieved = per_flops / (per_ms * 1e-3) / 1e12
         roof = {"bound": unit, "achieved": achieved, "peak": cpeak, "unit": "TFLOP/s",
                 "frac": achieved / cpeak, "traffic": None}
+    traffic, tsrc = (committed_traffic(dom, "mixed" if precision else "fp64", args.workload, r_vals[-1])
+                     if replay else (None, None))
+    roof["traffic"] = traffic
+    if tsrc:
+        roof["traffic_source"] = tsrc
     ip = prof[dom]
     roof.update({"kernel": dom, "avg_launch_us": 1e3 * per_ms, "bytes_per_launch": per_bytes,
                  "flops_per_launch": per_flops,
