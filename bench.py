@@ -93,8 +93,9 @@ def divmod_all(m, n):
     return i.astype(np.int32), j.astype(np.int32)
 
 
-def cpu_baseline(w, r, seed, budget_s=20.0):
-    """The FP64 oracle, as it stands, on the host: SVT steps from a state with an r-column basis."""
+def cpu_baseline(w, r, seed, budget_s=15.0, max_steps=200):
+    """The FP64 oracle, as it stands, on the host: SVT steps from a state with an r-column basis,
+    until about budget_s seconds of host work (bounded so the default run stays short)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -110,7 +111,7 @@ def cpu_baseline(w, r, seed, budget_s=20.0):
         state, _ = svt_step(prob, p, state)
         done += 1
         el = time.perf_counter() - t0
-        if el > budget_s or done >= 20:
+        if el > budget_s or done >= max_steps:
             break
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     return {"value": done / el, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
