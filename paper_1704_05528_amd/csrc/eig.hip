@@ -62,15 +62,14 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
   __shared__ int rank_of[kEigMax];
   const int tid = threadIdx.x;
 
-  // H is the sum of `splits` matrices sstride apart (partial products, added in split order)
+  // H is the sum of `splits` matrices sstride apart (partial products, added in a fixed order)
   for (int e = tid; e < bb * bb; e += blockDim.x) {
     const int i = e / bb, j = e - (e / bb) * bb;
     double hij = 0.0, hji = 0.0;
-    if (i < b && j < b)
-      for (int sp = 0; sp < splits; ++sp) {
-        hij += H[sp * sstride + (int64_t)i * ldh + j];
-        hji += H[sp * sstride + (int64_t)j * ldh + i];
-      }
+    if (i < b && j < b) {
+      hij = split_sum(H + (int64_t)i * ldh + j, splits, sstride);
+      hji = split_sum(H + (int64_t)j * ldh + i, splits, sstride);
+    }
     A[i * ld + j] = 0.5 * (hij + hji);
     V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }

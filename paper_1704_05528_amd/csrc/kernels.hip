@@ -294,16 +294,14 @@ __global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_
   }
 }
 
-// W[j, c] = sum_s partial[s][j][c] in split order
+// W[j, c] = sum_s partial[s][j][c] (fixed order)
 template <class T>
 __global__ void k_split_sum(int n, int r, const T* __restrict__ partial, int splits, int64_t split_stride, int ldp,
                             T* __restrict__ W, int ldw) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * r) return;
   const int j = (int)(t / r), c = (int)(t % r);
-  T v = (T)0;
-  for (int s = 0; s < splits; ++s) v += partial[s * split_stride + (int64_t)j * ldp + c];
-  W[(int64_t)j * ldw + c] = v;
+  W[(int64_t)j * ldw + c] = split_sum<T>(partial + (int64_t)j * ldp + c, splits, split_stride);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -344,8 +342,9 @@ __device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
 template <class TA, class TM, class TO>
 __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
                                                 const TM* __restrict__ M, int ldm, TO* __restrict__ out, int ldo,
-                                                int w, double alpha, double beta) {
+                                                int w, double alpha, double beta, double* __restrict__ gpart) {
   __shared__ double red[3][kWave][4];
+  __shared__ double tile[16][17];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int ia = i0 + (lane & 15), jb = j0 + (lane & 15), kl = lane >> 4;
@@ -386,11 +385,26 @@ __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __res
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = i0 + (lane >> 4) + 4 * v, col = j0 + (lane & 15);
+      double val = 0.0;
       if (row < rows && col < w) {
         TO* o = out + (int64_t)row * ldo + col;
-        *o = (TO)((beta == 0.0 ? 0.0 : beta * (double)*o) + alpha * acc[v]);
+        const TO stored = (TO)((beta == 0.0 ? 0.0 : beta * (double)*o) + alpha * acc[v]);
+        *o = stored;
+        val = (double)stored;
       }
+      tile[(lane >> 4) + 4 * v][lane & 15] = val;
     }
+  }
+  // Optional epilogue (w <= 16, one column tile): the Gram of this tile's 16 output rows,
+  // gpart[blockIdx.x][a][b] = sum_i out[i][a] out[i][b], for the CholeskyQR of the product
+  if (gpart == nullptr) return;  // uniform
+  __syncthreads();
+  const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
+  if (a < w && b < w) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sacc = fma(tile[i][a], tile[i][b], sacc);
+    gpart[(int64_t)blockIdx.x * w * w + a * w + b] = sacc;
   }
 }
 
@@ -456,7 +470,7 @@ __global__ void k_tn_finish(const double* __restrict__ partial, int splits, int 
   if (t >= (int64_t)na * nb) return;
   const int a = (int)(t / nb), b = (int)(t % nb);
   double v = 0.0;
-  for (int s = 0; s < splits; ++s) v += partial[((int64_t)s * na + a) * nb + b];
+  v = split_sum(partial + (int64_t)a * nb + b, splits, (int64_t)na * nb);
   out[(int64_t)a * ldo + b] = v;
 }
 
@@ -599,12 +613,12 @@ __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ g
   const int tid = threadIdx.x;
   int wa = w;
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
-  // the Gram is the sum of `splits` partial Grams (sstride apart), added in split order
+  // the Gram is the sum of `splits` partial Grams (sstride apart), added in a fixed order
   for (int e = tid; e < w * w; e += blockDim.x) {
     const int i = e / w, j = e % w;
     double v = 0.0;
     if (i < wa && j < wa)
-      for (int sp = 0; sp < splits; ++sp) v += gram[sp * sstride + (int64_t)i * ldg + j];
+      v = split_sum(gram + (int64_t)i * ldg + j, splits, sstride);
     A[i * ld + j] = v;
   }
   __syncthreads();
@@ -687,6 +701,133 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict
     if (c < w && Rs[c * ld + c] != 0.0) o[q++] = (T)z[c];
   }
   for (; q < w; ++q) o[q] = (T)0;
+}
+
+// ------------------------------------------------------------------------------------------
+// One CholeskyQR pass in one launch: every one-wave workgroup adds the Gram partials (in a fixed
+// order), factors the Gram with the column-drop rules of k_block_chol in LDS (the same pivots,
+// decisions and factor in every workgroup), and solves its 64 rows as k_trsm_rows does:
+// out = X[:, kept] R^{-1}, kept columns packed left, zeros after them.  The factorisation is
+// repeated per workgroup (w^3 / 6 flops) instead of being a launch of its own.  With gout, each
+// workgroup also writes the Gram of its 64 stored output rows (gout[blockIdx.x], w x w), so a
+// second pass needs no separate Gram launch.  Workgroup 0 writes the kept count to scal[slot];
+// with wk_slot_in >= 0 only the first scal[wk_slot_in] columns take part (second pass).
+// ------------------------------------------------------------------------------------------
+constexpr int kCholTrsmRows = 64;
+
+template <int WM, class T>
+__global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* __restrict__ X, int ldx, int w,
+                                                             const double* __restrict__ gram, int splits,
+                                                             int64_t sstride, const double* __restrict__ prenorm,
+                                                             double drop_tol, double dep_tol, int wk_slot_in,
+                                                             T* __restrict__ out, int ldo, double* __restrict__ gout,
+                                                             double* scal, int slot) {
+  constexpr int ld = WM + 1;
+  constexpr int kPer = WM * WM / kCholTrsmRows;  // entries of the WM x WM square per lane
+  __shared__ double A[WM * ld];             // Gram, Schur complements, then the rows of R
+  __shared__ double O[kCholTrsmRows][ld];   // stored output rows (for gout)
+  __shared__ int keep[WM];
+  __shared__ double gdiag[WM], rdiag[WM];
+  const int tid = threadIdx.x;
+  int wa = w;
+  if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
+  // the Gram is the sum of `splits` partial Grams (w x w, sstride apart), added in a fixed order;
+  // entry (i, j) of the WM x WM square is e = i WM + j (compile-time shifts, no division)
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int e = tid + k * kCholTrsmRows, i = e / WM, j = e % WM;
+    A[i * ld + j] = (i < wa && j < wa) ? split_sum(gram + i * w + j, splits, sstride) : 0.0;
+  }
+  __syncthreads();
+  for (int c = tid; c < w; c += kCholTrsmRows) {
+    const double g = (c < wa) ? fmax(A[c * ld + c], 0.0) : 0.0;
+    gdiag[c] = g;
+    const double lim = prenorm ? drop_tol * prenorm[c] : 0.0;
+    keep[c] = (c < wa) && (sqrt(g) > lim) ? 1 : 0;
+  }
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle (k_block_chol's order and decisions)
+  for (int c = 0; c < wa; ++c) {
+    if (!keep[c]) continue;  // uniform
+    const double d = A[c * ld + c];
+    const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
+    if (ok) {
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int e = tid + k * kCholTrsmRows, i = e / WM, j = e % WM;
+        if (i > c && i <= j && j < wa) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
+      }
+    }
+    __syncthreads();
+    if (!ok && tid == 0) keep[c] = 0;
+    __syncthreads();
+  }
+  // rows of R in place: R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c] (j > c); zero rows and
+  // columns for the dropped and inactive indices
+  for (int c = tid; c < WM; c += kCholTrsmRows) rdiag[c] = (c < wa && keep[c]) ? sqrt(A[c * ld + c]) : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int e = tid + k * kCholTrsmRows, c = e / WM, j = e % WM;
+    double v = 0.0;
+    if (j >= c && rdiag[c] != 0.0 && rdiag[j] != 0.0) v = (j == c) ? rdiag[c] : A[c * ld + j] / rdiag[c];
+    A[c * ld + j] = v;
+  }
+  __syncthreads();
+  // forward substitution of this thread's row
+  const int i = blockIdx.x * kCholTrsmRows + tid;
+  const bool live = i < rows;
+  double z[WM];
+#pragma unroll
+  for (int c = 0; c < WM; ++c) z[c] = (live && c < w) ? (double)X[(int64_t)i * ldx + c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < WM; ++c) {
+    if (c < w) {
+      double v = z[c];
+#pragma unroll
+      for (int l = 0; l < c; ++l) v = fma(-z[l], A[l * ld + c], v);
+      const double rcc = A[c * ld + c];
+      z[c] = (rcc != 0.0) ? v / rcc : 0.0;
+    }
+  }
+  int q = 0;
+#pragma unroll
+  for (int c = 0; c < WM; ++c) {
+    if (c < w && A[c * ld + c] != 0.0) {
+      const T t = (T)z[c];
+      if (live) out[(int64_t)i * ldo + q] = t;
+      O[tid][q] = live ? (double)t : 0.0;
+      ++q;
+    }
+  }
+  for (int c = q; c < w; ++c) {
+    if (live) out[(int64_t)i * ldo + c] = (T)0;
+    O[tid][c] = 0.0;
+  }
+  if (blockIdx.x == 0 && tid == 0) scal[slot] = (double)q;
+  if (gout == nullptr) return;  // uniform
+  __syncthreads();
+  // Gram of the 64 stored rows on the FP64 matrix cores: 16 x 16 tiles (ta, tb), lane l takes
+  // rows 4 s + l / 16 of columns l % 16; the result holds rows (l / 16) + 4 v of column l % 16
+  const int nt = (w + 15) / 16, lane = tid, kl = lane >> 4, cl = lane & 15;
+  double* go = gout + (int64_t)blockIdx.x * w * w;
+  for (int t = 0; t < nt * nt; ++t) {
+    const int ta = t / nt, tb = t % nt;
+    const int ca = ta * 16 + cl, cb = tb * 16 + cl;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < kCholTrsmRows / 4; ++st) {
+      const int r = st * 4 + kl;
+      const double av = (ca < w) ? O[r][ca] : 0.0, bv = (cb < w) ? O[r][cb] : 0.0;
+      acc = mfma_f64_16x16x4(av, bv, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ra = ta * 16 + kl + 4 * v, cbo = tb * 16 + cl;
+      if (ra < w && cbo < w) go[ra * w + cbo] = acc[v];
+    }
+  }
 }
 
 // 16-byte vectors of the storage type and their dot product, element by element in order
@@ -906,10 +1047,11 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
 
 template <class TA, class TM, class TO>
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
-                         int w, double alpha, double beta) {
+                         int w, double alpha, double beta, double* gpart) {
   if (rows == 0 || w == 0) return hipSuccess;
+  if (gpart != nullptr && w > 16) return hipErrorInvalidValue;  // the Gram epilogue needs whole rows in one tile
   hipLaunchKernelGGL((k_rowmul<TA, TM, TO>), dim3((rows + 15) / 16, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M,
-                     ldm, out, ldo, w, alpha, beta);
+                     ldm, out, ldo, w, alpha, beta, gpart);
   return hipGetLastError();
 }
 
@@ -1041,6 +1183,21 @@ hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w,
 }
 
 template <class T>
+hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w, const double* gram, int splits,
+                            int64_t sstride, const double* prenorm, double drop_tol, double dep_tol, int wk_slot_in,
+                            T* out, int ldo, double* gout, double* scal, int slot) {
+  if (rows <= 0 || w <= 0 || w > kCholTrsmMaxCols || splits <= 0) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((rows + kCholTrsmRows - 1) / kCholTrsmRows));
+  if (w <= 16)
+    hipLaunchKernelGGL((k_chol_trsm<16, T>), g, dim3(kCholTrsmRows), 0, s, rows, X, ldx, w, gram, splits, sstride,
+                       prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
+  else
+    hipLaunchKernelGGL((k_chol_trsm<32, T>), g, dim3(kCholTrsmRows), 0, s, rows, X, ldx, w, gram, splits, sstride,
+                       prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
                                const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
                                int ld, int k, double delta, double* partial, int* nblocks) {
@@ -1105,6 +1262,8 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
   template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \
   template hipError_t launch_colnorms<T>(hipStream_t, int, const T*, int, int, double*, double*, int64_t, double*);   \
   template hipError_t launch_trsm_rows<T>(hipStream_t, int, const T*, int, int, const double*, int, T*, int);         \
+  template hipError_t launch_chol_trsm<T>(hipStream_t, int, const T*, int, int, const double*, int, int64_t,          \
+                                          const double*, double, double, int, T*, int, double*, double*, int);        \
   template hipError_t launch_sddmm_update<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*,       \
                                              const T*, const T*, T*, const T*, const T*, int, int, double, double*,   \
                                              int*);                                                                   \
@@ -1118,11 +1277,11 @@ SVT_INST(float)
 #undef SVT_INST
 
 template hipError_t launch_rowmul<double, double, double>(hipStream_t, int, int, const double*, int, const double*,
-                                                          int, double*, int, int, double, double);
+                                                          int, double*, int, int, double, double, double*);
 template hipError_t launch_rowmul<float, double, float>(hipStream_t, int, int, const float*, int, const double*, int,
-                                                        float*, int, int, double, double);
+                                                        float*, int, int, double, double, double*);
 template hipError_t launch_rowmul<float, double, double>(hipStream_t, int, int, const float*, int, const double*, int,
-                                                         double*, int, int, double, double);
+                                                         double*, int, int, double, double, double*);
 template hipError_t launch_tn_narrow<float, double>(hipStream_t, int, const float*, int, int, const double*, int, int,
                                                     double*, int, double*, int64_t);
 template hipError_t launch_copy_cols<float, double>(hipStream_t, int, const float*, int, double*, int, int);

@@ -188,6 +188,17 @@ struct Engine {
     hipStream_t s = h->stream;
     const int64_t ss = (int64_t)wc * wc;  // stride of the split partial Grams
     int sp = 0;
+    if (fused_cholqr(rows, wc)) {
+      // Gram partials of X; pass 1 factors and solves into X2 and leaves the Gram partials of X2;
+      // pass 2 factors those and solves back into X
+      HIPCHK((launch_tn_partial<U, U>(s, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap / 2, &sp)));
+      double* g2 = h->partial + h->partial_cap / 2;
+      HIPCHK(launch_chol_trsm<U>(s, rows, X, ld, wc, h->partial, sp, ss, prenorm, kDropTol, kDepTol, -1, X2, ld, g2,
+                                 h->scal, S_WK1));
+      HIPCHK(launch_chol_trsm<U>(s, rows, X2, ld, wc, g2, row_groups(rows), ss, nullptr, 0.0, kDepTol, S_WK1, X, ld,
+                                 nullptr, h->scal, S_WK2));
+      return SVT_OK;
+    }
     HIPCHK((launch_tn_partial<U, U>(s, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap, &sp)));
     HIPCHK(launch_block_chol(s, h->partial, wc, wc, prenorm, kDropTol, kDepTol, h->Minv, kEigMax, h->scal, S_WK1, -1,
                              sp, ss));
@@ -196,6 +207,36 @@ struct Engine {
     HIPCHK(launch_block_chol(s, h->partial, wc, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2, S_WK1,
                              sp, ss));
     HIPCHK(launch_trsm_rows<U>(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
+    return SVT_OK;
+  }
+
+  // CholeskyQR in one launch per pass (k_chol_trsm) for blocks of at most 32 columns and 4096 rows
+  static bool fused_cholqr(int rows, int wc) { return wc <= kCholTrsmMaxCols && rows <= kCholTrsmMaxRows; }
+  static int row_groups(int rows) { return (rows + 63) / 64; }
+
+  // CholeskyQR of an eigensolver block, one or two passes (only dependent columns drop):
+  // Out = In R^{-1}, through Tmp when twice.  gram / splits: the Gram partials of In when the
+  // product that wrote In left them (k_rowmul's epilogue), else nullptr.
+  svt_status eig_cholqr(int rows, const double* In, double* Tmp, double* Out, int ld, int wc, bool twice,
+                        const double* gram, int splits) {
+    if (!fused_cholqr(rows, wc)) {
+      if (!twice) return chol_orth(rows, In, Out, ld, wc);
+      CHK(chol_orth(rows, In, Tmp, ld, wc));
+      return chol_orth(rows, Tmp, Out, ld, wc);
+    }
+    hipStream_t s = h->stream;
+    const int64_t ss = (int64_t)wc * wc;
+    if (gram == nullptr) {
+      HIPCHK((launch_tn_partial<double, double>(s, rows, In, ld, wc, In, ld, wc, h->partial, h->partial_cap / 2,
+                                                &splits)));
+      gram = h->partial;
+    }
+    double* g2 = h->partial + h->partial_cap / 2;
+    HIPCHK(launch_chol_trsm<double>(s, rows, In, ld, wc, gram, splits, ss, nullptr, 0.0, kEigDepTol, -1,
+                                    twice ? Tmp : Out, ld, twice ? g2 : nullptr, h->scal, S_WK2));
+    if (twice)
+      HIPCHK(launch_chol_trsm<double>(s, rows, Tmp, ld, wc, g2, row_groups(rows), ss, nullptr, 0.0, kEigDepTol, -1, Out,
+                                      ld, nullptr, h->scal, S_WK2));
     return SVT_OK;
   }
 
@@ -493,35 +534,38 @@ struct Engine {
             // Z = G^step V.  A product G V left by the previous Rayleigh-Ritz step counts as the first;
             // otherwise a double step is one product with G^2, formed once per SVT iteration (the
             // subspace iteration only needs the dominant invariant subspace, which G^2 shares).
+            // A product of at most 16 columns also leaves the Gram partials of its output for the
+            // CholeskyQR that follows (one per 16-row tile).
             const double* z = nullptr;
+            double* zg = (b <= 16) ? h->partial : nullptr;
+            const int zgs = (r + 15) / 16;
+            bool have_zg = false;
             if (have_gv) {
               z = h->EZ3;
               have_gv = false;
               if (step == 2) {
                 HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEigMax, h->EZ, kEigMax, b,
-                                                              1.0, 0.0)));
+                                                              1.0, 0.0, zg)));
                 z = h->EZ;
+                have_zg = zg != nullptr;
               }
             } else if (step == 2) {
               if (!have_g2) {
-                HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap,
-                                                              r, 1.0, 0.0)));
+                // G^2 on the LDS-tiled matrix-core product (an r x r x r contraction)
+                HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap));
                 have_g2 = true;
               }
               HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G2, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
-                                                            1.0, 0.0)));
+                                                            1.0, 0.0, zg)));
               z = h->EZ;
+              have_zg = zg != nullptr;
             } else {
               HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
-                                                            1.0, 0.0)));
+                                                            1.0, 0.0, zg)));
               z = h->EZ3;
+              have_zg = zg != nullptr;
             }
-            if (last) {
-              CHK(chol_orth(r, z, h->EZ2, kEigMax, b));
-              CHK(chol_orth(r, h->EZ2, h->EV, kEigMax, b));
-            } else {
-              CHK(chol_orth(r, z, h->EV, kEigMax, b));
-            }
+            CHK(eig_cholqr(r, z, h->EZ2, h->EV, kEigMax, b, last, have_zg ? zg : nullptr, zgs));
             powers += step;
           }
           // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; G V <- (G V) S; residual norms
@@ -743,6 +787,9 @@ struct Engine {
     HIPCHK(launch_sumsq<T>(s, n, v, h->partial, h->scal, S_B));
     CHK(readback(h, S_B + 1));
     HIPCHK((launch_scale_copy<T, T>(s, n, v, 1.0 / std::sqrt(h->hscal[S_B]), v)));
+    // stop when successive estimates agree to the storage precision: float products carry noise of
+    // a few units in 1e-7, so the double-precision test would never pass in the mixed form
+    const double tol = sizeof(T) == 4 ? 2e-6 : 1e-15;
     double sig = 0.0, sig_prev = 0.0;
     for (int itp = 0; itp < 5000; ++itp) {
       HIPCHK(launch_seg_spmm<T>(s, m, h->rowptr, h->colidx, h->csr2csc, a(), v, 1, u, 1, 1));
@@ -754,7 +801,7 @@ struct Engine {
       const double nv = std::sqrt(h->hscal[S_B]);
       if (!(nv > 0.0)) break;
       HIPCHK((launch_scale_copy<T, T>(s, n, v, 1.0 / nv, v)));
-      if (itp > 3 && std::fabs(sig - sig_prev) <= 1e-15 * sig) break;
+      if (itp > 3 && std::fabs(sig - sig_prev) <= tol * sig) break;
       sig_prev = sig;
     }
     *out = sig;

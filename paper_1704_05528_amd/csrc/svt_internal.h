@@ -18,6 +18,30 @@ constexpr int kScalars = 64;  // doubles in the device->host readback buffer
 constexpr int kStageDoubles = 4096;  // pinned staging doubles for small device->host copies
 constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
+// sum_{t < n} p[t * stride] in a fixed order (16 interleaved partial sums, then a fixed tree),
+// with 16 independent loads in flight: the split sums of the tall products are latency bound
+// when each load waits for the previous add.
+template <class T>
+__device__ inline T split_sum(const T* __restrict__ p, int n, int64_t stride) {
+  constexpr int kU = 16;
+  T acc[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) acc[u] = (T)0;
+  for (int t0 = 0; t0 < n; t0 += kU) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u;
+      const T x = p[(int64_t)min(t, n - 1) * stride];
+      acc[u] += (t < n) ? x : (T)0;
+    }
+  }
+#pragma unroll
+  for (int o = kU / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int u = 0; u < o; ++u) acc[u] += acc[u + o];
+  return acc[0];
+}
+
 // Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
 // marked (T) hold the storage type of the precision form: double (SVT_FP64) or float
 // (SVT_MIXED); the Gram matrices, the eigensolver and all reductions are double in both.
@@ -139,10 +163,11 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
                                const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
                                int64_t partial_cap);
 
-// out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w] (double accumulation)
+// out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w] (double accumulation).  With gpart
+// (w <= 16 only): gpart[t][a][b] (t = 16-row tile, w x w each) = the Gram of the tile's stored rows.
 template <class TA, class TM, class TO>
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
-                         int w, double alpha, double beta);
+                         int w, double alpha, double beta, double* gpart = nullptr);
 
 // out[a, b] = sum_i A[i, a] B[i, b] in double, a < na (any), b < nb (<= kEigMax)
 template <class TA, class TB>
@@ -187,6 +212,18 @@ hipError_t launch_tn_partial(hipStream_t s, int rows, const TA* A, int lda, int 
 template <class T>
 hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
                             int ldo);
+
+// One CholeskyQR pass out = X[:, kept] R^{-1} from the Gram partials of X (splits matrices w x w,
+// sstride apart) in one launch of one-wave workgroups of 64 rows, each factoring the Gram itself
+// (k_block_chol's drop rules: prenorm / drop_tol, dep_tol; wk_slot_in >= 0 limits the columns to
+// scal[wk_slot_in]).  gout (may be NULL): the Gram partials of out, one w x w matrix per 64 rows.
+// scal[slot] = kept count.  w <= kCholTrsmMaxCols; hipErrorInvalidValue otherwise.
+constexpr int kCholTrsmMaxCols = 32;
+constexpr int kCholTrsmMaxRows = 4096;  // above this a separate factor launch costs less than the repeats
+template <class T>
+hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w, const double* gram, int splits,
+                            int64_t sstride, const double* prenorm, double drop_tol, double dep_tol, int wk_slot_in,
+                            T* out, int ldo, double* gout, double* scal, int slot);
 
 // sampled product on Lambda (CSC order) with residual and dual update, one wave per chunk of at
 // most kSddmmChunk positions of one column (chunk c = [cstart[c], cstart[c+1]) in column ccol[c]);

@@ -84,3 +84,15 @@ def test_mixed_planted_reaches_tolerance(gpu_lib):
     k, s, U, V = h.factors()
     X = (U * s) @ V.T
     assert np.linalg.norm(X - w.A) / np.linalg.norm(w.A) < 2e-3
+
+
+@pytest.mark.parametrize("m,n,frac,seed", [(100, 90, 0.3, 49), (160, 120, 0.5, 64)])
+def test_mixed_kicking_start_matches_oracle(gpu_lib, m, n, frac, seed):
+    """The mixed form computes ||P_Lambda A||_2 by a float32 power iteration that stops at float
+    precision; the kicking count k0 is an integer, so Y^(0) = k0 delta a matches the FP64 oracle to
+    float32 rounding."""
+    w = W.tiny_dense(m, n, 3, frac, seed=seed)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    state, k0 = initial_state(prob, Params(tau=w.tau, delta=w.delta))
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, precision=gpu_lib.SVT_MIXED)
+    np.testing.assert_allclose(h.get_state()["y"], state.y, rtol=3e-7)
