@@ -317,8 +317,9 @@ __device__ inline dbl4 mfma_f64_16x16x4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Sum the accumulators of the four waves of a workgroup in wave order (deterministic); the
-// result is valid in wave 0.
+// Sum the accumulators of the NW waves of a workgroup in wave order (deterministic); the result
+// is valid in wave 0.
+template <int NW = 4>
 __device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   if (wv > 0) {
@@ -327,23 +328,29 @@ __device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
   }
   __syncthreads();
   if (wv == 0) {
+    // wave order; one 4-double row of partner g per step keeps few values live
+#pragma unroll 4
+    for (int g = 0; g < NW - 1; ++g) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = ((acc[v] + red[0][lane][v]) + red[1][lane][v]) + red[2][lane][v];
+      for (int v = 0; v < 4; ++v) acc[v] += red[g][lane][v];
+    }
   }
   return acc;
 }
 
 // ------------------------------------------------------------------------------------------
 // Row-times-matrix product out[i, :] = beta out[i, :] + alpha A[i, 0:K] M[0:K, :] on the FP64
-// matrix cores: one 16 x 16 output tile per workgroup, the four waves take contiguous quarters
-// of the K steps and their accumulators are added in LDS.  Used for Q C, W D, G V, V S and the
-// projections X - Q (Q^T X).
+// matrix cores: one 16 x 16 output tile per workgroup, the NW waves take contiguous slices of the
+// K steps and their accumulators are added in LDS in wave order.  NW = 16 when there are fewer
+// tiles than compute units (tall-skinny products with a few hundred K steps: more loads in
+// flight per tile), else 4.  Used for Q C, W D, G V, V S and the projections X - Q (Q^T X).
 // ------------------------------------------------------------------------------------------
-template <class TA, class TM, class TO>
-__global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
-                                                const TM* __restrict__ M, int ldm, TO* __restrict__ out, int ldo,
-                                                int w, double alpha, double beta, double* __restrict__ gpart) {
-  __shared__ double red[3][kWave][4];
+template <class TA, class TM, class TO, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
+                                                       const TM* __restrict__ M, int ldm, TO* __restrict__ out,
+                                                       int ldo, int w, double alpha, double beta,
+                                                       double* __restrict__ gpart) {
+  __shared__ double red[NW - 1][kWave][4];
   __shared__ double tile[16][17];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
@@ -353,19 +360,20 @@ __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __res
   const TA* arow = A + (int64_t)min(ia, rows - 1) * lda;
   const TM* mcol = M + min(jb, w - 1);
   const int steps = (K + 3) / 4;
-  const int per = (steps + 3) / 4;
+  const int per = (steps + NW - 1) / NW;
   const int s0 = wv * per, s1 = min(steps, s0 + per);
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int st = s0;
-  for (; st + kUnroll <= s1; st += kUnroll) {
+  // full batches of kUnroll k-steps (the last one predicated), so a slice's loads all issue together
+  for (int st = s0; st < s1; st += kUnroll) {
     double a[kUnroll], b[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int k = (st + u) * 4 + kl;
+      const bool ok = (st + u < s1) && (k < K);
       const int kc = min(k, K - 1);
       const double av = (double)arow[kc], bv = (double)mcol[(int64_t)kc * ldm];
-      a[u] = (rowok && k < K) ? av : 0.0;
-      b[u] = (colok && k < K) ? bv : 0.0;
+      a[u] = (rowok && ok) ? av : 0.0;
+      b[u] = (colok && ok) ? bv : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; u += 2) {
@@ -373,14 +381,8 @@ __global__ __launch_bounds__(256) void k_rowmul(int rows, int K, const TA* __res
       acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
   }
-  for (; st < s1; ++st) {
-    const int k = st * 4 + kl;
-    const int kc = min(k, K - 1);
-    const double av = (double)arow[kc], bv = (double)mcol[(int64_t)kc * ldm];
-    acc0 = mfma_f64_16x16x4((rowok && k < K) ? av : 0.0, (colok && k < K) ? bv : 0.0, acc0);
-  }
   dbl4 acc = acc0 + acc1;
-  acc = reduce_waves(acc, red);
+  acc = reduce_waves<NW>(acc, red);
   if (wv == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -429,28 +431,22 @@ __global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restric
   const int per = (steps + 3) / 4;
   const int s0 = wv * per, s1 = min(steps, s0 + per);
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  int st = s0;
-  for (; st + kUnroll <= s1; st += kUnroll) {
+  for (int st = s0; st < s1; st += kUnroll) {  // full batches, the last one predicated
     double a[kUnroll], b[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int row = i0 + (st + u) * 4 + kl;
+      const bool ok = (st + u < s1) && (row < i1);
       const int rc = min(row, i1 - 1);
       const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * ldb];
-      a[u] = (row < i1 && aok) ? av : 0.0;
-      b[u] = (row < i1 && bok) ? bv : 0.0;
+      a[u] = (ok && aok) ? av : 0.0;
+      b[u] = (ok && bok) ? bv : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; u += 2) {
       acc0 = mfma_f64_16x16x4(a[u], b[u], acc0);
       acc1 = mfma_f64_16x16x4(a[u + 1], b[u + 1], acc1);
     }
-  }
-  for (; st < s1; ++st) {
-    const int row = i0 + st * 4 + kl;
-    const int rc = min(row, i1 - 1);
-    const double av = (double)acol[(int64_t)rc * lda], bv = (double)bcol[(int64_t)rc * ldb];
-    acc0 = mfma_f64_16x16x4((row < i1 && aok) ? av : 0.0, (row < i1 && bok) ? bv : 0.0, acc0);
   }
   dbl4 acc = acc0 + acc1;
   acc = reduce_waves(acc, red);
@@ -1050,8 +1046,13 @@ hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, c
                          int w, double alpha, double beta, double* gpart) {
   if (rows == 0 || w == 0) return hipSuccess;
   if (gpart != nullptr && w > 16) return hipErrorInvalidValue;  // the Gram epilogue needs whole rows in one tile
-  hipLaunchKernelGGL((k_rowmul<TA, TM, TO>), dim3((rows + 15) / 16, (w + 15) / 16), dim3(256), 0, s, rows, K, A, lda, M,
-                     ldm, out, ldo, w, alpha, beta, gpart);
+  const dim3 grid((rows + 15) / 16, (w + 15) / 16);
+  if (grid.x * grid.y < 256)
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, rows, K, A, lda, M, ldm, out, ldo, w,
+                       alpha, beta, gpart);
+  else
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 4>), grid, dim3(4 * kWave), 0, s, rows, K, A, lda, M, ldm, out, ldo, w,
+                       alpha, beta, gpart);
   return hipGetLastError();
 }
 
