@@ -18,20 +18,6 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Newton-Raphson refinement (two steps each, quadratic convergence from the hardware estimates)
-// of the reciprocal and of the reciprocal square root.
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
-}
-__device__ inline double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  return y;
-}
 
 constexpr int kHalfMax = kEigMax / 2;
 

@@ -412,14 +412,17 @@ __global__ __launch_bounds__(NW * kWave) void k_rowmul(int rows, int K, const TA
 
 // ------------------------------------------------------------------------------------------
 // Tall-skinny A^T B on the FP64 matrix cores, split over rows: workgroup (x, y, s) computes the
-// 16 x 16 tile (a0, b0) of partial[s] = sum_{i in split s} A[i, :]^T B[i, :]; the four waves take
-// contiguous quarters of the split's rows.  k_tn_finish (or the consumer) adds the splits.
+// 16 x 16 tile (a0, b0) of partial[s] = sum_{i in split s} A[i, :]^T B[i, :] (row stride ldp,
+// sstride apart); the NW waves take contiguous slices of the split's rows and are added in wave
+// order.  With several splits k_tn_finish (or the consumer) adds them; up to a few thousand rows
+// one split of sixteen waves per tile writes the result directly.
 // ------------------------------------------------------------------------------------------
-template <class TA, class TB>
-__global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restrict__ A, int lda, int na,
-                                                   const TB* __restrict__ B, int ldb, int nb,
-                                                   double* __restrict__ partial, int rows_per_split) {
-  __shared__ double red[3][kWave][4];
+template <class TA, class TB, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_tn_narrow(int rows, const TA* __restrict__ A, int lda, int na,
+                                                          const TB* __restrict__ B, int ldb, int nb,
+                                                          double* __restrict__ partial, int64_t sstride, int ldp,
+                                                          int rows_per_split) {
+  __shared__ double red[NW - 1][kWave][4];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16, s = blockIdx.z;
   const int i0 = s * rows_per_split, i1 = min(rows, i0 + rows_per_split);
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restric
   const TA* acol = A + min(aa, na - 1);
   const TB* bcol = B + min(bb, nb - 1);
   const int steps = (max(i1 - i0, 0) + 3) / 4;
-  const int per = (steps + 3) / 4;
+  const int per = (steps + NW - 1) / NW;
   const int s0 = wv * per, s1 = min(steps, s0 + per);
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int st = s0; st < s1; st += kUnroll) {  // full batches, the last one predicated
@@ -449,13 +452,13 @@ __global__ __launch_bounds__(256) void k_tn_narrow(int rows, const TA* __restric
     }
   }
   dbl4 acc = acc0 + acc1;
-  acc = reduce_waves(acc, red);
+  acc = reduce_waves<NW>(acc, red);
   if (wv == 0) {
-    double* P = partial + (int64_t)s * na * nb;
+    double* P = partial + (int64_t)s * sstride;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ra = a0 + (lane >> 4) + 4 * v, cb = b0 + (lane & 15);
-      if (ra < na && cb < nb) P[(int64_t)ra * nb + cb] = acc[v];
+      if (ra < na && cb < nb) P[(int64_t)ra * ldp + cb] = acc[v];
     }
   }
 }
@@ -723,7 +726,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   __shared__ double A[WM * ld];             // Gram, Schur complements, then the rows of R
   __shared__ double O[kCholTrsmRows][ld];   // stored output rows (for gout)
   __shared__ int keep[WM];
-  __shared__ double gdiag[WM], rdiag[WM];
+  __shared__ double gdiag[WM], rdiag[WM], rinv[WM];
   const int tid = threadIdx.x;
   int wa = w;
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
@@ -748,7 +751,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
     const double d = A[c * ld + c];
     const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
     if (ok) {
-      const double inv = 1.0 / d;
+      const double inv = rcp_nr(d);
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
         const int e = tid + k * kCholTrsmRows, i = e / WM, j = e % WM;
@@ -761,13 +764,18 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   }
   // rows of R in place: R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c] (j > c); zero rows and
   // columns for the dropped and inactive indices
-  for (int c = tid; c < WM; c += kCholTrsmRows) rdiag[c] = (c < wa && keep[c]) ? sqrt(A[c * ld + c]) : 0.0;
+  for (int c = tid; c < WM; c += kCholTrsmRows) {
+    const bool kc = c < wa && keep[c];
+    const double ri = kc ? rsq_nr(A[c * ld + c]) : 0.0;  // 1 / R[c][c]
+    rinv[c] = ri;
+    rdiag[c] = kc ? A[c * ld + c] * ri : 0.0;
+  }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int e = tid + k * kCholTrsmRows, c = e / WM, j = e % WM;
     double v = 0.0;
-    if (j >= c && rdiag[c] != 0.0 && rdiag[j] != 0.0) v = (j == c) ? rdiag[c] : A[c * ld + j] / rdiag[c];
+    if (j >= c && rdiag[c] != 0.0 && rdiag[j] != 0.0) v = (j == c) ? rdiag[c] : A[c * ld + j] * rinv[c];
     A[c * ld + j] = v;
   }
   __syncthreads();
@@ -783,8 +791,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
       double v = z[c];
 #pragma unroll
       for (int l = 0; l < c; ++l) v = fma(-z[l], A[l * ld + c], v);
-      const double rcc = A[c * ld + c];
-      z[c] = (rcc != 0.0) ? v / rcc : 0.0;
+      z[c] = v * rinv[c];  // 0 for a dropped column
     }
   }
   int q = 0;
@@ -1056,17 +1063,25 @@ hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, c
   return hipGetLastError();
 }
 
+// A^T B over at most this many rows runs as one split of sixteen waves per 16 x 16 tile
+constexpr int kTnDirectRows = 2048;
+
 template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
                             double* out, int ldo, double* partial, int64_t partial_cap) {
   if (na == 0 || nb == 0) return hipSuccess;
   const int gx = (na + 15) / 16, gy = (nb + 15) / 16;
+  if (rows <= kTnDirectRows) {
+    hipLaunchKernelGGL((k_tn_narrow<TA, TB, 16>), dim3(gx, gy, 1), dim3(16 * kWave), 0, s, rows, A, lda, na, B, ldb, nb,
+                       out, (int64_t)0, ldo, std::max(rows, 1));
+    return hipGetLastError();
+  }
   // enough workgroups to fill the chip: about 512 in total, at least 64 rows per split
   int splits = std::max(1, std::min(std::max(1, rows / 64), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
   const int rps = (rows + splits - 1) / splits;
-  hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
-                     partial, std::max(rps, 1));
+  hipLaunchKernelGGL((k_tn_narrow<TA, TB, 4>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
+                     partial, (int64_t)na * nb, nb, std::max(rps, 1));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tn_finish, dim3(grid1((int64_t)na * nb)), dim3(256), 0, s, partial, splits, na, nb, out, ldo);
@@ -1122,11 +1137,17 @@ hipError_t launch_tn_partial(hipStream_t s, int rows, const TA* A, int lda, int 
   *splits_out = 0;
   if (na == 0 || nb == 0) return hipSuccess;
   const int gx = (na + 15) / 16, gy = (nb + 15) / 16;
+  if (rows <= kTnDirectRows && (int64_t)na * nb <= partial_cap) {  // one split
+    hipLaunchKernelGGL((k_tn_narrow<TA, TB, 16>), dim3(gx, gy, 1), dim3(16 * kWave), 0, s, rows, A, lda, na, B, ldb, nb,
+                       partial, (int64_t)na * nb, nb, std::max(rows, 1));
+    *splits_out = 1;
+    return hipGetLastError();
+  }
   int splits = std::max(1, std::min(std::max(1, rows / 64), 512 / std::max(1, gx * gy)));
   while (splits > 1 && (int64_t)splits * na * nb > partial_cap) --splits;
   const int rps = (rows + splits - 1) / splits;
-  hipLaunchKernelGGL((k_tn_narrow<TA, TB>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
-                     partial, std::max(rps, 1));
+  hipLaunchKernelGGL((k_tn_narrow<TA, TB, 4>), dim3(gx, gy, splits), dim3(256), 0, s, rows, A, lda, na, B, ldb, nb,
+                     partial, (int64_t)na * nb, nb, std::max(rps, 1));
   *splits_out = splits;
   return hipGetLastError();
 }

@@ -18,6 +18,22 @@ constexpr int kScalars = 64;  // doubles in the device->host readback buffer
 constexpr int kStageDoubles = 4096;  // pinned staging doubles for small device->host copies
 constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
+// Newton-Raphson refinement (two steps each, quadratic convergence from the hardware estimates)
+// of the double reciprocal and reciprocal square root: short dependent chains for the small
+// one-workgroup factorisations, where an IEEE division sits on the critical path.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+
 // sum_{t < n} p[t * stride] in a fixed order (16 interleaved partial sums, then a fixed tree),
 // with 16 independent loads in flight: the split sums of the tall products are latency bound
 // when each load waits for the previous add.
