@@ -119,14 +119,17 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
                                                          const int32_t* __restrict__ idx,
                                                          const int32_t* __restrict__ vperm, const T* __restrict__ val,
                                                          const T* __restrict__ D, int ldd, T* __restrict__ out,
-                                                         int ldo, int w) {
+                                                         int ldo, int w, const int32_t* __restrict__ seg_lo,
+                                                         const int32_t* __restrict__ seg_hi,
+                                                         const int32_t* __restrict__ skip) {
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= nrows) return;
+  if (skip != nullptr && skip[row] != 0) return;
   T acc[WN];
 #pragma unroll
   for (int c = 0; c < WN; ++c) acc[c] = (T)0;
-  const int p0 = ptr[row], p1 = ptr[row + 1];
+  const int p0 = seg_lo ? seg_lo[row] : ptr[row], p1 = seg_lo ? seg_hi[row] : ptr[row + 1];
   for (int p = p0 + lane; p < p1; p += kWave) {
     const T v = val[vperm ? vperm[p] : p];
     const T* d = D + (int64_t)idx[p] * ldd;
@@ -144,16 +147,22 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
 // Wide blocks: lanes over output columns (CPL = 4 per lane), nonzeros broadcast across the wave.
 // Four nonzeros' rows of D are loaded before their products issue; with VEC the four columns of a
 // lane come as one 16-byte (float) or two 16-byte (double) loads (ldd % 4 == 0, D 16-byte aligned).
+// Segment forms: with seg_lo / seg_hi, "row" s is the position range [seg_lo[s], seg_hi[s]) and
+// writes out row s (the chunk partials of long segments); with skip, rows whose flag is set are
+// left to that chunked form.
 template <int CPL, bool VEC, class T>
 __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ vperm, const T* __restrict__ val,
                                                        const T* __restrict__ D, int ldd, T* __restrict__ out, int ldo,
-                                                       int w) {
+                                                       int w, const int32_t* __restrict__ seg_lo,
+                                                       const int32_t* __restrict__ seg_hi,
+                                                       const int32_t* __restrict__ skip) {
   static_assert(CPL == 4, "four columns per lane");
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= nrows) return;
+  if (skip != nullptr && skip[row] != 0) return;
   const int c0 = blockIdx.y * (kWave * CPL) + lane * CPL;
   const bool vec = VEC && (c0 + CPL <= w);
   T acc[CPL];
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
       for (int c = 0; c < CPL; ++c) d[c] = (c0 + c < w) ? src[c] : (T)0;
     }
   };
-  const int p0 = ptr[row], p1 = ptr[row + 1];
+  const int p0 = seg_lo ? seg_lo[row] : ptr[row], p1 = seg_lo ? seg_hi[row] : ptr[row + 1];
   for (int base = p0; base < p1; base += kWave) {
     const int p = base + lane;
     int my_i = 0;
@@ -222,6 +231,18 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
 #pragma unroll
   for (int c = 0; c < CPL; ++c)
     if (c0 + c < w) out[(int64_t)row * ldo + c0 + c] = acc[c];
+}
+
+// out[lcol[t], c] = sum of the chunk partials P[q, c], q = lfirst[t] .. lfirst[t+1]-1, for the long
+// segments t (fixed order)
+template <class T>
+__global__ __launch_bounds__(256) void k_seg_chunk_sum(const int32_t* __restrict__ lcol,
+                                                       const int32_t* __restrict__ lfirst, const T* __restrict__ P,
+                                                       int ldp, T* __restrict__ out, int ldo, int w) {
+  const int t = blockIdx.y, c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= w) return;
+  const int q0 = lfirst[t];
+  out[(int64_t)lcol[t] * ldo + c] = split_sum<T>(P + (int64_t)q0 * ldp + c, lfirst[t + 1] - q0, ldp);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1001,23 +1022,34 @@ hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, i
 
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w) {
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, const SegChunks* ch) {
   if (nrows == 0 || w == 0) return hipSuccess;
-  const unsigned gx = (unsigned)((nrows + 3) / 4);
-  if (w <= kNarrow) {
-    hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, T>), dim3(gx), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D,
-                       ldd, out, ldo, w);
-  } else {
-    constexpr int CPL = 4;
-    const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
-    const bool vec = (ldd % CPL == 0) && ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
-    if (vec)
-      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val, D,
-                         ldd, out, ldo, w);
+  constexpr int CPL = 4;
+  const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
+  const bool vec = (ldd % CPL == 0) && ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
+  // one wave per segment: segments [ptr[q], ptr[q+1]) or, with lo given, [lo[q], hi[q])
+  auto segments = [&](int nseg, T* o, int ldo_, const int32_t* lo, const int32_t* hi, const int32_t* skip) {
+    const unsigned gx = (unsigned)((nseg + 3) / 4);
+    if (w <= kNarrow)
+      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, T>), dim3(gx), dim3(256), 0, s, nseg, ptr, idx, vperm, val, D,
+                         ldd, o, ldo_, w, lo, hi, skip);
+    else if (vec)
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+                         D, ldd, o, ldo_, w, lo, hi, skip);
     else
-      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, false, T>), dim3(gx, gy), dim3(256), 0, s, nrows, ptr, idx, vperm, val,
-                         D, ldd, out, ldo, w);
-  }
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, false, T>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+                         D, ldd, o, ldo_, w, lo, hi, skip);
+    return hipGetLastError();
+  };
+  const bool chunked = ch != nullptr && ch->nlong > 0 && w <= ch->ldp;
+  hipError_t e = segments(nrows, out, ldo, nullptr, nullptr, chunked ? ch->skip : nullptr);
+  if (e != hipSuccess || !chunked) return e;
+  // long segments: one wave per chunk into the partial rows, then the chunks of each segment added in order
+  T* P = reinterpret_cast<T*>(ch->P);
+  e = segments(ch->nchunk, P, ch->ldp, ch->lo, ch->hi, nullptr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_seg_chunk_sum<T>, dim3((w + 255) / 256, ch->nlong), dim3(256), 0, s, ch->lcol, ch->lfirst, P,
+                     ch->ldp, out, ldo, w);
   return hipGetLastError();
 }
 
@@ -1272,7 +1304,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
 #define SVT_INST(T)                                                                                                   \
   template hipError_t launch_omega<T>(hipStream_t, T*, int, int, int, int, uint64_t, uint64_t, uint64_t);             \
   template hipError_t launch_seg_spmm<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*, const T*,  \
-                                         const T*, int, T*, int, int);                                                \
+                                         const T*, int, T*, int, int, const SegChunks*);                              \
   template hipError_t launch_spmm_t_tiled<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,         \
                                              const T*, int, int, T*, int, double*, int64_t);                          \
   template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \

@@ -265,7 +265,8 @@ struct Engine {
       HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo));
       return SVT_OK;
     }
-    HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w));
+    HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w,
+                              &h->csc_long));
     return SVT_OK;
   }
 
@@ -1091,7 +1092,9 @@ void release(Handle* h) {
                   h->y_next,
                   h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->G2, h->small, h->Minv, h->prenorm, h->EV, h->EZ,
                   h->EZ2,
-                  h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal};
+                  h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal,
+                  h->csc_long.lo, h->csc_long.hi, h->csc_long.lcol, h->csc_long.lfirst, h->csc_long.skip,
+                  h->csc_long.P};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
@@ -1246,6 +1249,24 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     }
   cstart.push_back((int32_t)nnz);
 
+  // sparse path: columns longer than kSegLong positions are cut into chunks of kSegLong, so W = Y^T D
+  // on power-law columns is not serialised on one wave per column
+  std::vector<int32_t> llo, lhi, lcol, lfirst, lskip;
+  if (!dense_y) {
+    for (int64_t j = 0; j < n; ++j) {
+      if (colptr[j + 1] - colptr[j] <= kSegLong) continue;
+      if (lskip.empty()) lskip.assign(n, 0);
+      lskip[j] = 1;
+      lfirst.push_back((int32_t)llo.size());
+      lcol.push_back((int32_t)j);
+      for (int64_t q = colptr[j]; q < colptr[j + 1]; q += kSegLong) {
+        llo.push_back((int32_t)q);
+        lhi.push_back((int32_t)std::min<int64_t>(q + kSegLong, colptr[j + 1]));
+      }
+    }
+    if (!lcol.empty()) lfirst.push_back((int32_t)llo.size());
+  }
+
   h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
   h->w_cap = 64;
   h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
@@ -1296,6 +1317,18 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
   if (dense_y) A(dalloc_bytes(&h->yT, (size_t)m * n * es));
   h->nchunks = (int32_t)ccol.size();
+  if (!lcol.empty()) {
+    SegChunks& L = h->csc_long;
+    L.nlong = (int32_t)lcol.size();
+    L.nchunk = (int32_t)llo.size();
+    L.ldp = h->r_cap;
+    A(dalloc(&L.lo, llo.size()));
+    A(dalloc(&L.hi, lhi.size()));
+    A(dalloc(&L.lcol, lcol.size()));
+    A(dalloc(&L.lfirst, lfirst.size()));
+    A(dalloc(&L.skip, lskip.size()));
+    A(dalloc_bytes(&L.P, (size_t)L.nchunk * L.ldp * es));
+  }
   A(dalloc(&h->cstart, cstart.size()));
   A(dalloc(&h->ccol, std::max<size_t>(ccol.size(), 1)));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
@@ -1317,6 +1350,13 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (!tstart.empty()) up(h->tstart, tstart.data(), tstart.size() * sizeof(int32_t));
   up(h->cstart, cstart.data(), cstart.size() * sizeof(int32_t));
   if (!ccol.empty()) up(h->ccol, ccol.data(), ccol.size() * sizeof(int32_t));
+  if (!lcol.empty()) {
+    up(h->csc_long.lo, llo.data(), llo.size() * sizeof(int32_t));
+    up(h->csc_long.hi, lhi.data(), lhi.size() * sizeof(int32_t));
+    up(h->csc_long.lcol, lcol.data(), lcol.size() * sizeof(int32_t));
+    up(h->csc_long.lfirst, lfirst.data(), lfirst.size() * sizeof(int32_t));
+    up(h->csc_long.skip, lskip.data(), lskip.size() * sizeof(int32_t));
+  }
   if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * es, h->stream);
   if (e == hipSuccess && h->yT) e = hipMemsetAsync(h->yT, 0, (size_t)m * n * es, h->stream);
   // factor buffers start at zero: the fused update reads whole 16-byte vectors of a factor row and

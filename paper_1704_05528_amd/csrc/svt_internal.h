@@ -58,6 +58,17 @@ __device__ inline T split_sum(const T* __restrict__ p, int n, int64_t stride) {
   return acc[0];
 }
 
+// Long segments of a segment-gather product cut into chunks (device arrays): chunk q covers
+// positions [lo[q], hi[q]); long segment t = lcol[t] owns chunks lfirst[t] .. lfirst[t+1]-1;
+// skip[row] != 0 marks the rows the chunked form computes; P holds nchunk partial rows of ldp
+// values of the storage type.
+struct SegChunks {
+  int32_t nlong = 0, nchunk = 0, ldp = 0;
+  int32_t *lo = nullptr, *hi = nullptr, *lcol = nullptr, *lfirst = nullptr, *skip = nullptr;
+  void* P = nullptr;
+};
+constexpr int kSegLong = 2048;  // a segment longer than this is cut into chunks of this many positions
+
 // Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
 // marked (T) hold the storage type of the precision form: double (SVT_FP64) or float
 // (SVT_MIXED); the Gram matrices, the eigensolver and all reductions are double in both.
@@ -78,6 +89,7 @@ struct Handle {
   int32_t *cstart = nullptr, *ccol = nullptr;    // load-balanced chunks of the CSC order (fused update)
   void* yT = nullptr;  // (T) n x m dense transposed copy of Y (zeros off Lambda) when >= 25% is observed
   int32_t nchunks = 0;
+  SegChunks csc_long;  // long columns of Y for W = Y^T D on the sparse path
   std::vector<int64_t> user2csc;                 // caller order -> CSC position (host)
 
   // values on Lambda, CSC order (T)
@@ -166,10 +178,13 @@ struct Handle {
 template <class T>
 hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk, uint64_t it);
 
-// out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w]
+
+// out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w].  With
+// ch, the long segments (over kSegLong positions) run as kSegLong chunks spread over the chip,
+// their partial sums in ch->P, instead of on one wave each.
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w);
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, const SegChunks* ch = nullptr);
 
 // LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
 // position of its first entry in each row tile (n x (tiled_row_tiles(m) + 1) int32)

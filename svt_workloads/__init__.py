@@ -13,7 +13,8 @@ import math
 
 import numpy as np
 
-__all__ = ["Workload", "planted", "image", "ratings", "image_adjoint", "large_sparse", "tiny_dense", "by_name"]
+__all__ = ["Workload", "planted", "image", "ratings", "image_adjoint", "large_sparse", "tiny_dense", "heavy_columns",
+           "by_name"]
 
 
 @dataclass
@@ -218,6 +219,25 @@ def tiny_dense(m, n, rank, frac, seed, scale=1.0, tau=None, delta=None, tol=1e-4
     tau = 5.0 * math.sqrt(m * n) * scale if tau is None else tau
     delta = 1.2 * m * n / count if delta is None else delta
     return Workload("tiny", m, n, rows, cols, a, tau, delta, tol, A=A)
+
+
+def heavy_columns(m, n, rank, heavy, base, seed, tau=None, delta=None, tol=1e-4):
+    """Planted rank-`rank` problem whose first len(heavy) columns hold heavy[t] observed rows each and
+    every other column `base` rows (a sparse pattern with a few very long columns, as in power-law
+    degree distributions)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n))
+    lin = []
+    for j in range(n):
+        cnt = heavy[j] if j < len(heavy) else base
+        rows = rng.choice(m, size=cnt, replace=False)
+        lin.append(rows.astype(np.int64) * n + j)
+    lin = np.sort(np.concatenate(lin))
+    rows, cols = (lin // n).astype(np.int32), (lin % n).astype(np.int32)
+    a = A[rows, cols].astype(np.float64)
+    tau = 5.0 * math.sqrt(m * n) if tau is None else tau
+    delta = 1.2 * m * n / lin.size if delta is None else delta
+    return Workload("heavy_columns", m, n, rows, cols, a, tau, delta, tol, A=A)
 
 
 def by_name(name, **kw):

@@ -76,6 +76,21 @@ def test_free_run_with_replayed_decisions(gpu_lib, m, n, rank, frac, seed, extra
     assert s["iter"] == infos[-1].it
 
 
+@pytest.mark.parametrize("extra", [{"t0": 20}, {"t0": 6, "dt": 4}])
+def test_heavy_columns_chunked_gather(gpu_lib, extra):
+    """1% observed with three columns of 9000, 5000 and 2600 rows: Y^T Q takes the gather path
+    with the long columns cut into chunks (16-wide and wider blocks), 20 iterations at 1e-10."""
+    w = W.heavy_columns(30000, 60, 3, (9000, 5000, 2600), 40, seed=51, delta=1.2)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=51, maxit=20, **extra)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    h = _gpu(gpu_lib, w, k0, seed=51, maxit=20, **extra)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        st = h.iterate(1)
+        _compare_step(st, info, h, w, ("heavy", info.it))
+
+
 def test_free_run_decisions_agree(gpu_lib):
     """Without replay the device takes the same discrete decisions while margins are clear."""
     w = W.tiny_dense(100, 80, 3, 0.4, seed=41)
