@@ -1126,6 +1126,9 @@ hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, dou
   (void)partial;
   (void)partial_cap;
   if (na == 0) return hipSuccess;
+  // wide blocks over many rows: 64 x 64 LDS-staged tiles (16 x 16 tiles re-read every column
+  // block na / 16 times, and their operand traffic dominates there)
+  if ((int64_t)rows * na >= kGramTiledMin) return launch_gram_tn<T>(s, rows, A, lda, na, G, ldg);
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
   hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(kGramWaves * kWave), 0, s, rows, A, lda, na, G, ldg, nt);

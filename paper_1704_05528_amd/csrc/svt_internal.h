@@ -208,6 +208,13 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
 // dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation)
 template <class T>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc);
+// G = A^T A (A rows x na row-major, G na x na double) from 64 x 64 tiles staged in LDS on the
+// matrix cores; gram_tn_tiles(na) is the number of workgroups it launches.  launch_gram takes it
+// from rows * na >= kGramTiledMin on.
+constexpr int64_t kGramTiledMin = 40'000'000;
+template <class T>
+hipError_t launch_gram_tn(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg);
+int gram_tn_tiles(int na);
 // yT[j * ldy + i] = y(i, j) on Lambda (the other entries of yT are left untouched)
 template <class T>
 hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const T* y, T* yT,

@@ -10,6 +10,8 @@ import pytest
 
 import svt_workloads as W
 from oracle import Params, Problem, State, initial_state, svt_run, svt_step
+from oracle.svt import kicking_k0, spectral_norm
+from paper_1704_05528_amd._capi import SVT_F_EIG_INEXACT
 
 pytestmark = pytest.mark.gpu
 
@@ -122,6 +124,33 @@ def test_step_parity_from_oracle_state(gpu_lib):
     s = h.get_state()
     assert rel_err(s["y"], nxt.y) <= TOL
     # the device keeps an unrotated basis: compare projectors
+    Pg = s["Q"] @ s["Q"].T
+    Po = nxt.Q @ nxt.Q.T
+    assert np.abs(Pg - Po).max() <= 1e-10
+
+
+def test_wide_basis_tiled_gram(gpu_lib):
+    """A 1100-column basis on 36400 columns of Y (rows * r above the cut-over): the Gram matrix
+    W^T W comes from the 64 x 64 LDS-tiled kernel.  One step from a given state on both sides
+    (k = 9, with clear gaps at the threshold: in a dense part of the spectrum a cold-started
+    subspace iteration can stop at its product cap, which SVT_F_EIG_INEXACT reports)."""
+    m, n, r = 1200, 36400, 1100
+    w = W.tiny_dense(m, n, 5, 0.01, seed=61, delta=1.2)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=61, maxit=10, r_max=m)
+    rng = np.random.default_rng(62)
+    Q0, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    k0 = kicking_k0(w.tau, w.delta, spectral_norm(m, n, w.rows, w.cols, w.a))
+    state = State(it=4, y=1.2 * k0 * w.delta * w.a, Q=Q0, eps_thr=0.99, eps_min=math.inf)
+    nxt, info = svt_step(prob, p, state)
+    assert info.blocks == 0 and info.r == r
+    h = _gpu(gpu_lib, w, k0, seed=61, maxit=10, r_max=m)
+    h.set_state(state.y, state.Q, state.eps_thr, state.eps_min, state.it)
+    st = h.iterate(1)
+    assert info.k > 4 and not (st.flags & SVT_F_EIG_INEXACT)
+    _compare_step(st, info, h, w, "wide gram")
+    s = h.get_state()
+    assert rel_err(s["y"], nxt.y) <= TOL
     Pg = s["Q"] @ s["Q"].T
     Po = nxt.Q @ nxt.Q.T
     assert np.abs(Pg - Po).max() <= 1e-10
