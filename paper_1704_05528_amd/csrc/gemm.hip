@@ -2,6 +2,8 @@
 // of the entries are observed, Y is kept as a dense transposed copy (zeros off Lambda) and
 // Y^T Q becomes a plain dense product.  W is the transpose of the projection B of the sampled
 // basis (Alg. 1, Sec. 2.1), formed on the SVT iterate in Alg. 2-4.
+#include <type_traits>
+
 #include "svt_internal.h"
 
 namespace svt {
@@ -14,20 +16,21 @@ namespace {
 // A[l % 16][l / 16] and the B operand as B[l / 16][l % 16] in lane l; the f32 result holds rows
 // 4 (l / 16) + v, the f64 result rows (l / 16) + 4 v, v = 0..3, of column l % 16.
 //
-// A workgroup owns one 64 x 32 tile of C and is KG groups of four waves; group g takes the
-// 32-wide K chunks g, g + KG, g + 2 KG, ... (each wave 16 rows x 32 columns, two matrix
-// instructions per k-step sharing the A operand), staging its chunk in its own LDS area and
-// loading its next chunk into registers while the current one is consumed.  The groups'
-// accumulators are added in group order at the end (deterministic).  Splitting K inside the
-// workgroup keeps KG times more loads in flight per tile than one group alone: at the sizes of
-// the basis (a few hundred columns) there are fewer tiles than compute units, and one group
-// per tile would leave every CU waiting on memory latency.
+// A workgroup owns one 64 x GN tile of C (GN = 32 or 48) and is KG groups of four waves; group g
+// takes the 32-wide K chunks g, g + KG, g + 2 KG, ... (each wave 16 rows x GN columns, GN / 16
+// matrix instructions per k-step sharing the A operand), staging its chunk in its own LDS area
+// while its next DEPTH chunks are in flight in registers.  The groups' accumulators are added
+// in group order at the end (deterministic).  Splitting K inside the workgroup keeps KG times
+// more loads in flight per tile than one group alone: at the sizes of the basis (a few hundred
+// columns) there are few tiles per compute unit, and one group per tile would leave every CU
+// waiting on memory latency.  The launcher takes the tile width that puts the fewest tile
+// columns on the busiest CU (one round of 256 tiles of 48 rather than two of 32, say).
 //
 // Tiles are numbered row-block major and dealt to the eight XCDs in contiguous ranges (the
 // hardware deals consecutive workgroups round-robin over the XCDs), so the workgroups that
 // share a row block of A share one L2.
 // ------------------------------------------------------------------------------------------
-constexpr int kGM = 64, kGN = 32, kGK = 32;
+constexpr int kGM = 64, kGK = 32;
 constexpr int kXcd = 8;
 
 template <class T>
@@ -45,11 +48,15 @@ struct Mfma16<double> {
   __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-// K groups per workgroup: 4 for float (1024 threads), 2 for double (512 threads); about 50 KB of
-// LDS either way
+// K groups per workgroup: 4 for float (1024 threads), 2 for double (512 threads); register
+// prefetch depth: two chunks for float, one for double (two would spill)
 template <class T>
 constexpr int gemm_kgroups() {
   return sizeof(T) == 4 ? 4 : 2;
+}
+template <class T>
+constexpr int gemm_depth() {
+  return sizeof(T) == 4 ? 2 : 1;
 }
 
 // Tile of workgroup id when `total` tiles are dealt round-robin over the XCDs: XCD x receives the
@@ -59,66 +66,85 @@ __device__ inline int xcd_tile(int id, int total) {
   return x * per + min(x, rem) + slot;
 }
 
-template <class T>
-__global__ __launch_bounds__(1024) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A, int lda,
-                                                  const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc,
-                                                  int tiles_n) {
+template <class T, int GN>
+__global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A,
+                                                                     int lda, const T* __restrict__ B, int ldb,
+                                                                     T* __restrict__ C, int ldc, int tiles_n) {
   using MM = Mfma16<T>;
-  constexpr int KG = gemm_kgroups<T>();
-  constexpr int kAS = kGM * (kGK + 1), kBS = kGK * (kGN + 1);
-  static_assert((KG - 1) * 8 * 256 <= KG * (kAS + kBS), "the reduction area must fit in the staging area");
+  constexpr int KG = gemm_kgroups<T>(), DEPTH = gemm_depth<T>();
+  constexpr int NT = GN / 16, BL = kGK * GN / 256;  // column blocks; B elements per thread and chunk
+  constexpr int kAS = kGM * (kGK + 1), kBS = kGK * (GN + 1);
+  static_assert((KG - 1) * 4 * NT * 256 <= KG * (kAS + kBS), "the reduction area must fit in the staging area");
   __shared__ T smem[KG * (kAS + kBS)];
   const int tid = threadIdx.x & 255, kg = threadIdx.x >> 8, lane = tid & (kWave - 1), wv = tid / kWave;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int m0 = (tile / tiles_n) * kGM, n0 = (tile % tiles_n) * kGN;
+  const int m0 = (tile / tiles_n) * kGM, n0 = (tile % tiles_n) * GN;
   T* As = smem + kg * (kAS + kBS);  // [kGM][kGK + 1]
-  T* Bs = As + kAS;                  // [kGK][kGN + 1]
-  // global -> register staging: A chunk 64 x 32 (8 per thread), B chunk 32 x 32 (4 per thread)
-  T ra[8], rb[4];
-  auto load_chunk = [&](int k0) {
+  T* Bs = As + kAS;                  // [kGK][GN + 1]
+  // global -> register staging, DEPTH chunks: A chunk 64 x 32 (8 per thread), B chunk 32 x GN
+  T ra[DEPTH][8], rb[DEPTH][BL];
+  auto load_chunk = [&](auto P, int k0) {
+    constexpr int p = decltype(P)::value;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = tid + u * 256, i = e / kGK, kk = e % kGK;
       const int gi = m0 + i, gk = k0 + kk;
-      ra[u] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : (T)0;
+      ra[p][u] = (gi < M && gk < K) ? A[(int64_t)gi * lda + gk] : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + u * 256, kk = e / kGN, j = e % kGN;
+    for (int u = 0; u < BL; ++u) {
+      const int e = tid + u * 256, kk = e / GN, j = e % GN;
       const int gk = k0 + kk, gj = n0 + j;
-      rb[u] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : (T)0;
+      rb[p][u] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : (T)0;
     }
   };
-  auto store_chunk = [&]() {
+  auto store_chunk = [&](auto P) {
+    constexpr int p = decltype(P)::value;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = tid + u * 256;
-      As[(e / kGK) * (kGK + 1) + e % kGK] = ra[u];
+      As[(e / kGK) * (kGK + 1) + e % kGK] = ra[p][u];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < BL; ++u) {
       const int e = tid + u * 256;
-      Bs[(e / kGN) * (kGN + 1) + e % kGN] = rb[u];
+      Bs[(e / GN) * (GN + 1) + e % GN] = rb[p][u];
     }
   };
-  typename MM::acc_t acc[2];
+  typename MM::acc_t acc[NT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) acc[t] = typename MM::acc_t{0, 0, 0, 0};
+  for (int t = 0; t < NT; ++t) acc[t] = typename MM::acc_t{0, 0, 0, 0};
   const int ar = wv * 16 + (lane & 15), kl = lane >> 4, bc = lane & 15;
   const int nchunk = (K + kGK - 1) / kGK, rounds = (nchunk + KG - 1) / KG;
-  int c = kg;
-  if (c < nchunk) load_chunk(c * kGK);
-  for (int rd = 0; rd < rounds; ++rd, c += KG) {  // rounds is uniform over the workgroup
+  // one round: stage chunk c from register buffer P, refill P with chunk c + DEPTH KG, multiply
+  auto round = [&](auto P, int c) {
     __syncthreads();  // the previous chunk has been consumed
-    if (c < nchunk) store_chunk();
+    if (c < nchunk) store_chunk(P);
     __syncthreads();
-    if (c + KG < nchunk) load_chunk((c + KG) * kGK);
+    if (c + DEPTH * KG < nchunk) load_chunk(P, (c + DEPTH * KG) * kGK);
     if (c < nchunk) {
 #pragma unroll
       for (int ks = 0; ks < kGK / 4; ++ks) {
         const T a = As[ar * (kGK + 1) + ks * 4 + kl];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[t] = MM::mma(a, Bs[(ks * 4 + kl) * (kGN + 1) + 16 * t + bc], acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = MM::mma(a, Bs[(ks * 4 + kl) * (GN + 1) + 16 * t + bc], acc[t]);
+      }
+    }
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, DEPTH - 1>;
+  int c = kg;
+  if (c < nchunk) load_chunk(B0{}, c * kGK);
+  if constexpr (DEPTH == 2) {
+    if (c + KG < nchunk) load_chunk(B1{}, (c + KG) * kGK);
+  }
+  for (int rd = 0; rd < rounds; rd += DEPTH) {  // rounds is uniform over the workgroup
+    round(B0{}, c);
+    c += KG;
+    if constexpr (DEPTH == 2) {
+      if (rd + 1 < rounds) {
+        round(B1{}, c);
+        c += KG;
       }
     }
   }
@@ -126,9 +152,9 @@ __global__ __launch_bounds__(1024) void k_gemm_nn(int M, int N, int K, const T* 
   __syncthreads();
   if (kg > 0) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) smem[((kg - 1) * 8 + t * 4 + v) * 256 + tid] = acc[t][v];
+      for (int v = 0; v < 4; ++v) smem[((kg - 1) * 4 * NT + t * 4 + v) * 256 + tid] = acc[t][v];
   }
   __syncthreads();
   if (kg > 0) return;
@@ -137,11 +163,11 @@ __global__ __launch_bounds__(1024) void k_gemm_nn(int M, int N, int K, const T* 
     const int row = m0 + wv * 16 + MM::row(lane, v);
     if (row >= M) continue;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
       const int col = n0 + 16 * t + bc;
       T sum = acc[t][v];
 #pragma unroll
-      for (int g = 1; g < KG; ++g) sum += smem[((g - 1) * 8 + t * 4 + v) * 256 + tid];
+      for (int g = 1; g < KG; ++g) sum += smem[((g - 1) * 4 * NT + t * 4 + v) * 256 + tid];
       if (col < N) C[(int64_t)row * ldc + col] = sum;
     }
   }
@@ -165,9 +191,19 @@ template <class T>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc) {
   if (M == 0 || N == 0) return hipSuccess;
   if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
-  const int tm = (M + kGM - 1) / kGM, tn = (N + kGN - 1) / kGN;
-  hipLaunchKernelGGL(k_gemm_nn<T>, dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C, ldc,
-                     tn);
+  const int tm = (M + kGM - 1) / kGM;
+  // tile columns on the busiest of the 256 CUs, rounds of 256 tiles: 48-wide tiles when that is
+  // fewer than with 32-wide ones
+  auto load = [&](int gn) { return (int64_t)((tm * ((N + gn - 1) / gn) + 255) / 256) * gn; };
+  if (load(48) < load(32)) {
+    const int tn = (N + 47) / 48;
+    hipLaunchKernelGGL((k_gemm_nn<T, 48>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+                       C, ldc, tn);
+  } else {
+    const int tn = (N + 31) / 32;
+    hipLaunchKernelGGL((k_gemm_nn<T, 32>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+                       C, ldc, tn);
+  }
   return hipGetLastError();
 }
 

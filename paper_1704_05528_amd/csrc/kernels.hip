@@ -609,6 +609,8 @@ __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double
   if (c < w) out[c] = sqrt(fmax(G[(int64_t)c * ldg + c], 0.0));
 }
 
+constexpr int kBlockCholThreads = 1024;
+
 // ------------------------------------------------------------------------------------------
 // Cholesky factor of a block's Gram (CholeskyQR with column dropping), one workgroup, double.
 // Input: the w x w Gram of the projected block and the column norms before projection.
@@ -621,26 +623,27 @@ __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double
 // only the first wk_in columns take part (second pass of CholeskyQR2 reads the count of the
 // first pass from scal[wk_slot_in]).  scal[slot] = wk.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ gram, int ldg, int splits,
-                                                    int64_t sstride, int w, const double* __restrict__ prenorm,
-                                                    double drop_tol, double dep_tol, double* __restrict__ Rout,
-                                                    int ldm, double* scal, int slot, int wk_slot_in) {
+__global__ __launch_bounds__(kBlockCholThreads) void k_block_chol(const double* __restrict__ gram, int ldg,
+                                                                  int splits, int64_t sstride, int w,
+                                                                  const double* __restrict__ prenorm, double drop_tol,
+                                                                  double dep_tol, double* __restrict__ Rout, int ldm,
+                                                                  double* scal, int slot, int wk_slot_in) {
   extern __shared__ double sm[];
   const int ld = w + 1;
   double* A = sm;  // w x (w + 1): Gram, overwritten by the Schur complements / rows of R
   __shared__ int keep[kEigMax];
   __shared__ double gdiag[kEigMax];
-  const int tid = threadIdx.x;
+  // a 32 x 32 grid of threads: row ty, column tx
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   int wa = w;
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
   // the Gram is the sum of `splits` partial Grams (sstride apart), added in a fixed order
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int i = e / w, j = e % w;
-    double v = 0.0;
-    if (i < wa && j < wa)
-      v = split_sum(gram + (int64_t)i * ldg + j, splits, sstride);
-    A[i * ld + j] = v;
-  }
+  for (int i = ty; i < w; i += 32)
+    for (int j = tx; j < w; j += 32) {
+      double v = 0.0;
+      if (i < wa && j < wa) v = split_sum(gram + (int64_t)i * ldg + j, splits, sstride);
+      A[i * ld + j] = v;
+    }
   __syncthreads();
   for (int c = tid; c < w; c += blockDim.x) {
     const double g = (c < wa) ? fmax(A[c * ld + c], 0.0) : 0.0;
@@ -651,34 +654,37 @@ __global__ __launch_bounds__(256) void k_block_chol(const double* __restrict__ g
   __syncthreads();
   // Right-looking Cholesky on the upper triangle.  At step c every thread reads the pivot
   // d = A[c][c] (the Schur complement) and takes the same keep decision; a kept column then
-  // updates the trailing upper triangle A[i][j] -= A[c][i] A[c][j] / d, i, j > c.
+  // updates the trailing upper triangle A[i][j] -= A[c][i] A[c][j] / d, i, j > c.  The decision
+  // is uniform, so a step without an update needs no barrier, and keep[c] (read only after the
+  // loop) is cleared without one.
   for (int c = 0; c < wa; ++c) {
-    if (!keep[c]) continue;  // uniform: keep[] only changes below, after a barrier
+    if (!keep[c]) continue;  // uniform: keep[c] is only written at step c itself
     const double d = A[c * ld + c];
     const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
-    if (ok) {
-      const int L = wa - c - 1;
-      const double inv = 1.0 / d;
-      for (int e = tid; e < L * L; e += blockDim.x) {
-        const int i = c + 1 + e / L, j = c + 1 + e % L;
-        if (i <= j) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
-      }
+    if (!ok) {
+      if (tid == 0) keep[c] = 0;
+      continue;
+    }
+    const double inv = 1.0 / d;
+    for (int i = c + 1 + ty; i < wa; i += 32) {
+      const double aci = A[c * ld + i];
+      for (int j = c + 1 + tx; j < wa; j += 32)
+        if (i <= j) A[i * ld + j] -= aci * A[c * ld + j] * inv;
     }
     __syncthreads();
-    if (!ok && tid == 0) keep[c] = 0;
-    __syncthreads();
   }
+  __syncthreads();
   // Rout: row c of the factor for kept c (R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c]);
   // a dropped column keeps an all-zero row and column, R[c][c] = 0 marking it for the row solve.
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int c = e / w, j = e % w;
-    double v = 0.0;
-    if (c < wa && j < wa && j >= c && keep[c] && keep[j]) {
-      const double rc = sqrt(A[c * ld + c]);
-      v = (j == c) ? rc : A[c * ld + j] / rc;
+  for (int c = ty; c < w; c += 32)
+    for (int j = tx; j < w; j += 32) {
+      double v = 0.0;
+      if (c < wa && j < wa && j >= c && keep[c] && keep[j]) {
+        const double rc = sqrt(A[c * ld + c]);
+        v = (j == c) ? rc : A[c * ld + j] / rc;
+      }
+      Rout[(int64_t)c * ldm + j] = v;
     }
-    Rout[(int64_t)c * ldm + j] = v;
-  }
   if (tid == 0) {
     int q = 0;
     for (int c = 0; c < wa; ++c) q += keep[c];
@@ -1199,7 +1205,8 @@ hipError_t launch_block_chol(hipStream_t s, const double* gram, int ldg, int w, 
     attr_set = true;
   }
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(256), lds, s, gram, ldg, splits, sstride, w, prenorm, drop_tol,
+  hipLaunchKernelGGL(k_block_chol, dim3(1), dim3(kBlockCholThreads), lds, s, gram, ldg, splits, sstride, w, prenorm,
+                     drop_tol,
                      dep_tol, Rout, ldm, scal, slot, wk_slot_in);
   return hipGetLastError();
 }
