@@ -739,17 +739,18 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict
 // second pass needs no separate Gram launch.  Workgroup 0 writes the kept count to scal[slot];
 // with wk_slot_in >= 0 only the first scal[wk_slot_in] columns take part (second pass).
 // ------------------------------------------------------------------------------------------
-constexpr int kCholTrsmRows = 64;
+constexpr int kCholTrsmRows = 64;      // rows solved per workgroup
+constexpr int kCholTrsmThreads = 256;  // threads that load and factor the Gram
 
 template <int WM, class T>
-__global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* __restrict__ X, int ldx, int w,
+__global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const T* __restrict__ X, int ldx, int w,
                                                              const double* __restrict__ gram, int splits,
                                                              int64_t sstride, const double* __restrict__ prenorm,
                                                              double drop_tol, double dep_tol, int wk_slot_in,
                                                              T* __restrict__ out, int ldo, double* __restrict__ gout,
                                                              double* scal, int slot) {
   constexpr int ld = WM + 1;
-  constexpr int kPer = WM * WM / kCholTrsmRows;  // entries of the WM x WM square per lane
+  constexpr int kPer = WM * WM / kCholTrsmThreads;  // entries of the WM x WM square per thread
   __shared__ double A[WM * ld];             // Gram, Schur complements, then the rows of R
   __shared__ double O[kCholTrsmRows][ld];   // stored output rows (for gout)
   __shared__ int keep[WM];
@@ -761,11 +762,11 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   // entry (i, j) of the WM x WM square is e = i WM + j (compile-time shifts, no division)
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int e = tid + k * kCholTrsmRows, i = e / WM, j = e % WM;
+    const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
     A[i * ld + j] = (i < wa && j < wa) ? split_sum(gram + i * w + j, splits, sstride) : 0.0;
   }
   __syncthreads();
-  for (int c = tid; c < w; c += kCholTrsmRows) {
+  for (int c = tid; c < w; c += kCholTrsmThreads) {
     const double g = (c < wa) ? fmax(A[c * ld + c], 0.0) : 0.0;
     gdiag[c] = g;
     const double lim = prenorm ? drop_tol * prenorm[c] : 0.0;
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
       const double inv = rcp_nr(d);
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
-        const int e = tid + k * kCholTrsmRows, i = e / WM, j = e % WM;
+        const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
         if (i > c && i <= j && j < wa) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
       }
     }
@@ -791,7 +792,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   }
   // rows of R in place: R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c] (j > c); zero rows and
   // columns for the dropped and inactive indices
-  for (int c = tid; c < WM; c += kCholTrsmRows) {
+  for (int c = tid; c < WM; c += kCholTrsmThreads) {
     const bool kc = c < wa && keep[c];
     const double ri = kc ? rsq_nr(A[c * ld + c]) : 0.0;  // 1 / R[c][c]
     rinv[c] = ri;
@@ -800,13 +801,15 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int e = tid + k * kCholTrsmRows, c = e / WM, j = e % WM;
+    const int e = tid + k * kCholTrsmThreads, c = e / WM, j = e % WM;
     double v = 0.0;
     if (j >= c && rdiag[c] != 0.0 && rdiag[j] != 0.0) v = (j == c) ? rdiag[c] : A[c * ld + j] * rinv[c];
     A[c * ld + j] = v;
   }
   __syncthreads();
   // forward substitution of this thread's row
+  // the first wave solves the workgroup's 64 rows, one per lane
+  if (tid >= kCholTrsmRows) return;
   const int i = blockIdx.x * kCholTrsmRows + tid;
   const bool live = i < rows;
   double z[WM];
@@ -837,7 +840,7 @@ __global__ __launch_bounds__(kCholTrsmRows) void k_chol_trsm(int rows, const T* 
   }
   if (blockIdx.x == 0 && tid == 0) scal[slot] = (double)q;
   if (gout == nullptr) return;  // uniform
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();  // one wave from here: its LDS writes are visible to its reads
   // Gram of the 64 stored rows on the FP64 matrix cores: 16 x 16 tiles (ta, tb), lane l takes
   // rows 4 s + l / 16 of columns l % 16; the result holds rows (l / 16) + 4 v of column l % 16
   const int nt = (w + 15) / 16, lane = tid, kl = lane >> 4, cl = lane & 15;
@@ -1253,10 +1256,10 @@ hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w,
   if (rows <= 0 || w <= 0 || w > kCholTrsmMaxCols || splits <= 0) return hipErrorInvalidValue;
   const dim3 g((unsigned)((rows + kCholTrsmRows - 1) / kCholTrsmRows));
   if (w <= 16)
-    hipLaunchKernelGGL((k_chol_trsm<16, T>), g, dim3(kCholTrsmRows), 0, s, rows, X, ldx, w, gram, splits, sstride,
+    hipLaunchKernelGGL((k_chol_trsm<16, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
                        prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
   else
-    hipLaunchKernelGGL((k_chol_trsm<32, T>), g, dim3(kCholTrsmRows), 0, s, rows, X, ldx, w, gram, splits, sstride,
+    hipLaunchKernelGGL((k_chol_trsm<32, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
                        prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
   return hipGetLastError();
 }
