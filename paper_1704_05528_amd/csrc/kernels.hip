@@ -113,8 +113,13 @@ __global__ void k_set_unit(double* __restrict__ V, int rows, int ld, int c0, int
 // (idx = column indices, vperm = CSR->CSC map, D = Omega) it is X = Y Omega.
 // ------------------------------------------------------------------------------------------
 
-// Narrow blocks (w <= 16): lanes stride over the nonzeros, each keeps w partial sums.
-template <int WN, class T>
+// Narrow blocks (w <= 16): a segment is shared by SPLIT waves (1: one segment per wave; 4: one
+// per workgroup, for long segments); their lanes form 16 SPLIT groups of four, group gg takes the
+// nonzeros p0 + gg, p0 + gg + 16 SPLIT, ..., and lane q of a group the columns 4q .. 4q + 3 of D's
+// row (one 16-byte load for float when the row is aligned).  Each lane keeps four partial sums;
+// a wave adds its 16 groups with four butterfly steps, and the SPLIT waves' sums are added in
+// wave order (fixed order, deterministic).
+template <int WN, int SPLIT, class T>
 __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const int32_t* __restrict__ vperm, const T* __restrict__ val,
@@ -122,25 +127,70 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
                                                          int ldo, int w, const int32_t* __restrict__ seg_lo,
                                                          const int32_t* __restrict__ seg_hi,
                                                          const int32_t* __restrict__ skip) {
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (row >= nrows) return;
-  if (skip != nullptr && skip[row] != 0) return;
-  T acc[WN];
-#pragma unroll
-  for (int c = 0; c < WN; ++c) acc[c] = (T)0;
+  static_assert(WN == 16, "four lanes of four columns");
+  static_assert(SPLIT == 1 || SPLIT == 4, "one segment per wave or per workgroup");
+  constexpr int kU = 4;  // nonzeros per lane in flight
+  constexpr int kG = 16 * SPLIT;  // lane groups per segment
+  __shared__ T red[SPLIT][WN];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * (4 / SPLIT) + wave / SPLIT, sub = wave % SPLIT;
+  if (row >= nrows) return;                         // uniform over the waves of a segment
+  if (skip != nullptr && skip[row] != 0) return;  // uniform over the waves of a segment
+  const int gg = sub * 16 + (lane >> 2), c0 = (lane & 3) * 4;
+  const bool vec = (sizeof(T) == 4) && (c0 + 4 <= w) && (ldd % 4 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
+  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
   const int p0 = seg_lo ? seg_lo[row] : ptr[row], p1 = seg_lo ? seg_hi[row] : ptr[row + 1];
-  for (int p = p0 + lane; p < p1; p += kWave) {
-    const T v = val[vperm ? vperm[p] : p];
-    const T* d = D + (int64_t)idx[p] * ldd;
+  for (int base = p0 + gg; base < p1; base += kG * kU) {
+    T v[kU], d[kU][4];
 #pragma unroll
-    for (int c = 0; c < WN; ++c)
-      if (c < w) acc[c] = fma(v, d[c], acc[c]);
+    for (int u = 0; u < kU; ++u) {
+      const int p = base + kG * u;
+      const bool ok = p < p1;
+      const int pc = ok ? p : p0;  // a valid position (the segment is not empty here)
+      v[u] = ok ? val[vperm ? vperm[pc] : pc] : (T)0;
+      const T* src = D + (int64_t)idx[pc] * ldd + c0;
+      if (vec) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 x = *reinterpret_cast<const f4*>(src);
+        d[u][0] = x.x;
+        d[u][1] = x.y;
+        d[u][2] = x.z;
+        d[u][3] = x.w;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) d[u][c] = (c0 + c < w) ? src[c] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = fma(v[u], d[u][c], acc[c]);
   }
 #pragma unroll
-  for (int c = 0; c < WN; ++c) {
-    const T s = wave_sum(acc[c]);
-    if (lane == 0 && c < w) out[(int64_t)row * ldo + c] = s;
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int o = 4; o < kWave; o <<= 1) acc[c] += __shfl_xor(acc[c], o, kWave);
+  }
+  if constexpr (SPLIT > 1) {
+    if (lane < 4) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[sub][c0 + c] = acc[c];
+    }
+    __syncthreads();
+    if (sub != 0 || lane >= 4) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T t = red[0][c0 + c];
+#pragma unroll
+      for (int q = 1; q < SPLIT; ++q) t += red[q][c0 + c];
+      acc[c] = t;
+    }
+  }
+  if (lane < 4) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c0 + c < w) out[(int64_t)row * ldo + c0 + c] = acc[c];
   }
 }
 
@@ -1031,17 +1081,23 @@ hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, i
 
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, const SegChunks* ch) {
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total,
+                           const SegChunks* ch) {
   if (nrows == 0 || w == 0) return hipSuccess;
   constexpr int CPL = 4;
   const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
   const bool vec = (ldd % CPL == 0) && ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
-  // one wave per segment: segments [ptr[q], ptr[q+1]) or, with lo given, [lo[q], hi[q])
-  auto segments = [&](int nseg, T* o, int ldo_, const int32_t* lo, const int32_t* hi, const int32_t* skip) {
+  // one wave per segment: segments [ptr[q], ptr[q+1]) or, with lo given, [lo[q], hi[q]); narrow
+  // blocks give a whole workgroup to each segment when segments average 256 positions or more
+  auto segments = [&](int nseg, T* o, int ldo_, const int32_t* lo, const int32_t* hi, const int32_t* skip,
+                      bool long_segments) {
     const unsigned gx = (unsigned)((nseg + 3) / 4);
-    if (w <= kNarrow)
-      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, T>), dim3(gx), dim3(256), 0, s, nseg, ptr, idx, vperm, val, D,
-                         ldd, o, ldo_, w, lo, hi, skip);
+    if (w <= kNarrow && long_segments)
+      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 4, T>), dim3(nseg), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+                         D, ldd, o, ldo_, w, lo, hi, skip);
+    else if (w <= kNarrow)
+      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 1, T>), dim3(gx), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+                         D, ldd, o, ldo_, w, lo, hi, skip);
     else if (vec)
       hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
                          D, ldd, o, ldo_, w, lo, hi, skip);
@@ -1051,11 +1107,12 @@ hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const i
     return hipGetLastError();
   };
   const bool chunked = ch != nullptr && ch->nlong > 0 && w <= ch->ldp;
-  hipError_t e = segments(nrows, out, ldo, nullptr, nullptr, chunked ? ch->skip : nullptr);
+  hipError_t e = segments(nrows, out, ldo, nullptr, nullptr, chunked ? ch->skip : nullptr,
+                          total >= (int64_t)kNarrowSplitLen * nrows);
   if (e != hipSuccess || !chunked) return e;
   // long segments: one wave per chunk into the partial rows, then the chunks of each segment added in order
   T* P = reinterpret_cast<T*>(ch->P);
-  e = segments(ch->nchunk, P, ch->ldp, ch->lo, ch->hi, nullptr);
+  e = segments(ch->nchunk, P, ch->ldp, ch->lo, ch->hi, nullptr, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_chunk_sum<T>, dim3((w + 255) / 256, ch->nlong), dim3(256), 0, s, ch->lcol, ch->lfirst, P,
                      ch->ldp, out, ldo, w);
@@ -1317,7 +1374,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
 #define SVT_INST(T)                                                                                                   \
   template hipError_t launch_omega<T>(hipStream_t, T*, int, int, int, int, uint64_t, uint64_t, uint64_t);             \
   template hipError_t launch_seg_spmm<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*, const T*,  \
-                                         const T*, int, T*, int, int, const SegChunks*);                              \
+                                         const T*, int, T*, int, int, int64_t, const SegChunks*);                     \
   template hipError_t launch_spmm_t_tiled<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,         \
                                              const T*, int, int, T*, int, double*, int64_t);                          \
   template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \

@@ -179,12 +179,15 @@ template <class T>
 hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk, uint64_t it);
 
 
-// out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w].  With
-// ch, the long segments (over kSegLong positions) run as kSegLong chunks spread over the chip,
-// their partial sums in ch->P, instead of on one wave each.
+// out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w].  total is
+// the number of positions in all segments (it picks the launch shape only).  With ch, the long
+// segments (over kSegLong positions) run as kSegLong chunks spread over the chip, their partial
+// sums in ch->P, instead of on one wave each.
+constexpr int kNarrowSplitLen = 256;  // narrow blocks: a workgroup per segment from this mean length on
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, const SegChunks* ch = nullptr);
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total,
+                           const SegChunks* ch = nullptr);
 
 // LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
 // position of its first entry in each row tile (n x (tiled_row_tiles(m) + 1) int32)
