@@ -417,14 +417,20 @@ __device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
 // flight per tile), else 4.  Used for Q C, W D, G V, V S and the projections X - Q (Q^T X).
 // ------------------------------------------------------------------------------------------
 template <class TA, class TM, class TO, int NW>
-__global__ __launch_bounds__(NW * kWave) void k_rowmul(int rows, int K, const TA* __restrict__ A, int lda,
-                                                       const TM* __restrict__ M, int ldm, TO* __restrict__ out,
-                                                       int ldo, int w, double alpha, double beta,
-                                                       double* __restrict__ gpart) {
+__global__ __launch_bounds__(NW * kWave) void k_rowmul(RowmulProblem<TA, TM, TO> pr0, RowmulProblem<TA, TM, TO> pr1) {
+  // two independent products in one launch: blockIdx.z picks one (tiles past its grid exit)
+  const RowmulProblem<TA, TM, TO>& pr = blockIdx.z == 0 ? pr0 : pr1;
+  const int rows = pr.rows, K = pr.K, lda = pr.lda, ldm = pr.ldm, ldo = pr.ldo, w = pr.w;
+  const TA* __restrict__ A = pr.A;
+  const TM* __restrict__ M = pr.M;
+  TO* __restrict__ out = pr.out;
+  const double alpha = pr.alpha, beta = pr.beta;
+  double* __restrict__ gpart = pr.gpart;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  if (i0 >= rows || j0 >= w) return;  // uniform over the workgroup
   __shared__ double red[NW - 1][kWave][4];
   __shared__ double tile[16][17];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int ia = i0 + (lane & 15), jb = j0 + (lane & 15), kl = lane >> 4;
   const bool rowok = ia < rows, colok = jb < w;
   // out-of-range operands are loaded from a clamped, valid address and replaced by zero
@@ -1147,17 +1153,39 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
 }
 
 template <class TA, class TM, class TO>
+hipError_t launch_rowmul_pair(hipStream_t s, const RowmulProblem<TA, TM, TO>& p0, const RowmulProblem<TA, TM, TO>& p1) {
+  const RowmulProblem<TA, TM, TO>* pp[2] = {&p0, &p1};
+  unsigned gx = 0, gy = 0, tiles = 0;
+  for (const auto* p : pp) {
+    if (p->rows < 0 || p->w < 0) return hipErrorInvalidValue;
+    if (p->gpart != nullptr && p->w > 16) return hipErrorInvalidValue;  // the Gram epilogue needs whole rows in one tile
+    const unsigned x = (unsigned)((p->rows + 15) / 16), y = (unsigned)((p->w + 15) / 16);
+    gx = std::max(gx, x);
+    gy = std::max(gy, y);
+    tiles += x * y;
+  }
+  if (tiles == 0) return hipSuccess;
+  const dim3 grid(gx, gy, 2);
+  if (tiles < 256)
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, p0, p1);
+  else
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 4>), grid, dim3(4 * kWave), 0, s, p0, p1);
+  return hipGetLastError();
+}
+
+template <class TA, class TM, class TO>
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
                          int w, double alpha, double beta, double* gpart) {
   if (rows == 0 || w == 0) return hipSuccess;
   if (gpart != nullptr && w > 16) return hipErrorInvalidValue;  // the Gram epilogue needs whole rows in one tile
-  const dim3 grid((rows + 15) / 16, (w + 15) / 16);
+  const RowmulProblem<TA, TM, TO> p{rows, K, A, lda, M, ldm, out, ldo, w, alpha, beta, gpart};
+  RowmulProblem<TA, TM, TO> none = p;
+  none.rows = 0;
+  const dim3 grid((rows + 15) / 16, (w + 15) / 16, 1);
   if (grid.x * grid.y < 256)
-    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, rows, K, A, lda, M, ldm, out, ldo, w,
-                       alpha, beta, gpart);
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, p, none);
   else
-    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 4>), grid, dim3(4 * kWave), 0, s, rows, K, A, lda, M, ldm, out, ldo, w,
-                       alpha, beta, gpart);
+    hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 4>), grid, dim3(4 * kWave), 0, s, p, none);
   return hipGetLastError();
 }
 
@@ -1400,10 +1428,16 @@ SVT_INST(double)
 SVT_INST(float)
 #undef SVT_INST
 
+template hipError_t launch_rowmul_pair<double, double, double>(hipStream_t, const RowmulProblem<double, double, double>&,
+                                                               const RowmulProblem<double, double, double>&);
 template hipError_t launch_rowmul<double, double, double>(hipStream_t, int, int, const double*, int, const double*,
                                                           int, double*, int, int, double, double, double*);
+template hipError_t launch_rowmul_pair<float, double, float>(hipStream_t, const RowmulProblem<float, double, float>&,
+                                                               const RowmulProblem<float, double, float>&);
 template hipError_t launch_rowmul<float, double, float>(hipStream_t, int, int, const float*, int, const double*, int,
                                                         float*, int, int, double, double, double*);
+template hipError_t launch_rowmul_pair<float, double, double>(hipStream_t, const RowmulProblem<float, double, double>&,
+                                                               const RowmulProblem<float, double, double>&);
 template hipError_t launch_rowmul<float, double, double>(hipStream_t, int, int, const float*, int, const double*, int,
                                                          double*, int, int, double, double, double*);
 template hipError_t launch_tn_narrow<float, double>(hipStream_t, int, const float*, int, int, const double*, int, int,

@@ -578,10 +578,13 @@ struct Engine {
                                                     h->partial_cap, &sp)));
           HIPCHK(launch_jacobi(s, h->partial, b, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS, 40, sp,
                                (int64_t)b * b));
-          HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b,
-                                                        1.0, 0.0)));
-          HIPCHK((launch_rowmul<double, double, double>(s, r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b,
-                                                        1.0, 0.0)));
+          {  // V S and (G V) S in one launch
+            const RowmulProblem<double, double, double> pa{r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b,
+                                                          1.0, 0.0, nullptr};
+            const RowmulProblem<double, double, double> pb{r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b,
+                                                          1.0, 0.0, nullptr};
+            HIPCHK((launch_rowmul_pair<double, double, double>(s, pa, pb)));
+          }
           std::swap(h->EV, h->EZ2);
           HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
           have_gv = true;
@@ -662,10 +665,12 @@ struct Engine {
                     2.0 * (double)(h->m + h->n) * r * k);
       HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
       HIPCHK((launch_copy_cols<double, double>(s, r, S, kEigMax, h->Sk, kEigMax, k)));
-      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, kEigMax, Ut(), kEigMax, k, 1.0,
-                                          0.0)));
-      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, kEigMax, Vt(), kEigMax, k, 1.0,
-                                          0.0)));
+      // Ut = Q C and Vt = W D side by side in one launch
+      const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, kEigMax, Ut(), kEigMax, k, 1.0, 0.0,
+                                           nullptr};
+      const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, kEigMax, Vt(), kEigMax, k, 1.0, 0.0,
+                                           nullptr};
+      HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
     }
     h->have_factors = true;
     return SVT_OK;

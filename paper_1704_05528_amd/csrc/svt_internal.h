@@ -197,11 +197,28 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
                                const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
                                int64_t partial_cap);
 
+// One product of launch_rowmul / launch_rowmul_pair (see below)
+template <class TA, class TM, class TO>
+struct RowmulProblem {
+  int rows, K;
+  const TA* A;
+  int lda;
+  const TM* M;
+  int ldm;
+  TO* out;
+  int ldo, w;
+  double alpha, beta;
+  double* gpart;
+};
+
 // out[i, 0:w] = beta * out[i, 0:w] + alpha * A[i, 0:K] M[0:K, 0:w] (double accumulation).  With gpart
 // (w <= 16 only): gpart[t][a][b] (t = 16-row tile, w x w each) = the Gram of the tile's stored rows.
 template <class TA, class TM, class TO>
 hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, const TM* M, int ldm, TO* out, int ldo,
                          int w, double alpha, double beta, double* gpart = nullptr);
+// two independent products of launch_rowmul in one launch (they run side by side)
+template <class TA, class TM, class TO>
+hipError_t launch_rowmul_pair(hipStream_t s, const RowmulProblem<TA, TM, TO>& p0, const RowmulProblem<TA, TM, TO>& p1);
 
 // out[a, b] = sum_i A[i, a] B[i, b] in double, a < na (any), b < nb (<= kEigMax)
 template <class TA, class TB>
