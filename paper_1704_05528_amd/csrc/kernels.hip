@@ -796,7 +796,7 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict
 // with wk_slot_in >= 0 only the first scal[wk_slot_in] columns take part (second pass).
 // ------------------------------------------------------------------------------------------
 constexpr int kCholTrsmRows = 64;      // rows solved per workgroup
-constexpr int kCholTrsmThreads = 256;  // threads that load and factor the Gram
+constexpr int kCholTrsmThreads = 256;  // threads that load and factor the Gram (a 16 x 16 grid)
 
 template <int WM, class T>
 __global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const T* __restrict__ X, int ldx, int w,
@@ -816,10 +816,18 @@ __global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const 
   if (wk_slot_in >= 0) wa = min(w, (int)scal[wk_slot_in]);
   // the Gram is the sum of `splits` partial Grams (w x w, sstride apart), added in a fixed order;
   // entry (i, j) of the WM x WM square is e = i WM + j (compile-time shifts, no division)
+  if (splits == 1) {  // uniform: one Gram, every entry's load in flight at once
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
-    A[i * ld + j] = (i < wa && j < wa) ? split_sum(gram + i * w + j, splits, sstride) : 0.0;
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
+      A[i * ld + j] = (i < wa && j < wa) ? gram[i * w + j] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
+      A[i * ld + j] = (i < wa && j < wa) ? split_sum(gram + i * w + j, splits, sstride) : 0.0;
+    }
   }
   __syncthreads();
   for (int c = tid; c < w; c += kCholTrsmThreads) {
@@ -829,21 +837,45 @@ __global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const 
     keep[c] = (c < wa) && (sqrt(g) > lim) ? 1 : 0;
   }
   __syncthreads();
-  // right-looking Cholesky on the upper triangle (k_block_chol's order and decisions)
-  for (int c = 0; c < wa; ++c) {
-    if (!keep[c]) continue;  // uniform
-    const double d = A[c * ld + c];
-    const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
-    if (ok) {
-      const double inv = rcp_nr(d);
+  // right-looking Cholesky on the upper triangle (k_block_chol's order and decisions).  Up to 32
+  // columns each thread owns fixed entries of the square (unrolled); wider blocks spread the
+  // trailing triangle over a 16 x 16 grid of threads.  The keep decision is uniform: a step without
+  // an update needs no barrier, and keep[c] (read only after the loop) is cleared without one.
+  if constexpr (WM <= 32) {
+    for (int c = 0; c < wa; ++c) {
+      if (!keep[c]) continue;  // uniform
+      const double d = A[c * ld + c];
+      const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
+      if (ok) {
+        const double inv = rcp_nr(d);
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
-        if (i > c && i <= j && j < wa) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
+        for (int k = 0; k < kPer; ++k) {
+          const int e = tid + k * kCholTrsmThreads, i = e / WM, j = e % WM;
+          if (i > c && i <= j && j < wa) A[i * ld + j] -= A[c * ld + i] * A[c * ld + j] * inv;
+        }
       }
+      __syncthreads();
+      if (!ok && tid == 0) keep[c] = 0;
+      __syncthreads();
     }
-    __syncthreads();
-    if (!ok && tid == 0) keep[c] = 0;
+  } else {
+    const int tx = tid & 15, ty = tid >> 4;
+    for (int c = 0; c < wa; ++c) {
+      if (!keep[c]) continue;  // uniform: keep[c] is only written at step c itself
+      const double d = A[c * ld + c];
+      const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
+      if (!ok) {
+        if (tid == 0) keep[c] = 0;
+        continue;
+      }
+      const double inv = rcp_nr(d);
+      for (int i = c + 1 + ty; i < wa; i += 16) {
+        const double aci = A[c * ld + i];
+        for (int j = c + 1 + tx; j < wa; j += 16)
+          if (i <= j) A[i * ld + j] -= aci * A[c * ld + j] * inv;
+      }
+      __syncthreads();
+    }
     __syncthreads();
   }
   // rows of R in place: R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c] (j > c); zero rows and
@@ -1214,6 +1246,13 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
   return hipGetLastError();
 }
 
+hipError_t launch_tn_finish(hipStream_t s, const double* partial, int splits, int na, int nb, double* out, int ldo) {
+  if (na <= 0 || nb <= 0) return hipSuccess;
+  if (splits <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tn_finish, dim3(grid1((int64_t)na * nb)), dim3(256), 0, s, partial, splits, na, nb, out, ldo);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
                        int64_t partial_cap) {
@@ -1343,8 +1382,14 @@ hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w,
   if (w <= 16)
     hipLaunchKernelGGL((k_chol_trsm<16, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
                        prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
-  else
+  else if (w <= 32)
     hipLaunchKernelGGL((k_chol_trsm<32, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
+                       prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
+  else if (w <= 64)
+    hipLaunchKernelGGL((k_chol_trsm<64, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
+                       prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
+  else
+    hipLaunchKernelGGL((k_chol_trsm<96, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
                        prenorm, drop_tol, dep_tol, wk_slot_in, out, ldo, gout, scal, slot);
   return hipGetLastError();
 }

@@ -189,14 +189,19 @@ struct Engine {
     const int64_t ss = (int64_t)wc * wc;  // stride of the split partial Grams
     int sp = 0;
     if (fused_cholqr(rows, wc)) {
-      // Gram partials of X; pass 1 factors and solves into X2 and leaves the Gram partials of X2;
-      // pass 2 factors those and solves back into X
-      HIPCHK((launch_tn_partial<U, U>(s, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap / 2, &sp)));
+      // Gram of X; pass 1 factors and solves into X2 (and, up to 32 columns, leaves the Gram
+      // partials of X2); pass 2 factors the Gram of X2 and solves back into X
+      const double* g1 = nullptr;
+      CHK(pass_gram<U>(rows, X, ld, wc, &g1, &sp));
+      const bool ep = wc <= kCholTrsmGoutCols;
       double* g2 = h->partial + h->partial_cap / 2;
-      HIPCHK(launch_chol_trsm<U>(s, rows, X, ld, wc, h->partial, sp, ss, prenorm, kDropTol, kDepTol, -1, X2, ld, g2,
-                                 h->scal, S_WK1));
-      HIPCHK(launch_chol_trsm<U>(s, rows, X2, ld, wc, g2, row_groups(rows), ss, nullptr, 0.0, kDepTol, S_WK1, X, ld,
-                                 nullptr, h->scal, S_WK2));
+      HIPCHK(launch_chol_trsm<U>(s, rows, X, ld, wc, g1, sp, ss, prenorm, kDropTol, kDepTol, -1, X2, ld,
+                                 ep ? g2 : nullptr, h->scal, S_WK1));
+      const double* gg = g2;
+      int s2 = row_groups(rows);
+      if (!ep) CHK(pass_gram<U>(rows, X2, ld, wc, &gg, &s2));
+      HIPCHK(launch_chol_trsm<U>(s, rows, X2, ld, wc, gg, s2, ss, nullptr, 0.0, kDepTol, S_WK1, X, ld, nullptr,
+                                 h->scal, S_WK2));
       return SVT_OK;
     }
     HIPCHK((launch_tn_partial<U, U>(s, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap, &sp)));
@@ -212,6 +217,24 @@ struct Engine {
 
   // CholeskyQR in one launch per pass (k_chol_trsm) for blocks of at most 32 columns and 4096 rows
   static bool fused_cholqr(int rows, int wc) { return wc <= kCholTrsmMaxCols && rows <= kCholTrsmMaxRows; }
+  // widest block whose one-launch pass also writes the Gram partials of its output (wider ones
+  // would spend longer on that one-wave epilogue than a separate Gram launch takes)
+  static constexpr int kCholTrsmGoutCols = 32;
+
+  // Gram of X (rows x wc) for a one-launch CholeskyQR pass, as split partials in the first half of
+  // the partial buffer.  Blocks wider than kCholTrsmGoutCols get the splits added first, into Minv
+  // (every workgroup of the pass would otherwise add all of them itself): then *splits = 1.
+  template <class U>
+  svt_status pass_gram(int rows, const U* X, int ld, int wc, const double** gram, int* splits) {
+    HIPCHK((launch_tn_partial<U, U>(h->stream, rows, X, ld, wc, X, ld, wc, h->partial, h->partial_cap / 2, splits)));
+    *gram = h->partial;
+    if (wc > kCholTrsmGoutCols && *splits > 1) {
+      HIPCHK(launch_tn_finish(h->stream, h->partial, *splits, wc, wc, h->Minv, wc));
+      *gram = h->Minv;
+      *splits = 1;
+    }
+    return SVT_OK;
+  }
   static int row_groups(int rows) { return (rows + 63) / 64; }
 
   // CholeskyQR of an eigensolver block, one or two passes (only dependent columns drop):
@@ -226,17 +249,18 @@ struct Engine {
     }
     hipStream_t s = h->stream;
     const int64_t ss = (int64_t)wc * wc;
-    if (gram == nullptr) {
-      HIPCHK((launch_tn_partial<double, double>(s, rows, In, ld, wc, In, ld, wc, h->partial, h->partial_cap / 2,
-                                                &splits)));
-      gram = h->partial;
-    }
+    if (gram == nullptr) CHK(pass_gram<double>(rows, In, ld, wc, &gram, &splits));
+    const bool ep = wc <= kCholTrsmGoutCols;
     double* g2 = h->partial + h->partial_cap / 2;
     HIPCHK(launch_chol_trsm<double>(s, rows, In, ld, wc, gram, splits, ss, nullptr, 0.0, kEigDepTol, -1,
-                                    twice ? Tmp : Out, ld, twice ? g2 : nullptr, h->scal, S_WK2));
-    if (twice)
-      HIPCHK(launch_chol_trsm<double>(s, rows, Tmp, ld, wc, g2, row_groups(rows), ss, nullptr, 0.0, kEigDepTol, -1, Out,
-                                      ld, nullptr, h->scal, S_WK2));
+                                    twice ? Tmp : Out, ld, (twice && ep) ? g2 : nullptr, h->scal, S_WK2));
+    if (twice) {
+      const double* gg = g2;
+      int s2 = row_groups(rows);
+      if (!ep) CHK(pass_gram<double>(rows, Tmp, ld, wc, &gg, &s2));
+      HIPCHK(launch_chol_trsm<double>(s, rows, Tmp, ld, wc, gg, s2, ss, nullptr, 0.0, kEigDepTol, -1, Out, ld, nullptr,
+                                      h->scal, S_WK2));
+    }
     return SVT_OK;
   }
 
@@ -600,8 +624,9 @@ struct Engine {
             if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks");
             if (nconv > b) return fail(h, SVT_E_LIMIT, "truncated recycling keeps more vectors than the eigensolver tracks");
           } else {
-            // widen the block with Gaussian columns and continue from the enlarged block
-            const int nb = std::min(std::min(h->b_cap, r), b + 16);
+            // widen the block with Gaussian columns and continue from the enlarged block: to the
+            // width the current count asks for (2 nconv + 8) at once, at least 16 more columns
+            const int nb = std::min(std::min(h->b_cap, r), std::max(b + 16, 2 * nconv + 8));
             PhaseTimer tm(h, SVT_PH_EIG);
             HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
             b = nb;
@@ -653,6 +678,10 @@ struct Engine {
       h->ev_rows = r;
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
     }
+    // an iterate that has left the storage type's range (a diverging step size) makes the
+    // projected Gram, and with it every eigenvalue, non-finite: stop instead of thresholding nothing
+    if (r > 0 && !std::isfinite(theta[0]))
+      return fail(h, SVT_E_NUMERIC, "non-finite eigenvalues of the projected Gram (the iterate has overflowed)");
     if (h->p.mode == SVT_MODE_RSVD) k = std::min(k, h->p.rank);  // Alg. 1 keeps `rank` leading triplets
     if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
     h->k = k;

@@ -220,6 +220,9 @@ hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, c
 template <class TA, class TM, class TO>
 hipError_t launch_rowmul_pair(hipStream_t s, const RowmulProblem<TA, TM, TO>& p0, const RowmulProblem<TA, TM, TO>& p1);
 
+// out[a * ldo + b] = sum over s < splits of partial[s * na * nb + a * nb + b] (fixed order)
+hipError_t launch_tn_finish(hipStream_t s, const double* partial, int splits, int na, int nb, double* out, int ldo);
+
 // out[a, b] = sum_i A[i, a] B[i, b] in double, a < na (any), b < nb (<= kEigMax)
 template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
@@ -276,7 +279,7 @@ hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w,
 // (k_block_chol's drop rules: prenorm / drop_tol, dep_tol; wk_slot_in >= 0 limits the columns to
 // scal[wk_slot_in]).  gout (may be NULL): the Gram partials of out, one w x w matrix per 64 rows.
 // scal[slot] = kept count.  w <= kCholTrsmMaxCols; hipErrorInvalidValue otherwise.
-constexpr int kCholTrsmMaxCols = 32;
+constexpr int kCholTrsmMaxCols = 96;
 constexpr int kCholTrsmMaxRows = 4096;  // above this a separate factor launch costs less than the repeats
 template <class T>
 hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w, const double* gram, int splits,

@@ -96,3 +96,18 @@ def test_mixed_kicking_start_matches_oracle(gpu_lib, m, n, frac, seed):
     state, k0 = initial_state(prob, Params(tau=w.tau, delta=w.delta))
     h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, precision=gpu_lib.SVT_MIXED)
     np.testing.assert_allclose(h.get_state()["y"], state.y, rtol=3e-7)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_diverging_step_size_stops_with_numeric_error(gpu_lib, precision):
+    """A step size far above the stable bound makes Y grow without limit; once the iterate leaves
+    the storage type's range the call must stop with SVT_E_NUMERIC (the mixed form's float iterate
+    overflows long before the residual sums in double do)."""
+    from paper_1704_05528_amd._capi import SVT_E_NUMERIC, SVTError
+    w = W.tiny_dense(60, 50, 3, 0.5, seed=71, delta=40.0)
+    prec = gpu_lib.SVT_MIXED if precision == "mixed" else gpu_lib.SVT_FP64
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=71, maxit=5000,
+                         precision=prec)
+    with pytest.raises(SVTError) as ei:
+        h.iterate(5000)
+    assert ei.value.status == SVT_E_NUMERIC, ei.value

@@ -57,6 +57,7 @@ SHAPES = [
     (150, 40, 3, 0.6, 35, {"eps_thr0": 0.3}),     # tall, explicit threshold
     (500, 400, 2, 0.04, 36, {"t0": 12}),          # 4% observed: gather path for Y^T Q
     (300, 250, 3, 0.15, 37, {}),                   # 15% observed: LDS-tiled Y^T Q
+    (400, 300, 40, 0.5, 81, {"dt": 40}),          # k up to 58: eigensolver blocks and growth blocks over 32 columns
 ]
 # 25% or more observed (the rows above with frac >= 0.25): Y^T Q on the matrix cores with a dense copy of Y
 
