@@ -1119,7 +1119,7 @@ hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, i
 
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total,
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
                            const SegChunks* ch) {
   if (nrows == 0 || w == 0) return hipSuccess;
   constexpr int CPL = 4;
@@ -1146,7 +1146,8 @@ hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const i
   };
   const bool chunked = ch != nullptr && ch->nlong > 0 && w <= ch->ldp;
   hipError_t e = segments(nrows, out, ldo, nullptr, nullptr, chunked ? ch->skip : nullptr,
-                          total >= (int64_t)kNarrowSplitLen * nrows);
+                          total >= (int64_t)kNarrowSplitLen * nrows ||
+                              std::min(max_len, chunked ? kSegLong : max_len) >= kNarrowSplitMax);
   if (e != hipSuccess || !chunked) return e;
   // long segments: one wave per chunk into the partial rows, then the chunks of each segment added in order
   T* P = reinterpret_cast<T*>(ch->P);
@@ -1447,7 +1448,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
 #define SVT_INST(T)                                                                                                   \
   template hipError_t launch_omega<T>(hipStream_t, T*, int, int, int, int, uint64_t, uint64_t, uint64_t);             \
   template hipError_t launch_seg_spmm<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*, const T*,  \
-                                         const T*, int, T*, int, int, int64_t, const SegChunks*);                     \
+                                         const T*, int, T*, int, int, int64_t, int, const SegChunks*);                \
   template hipError_t launch_spmm_t_tiled<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,         \
                                              const T*, int, int, T*, int, double*, int64_t);                          \
   template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \

@@ -278,7 +278,7 @@ struct Engine {
   // X = Y Om (CSR order, values through the CSR->CSC map)
   svt_status spmm_y(const T* D, int ldd, T* out, int ldo, int w) {
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->m, h->rowptr, h->colidx, h->csr2csc, y(), D, ldd, out, ldo, w,
-                              h->nnz));
+                              h->nnz, h->max_row_nnz));
     return SVT_OK;
   }
 
@@ -291,7 +291,7 @@ struct Engine {
       return SVT_OK;
     }
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w,
-                              h->nnz, &h->csc_long));
+                              h->nnz, h->max_col_nnz, &h->csc_long));
     return SVT_OK;
   }
 
@@ -828,8 +828,8 @@ struct Engine {
     const double tol = sizeof(T) == 4 ? 2e-6 : 1e-15;
     double sig = 0.0, sig_prev = 0.0;
     for (int itp = 0; itp < 5000; ++itp) {
-      HIPCHK(launch_seg_spmm<T>(s, m, h->rowptr, h->colidx, h->csr2csc, a(), v, 1, u, 1, 1, h->nnz));
-      HIPCHK(launch_seg_spmm<T>(s, n, h->colptr, h->rowidx, nullptr, a(), u, 1, v, 1, 1, h->nnz));
+      HIPCHK(launch_seg_spmm<T>(s, m, h->rowptr, h->colidx, h->csr2csc, a(), v, 1, u, 1, 1, h->nnz, h->max_row_nnz));
+      HIPCHK(launch_seg_spmm<T>(s, n, h->colptr, h->rowidx, nullptr, a(), u, 1, v, 1, 1, h->nnz, h->max_col_nnz));
       HIPCHK(launch_sumsq<T>(s, m, u, h->partial, h->scal, S_A));
       HIPCHK(launch_sumsq<T>(s, n, v, h->partial + 2048, h->scal, S_B));
       CHK(readback(h, S_B + 1));
@@ -1024,7 +1024,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   // Frozen map of iteration i on yi: W_i, eigenpairs (U, th) of G = W_i^T W_i, k, and the
   // factors Ut = Q_i U_K diag(s - tau), Vt = W_i U_K diag(1/s) = V_K.  Returns k.
   auto frozen_map = [&](const double* yi, int ri, int* kout) -> svt_status {
-    HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, yi, Q, ldq, Wb, kEigMax, ri, h->nnz));
+    HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, yi, Q, ldq, Wb, kEigMax, ri, h->nnz,
+                                   h->max_col_nnz));
     HIPCHK(launch_gram<double>(s, n, Wb, kEigMax, ri, h->G, h->r_cap, h->partial, h->partial_cap));
     HIPCHK(launch_jacobi(s, h->G, h->r_cap, ri, th, U, kEigMax, h->scal, S_SWEEPS));
     CHK(to_host<double>(h, theta.data(), th, ri));
@@ -1084,10 +1085,11 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
         d_bar += h->hscal[S_DOT];
         if (k == 0) continue;
         HIPCHK((launch_scale_copy<double, double>(s, nnz, ybar, -delta, tmp)));
-        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, kEigMax, ri, h->nnz));
+        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, kEigMax, ri, h->nnz,
+                                         h->max_col_nnz));
       } else {
         if (k == 0 || nh == 0) continue;
-        HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, kEigMax, ri, nh));
+        HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, kEigMax, ri, nh, 0));
       }
       // F = Xbar^T Q_i = Bbar^T; Z1 = Bbar V_K, Z2 = Bbar W_i, R = [F U_K | V_K | W_i]
       const int wl = 2 * k + ri;
@@ -1255,6 +1257,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     rowptr[rows[u] + 1]++;
   }
   for (int64_t i = 0; i < m; ++i) rowptr[i + 1] += rowptr[i];
+  for (int64_t i = 0; i < m; ++i) h->max_row_nnz = std::max(h->max_row_nnz, rowptr[i + 1] - rowptr[i]);
+  for (int64_t j = 0; j < n; ++j) h->max_col_nnz = std::max(h->max_col_nnz, colptr[j + 1] - colptr[j]);
 
   // Row-tile starts for the LDS-tiled Y^T Q when most tiles hold observed entries (at least 5% of
   // the entries observed); very sparse patterns use the gather kernel instead.

@@ -89,6 +89,7 @@ struct Handle {
   int32_t *cstart = nullptr, *ccol = nullptr;    // load-balanced chunks of the CSC order (fused update)
   void* yT = nullptr;  // (T) n x m dense transposed copy of Y (zeros off Lambda) when >= 25% is observed
   int32_t nchunks = 0;
+  int32_t max_row_nnz = 0, max_col_nnz = 0;  // longest row / column of Lambda (picks the gather's launch shape)
   SegChunks csc_long;  // long columns of Y for W = Y^T D on the sparse path
   std::vector<int64_t> user2csc;                 // caller order -> CSC position (host)
 
@@ -180,13 +181,15 @@ hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint
 
 
 // out[row, 0:w] = sum over the row's segment of val[vperm ? vperm[p] : p] * D[idx[p], 0:w].  total is
-// the number of positions in all segments (it picks the launch shape only).  With ch, the long
+// the number of positions in all segments and max_len the longest segment (they pick the launch
+// shape only).  With ch, the long
 // segments (over kSegLong positions) run as kSegLong chunks spread over the chip, their partial
 // sums in ch->P, instead of on one wave each.
-constexpr int kNarrowSplitLen = 256;  // narrow blocks: a workgroup per segment from this mean length on
+constexpr int kNarrowSplitLen = 256;   // narrow blocks: a workgroup per segment from this mean length on,
+constexpr int kNarrowSplitMax = 1024;  // or from this longest segment on
 template <class T>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total,
+                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
                            const SegChunks* ch = nullptr);
 
 // LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
