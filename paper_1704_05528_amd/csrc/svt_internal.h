@@ -67,7 +67,7 @@ struct SegChunks {
   int32_t *lo = nullptr, *hi = nullptr, *lcol = nullptr, *lfirst = nullptr, *skip = nullptr;
   void* P = nullptr;
 };
-constexpr int kSegLong = 2048;  // a segment longer than this is cut into chunks of this many positions
+constexpr int kSegLong = 256;  // a segment longer than this is cut into chunks of this many positions
 
 // Device buffers of one problem.  Matrices are row-major; "ld" is the row stride.  Buffers
 // marked (T) hold the storage type of the precision form: double (SVT_FP64) or float
