@@ -111,3 +111,26 @@ def test_diverging_step_size_stops_with_numeric_error(gpu_lib, precision):
     with pytest.raises(SVTError) as ei:
         h.iterate(5000)
     assert ei.value.status == SVT_E_NUMERIC, ei.value
+
+
+@pytest.mark.parametrize("extra", [{"t0": 20}, {"t0": 6, "dt": 4}])
+def test_mixed_step_heavy_columns_chunked_gather(gpu_lib, extra):
+    """The mixed form on a 1%-observed pattern with three columns of 9000, 5000 and 2600 rows: W = Y^T Q
+    on the gather path with the long columns in chunks (float partial rows added in order), wide and
+    narrow blocks, one step from a state after eight FP64 steps, against the emulated oracle."""
+    w = W.heavy_columns(30000, 60, 3, (9000, 5000, 2600), 40, seed=51, delta=1.2)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=51, **extra)
+    s64, k0 = _state_after(prob, p, 8)
+    st32 = State(it=s64.it, y=f32(s64.y), Q=f32(s64.Q), eps_thr=s64.eps_thr, eps_min=s64.eps_min)
+    nxt_emu, info_emu = svt_step_mixed(prob, p, st32)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, seed=51,
+                         precision=gpu_lib.SVT_MIXED, **extra)
+    h.set_state(st32.y, st32.Q, st32.eps_thr, st32.eps_min, st32.it)
+    st = h.iterate(1)
+    x = h.sample(w.rows, w.cols)
+    assert info_emu.k > 0
+    assert st.r == info_emu.r and st.k == info_emu.k and st.blocks == info_emu.blocks
+    assert rel_err(x, info_emu.x) <= TOL_EMU, rel_err(x, info_emu.x)
+    assert abs(st.rel_res - info_emu.rel) <= TOL_EMU * info_emu.rel
+    assert rel_err(h.get_state()["y"], nxt_emu.y) <= TOL_EMU
