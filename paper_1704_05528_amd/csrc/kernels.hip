@@ -896,6 +896,64 @@ __global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const 
   }
   __syncthreads();
   // forward substitution of this thread's row
+  if constexpr (WM > 32) {
+    // Wide blocks: the workgroup's 64 rows are solved in 16-column panels.  The rows sit in O as
+    // double; for panel J the update from the solved panels, O[:, J] -= O[:, <J] R[<J, J], runs on
+    // the matrix cores (wave v: rows 16 v .. 16 v + 15), and only the panel's own 16 x 16 triangle
+    // is solved row by row.  Kept columns are then written packed to the left of out.
+    static_assert(WM % 16 == 0 && kCholTrsmRows == 64 && kCholTrsmThreads == 256, "four waves of 16 rows");
+    const int row0 = blockIdx.x * kCholTrsmRows;
+    for (int e = tid; e < kCholTrsmRows * WM; e += kCholTrsmThreads) {
+      const int r = e / WM, c = e % WM, gi = row0 + r;
+      O[r][c] = (gi < rows && c < w) ? (double)X[(int64_t)gi * ldx + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+    for (int c0 = 0; c0 < w; c0 += 16) {
+      if (c0 > 0) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < c0; k0 += 4) {
+          const double a = O[16 * wv + (lane & 15)][k0 + (lane >> 4)];
+          const double b = A[(k0 + (lane >> 4)) * ld + c0 + (lane & 15)];
+          acc = mfma_f64_16x16x4(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) O[16 * wv + (lane >> 4) + 4 * v][c0 + (lane & 15)] -= acc[v];
+        __syncthreads();
+      }
+      if (tid < kCholTrsmRows) {
+        // the panel's 16 values of this row in registers (columns past w are zero and stay zero)
+        double z[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) z[c] = O[tid][c0 + c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          double v = z[c];
+#pragma unroll
+          for (int l = 0; l < c; ++l) v = fma(-z[l], A[(c0 + l) * ld + c0 + c], v);
+          z[c] = v * rinv[c0 + c];  // 0 for a dropped column
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) O[tid][c0 + c] = z[c];
+      }
+      __syncthreads();
+    }
+    if (tid < kCholTrsmRows) {
+      const int i = row0 + tid;
+      const bool live = i < rows;
+      int q = 0;
+      for (int c = 0; c < w; ++c) {
+        if (A[c * ld + c] != 0.0) {
+          if (live) out[(int64_t)i * ldo + q] = (T)O[tid][c];
+          ++q;
+        }
+      }
+      for (int c = q; c < w; ++c)
+        if (live) out[(int64_t)i * ldo + c] = (T)0;
+      if (blockIdx.x == 0 && tid == 0) scal[slot] = (double)q;
+    }
+    return;  // no Gram of the output for wide blocks (gout is for at most 32 columns)
+  }
   // the first wave solves the workgroup's 64 rows, one per lane
   if (tid >= kCholTrsmRows) return;
   const int i = blockIdx.x * kCholTrsmRows + tid;
@@ -1379,6 +1437,7 @@ hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w,
                             int64_t sstride, const double* prenorm, double drop_tol, double dep_tol, int wk_slot_in,
                             T* out, int ldo, double* gout, double* scal, int slot) {
   if (rows <= 0 || w <= 0 || w > kCholTrsmMaxCols || splits <= 0) return hipErrorInvalidValue;
+  if (gout != nullptr && w > 32) return hipErrorInvalidValue;  // the Gram epilogue is for at most 32 columns
   const dim3 g((unsigned)((rows + kCholTrsmRows - 1) / kCholTrsmRows));
   if (w <= 16)
     hipLaunchKernelGGL((k_chol_trsm<16, T>), g, dim3(kCholTrsmThreads), 0, s, rows, X, ldx, w, gram, splits, sstride,
