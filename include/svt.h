@@ -49,7 +49,9 @@ typedef enum {
   SVT_E_INVALID_ARG = -1, /* bad size, index out of range, duplicate entry, bad parameter */
   SVT_E_OOM = -2,         /* device or host allocation failed */
   SVT_E_HIP = -3,         /* a HIP runtime call failed; the handle must be destroyed */
-  SVT_E_NUMERIC = -4,     /* NaN/Inf in a reduction, or a non-positive ||Y||_F */
+  SVT_E_NUMERIC = -4,     /* NaN/Inf in a reduction or in the projected Gram's eigenvalues (an iterate that
+                             has left the storage type's range, e.g. under a step size above the stable
+                             bound), or a non-positive ||Y||_F */
   SVT_E_STATE = -5,       /* call not valid in the handle's current state */
   SVT_E_LIMIT = -6        /* more singular values above tau than the tracked maximum (kmax) */
 } svt_status;
@@ -152,7 +154,9 @@ svt_status r4svd_step(svt_handle* h, svt_step_stats* st);
 
 /* Up to max_steps iterations of Alg. 4, stopping early at convergence or at
  * maxit.  *last receives the report of the last iteration run (may be NULL).
- * Returns SVT_E_STATE if the run had already converged. */
+ * Returns SVT_E_STATE if the run had already converged, SVT_E_NUMERIC when the
+ * iterate stops being finite (a diverging step size), SVT_E_LIMIT when more than
+ * kmax singular values rise above tau. */
 svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last);
 
 /* Reports of the iterations run by svt_iterate on this handle, oldest first (iteration i of the
