@@ -136,6 +136,15 @@ svt_status wait_stream(Handle* h) {
   }
 }
 
+// Spin until an event recorded earlier on the handle's stream has completed.
+svt_status wait_event(Handle* h, hipEvent_t ev) {
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) return SVT_OK;
+    if (e != hipErrorNotReady) HIPCHK(e);
+  }
+}
+
 svt_status readback(Handle* h, int count) {
   HIPCHK(hipMemcpyAsync(h->hscal, h->scal, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   CHK(wait_stream(h));
@@ -426,11 +435,16 @@ struct Engine {
   // ----------------------------------------------------------------------------------------
   svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
     double normB = 0.0;
-    if (h->yT) {
+    const bool pre = h->spec_ready && h->r > 0;  // leading work already enqueued (see iteration())
+    h->spec_ready = false;
+    if (h->yT && !pre) {
       PhaseTimer tm(h, SVT_PH_DENSIFY, work_bytes(SVT_PH_DENSIFY));
       CHK(run_densify());
     }
-    if (h->r == 0) {
+    if (pre) {
+      CHK(wait_event(h, h->spec_ev));
+      normB = h->hscal[kSpecSlot];
+    } else if (h->r == 0) {
       int got = 0;
       double add = 0.0;
       CHK(append_block(it, 0, h->p.t0, &got, &add));
@@ -730,6 +744,27 @@ struct Engine {
     return SVT_OK;
   }
 
+  // The leading work of an R4SVD call on the current Y and basis: the dense copy of Y, W = Y^T Q and
+  // ||W||^2 (to hscal[kSpecSlot], spec_ev recorded after the copy).
+  svt_status lead_work() {
+    hipStream_t s = h->stream;
+    if (h->yT) {
+      PhaseTimer tm(h, SVT_PH_DENSIFY, work_bytes(SVT_PH_DENSIFY));
+      CHK(run_densify());
+    }
+    {
+      PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
+      CHK(run_spmm_t());
+    }
+    {
+      PhaseTimer tm(h, SVT_PH_REDUCE);
+      HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+    }
+    HIPCHK(hipMemcpyAsync(h->hscal + kSpecSlot, h->scal + S_NORMB, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(h->spec_ev, s));
+    return SVT_OK;
+  }
+
   // ----------------------------------------------------------------------------------------
   // One iteration of Alg. 4 (reading: X^(i) on Lambda, residual, annealing, stop, update).
   // ----------------------------------------------------------------------------------------
@@ -763,7 +798,20 @@ struct Engine {
       HIPCHK(launch_finish(h->stream, h->partial, nbl, 3, 3, h->scal, S_RES2));
     }
     CHK(recycle_truncated());
-    CHK(readback(h, S_ABS + 1));
+    // This iteration's sums go to the host first.  In R4SVD mode the next iteration's leading work
+    // (dense copy, W = Y^T Q, ||W||^2 on the updated iterate and the recycled basis) is enqueued
+    // behind them, so the GPU runs it while the host waits for the sums and takes this iteration's
+    // decisions: none of them changes its inputs, and a stop leaves it unused.
+    HIPCHK(hipMemcpyAsync(h->hscal, h->scal, (size_t)(S_ABS + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipEventRecord(h->sync_ev, h->stream));
+    if (h->p.mode == SVT_MODE_R4SVD && h->r > 0) {
+      std::swap(h->y, h->y_next);
+      const svt_status ls = lead_work();
+      std::swap(h->y, h->y_next);
+      CHK(ls);
+      h->spec_ready = true;
+    }
+    CHK(wait_event(h, h->sync_ev));
     const double res2 = h->hscal[S_RES2], yn2 = h->hscal[S_YN2];
     const double rel = std::sqrt(res2) / h->norm_a;
     if (!std::isfinite(rel) || !std::isfinite(yn2)) return fail(h, SVT_E_NUMERIC, "non-finite residual");
@@ -785,6 +833,7 @@ struct Engine {
       st->stopped = 1;
       st->flags |= SVT_F_CONVERGED;
       h->converged = true;
+      h->spec_ready = false;
       return SVT_OK;
     }
     std::swap(h->y, h->y_next);
@@ -1142,6 +1191,7 @@ void release(Handle* h) {
   }
   for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
   if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
+  if (h->spec_ev) (void)hipEventDestroy(h->spec_ev);
 }
 
 }  // namespace
@@ -1373,6 +1423,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hscal, kScalars * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hstage, kStageDoubles * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->spec_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     svt_destroy(h);
@@ -1463,6 +1514,7 @@ svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
     }
     return SVT_OK;
   });
+  if (status != SVT_OK) h->spec_ready = false;
   if (last) *last = st;
   return status;
 }
@@ -1565,6 +1617,7 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   if (!y) return fail(h, SVT_E_INVALID_ARG, "y is NULL");
   if (r < 0 || r > h->p.r_max || (r > 0 && !Q)) return fail(h, SVT_E_INVALID_ARG, "bad basis width");
   if (iter < 0) return fail(h, SVT_E_INVALID_ARG, "iter must be non-negative");
+  h->spec_ready = false;  // the enqueued leading work was done on the state being replaced
   svt_status st = dispatch(h, [&](auto& eng) -> svt_status {
     using TT = std::remove_pointer_t<decltype(eng.a())>;
     CHK(eng.upload_lambda((TT*)h->y, y));
@@ -1623,6 +1676,7 @@ svt_status svt_time_phase(svt_handle* h, int32_t phase, int32_t reps, double* ms
     return fail(h, SVT_E_INVALID_ARG, "svt_time_phase times single-kernel phases only");
   if (reps < 1 || !ms) return fail(h, SVT_E_INVALID_ARG, "reps must be positive and ms non-NULL");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no iteration has run yet");
+  h->spec_ready = false;  // the replayed kernels reuse the buffers the enqueued leading work wrote
   return dispatch(h, [&](auto& eng) -> svt_status {
     CHK(eng.replay_phase(phase, reps, ms));
     if (bytes) *bytes = eng.work_bytes(phase);
@@ -1665,7 +1719,10 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
     return fail(h, SVT_E_STATE, "svt_grad needs T iterations run by svt_iterate since svt_init");
   for (int i = 0; i < T; ++i)
     if (h->hist_r[i] > kEigMax) return fail(h, SVT_E_LIMIT, "svt_grad supports bases of at most 96 columns");
-  return grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, dtau, ddelta, da);
+  h->spec_ready = false;  // the adjoint reuses the buffers the enqueued leading work wrote
+  const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, dtau, ddelta, da);
+  h->spec_ready = false;
+  return gs;
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
 constexpr int kScalars = 64;  // doubles in the device->host readback buffer
+constexpr int kSpecSlot = 48;  // host slot of the next iteration's ||W||^2 (past every readback's range)
 constexpr int kStageDoubles = 4096;  // pinned staging doubles for small device->host copies
 constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
@@ -136,6 +137,10 @@ struct Handle {
   double* hscal = nullptr;  // pinned host mirror
   double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks
   hipEvent_t sync_ev = nullptr;  // timing-free event the host spins on at decision points
+  // The next iteration's leading work (dense copy of Y, W = Y^T Q, ||W||^2) was enqueued at the end
+  // of the previous iteration; ||W||^2 lands in hscal[kSpecSlot] when spec_ev completes.
+  bool spec_ready = false;
+  hipEvent_t spec_ev = nullptr;
 
   // iteration state (host)
   int32_t r = 0;
