@@ -229,6 +229,35 @@ def test_run_twice_bitwise_identical(gpu_lib):
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
 
 
+@pytest.mark.parametrize("frac", [0.4, 0.15])
+def test_calls_between_steps_leave_trajectory_unchanged(gpu_lib, frac):
+    """R4SVD enqueues the next step's leading work (dense copy, W = Y^T Q, ||W||^2) at the end of a step.  Steps
+    taken one call at a time, with reads and single-phase replays between them (which drop or keep that work),
+    must follow the trajectory of one call taking them all, bit for bit (dense-copy and gather paths)."""
+    w = W.tiny_dense(160, 140, 5, frac, seed=48)
+    _, k0 = initial_state(_problem(w), Params(tau=w.tau, delta=w.delta))
+    ref = _gpu(gpu_lib, w, k0, seed=9, tol=1e-13)  # no stop within the 16 steps
+    st_ref = ref.iterate(16)
+    h = _gpu(gpu_lib, w, k0, seed=9, tol=1e-13)
+    qi, qj = w.rows[:50], w.cols[:50]
+    for it in range(16):
+        st = h.iterate(1)
+        if it % 4 == 0:
+            h.sample(qi, qj)
+            h.get_state()
+        if it % 4 == 1:
+            h.time_phase("spmm_t", reps=2)
+        if it % 4 == 2:
+            h.time_phase("gram", reps=2)
+            h.time_phase("sddmm", reps=2)
+        if it % 4 == 3 and h.get_state()["r"] > 0:
+            h.factors()
+    assert st.iter == st_ref.iter and st.rel_res == st_ref.rel_res and st.r == st_ref.r
+    a, b = ref.get_state(), h.get_state()
+    np.testing.assert_array_equal(a["y"], b["y"])
+    np.testing.assert_array_equal(a["Q"], b["Q"])
+
+
 def test_rmax_and_range_exhaustion_flags(gpu_lib):
     import paper_1704_05528_amd as svt
     w = W.tiny_dense(60, 50, 3, 0.5, seed=47)
