@@ -617,6 +617,97 @@ __global__ __launch_bounds__(kGramWaves * kWave) void k_gram_tiles(int rows, con
   }
 }
 
+// The same Gram with 32 x 32 tiles, for blocks of several hundred columns: each wave holds the
+// tile as 2 x 2 matrix-instruction blocks, so a k-step loads two 64-byte segments per side and
+// issues four independent products (twice the products per load of the 16 x 16 tiles, and a
+// quarter of the workgroups re-reading A).  Eight waves split the rows.
+constexpr int kGT2 = 32;
+constexpr int kGram2Waves = 8;
+constexpr int kGram32MinCols = 416;  // measured crossover with the 16 x 16 tiles (1024 and 3706 rows)
+
+template <class T>
+__global__ __launch_bounds__(kGram2Waves * kWave) void k_gram_tiles32(int rows, const T* __restrict__ A, int lda,
+                                                                      int na, double* __restrict__ G, int ldg,
+                                                                      int ntile) {
+  __shared__ double red[kGram2Waves - 1][16][kWave];
+  int t = blockIdx.x, ti = 0;
+  while (t >= ntile - ti) {
+    t -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + t;
+  const bool diag = ti == tj;
+  const int lane = threadIdx.x & (kWave - 1), grp = threadIdx.x / kWave;
+  const int a0 = ti * kGT2, b0 = tj * kGT2;
+  const int c = lane & 15, kl = lane >> 4;
+  // Columns past na are read at column na - 1: a lane's A operand only reaches output row
+  // a0 + 16 i + c and its B operand only output column b0 + 16 j + c, which are not stored.
+  const T* acol[2];
+  const T* bcol[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    acol[h] = A + min(a0 + 16 * h + c, na - 1);
+    bcol[h] = A + min(b0 + 16 * h + c, na - 1);
+  }
+  const int steps = (rows + 3) / 4;
+  const int per = (steps + kGram2Waves - 1) / kGram2Waves;
+  const int s0 = grp * per, s1 = min(steps, s0 + per);
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  auto batch = [&](int st, bool tail) {
+    double a[kUnroll][2], b[kUnroll][2];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int row = (st + u) * 4 + kl;
+      const int64_t off = (int64_t)(tail ? min(row, rows - 1) : row) * lda;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[u][h] = (double)acol[h][off];
+        b[u][h] = (double)bcol[h][off];
+      }
+      // rows past this wave's range or past the end add nothing (a zero A operand)
+      if (tail && !((st + u < s1) && (row < rows))) a[u][0] = a[u][1] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64_16x16x4(a[u][i], b[u][j], acc[i][j]);
+  };
+  int st = s0;
+  // full batches: every row of the batch lies in this wave's range and in A
+  for (; st + kUnroll <= s1 && (st + kUnroll) * 4 <= rows; st += kUnroll) batch(st, false);
+  for (; st < s1; st += kUnroll) batch(st, true);
+  if (grp > 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[grp - 1][(i * 2 + j) * 4 + v][lane] = acc[i][j][v];
+  }
+  __syncthreads();
+  if (grp > 0) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double sum = acc[i][j][v];
+        for (int g = 0; g < kGram2Waves - 1; ++g) sum += red[g][(i * 2 + j) * 4 + v][lane];
+        const int ra = a0 + 16 * i + kl + 4 * v, cb = b0 + 16 * j + c;
+        if (ra < na && cb < na) {
+          G[(int64_t)ra * ldg + cb] = sum;
+          if (!diag) G[(int64_t)cb * ldg + ra] = sum;
+        }
+      }
+}
+
 // ------------------------------------------------------------------------------------------
 // Reductions (double accumulation)
 // ------------------------------------------------------------------------------------------
@@ -1321,6 +1412,14 @@ hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, dou
   // wide blocks over many rows: 64 x 64 LDS-staged tiles (16 x 16 tiles re-read every column
   // block na / 16 times, and their operand traffic dominates there)
   if ((int64_t)rows * na >= kGramTiledMin) return launch_gram_tn<T>(s, rows, A, lda, na, G, ldg);
+  // from a few hundred columns on, 32 x 32 tiles (half the operand loads per product); below, the
+  // 16 x 16 tiles spread more workgroups over the compute units
+  if (na >= kGram32MinCols) {
+    const int nt = (na + kGT2 - 1) / kGT2;
+    hipLaunchKernelGGL(k_gram_tiles32<T>, dim3(nt * (nt + 1) / 2), dim3(kGram2Waves * kWave), 0, s, rows, A, lda, na,
+                       G, ldg, nt);
+    return hipGetLastError();
+  }
   const int nt = (na + kGT - 1) / kGT;
   const int ntri = nt * (nt + 1) / 2;
   hipLaunchKernelGGL(k_gram_tiles<T>, dim3(ntri), dim3(kGramWaves * kWave), 0, s, rows, A, lda, na, G, ldg, nt);

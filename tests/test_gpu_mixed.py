@@ -5,12 +5,15 @@ Bars: against the emulated oracle, values within 2e-5 relative (float32 accumula
 about sqrt(row length) x 6e-8, amplified by the conditioning of the step); against the FP64
 oracle the same step stays within 1e-4 relative; integers (r, k, blocks) exact.
 """
+import math
+
 import numpy as np
 import pytest
 
 import svt_workloads as W
 from oracle import Params, Problem, State, initial_state, svt_run, svt_step
 from oracle.mixed import f32, svt_step_mixed
+from oracle.svt import kicking_k0, spectral_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +133,30 @@ def test_mixed_step_heavy_columns_chunked_gather(gpu_lib, extra):
     st = h.iterate(1)
     x = h.sample(w.rows, w.cols)
     assert info_emu.k > 0
+    assert st.r == info_emu.r and st.k == info_emu.k and st.blocks == info_emu.blocks
+    assert rel_err(x, info_emu.x) <= TOL_EMU, rel_err(x, info_emu.x)
+    assert abs(st.rel_res - info_emu.rel) <= TOL_EMU * info_emu.rel
+    assert rel_err(h.get_state()["y"], nxt_emu.y) <= TOL_EMU
+
+
+def test_mixed_step_wide_basis_gram_32_tiles(gpu_lib):
+    """The mixed form with a 537-column basis on 997 columns of Y: the float W gives its FP64 Gram
+    matrix through the 32 x 32-tile kernel.  One step from a given state against the emulated oracle."""
+    m, n, r = 700, 997, 537
+    w = W.tiny_dense(m, n, 5, 0.3, seed=63, delta=1.2)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=63, maxit=10, r_max=m)
+    rng = np.random.default_rng(64)
+    Q0, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    k0 = kicking_k0(w.tau, w.delta, spectral_norm(m, n, w.rows, w.cols, w.a))
+    st32 = State(it=4, y=f32(2.0 * k0 * w.delta * w.a), Q=f32(Q0), eps_thr=0.99, eps_min=math.inf)
+    nxt_emu, info_emu = svt_step_mixed(prob, p, st32)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, seed=63, maxit=10, r_max=m,
+                         precision=gpu_lib.SVT_MIXED)
+    h.set_state(st32.y, st32.Q, st32.eps_thr, st32.eps_min, st32.it)
+    st = h.iterate(1)
+    x = h.sample(w.rows, w.cols)
+    assert info_emu.k == 5 and info_emu.blocks == 0
     assert st.r == info_emu.r and st.k == info_emu.k and st.blocks == info_emu.blocks
     assert rel_err(x, info_emu.x) <= TOL_EMU, rel_err(x, info_emu.x)
     assert abs(st.rel_res - info_emu.rel) <= TOL_EMU * info_emu.rel

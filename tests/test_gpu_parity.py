@@ -157,6 +157,31 @@ def test_wide_basis_tiled_gram(gpu_lib):
     assert np.abs(Pg - Po).max() <= 1e-10
 
 
+@pytest.mark.parametrize("m,r", [(600, 450), (700, 537)])
+def test_wide_basis_gram_32_tiles(gpu_lib, m, r):
+    """A basis of several hundred columns on 997 columns of Y: the Gram matrix W^T W comes from the
+    32 x 32-tile kernel (537 columns leave a ragged tile, 997 rows a partial last k-step).  One step
+    from a given state on both sides (k = 5, the planted rank, with a clear gap below it)."""
+    n = 997
+    w = W.tiny_dense(m, n, 5, 0.3, seed=63, delta=1.2)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=63, maxit=10, r_max=m)
+    rng = np.random.default_rng(64)
+    Q0, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    k0 = kicking_k0(w.tau, w.delta, spectral_norm(m, n, w.rows, w.cols, w.a))
+    state = State(it=4, y=2.0 * k0 * w.delta * w.a, Q=Q0, eps_thr=0.99, eps_min=math.inf)
+    nxt, info = svt_step(prob, p, state)
+    assert info.blocks == 0 and info.r == r and info.k == 5
+    h = _gpu(gpu_lib, w, k0, seed=63, maxit=10, r_max=m)
+    h.set_state(state.y, state.Q, state.eps_thr, state.eps_min, state.it)
+    st = h.iterate(1)
+    assert not (st.flags & SVT_F_EIG_INEXACT)
+    _compare_step(st, info, h, w, "gram 32")
+    s = h.get_state()
+    assert rel_err(s["y"], nxt.y) <= TOL
+    assert np.abs(s["Q"] @ s["Q"].T - nxt.Q @ nxt.Q.T).max() <= 1e-10
+
+
 def test_state_roundtrip_and_orthonormal_basis(gpu_lib):
     w = W.tiny_dense(80, 60, 3, 0.5, seed=43)
     prob = _problem(w)
