@@ -442,15 +442,22 @@ __global__ __launch_bounds__(NW * kWave) void k_rowmul(RowmulProblem<TA, TM, TO>
   dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   // full batches of kUnroll k-steps (the last one predicated), so a slice's loads all issue together
   for (int st = s0; st < s1; st += kUnroll) {
+    // the loads of the batch first, in the operands' own types, then conversion and masking (with
+    // a conversion between them the compiler issued each load only after the previous one returned)
+    TA ar[kUnroll];
+    TM br[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int kc = min((st + u) * 4 + kl, K - 1);
+      ar[u] = arow[kc];
+      br[u] = mcol[(int64_t)kc * ldm];
+    }
     double a[kUnroll], b[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int k = (st + u) * 4 + kl;
-      const bool ok = (st + u < s1) && (k < K);
-      const int kc = min(k, K - 1);
-      const double av = (double)arow[kc], bv = (double)mcol[(int64_t)kc * ldm];
-      a[u] = (rowok && ok) ? av : 0.0;
-      b[u] = (colok && ok) ? bv : 0.0;
+      const bool ok = (st + u < s1) && ((st + u) * 4 + kl < K);
+      a[u] = (rowok && ok) ? (double)ar[u] : 0.0;
+      b[u] = (colok && ok) ? (double)br[u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; u += 2) {
@@ -854,9 +861,13 @@ __global__ __launch_bounds__(256) void k_trsm_rows(int rows, const T* __restrict
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
+  // loads first (columns clamped to w - 1, w >= 1), then conversion and masking, so they issue together
+  T xr[WM];
+#pragma unroll
+  for (int c = 0; c < WM; ++c) xr[c] = X[(int64_t)i * ldx + min(c, w - 1)];
   double z[WM];
 #pragma unroll
-  for (int c = 0; c < WM; ++c) z[c] = (c < w) ? (double)X[(int64_t)i * ldx + c] : 0.0;
+  for (int c = 0; c < WM; ++c) z[c] = (c < w) ? (double)xr[c] : 0.0;
 #pragma unroll
   for (int c = 0; c < WM; ++c) {
     if (c < w) {
@@ -1049,9 +1060,15 @@ __global__ __launch_bounds__(kCholTrsmThreads) void k_chol_trsm(int rows, const 
   if (tid >= kCholTrsmRows) return;
   const int i = blockIdx.x * kCholTrsmRows + tid;
   const bool live = i < rows;
+  // the row's loads first (clamped, valid addresses: rows, w >= 1), then conversion and masking; with
+  // a masked conversion per load the compiler issued each load only after the previous one returned
+  T xr[WM];
+  const T* xrow = X + (int64_t)min(i, rows - 1) * ldx;
+#pragma unroll
+  for (int c = 0; c < WM; ++c) xr[c] = xrow[min(c, w - 1)];
   double z[WM];
 #pragma unroll
-  for (int c = 0; c < WM; ++c) z[c] = (live && c < w) ? (double)X[(int64_t)i * ldx + c] : 0.0;
+  for (int c = 0; c < WM; ++c) z[c] = (live && c < w) ? (double)xr[c] : 0.0;
 #pragma unroll
   for (int c = 0; c < WM; ++c) {
     if (c < w) {
@@ -1509,6 +1526,7 @@ hipError_t set_trsm_attr() {
 template <class T>
 hipError_t launch_trsm_rows(hipStream_t s, int rows, const T* X, int ldx, int w, const double* R, int ldr, T* out,
                             int ldo) {
+  if (rows < 0 || w < 0 || w > kEigMax) return hipErrorInvalidValue;
   if (rows == 0 || w == 0) return hipSuccess;
   const size_t lds = (size_t)w * (w + 1) * sizeof(double);
   // one row per thread in 64-thread workgroups: a few hundred rows still occupy many CUs
