@@ -139,7 +139,8 @@ void svt_default_params(svt_params* p);
  * the device, builds the column-major (CSC) and row-major (CSR) orders,
  * computes ||P_Lambda A||_F and, when p->k0 < 0, ||P_Lambda A||_2 by power
  * iteration, and sets Y^(0) = k0 * delta * P_Lambda(A) (kicking, Alg. 4
- * initialisation).  stream: a hipStream_t, or NULL for the default stream.
+ * initialisation).  stream: a hipStream_t, or NULL for the default stream; every
+ * later call on the handle works on it, so it must stay valid until svt_destroy.
  * Errors: SVT_E_INVALID_ARG for m, n, nnz <= 0, indices out of range,
  * duplicate (row, col), tau <= 0, delta <= 0, beta outside (0, 1), dt < 1,
  * kmax > 96, non-finite values. */
@@ -156,7 +157,10 @@ svt_status r4svd_step(svt_handle* h, svt_step_stats* st);
  * maxit.  *last receives the report of the last iteration run (may be NULL).
  * Returns SVT_E_STATE if the run had already converged, SVT_E_NUMERIC when the
  * iterate stops being finite (a diverging step size), SVT_E_LIMIT when more than
- * kmax singular values rise above tau. */
+ * kmax singular values rise above tau.  In R4SVD mode, unless the run stopped,
+ * the call returns with the next step's first kernels (the projection of the
+ * new iterate on the recycled basis) queued on the handle's stream; later calls
+ * on the handle are ordered after them. */
 svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last);
 
 /* Reports of the iterations run by svt_iterate on this handle, oldest first (iteration i of the
@@ -262,7 +266,9 @@ svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* fl
 /* Text of the last error on this handle (or of the last failed svt_init when h is NULL). */
 const char* svt_last_error(const svt_handle* h);
 
-/* Release every device and host buffer of the handle.  NULL is allowed. */
+/* Wait for the handle's stream (svt_iterate may return with the next step's
+ * first kernels still queued), then release every device and host buffer of
+ * the handle.  NULL is allowed. */
 void svt_destroy(svt_handle* h);
 
 #ifdef __cplusplus

@@ -1173,6 +1173,9 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
 }
 
 void release(Handle* h) {
+  // work may still be queued on the stream (svt_iterate returns with the next step's leading
+  // kernels and their copy into pinned memory enqueued): let it finish before anything is freed
+  (void)hipStreamSynchronize(h->stream);
   void* bufs[] = {h->colptr, h->rowidx, h->rowptr, h->colidx, h->csr2csc, h->tstart, h->cstart, h->ccol, h->yT, h->a,
                   h->y,
                   h->y_next,

@@ -52,6 +52,7 @@ class SVT:
         check(L.svt_init(C.byref(h), self.m, self.n, self.nnz, rp, cp, vp, C.byref(self.params),
                          _stream_handle(stream)), None)
         self._h = h
+        self._stream = stream  # the library works on this stream until close(): keep it alive
 
     def close(self):
         if getattr(self, "_h", None):
