@@ -53,7 +53,8 @@ typedef enum {
                              has left the storage type's range, e.g. under a step size above the stable
                              bound), or a non-positive ||Y||_F */
   SVT_E_STATE = -5,       /* call not valid in the handle's current state */
-  SVT_E_LIMIT = -6        /* more singular values above tau than the tracked maximum (kmax) */
+  SVT_E_LIMIT = -6        /* more singular values above tau than the tracked maximum (kmax), or a basis
+                             wider than the full eigen-solver's largest order (4096) */
 } svt_status;
 
 /* Precision forms. */
@@ -79,7 +80,8 @@ enum {
   SVT_F_RMAX_HIT = 4,  /* growth stopped because the basis reached r_max */
   SVT_F_EXHAUSTED = 8, /* a growth block had no direction outside span(Q) */
   SVT_F_ANNEALED = 16, /* eps_threshold was multiplied by beta in this iteration */
-  SVT_F_EIG_INEXACT = 32 /* the top-eigenpair solver stopped at its iteration cap */
+  SVT_F_EIG_INEXACT = 32 /* the eigen-solver stopped at its cap (products of the subspace solver, or
+                            sweeps of the full decomposition) */
 };
 
 /* Inputs of Alg. 4 plus the values the paper leaves open.  Fill with
@@ -100,7 +102,10 @@ typedef struct {
   int32_t k0;      /* kicking count; < 0 => ceil(tau / (delta ||P_Lambda A||_2)) */
   uint64_t seed;   /* key of the Philox4x64-10 Omega stream */
   int32_t precision; /* SVT_FP64 or SVT_MIXED */
-  int32_t kmax;    /* most singular values above tau the eigensolver tracks; <= 0 => 64 (max 96) */
+  int32_t kmax;    /* most singular values above tau tracked (the factor buffers hold this many
+                      columns); <= 0 => r_max, i.e. every singular value the basis can hold.  Counts
+                      that need a wider block than the subspace solver's 96 columns are found by a full
+                      eigen-decomposition of the projected Gram (Jacobi over many workgroups) */
   int32_t mode;    /* SVT_MODE_R4SVD (default), SVT_MODE_R3SVD or SVT_MODE_RSVD */
   int32_t recycle_extra; /* R4SVD: < 0 recycles all r columns (default); e >= 0 recycles only the
                             k + e leading left singular vectors of B */
@@ -119,7 +124,8 @@ typedef struct {
   int32_t annealed;  /* 1 if eps_threshold was multiplied by beta */
   int32_t stopped;   /* 1 if rel_res < tol (Y not updated) */
   int32_t flags;     /* SVT_F_* bits */
-  int32_t eig_iters; /* subspace iterations spent by the top-eigenpair solver */
+  int32_t eig_iters; /* products and tests of the subspace eigen-solver, or the sweeps of the full
+                        Jacobi decomposition of the projected Gram */
   double eps;        /* error percentage when R4SVD returned */
   double eps_thr;    /* eps_threshold R4SVD ran with */
   double rel_res;    /* ||P_Lambda(A - X)||_F / ||P_Lambda A||_F */
@@ -142,8 +148,8 @@ void svt_default_params(svt_params* p);
  * initialisation).  stream: a hipStream_t, or NULL for the default stream; every
  * later call on the handle works on it, so it must stay valid until svt_destroy.
  * Errors: SVT_E_INVALID_ARG for m, n, nnz <= 0, indices out of range,
- * duplicate (row, col), tau <= 0, delta <= 0, beta outside (0, 1), dt < 1,
- * kmax > 96, non-finite values. */
+ * duplicate (row, col), tau <= 0, delta <= 0, beta outside (0, 1), eta outside
+ * [0, 1), npow < 0, non-finite values. */
 svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows,
                     const int32_t* cols, const double* vals, const svt_params* p, void* stream);
 
@@ -206,18 +212,22 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
  * the forward run are held fixed, so iteration i is the map
  * Y_i -> X_i = Q_i D_tau(Q_i^T Y_i) (Eq. 5) followed by the dual update.
  * The handle must have run at least T iterations since svt_init (svt_iterate,
- * no svt_set_state since), in the FP64 form, with bases of at most 96 columns
- * over those T iterations.  The Y_i are recomputed from Y_1 = k0 delta P(A),
- * checkpointed every ckpt iterations (ckpt <= 0: about sqrt(T)); device
- * memory of (T / ckpt + ckpt) nnz doubles plus a few m x 288 and n x 288
- * blocks is allocated for the call and released before it returns.
+ * no svt_set_state since), in the FP64 form.  Every eigenpair of each projected
+ * Gram enters the derivative: bases up to 96 columns are diagonalised in one
+ * workgroup, wider ones (up to 4096) by the many-workgroup Jacobi.  The Y_i are
+ * recomputed from Y_1 = k0 delta P(A), checkpointed every ckpt iterations
+ * (ckpt <= 0: about sqrt(T)); device memory of (T / ckpt + ckpt) nnz doubles
+ * plus blocks of m x 3w and n x 3w doubles (w = the widest basis plus 2, rounded
+ * up to 8) and a few w x w matrices is allocated for the call and released
+ * before it returns.
  * Input: gx_h[l] = dL/dX_T(hi[l], hj[l]) on the held-out set H (nh entries,
  * repeats add up; nh = 0 gives zero gradients).
  * Outputs: *dtau, *ddelta, and da (nnz, caller order) = dL/dA on Lambda.
  * The iteration state of the handle is left unchanged.
  * Errors: SVT_E_INVALID_ARG (T <= 0, NULL outputs, H index out of range),
  * SVT_E_STATE (fewer than T recorded iterations, state replaced, mixed form),
- * SVT_E_LIMIT (a basis wider than 96 columns). */
+ * SVT_E_LIMIT (a basis wider than 4096 columns), SVT_E_NUMERIC (an eigen-
+ * decomposition that did not converge). */
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
                     const double* gx_h, double* dtau, double* ddelta, double* da);
 

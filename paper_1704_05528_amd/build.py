@@ -14,7 +14,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsvt.so")
-SOURCES = ["kernels.hip", "gemm.hip", "gram.hip", "eig.hip", "adjoint.hip", "svt_api.hip"]
+SOURCES = ["kernels.hip", "gemm.hip", "gram.hip", "eig.hip", "eigfull.hip", "adjoint.hip", "svt_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -41,101 +41,116 @@ __device__ inline double block_sum(double v, double* lds) {
   return t;
 }
 
-// One workgroup, double.  U: r x r eigenvectors of G (columns, descending eigenvalues theta),
-// Z1 = Bbar V_K (r x k), Z2 = Bbar B^T (r x r).  Writes Cmat (r x (2k + r), ld ldc) and
-// scal[slot] = tau_bar; scratch: r x r (ld r) in global memory.  LDS: 4 r k + r doubles.
-__global__ __launch_bounds__(256) void k_adjoint_coeffs(int r, int k, const double* __restrict__ U, int ldu,
-                                                        const double* __restrict__ theta,
-                                                        const double* __restrict__ Z1, int ldz1,
-                                                        const double* __restrict__ Z2, int ldz2, double tau,
-                                                        double* __restrict__ Cmat, int ldc, double* __restrict__ scratch,
-                                                        double* scal, int slot) {
-  extern __shared__ double sm[];
-  double* M1 = sm;                      // r x k : U^T Bbar V_K
-  double* M2 = M1 + r * k;              // k x r : U_K^T Bbar B^T U
-  double* T2 = M2 + k * r;              // k x r : U_K^T Z2, then r x k : coefficient matrix Ec
-  double* Bt = T2 + k * r;              // r x k : Beta (rows j in N)
-  double* sg = Bt + r * k;              // r singular values
-  __shared__ double lds[4];
-  const int tid = threadIdx.x;
-  for (int j = tid; j < r; j += blockDim.x) sg[j] = sqrt(fmax(theta[j], 0.0));
-  for (int e = tid; e < r * k; e += blockDim.x) {
-    const int j = e / k, c = e % k;
+// The coefficient block of one unrolled iteration, in global memory (any r), as five grid-wide
+// passes with one thread per output entry.  U: r x r eigenvectors of G (columns, descending
+// eigenvalues theta), Z1 = Bbar V_K (r x k), Z2 = Bbar B^T (r x r).  Work arrays (ld as noted):
+// M1 = U^T Z1 (r x k), T2 = U_K^T Z2 (k x r), M2 = T2 U (k x r), Ec (r x k), Bt (r x k), S = U_K Bt^T
+// (r x r).  Cmat = [U_K diag(f/s) | U Ec | S U^T restricted to j in N] (r x (2k + r), ld ldc).
+struct AdjWork {
+  double *M1, *T2, *M2, *Ec, *Bt, *S;
+};
+
+__device__ inline double sg_of(const double* theta, int j) { return sqrt(fmax(theta[j], 0.0)); }
+
+__global__ void k_adj_m1t2(int r, int k, const double* __restrict__ U, int ldu, const double* __restrict__ Z1, int ldz1,
+                           const double* __restrict__ Z2, int ldz2, AdjWork w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rk = (int64_t)r * k;
+  if (e < rk) {
+    const int j = (int)(e / k), c = (int)(e % k);
     double v = 0.0;
     for (int l = 0; l < r; ++l) v = fma(U[(int64_t)l * ldu + j], Z1[(int64_t)l * ldz1 + c], v);
-    M1[j * k + c] = v;
-  }
-  for (int e = tid; e < k * r; e += blockDim.x) {
-    const int c = e / r, j = e % r;
+    w.M1[j * (int64_t)k + c] = v;
+  } else if (e < 2 * rk) {
+    const int64_t f = e - rk;
+    const int c = (int)(f / r), j = (int)(f % r);
     double v = 0.0;
     for (int l = 0; l < r; ++l) v = fma(U[(int64_t)l * ldu + c], Z2[(int64_t)l * ldz2 + j], v);
-    T2[c * r + j] = v;
+    w.T2[c * (int64_t)r + j] = v;
   }
-  __syncthreads();
-  for (int e = tid; e < k * r; e += blockDim.x) {
-    const int c = e / r, j = e % r;
-    double v = 0.0;
-    for (int l = 0; l < r; ++l) v = fma(T2[c * r + l], U[(int64_t)l * ldu + j], v);
-    M2[c * r + j] = v;
-  }
-  __syncthreads();
+}
+
+__global__ void k_adj_m2(int r, int k, const double* __restrict__ U, int ldu, AdjWork w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * r) return;
+  const int c = (int)(e / r), j = (int)(e % r);
+  double v = 0.0;
+  for (int l = 0; l < r; ++l) v = fma(w.T2[c * (int64_t)r + l], U[(int64_t)l * ldu + j], v);
+  w.M2[c * (int64_t)r + j] = v;
+}
+
+// tau_bar = -trace(M1_KK) in the order of one 256-thread block sum
+__global__ __launch_bounds__(256) void k_adj_trace(int k, AdjWork w, double* scal, int slot) {
+  __shared__ double lds[4];
   double tr = 0.0;
-  for (int c = tid; c < k; c += blockDim.x) tr += M1[c * k + c];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) tr += w.M1[c * (int64_t)k + c];
   const double trs = block_sum(tr, lds);
-  if (tid == 0) scal[slot] = -trs;
-  // Ec[i][c]: Gamma_ic for i in K, Kappa_ic for i in N; Beta[j][i] for j in N (zero for j in K)
-  double* Ec = T2;
-  for (int e = tid; e < r * k; e += blockDim.x) {
-    const int i = e / k, c = e % k;
-    const double sc = sg[c], fc = sc - tau;
-    double v;
-    if (i < k) {
-      const double si = sg[i], fi = si - tau;
-      if (i == c) {
-        v = M1[i * k + c] - fi / si * M1[i * k + c];
-      } else {
-        const double a = (si != sc) ? (fi - fc) / (si - sc) : 1.0;
-        const double b = (fi + fc) / (si + sc);
-        v = 0.5 * (a + b) * M1[i * k + c] + 0.5 * (a - b) * M1[c * k + i] - fi / si * M1[i * k + c];
-      }
+  if (threadIdx.x == 0) scal[slot] = -trs;
+}
+
+// Ec[i][c]: Gamma_ic for i in K, Kappa_ic for i in N; Bt[j][c] = Beta_jc for j in N (zero in K);
+// Cmat[:, c] = U_K diag(f/s) for c < k
+__global__ void k_adj_coeffs(int r, int k, const double* __restrict__ U, int ldu, const double* __restrict__ theta,
+                             double tau, AdjWork w, double* __restrict__ Cmat, int ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * k) return;
+  const int i = (int)(e / k), c = (int)(e % k);
+  const double* M1 = w.M1;
+  const double* M2 = w.M2;
+  const double sc = sg_of(theta, c), fc = sc - tau;
+  double v;
+  if (i < k) {
+    const double si = sg_of(theta, i), fi = si - tau;
+    if (i == c) {
+      v = M1[i * (int64_t)k + c] - fi / si * M1[i * (int64_t)k + c];
     } else {
-      const double si = sg[i];
-      v = fc * (sc * M1[i * k + c] + M2[c * r + i]) / (sc * sc - si * si);
+      const double a = (si != sc) ? (fi - fc) / (si - sc) : 1.0;
+      const double b = (fi + fc) / (si + sc);
+      v = 0.5 * (a + b) * M1[i * (int64_t)k + c] + 0.5 * (a - b) * M1[c * (int64_t)k + i] - fi / si * M1[i * (int64_t)k + c];
     }
-    Ec[i * k + c] = v;
-    // Beta[j = i][c]  (the role of the K index is played by c here)
-    double bt = 0.0;
-    if (i >= k) {
-      const double sj = sg[i];
-      bt = (fc / sc * M2[c * r + i] + fc * M1[i * k + c]) / (sc * sc - sj * sj);
-    }
-    Bt[i * k + c] = bt;
+  } else {
+    const double si = sg_of(theta, i);
+    v = fc * (sc * M1[i * (int64_t)k + c] + M2[c * (int64_t)r + i]) / (sc * sc - si * si);
   }
-  __syncthreads();
-  // Cmat[:, 0:k] = U_K diag(f/s);  Cmat[:, k:2k] = U Ec;  scratch = U_K Beta^T (r x r)
-  for (int e = tid; e < r * k; e += blockDim.x) {
-    const int l = e / k, c = e % k;
-    const double sc = sg[c];
-    Cmat[(int64_t)l * ldc + c] = U[(int64_t)l * ldu + c] * (sc - tau) / sc;
+  w.Ec[i * (int64_t)k + c] = v;
+  double bt = 0.0;
+  if (i >= k) {
+    const double sj = sg_of(theta, i);
+    bt = (fc / sc * M2[c * (int64_t)r + i] + fc * M1[i * (int64_t)k + c]) / (sc * sc - sj * sj);
+  }
+  w.Bt[i * (int64_t)k + c] = bt;
+  // Cmat[:, 0:k]: row i of U_K diag(f/s) (i plays the row index l here)
+  Cmat[(int64_t)i * ldc + c] = U[(int64_t)i * ldu + c] * (sc - tau) / sc;
+}
+
+// Cmat[:, k:2k] = U Ec and S = U_K Bt^T (r x r)
+__global__ void k_adj_uec(int r, int k, const double* __restrict__ U, int ldu, AdjWork w, double* __restrict__ Cmat,
+                          int ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rk = (int64_t)r * k;
+  if (e < rk) {
+    const int l = (int)(e / k), c = (int)(e % k);
     double v = 0.0;
-    for (int i = 0; i < r; ++i) v = fma(U[(int64_t)l * ldu + i], Ec[i * k + c], v);
+    for (int i = 0; i < r; ++i) v = fma(U[(int64_t)l * ldu + i], w.Ec[i * (int64_t)k + c], v);
     Cmat[(int64_t)l * ldc + k + c] = v;
-  }
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int l = e / r, j = e % r;
+  } else if (e < rk + (int64_t)r * r) {
+    const int64_t f = e - rk;
+    const int l = (int)(f / r), j = (int)(f % r);
     double v = 0.0;
-    for (int i = 0; i < k; ++i) v = fma(U[(int64_t)l * ldu + i], Bt[j * k + i], v);
-    scratch[(int64_t)l * r + j] = v;
+    for (int i = 0; i < k; ++i) v = fma(U[(int64_t)l * ldu + i], w.Bt[j * (int64_t)k + i], v);
+    w.S[(int64_t)l * r + j] = v;
   }
-  __threadfence_block();
-  __syncthreads();
-  // Cmat[:, 2k:2k+r] = (U_K Beta^T) U^T
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const int l = e / r, q = e % r;
-    double v = 0.0;
-    for (int j = k; j < r; ++j) v = fma(scratch[(int64_t)l * r + j], U[(int64_t)q * ldu + j], v);
-    Cmat[(int64_t)l * ldc + 2 * k + q] = v;
-  }
+}
+
+// Cmat[:, 2k:2k+r] = S U^T over the columns j in N
+__global__ void k_adj_sut(int r, int k, const double* __restrict__ U, int ldu, AdjWork w, double* __restrict__ Cmat,
+                          int ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int l = (int)(e / r), q = (int)(e % r);
+  double v = 0.0;
+  for (int j = k; j < r; ++j) v = fma(w.S[(int64_t)l * r + j], U[(int64_t)q * ldu + j], v);
+  Cmat[(int64_t)l * ldc + 2 * k + q] = v;
 }
 
 // out[p] = sum_l L[row(p), l] R[col(p), l] for the CSC positions p of Lambda (one thread each)
@@ -189,20 +204,25 @@ inline unsigned grid1(int64_t work, int per = 256) { return (unsigned)((work + p
 hipError_t launch_adjoint_coeffs(hipStream_t s, int r, int k, const double* U, int ldu, const double* theta,
                                  const double* Z1, int ldz1, const double* Z2, int ldz2, double tau, double* Cmat,
                                  int ldc, double* scratch, double* scal, int slot) {
-  constexpr int kMaxLds = 160 * 1024 - 256;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_adjoint_coeffs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxLds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const size_t lds = (size_t)(4 * r * std::max(k, 1) + r) * sizeof(double);
-  if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_adjoint_coeffs, dim3(1), dim3(256), lds, s, r, k, U, ldu, theta, Z1, ldz1, Z2, ldz2, tau, Cmat,
-                     ldc, scratch, scal, slot);
+  if (r <= 0 || k <= 0 || k > r) return hipErrorInvalidValue;
+  const int64_t rk = (int64_t)r * k, rr = (int64_t)r * r;
+  AdjWork w;
+  w.M1 = scratch;
+  w.T2 = w.M1 + rk;
+  w.M2 = w.T2 + rk;
+  w.Ec = w.M2 + rk;
+  w.Bt = w.Ec + rk;
+  w.S = w.Bt + rk;
+  hipLaunchKernelGGL(k_adj_m1t2, dim3(grid1(2 * rk)), dim3(256), 0, s, r, k, U, ldu, Z1, ldz1, Z2, ldz2, w);
+  hipLaunchKernelGGL(k_adj_m2, dim3(grid1(rk)), dim3(256), 0, s, r, k, U, ldu, w);
+  hipLaunchKernelGGL(k_adj_trace, dim3(1), dim3(256), 0, s, k, w, scal, slot);
+  hipLaunchKernelGGL(k_adj_coeffs, dim3(grid1(rk)), dim3(256), 0, s, r, k, U, ldu, theta, tau, w, Cmat, ldc);
+  hipLaunchKernelGGL(k_adj_uec, dim3(grid1(rk + rr)), dim3(256), 0, s, r, k, U, ldu, w, Cmat, ldc);
+  hipLaunchKernelGGL(k_adj_sut, dim3(grid1(rr)), dim3(256), 0, s, r, k, U, ldu, w, Cmat, ldc);
   return hipGetLastError();
 }
+
+size_t adjoint_coeffs_scratch(int r, int k) { return (size_t)5 * r * k + (size_t)r * r; }
 
 hipError_t launch_lambda_dot(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* L,
                              int ldl, const double* R, int ldr, int w, double* out) {

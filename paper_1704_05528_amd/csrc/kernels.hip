@@ -1158,11 +1158,12 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
                                                       int k, T delta, double* __restrict__ partial) {
   using V = typename Vec16<T>::type;  // 16-byte vector of T
   constexpr int E = Vec16<T>::n;
-  __shared__ __align__(16) T vs[4][kEigMax];
+  extern __shared__ __align__(16) unsigned char sdd_lds[];
   __shared__ double lds[4];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int c = blockIdx.x * 4 + wid;
   const int kv = (k + E - 1) / E;  // 16-byte vectors per factor row (ld is a multiple of E)
+  T* vsw = reinterpret_cast<T*>(sdd_lds) + (size_t)wid * kv * E;  // this wave's row of Vt
   double s_res = 0.0, s_y = 0.0, s_abs = 0.0;
   int p0 = 0, p1 = 0;
   if (c < nchunks) {
@@ -1171,10 +1172,10 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
     const int j = ccol[c];
     // Vt[j, :k] and zeros up to the vector boundary (the factor buffers are zero-initialised, so
     // the padded products are exact zeros)
-    for (int l = lane; l < kv * E; l += kWave) vs[wid][l] = (l < k) ? Vt[(int64_t)j * ld + l] : (T)0;
+    for (int l = lane; l < kv * E; l += kWave) vsw[l] = (l < k) ? Vt[(int64_t)j * ld + l] : (T)0;
   }
   __syncthreads();
-  const V* vv = reinterpret_cast<const V*>(vs[wid]);
+  const V* vv = reinterpret_cast<const V*>(vsw);
   auto update = [&](int p, T x) {
     const T res = a[p] - x;
     const T yn = fma(delta, res, y[p]);
@@ -1577,7 +1578,19 @@ hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart
                                int ld, int k, double delta, double* partial, int* nblocks) {
   const int nb = std::max(1, (nchunks + 3) / 4);
   *nblocks = nb;
-  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), 0, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut,
+  constexpr int E = (int)(16 / sizeof(T));
+  const size_t lds = (size_t)4 * ((std::max(k, 1) + E - 1) / E) * E * sizeof(T);
+  if (lds > 64 * 1024) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_sddmm_update<T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), lds, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut,
                      Vt, ld, k, (T)delta, partial);
   return hipGetLastError();
 }

@@ -36,7 +36,7 @@ constexpr int kDirect = 32;           // basis widths up to this are diagonalise
 
 // scalar slots of the device readback buffer
 enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_SWEEPS = 6, S_NORMY = 7, S_A = 8, S_B = 9, S_TBAR = 10,
-       S_DOT = 11, S_RES2 = 12, S_YN2 = 13, S_ABS = 14, S_MAE = 15 };
+       S_DOT = 11, S_RES2 = 12, S_YN2 = 13, S_ABS = 14, S_MAE = 15, S_JOFF = 16 /* and 17 */ };
 
 #define HIPCHK(expr)                                                     \
   do {                                                                   \
@@ -166,6 +166,48 @@ svt_status to_host(Handle* h, T* dst, const T* src, size_t count) {
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   if (h->pending.size() >= kMaxPending) resolve_pending(h);
+  return SVT_OK;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Full eigen-decomposition of a symmetric matrix by the many-workgroup Jacobi of eigfull.hip.
+// ----------------------------------------------------------------------------------------------
+struct JacobiWork {
+  double *A = nullptr, *V = nullptr, *pin = nullptr, *tol = nullptr, *part = nullptr;
+  int32_t *perm = nullptr, *flag = nullptr;
+  int ld = 0;             // row stride of A and V (at least n + 1)
+  int64_t pin_half = 0;   // doubles of one round's rotation inputs
+};
+constexpr int kJgMaxSweeps = 60;
+
+// Eigenpairs of the symmetric n x n matrix held in w.A (overwritten; n + 1 rows and columns of
+// storage): eigenvalues descending in eval (device), eigenvector c as row c of Et and column c of EU
+// (either may be NULL).  A sweep runs only while the largest upper off-diagonal entry exceeds the
+// rotation threshold, so no sweep is spent confirming convergence.  *inexact is set when the sweep
+// cap is reached.
+svt_status jacobi_full(Handle* h, const JacobiWork& w, int n, double* eval, double* Et, int ldet, double* EU, int ldeu,
+                       int* sweeps, bool* inexact) {
+  hipStream_t s = h->stream;
+  if (n > kJgMaxOrder) return fail(h, SVT_E_LIMIT, "basis wider than the full eigen-solver's largest order");
+  HIPCHK(launch_jg_start(s, w.A, w.ld, n, w.V, w.ld, true, w.pin, w.tol));
+  const int nn = n + (n & 1);
+  int64_t g = 0;
+  int sw = 0;
+  *inexact = true;
+  for (;; ++sw) {
+    HIPCHK(launch_jg_offmax(s, w.A, w.ld, nn, w.tol, w.part, h->scal + S_JOFF));
+    CHK(readback(h, S_JOFF + 2));
+    if (!(h->hscal[S_JOFF] > h->hscal[S_JOFF + 1])) {
+      *inexact = false;
+      break;
+    }
+    if (sw == kJgMaxSweeps) break;
+    for (int rd = 0; rd < nn - 1; ++rd, ++g)
+      HIPCHK(launch_jg_round(s, w.A, w.ld, w.V, w.ld, nn, rd, w.pin + (g & 1) * w.pin_half,
+                             w.pin + ((g + 1) & 1) * w.pin_half, w.tol, w.flag));
+  }
+  *sweeps = sw;
+  HIPCHK(launch_jg_finish(s, w.A, w.ld, w.V, w.ld, n, w.perm, eval, Et, ldet, EU, ldeu));
   return SVT_OK;
 }
 
@@ -377,7 +419,7 @@ struct Engine {
   // y_next = y + delta P_Lambda(A - Ut Vt^T), with the residual sums in partial
   svt_status run_sddmm(int* nbl) {
     HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
-                                  kEigMax, h->k, h->p.delta, h->partial, nbl));
+                                  h->ldf, h->k, h->p.delta, h->partial, nbl));
     return SVT_OK;
   }
   double work_bytes(int ph) const {
@@ -508,6 +550,74 @@ struct Engine {
   }
 
   // ----------------------------------------------------------------------------------------
+  // Workspace of the full eigen-decomposition: r_cap x r_cap matrices, allocated on first use.
+  // ----------------------------------------------------------------------------------------
+  svt_status ensure_full_work() {
+    if (h->JA) return SVT_OK;
+    const size_t rc = (size_t)h->r_cap;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) {
+      if (e == hipSuccess) e = x;
+    };
+    for (double** p : {&h->JA, &h->JV, &h->FM, &h->FEt, &h->FEU}) A(dalloc(p, rc * rc));
+    A(dalloc(&h->Fval, rc));
+    A(dalloc(&h->Jpin, 2 * 3 * (rc / 2 + 1)));
+    A(dalloc(&h->Jtol, 1));
+    A(dalloc(&h->Jpart, 256));
+    A(dalloc(&h->Jperm, rc));
+    A(dalloc(&h->Jflag, 1));
+    if (e != hipSuccess)
+      return fail(h, e == hipErrorOutOfMemory ? SVT_E_OOM : SVT_E_HIP,
+                  std::string("full eigen-solver workspace: ") + hipGetErrorString(e));
+    return SVT_OK;
+  }
+  JacobiWork full_work() const {
+    JacobiWork w;
+    w.A = h->JA;
+    w.V = h->JV;
+    w.pin = h->Jpin;
+    w.tol = h->Jtol;
+    w.part = h->Jpart;
+    w.perm = h->Jperm;
+    w.flag = h->Jflag;
+    w.ld = h->r_cap;
+    w.pin_half = 3 * (h->r_cap / 2 + 1);
+    return w;
+  }
+
+  // Every eigenpair of G (r x r): Jacobi on U^T G U, with U the previous full solve's eigenvectors
+  // extended by the identity on the basis columns appended since (U = I on a cold start).  Leaves the
+  // eigenvalues (descending) in Fval and the eigenvectors of G as rows of FEt and columns of FEU.
+  svt_status full_eig(int r, svt_step_stats* st) {
+    CHK(ensure_full_work());
+    hipStream_t s = h->stream;
+    const int ld = h->r_cap;
+    const int r0 = (h->fe_rows > 0 && h->fe_rows <= r) ? h->fe_rows : 0;
+    if (r0 > 0) {
+      HIPCHK(launch_extend_identity(s, h->FEt, ld, r0, r));
+      HIPCHK(launch_extend_identity(s, h->FEU, ld, r0, r));
+      HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->FEt, ld, h->G, h->r_cap, h->FM, ld));
+      HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->FM, ld, h->FEU, ld, h->JA, ld));
+    } else {
+      HIPCHK((launch_copy_cols<double, double>(s, r, h->G, h->r_cap, h->JA, ld, r)));
+    }
+    int sweeps = 0;
+    bool inexact = false;
+    CHK(jacobi_full(h, full_work(), r, h->Fval, r0 > 0 ? h->FM : h->FEt, ld, r0 > 0 ? nullptr : h->FEU, ld, &sweeps,
+                    &inexact));
+    if (r0 > 0) {
+      // eigenvectors of G: (rotations of the warm basis, sorted) times the warm basis
+      HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->FM, ld, h->FEt, ld, h->JA, ld));
+      std::swap(h->JA, h->FEt);
+      HIPCHK(launch_transpose(s, h->FEt, ld, r, r, h->FEU, ld));
+    }
+    h->fe_rows = r;
+    st->eig_iters = sweeps;
+    if (inexact) st->flags |= SVT_F_EIG_INEXACT;
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
   // svd(B) through eig(W^T W): eigenpairs with sigma > tau, factor matrices Ut = Q C, Vt = W D.
   // ----------------------------------------------------------------------------------------
   svt_status projected_svd(svt_step_stats* st) {
@@ -518,10 +628,13 @@ struct Engine {
       PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
       CHK(run_gram());
     }
-    std::vector<double> theta(2 * kEigMax), res(kEigMax);
-    const double* S = nullptr;
+    std::vector<double> theta(std::max(2 * kEigMax, r)), res(kEigMax);
+    const double* S = nullptr;       // eigenvectors of G as columns (descending)
+    int lds_ = kEigMax;              // their row stride
+    const double* dtheta = h->Eval;  // the eigenvalues on the device
     int k = 0;
     st->eig_iters = 0;
+    bool go_full = r > kDirect && h->full_mode;
     if (r <= kDirect) {
       {
         PhaseTimer tm(h, SVT_PH_EIG);
@@ -535,7 +648,7 @@ struct Engine {
       h->ev_valid = r;
       h->ev_rows = r;
       st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
-    } else {
+    } else if (!go_full) {
       // Warm-started subspace iteration on G.  Start block: the previous iteration's Ritz vectors
       // (rows of basis columns appended since then set to zero) and Gaussian columns.  Products
       // with G come in pairs, each pair followed by one CholeskyQR pass (the last pass before a
@@ -635,8 +748,9 @@ struct Engine {
         const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
         if (nconv + 4 > b && b < r) {
           if (b >= h->b_cap) {
-            if (k >= b) return fail(h, SVT_E_LIMIT, "more singular values above tau than the eigensolver tracks");
-            if (nconv > b) return fail(h, SVT_E_LIMIT, "truncated recycling keeps more vectors than the eigensolver tracks");
+            // the count (with its four guard pairs) outgrows the widest block: diagonalise all of G
+            go_full = true;
+            break;
           } else {
             // widen the block with Gaussian columns and continue from the enlarged block: to the
             // width the current count asks for (2 nconv + 8) at once, at least 16 more columns
@@ -672,6 +786,7 @@ struct Engine {
         prev_k = k;
         if (!done) target = powers + 2;
       }
+      if (!go_full) {
       // a failed first test costs a Rayleigh-Ritz step and a readback, far more than one product:
       // keep the count after a first-test pass, and probe one lower only after four in a row
       if (tests == 1) {
@@ -691,13 +806,42 @@ struct Engine {
       h->ev_valid = b;
       h->ev_rows = r;
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
+      }
+    }
+    if (go_full) {
+      // every eigenpair of G (Jacobi over many workgroups), warm-started from the previous full solve
+      {
+        PhaseTimer tm(h, SVT_PH_EIG);
+        CHK(full_eig(r, st));
+      }
+      CHK(to_host<double>(h, theta.data(), h->Fval, r));
+      k = 0;
+      while (k < r && theta[k] > tau2) ++k;
+      S = h->FEU;
+      lds_ = h->r_cap;
+      dtheta = h->Fval;
+      h->full_mode = true;
+      st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
+      const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
+      const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
+      if (2 * std::max(nconv, 4) + 8 <= 64) {
+        // the count is small again: the block solver takes over from the leading eigenvectors
+        const int b = std::min(kEigMax, r);
+        HIPCHK((launch_copy_cols<double, double>(h->stream, r, h->FEU, h->r_cap, h->EV, kEigMax, b)));
+        h->ev_valid = b;
+        h->ev_rows = r;
+        h->full_mode = false;
+        h->fe_rows = 0;
+      } else {
+        h->ev_valid = 0;
+      }
     }
     // an iterate that has left the storage type's range (a diverging step size) makes the
     // projected Gram, and with it every eigenvalue, non-finite: stop instead of thresholding nothing
     if (r > 0 && !std::isfinite(theta[0]))
       return fail(h, SVT_E_NUMERIC, "non-finite eigenvalues of the projected Gram (the iterate has overflowed)");
     if (h->p.mode == SVT_MODE_RSVD) k = std::min(k, h->p.rank);  // Alg. 1 keeps `rank` leading triplets
-    if (k > h->p.kmax) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
+    if (k > h->p.kmax || k > h->ldf) return fail(h, SVT_E_LIMIT, "more singular values above tau than kmax");
     h->k = k;
     h->sigma_k.assign(theta.begin(), theta.begin() + k);
     for (auto& v : h->sigma_k) v = std::sqrt(v);
@@ -706,12 +850,12 @@ struct Engine {
     if (k > 0) {
       PhaseTimer tm(h, SVT_PH_FACTORS, es * (double)(h->m + h->n) * (r + k) + 16.0 * r * k,
                     2.0 * (double)(h->m + h->n) * r * k);
-      HIPCHK(launch_factor_coeffs(s, r, k, S, kEigMax, h->Eval, h->p.tau, h->C, h->D, kEigMax));
-      HIPCHK((launch_copy_cols<double, double>(s, r, S, kEigMax, h->Sk, kEigMax, k)));
+      HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf));
+      HIPCHK((launch_copy_cols<double, double>(s, r, S, lds_, h->Sk, h->ldf, k)));
       // Ut = Q C and Vt = W D side by side in one launch
-      const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, kEigMax, Ut(), kEigMax, k, 1.0, 0.0,
+      const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0,
                                            nullptr};
-      const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, kEigMax, Vt(), kEigMax, k, 1.0, 0.0,
+      const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0, 0.0,
                                            nullptr};
       HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
     }
@@ -728,19 +872,28 @@ struct Engine {
     if (h->p.mode != SVT_MODE_R4SVD || h->p.recycle_extra < 0) return SVT_OK;
     const int r = h->r, keep = std::min(r, h->k + h->p.recycle_extra);
     if (keep >= r) return SVT_OK;
+    if (keep > h->ldf) return fail(h, SVT_E_LIMIT, "truncated recycling keeps more vectors than kmax");
     hipStream_t s = h->stream;
     h->hist_ok = false;
+    // the Ritz vectors of this iteration: the block solver's, or every eigenvector of G in full mode
+    const double* S = h->full_mode ? h->FEU : h->EV;
+    const int lds_ = h->full_mode ? h->r_cap : kEigMax;
     if (keep > 0) {
-      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->EV, kEigMax, Utmp(), kEigMax, keep, 1.0,
-                                          0.0)));
-      HIPCHK((launch_copy_cols<T, T>(s, (int)h->m, Utmp(), kEigMax, Q(), h->r_cap, keep)));
+      HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, S, lds_, Utmp(), h->ldf, keep, 1.0, 0.0)));
+      HIPCHK((launch_copy_cols<T, T>(s, (int)h->m, Utmp(), h->ldf, Q(), h->r_cap, keep)));
       // in the new basis the Ritz vectors are unit vectors
-      HIPCHK(launch_set_unit(s, h->EV, keep, kEigMax, 0, keep, 0));
-      if (h->k > 0) HIPCHK(launch_set_unit(s, h->Sk, keep, kEigMax, 0, h->k, 0));
+      if (h->full_mode) {
+        HIPCHK(launch_set_unit(s, h->FEt, keep, h->r_cap, 0, keep, 0));
+        HIPCHK(launch_set_unit(s, h->FEU, keep, h->r_cap, 0, keep, 0));
+      } else {
+        HIPCHK(launch_set_unit(s, h->EV, keep, kEigMax, 0, keep, 0));
+      }
+      if (h->k > 0) HIPCHK(launch_set_unit(s, h->Sk, keep, h->ldf, 0, h->k, 0));
     }
     h->r = keep;
-    h->ev_valid = keep;
+    h->ev_valid = h->full_mode ? 0 : keep;
     h->ev_rows = keep;
+    h->fe_rows = h->full_mode ? keep : 0;
     return SVT_OK;
   }
 
@@ -783,6 +936,7 @@ struct Engine {
       h->r = 0;
       h->ev_valid = 0;
       h->ev_rows = 0;
+      h->fe_rows = 0;
       h->hist_ok = false;
     }
     CHK(r4svd_core(it, rb, st));
@@ -851,6 +1005,7 @@ struct Engine {
     if (h->p.mode != SVT_MODE_R4SVD) {
       h->r = 0;  // R3SVD / RSVD start from a fresh sample (the basis buffer is scratch in these modes)
       h->ev_valid = 0;
+      h->fe_rows = 0;
     }
     svt_status s1 = r4svd_core(h->iter + 1, -1, st);
     if (s1 == SVT_OK) s1 = projected_svd(st);
@@ -858,6 +1013,7 @@ struct Engine {
     h->eps_thr_set = thr_set;
     h->eps_thr = thr;
     if (h->ev_rows > h->r) h->ev_valid = 0;
+    if (h->fe_rows > h->r) h->fe_rows = 0;
     return s1;
   }
 
@@ -865,7 +1021,7 @@ struct Engine {
   svt_status spectral_norm(double* out) {
     hipStream_t s = h->stream;
     const int m = (int)h->m, n = (int)h->n;
-    T* v = Utmp();  // n-vector (Utmp holds max(m, n) * kEigMax values)
+    T* v = Utmp();  // n-vector (Utmp holds max(m, n) * ldf values)
     T* u = X2();    // m-vector (X2 holds m * w_cap values)
     HIPCHK(launch_fill_random(s, h->EV, n, 1, 0, 1, h->p.seed ^ 0x3C3C3C3Cull, 7));
     HIPCHK((launch_copy_cols<double, T>(s, n, h->EV, 1, v, 1, 1)));
@@ -931,24 +1087,24 @@ struct Engine {
   svt_status factors(int kk, int kcap, double* U, double* V) {
     std::vector<T> buf;
     if (U) {
-      HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, kEigMax, Utmp(), kEigMax,
+      HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
                                           kk, 1.0, 0.0)));
-      buf.resize((size_t)h->m * kEigMax);
+      buf.resize((size_t)h->m * h->ldf);
       CHK(to_host<T>(h, buf.data(), Utmp(), buf.size()));
       for (int64_t i = 0; i < h->m; ++i)
-        for (int c = 0; c < kk; ++c) U[i * kcap + c] = (double)buf[i * kEigMax + c];
+        for (int c = 0; c < kk; ++c) U[i * kcap + c] = (double)buf[i * h->ldf + c];
     }
     if (V) {
-      buf.resize((size_t)h->n * kEigMax);
+      buf.resize((size_t)h->n * h->ldf);
       CHK(to_host<T>(h, buf.data(), Vt(), buf.size()));
       for (int64_t j = 0; j < h->n; ++j)
-        for (int c = 0; c < kk; ++c) V[j * kcap + c] = (double)buf[j * kEigMax + c];
+        for (int c = 0; c < kk; ++c) V[j * kcap + c] = (double)buf[j * h->ldf + c];
     }
     return SVT_OK;
   }
 
   svt_status sample(int64_t nq, const int32_t* di, const int32_t* dj, double* dx) {
-    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), kEigMax, h->k, dx));
+    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), h->ldf, h->k, dx));
     return SVT_OK;
   }
 
@@ -1014,7 +1170,13 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   const int m = (int)h->m, n = (int)h->n;
   const int64_t nnz = h->nnz;
   const double tau = h->p.tau, delta = h->p.delta, tau2 = tau * tau;
-  constexpr int kW = 3 * kEigMax;  // widest factor pair of the sampled adjoint: 2 k + r
+  // widest basis over the T iterations; every per-iteration block has ldw columns of storage (the
+  // Jacobi matrix of a full decomposition needs one more row and column for an odd order)
+  int rmax = 1;
+  for (int i = 0; i < T; ++i) rmax = std::max(rmax, h->hist_r[i]);
+  const int ldw = ((rmax + 2 + 7) / 8) * 8;
+  const int kW = 3 * ldw;  // widest factor pair of the sampled adjoint: 2 k + r
+  const bool wide = rmax > kEigMax;  // bases beyond the one-workgroup Jacobi use the many-workgroup one
   if (ckpt <= 0) ckpt = (int)std::ceil(std::sqrt((double)T));
   ckpt = std::min(ckpt, T);
   const int nseg = (T + ckpt - 1) / ckpt;
@@ -1039,6 +1201,7 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   double *xb = nullptr, *tmp = nullptr, *Wb = nullptr, *F = nullptr, *R = nullptr, *L = nullptr, *Cm = nullptr;
   double *Z1 = nullptr, *Z2 = nullptr, *scr = nullptr, *U = nullptr, *th = nullptr, *Cc = nullptr, *Dc = nullptr;
   double *Ut = nullptr, *Vt = nullptr;
+  JacobiWork jw;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
@@ -1049,15 +1212,27 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   A(ar.get(&ycp, (size_t)nseg * nnz));
   A(ar.get(&yseg, (size_t)ckpt * nnz));
   for (double** p : {&ybar, &abar, &res, &xb, &tmp}) A(ar.get(p, nnz));
-  A(ar.get(&Wb, (size_t)n * kEigMax));
-  A(ar.get(&F, (size_t)n * kEigMax));
-  A(ar.get(&Vt, (size_t)n * kEigMax));
-  A(ar.get(&Ut, (size_t)m * kEigMax));
+  A(ar.get(&Wb, (size_t)n * ldw));
+  A(ar.get(&F, (size_t)n * ldw));
+  A(ar.get(&Vt, (size_t)n * ldw));
+  A(ar.get(&Ut, (size_t)m * ldw));
   A(ar.get(&R, (size_t)n * kW));
   A(ar.get(&L, (size_t)m * kW));
-  A(ar.get(&Cm, (size_t)kEigMax * kW));
-  for (double** p : {&Z1, &Z2, &scr, &U, &Cc, &Dc}) A(ar.get(p, (size_t)kEigMax * kEigMax));
-  A(ar.get(&th, 2 * kEigMax));
+  A(ar.get(&Cm, (size_t)ldw * kW));
+  for (double** p : {&Z1, &Z2, &U, &Cc, &Dc}) A(ar.get(p, (size_t)ldw * ldw));
+  A(ar.get(&scr, adjoint_coeffs_scratch(ldw, ldw)));
+  A(ar.get(&th, 2 * (size_t)ldw));
+  if (wide) {
+    jw.ld = ldw;
+    jw.pin_half = 3 * (ldw / 2 + 1);
+    A(ar.get(&jw.A, (size_t)ldw * ldw));
+    A(ar.get(&jw.V, (size_t)ldw * ldw));
+    A(ar.get(&jw.pin, 2 * (size_t)jw.pin_half));
+    A(ar.get(&jw.tol, 1));
+    A(ar.get(&jw.part, 256));
+    A(ar.get(&jw.perm, ldw));
+    A(ar.get(&jw.flag, 1));
+  }
   if (e != hipSuccess)
     return fail(h, e == hipErrorOutOfMemory ? SVT_E_OOM : SVT_E_HIP,
                 std::string("svt_grad: device allocation failed: ") + hipGetErrorString(e));
@@ -1068,29 +1243,39 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   const double* Q = eng.Q();
   const double* a = eng.a();
   const int ldq = h->r_cap;
-  std::vector<double> theta(kEigMax);
+  std::vector<double> theta(ldw);
 
   // Frozen map of iteration i on yi: W_i, eigenpairs (U, th) of G = W_i^T W_i, k, and the
-  // factors Ut = Q_i U_K diag(s - tau), Vt = W_i U_K diag(1/s) = V_K.  Returns k.
+  // factors Ut = Q_i U_K diag(s - tau), Vt = W_i U_K diag(1/s) = V_K.  Returns k.  The
+  // eigen-decomposition is the one-workgroup Jacobi up to kEigMax columns, else the many-workgroup
+  // one (always from the identity, so a recomputation repeats the same launches and values).
   auto frozen_map = [&](const double* yi, int ri, int* kout) -> svt_status {
-    HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, yi, Q, ldq, Wb, kEigMax, ri, h->nnz,
+    HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, yi, Q, ldq, Wb, ldw, ri, h->nnz,
                                    h->max_col_nnz));
-    HIPCHK(launch_gram<double>(s, n, Wb, kEigMax, ri, h->G, h->r_cap, h->partial, h->partial_cap));
-    HIPCHK(launch_jacobi(s, h->G, h->r_cap, ri, th, U, kEigMax, h->scal, S_SWEEPS));
+    HIPCHK(launch_gram<double>(s, n, Wb, ldw, ri, h->G, h->r_cap, h->partial, h->partial_cap));
+    if (ri <= kEigMax) {
+      HIPCHK(launch_jacobi(s, h->G, h->r_cap, ri, th, U, ldw, h->scal, S_SWEEPS));
+    } else {
+      HIPCHK((launch_copy_cols<double, double>(s, ri, h->G, h->r_cap, jw.A, jw.ld, ri)));
+      int sweeps = 0;
+      bool inexact = false;
+      CHK(jacobi_full(h, jw, ri, th, nullptr, 0, U, ldw, &sweeps, &inexact));
+      if (inexact) return fail(h, SVT_E_NUMERIC, "svt_grad: the eigen-decomposition of a projected Gram did not converge");
+    }
     CHK(to_host<double>(h, theta.data(), th, ri));
     int k = 0;
     while (k < ri && theta[k] > tau2) ++k;
     if (k > 0) {
-      HIPCHK(launch_factor_coeffs(s, ri, k, U, kEigMax, th, tau, Cc, Dc, kEigMax));
-      HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cc, kEigMax, Ut, kEigMax, k, 1.0, 0.0)));
-      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, Wb, kEigMax, Dc, kEigMax, Vt, kEigMax, k, 1.0, 0.0)));
+      HIPCHK(launch_factor_coeffs(s, ri, k, U, ldw, th, tau, Cc, Dc, ldw));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cc, ldw, Ut, ldw, k, 1.0, 0.0)));
+      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, Wb, ldw, Dc, ldw, Vt, ldw, k, 1.0, 0.0)));
     }
     *kout = k;
     return SVT_OK;
   };
   // X_i on Lambda, the residual P(A - X_i) and Y_{i+1} (ynext may alias tmp when unused)
   auto dual_step = [&](const double* yi, int k, double* rs, double* ynext) -> svt_status {
-    HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, Ut, kEigMax, Vt, kEigMax, k, xb));
+    HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, Ut, ldw, Vt, ldw, k, xb));
     HIPCHK(launch_dual_update(s, nnz, a, xb, yi, delta, rs, ynext));
     return SVT_OK;
   };
@@ -1134,26 +1319,22 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
         d_bar += h->hscal[S_DOT];
         if (k == 0) continue;
         HIPCHK((launch_scale_copy<double, double>(s, nnz, ybar, -delta, tmp)));
-        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, kEigMax, ri, h->nnz,
+        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, ldw, ri, h->nnz,
                                          h->max_col_nnz));
       } else {
         if (k == 0 || nh == 0) continue;
-        HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, kEigMax, ri, nh, 0));
+        HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, ldw, ri, nh, 0));
       }
       // F = Xbar^T Q_i = Bbar^T; Z1 = Bbar V_K, Z2 = Bbar W_i, R = [F U_K | V_K | W_i]
       const int wl = 2 * k + ri;
-      HIPCHK((launch_tn_narrow<double, double>(s, n, F, kEigMax, ri, Vt, kEigMax, k, Z1, kEigMax, h->partial,
+      HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Vt, ldw, k, Z1, ldw, h->partial,
                                                h->partial_cap)));
-      HIPCHK((launch_tn_narrow<double, double>(s, n, F, kEigMax, ri, Wb, kEigMax, ri, Z2, kEigMax, h->partial,
+      HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Wb, ldw, ri, Z2, ldw, h->partial,
                                                h->partial_cap)));
-      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, F, kEigMax, U, kEigMax, R, kW, k, 1.0, 0.0)));
-      HIPCHK((launch_copy_cols<double, double>(s, n, Vt, kEigMax, R + k, kW, k)));
-      HIPCHK((launch_copy_cols<double, double>(s, n, Wb, kEigMax, R + 2 * k, kW, ri)));
-      hipError_t ec = launch_adjoint_coeffs(s, ri, k, U, kEigMax, th, Z1, kEigMax, Z2, kEigMax, tau, Cm, kW, scr,
-                                            h->scal, S_TBAR);
-      if (ec == hipErrorInvalidValue)
-        return fail(h, SVT_E_LIMIT, "svt_grad: r * k too large for the one-workgroup adjoint coefficients");
-      HIPCHK(ec);
+      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, F, ldw, U, ldw, R, kW, k, 1.0, 0.0)));
+      HIPCHK((launch_copy_cols<double, double>(s, n, Vt, ldw, R + k, kW, k)));
+      HIPCHK((launch_copy_cols<double, double>(s, n, Wb, ldw, R + 2 * k, kW, ri)));
+      HIPCHK(launch_adjoint_coeffs(s, ri, k, U, ldw, th, Z1, ldw, Z2, ldw, tau, Cm, kW, scr, h->scal, S_TBAR));
       HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cm, kW, L, kW, wl, 1.0, 0.0)));
       HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, L, kW, R, kW, wl, tmp));
       HIPCHK(launch_axpby(s, nnz, 1.0, tmp, 1.0, ybar));
@@ -1182,6 +1363,7 @@ void release(Handle* h) {
                   h->Q, h->W, h->X, h->X2, h->Om, h->T, h->G, h->G2, h->small, h->Minv, h->prenorm, h->EV, h->EZ,
                   h->EZ2,
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal,
+                  h->JA, h->JV, h->FM, h->FEt, h->FEU, h->Fval, h->Jpin, h->Jtol, h->Jpart, h->Jperm, h->Jflag,
                   h->csc_long.lo, h->csc_long.hi, h->csc_long.lcol, h->csc_long.lfirst, h->csc_long.skip,
                   h->csc_long.P};
   for (void* b : bufs)
@@ -1259,8 +1441,6 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.dt <= 0) p.dt = 10;
   if (p.maxit <= 0) p.maxit = 500;
   if (p.npow < 0) return bad("npow must be non-negative");
-  if (p.kmax <= 0) p.kmax = 64;
-  if (p.kmax > kEigMax) return bad("kmax must not exceed 96");
   if (p.precision != SVT_FP64 && p.precision != SVT_MIXED) return bad("unknown precision form");
   if (p.mode != SVT_MODE_R4SVD && p.mode != SVT_MODE_R3SVD && p.mode != SVT_MODE_RSVD) return bad("unknown mode");
   if (p.mode == SVT_MODE_RSVD && p.rank <= 0) return bad("the RSVD mode needs rank > 0");
@@ -1271,6 +1451,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.mode == SVT_MODE_RSVD) p.t0 = (int32_t)std::min<int64_t>((int64_t)p.rank + p.oversample, 1 << 30);
   p.r_max = (p.r_max <= 0) ? (int32_t)m : (int32_t)std::min<int64_t>(p.r_max, m);
   p.t0 = std::min(p.t0, p.r_max);
+  // kmax <= 0: every singular value above tau the basis can hold
+  p.kmax = (p.kmax <= 0) ? p.r_max : std::min(p.kmax, p.r_max);
 
   // host-side validation and orders
   std::vector<int64_t> key(nnz), order(nnz);
@@ -1361,7 +1543,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
 
   h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
   h->w_cap = 64;
-  h->b_cap = std::min(kEigMax, std::max(32, ((p.kmax + 16 + 15) / 16) * 16));
+  h->b_cap = kEigMax;
+  h->ldf = std::max(kEigMax, ((p.kmax + 7) / 8) * 8);
   h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
   h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
   h->partial_cap = std::max<int64_t>(h->partial_cap, 3 * ((int64_t)ccol.size() / 4 + 2));  // fused-update sums
@@ -1385,9 +1568,9 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc_bytes(&h->X, (size_t)m * h->w_cap * es));
   A(dalloc_bytes(&h->X2, (size_t)m * h->w_cap * es));
   A(dalloc_bytes(&h->Om, mx * h->w_cap * es));
-  A(dalloc_bytes(&h->Ut, (size_t)m * kEigMax * es));
-  A(dalloc_bytes(&h->Vt, (size_t)n * kEigMax * es));
-  A(dalloc_bytes(&h->Utmp, mx * kEigMax * es));
+  A(dalloc_bytes(&h->Ut, (size_t)m * h->ldf * es));
+  A(dalloc_bytes(&h->Vt, (size_t)n * h->ldf * es));
+  A(dalloc_bytes(&h->Utmp, mx * h->ldf * es));
   A(dalloc(&h->T, (size_t)h->r_cap * h->w_cap));
   A(dalloc(&h->G, (size_t)h->r_cap * h->r_cap));
   A(dalloc(&h->G2, (size_t)h->r_cap * h->r_cap));
@@ -1401,9 +1584,9 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->EH, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->ES, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->Eval, 2 * kEigMax));
-  A(dalloc(&h->C, (size_t)h->r_cap * kEigMax));
-  A(dalloc(&h->D, (size_t)h->r_cap * kEigMax));
-  A(dalloc(&h->Sk, (size_t)h->r_cap * kEigMax));
+  A(dalloc(&h->C, (size_t)h->r_cap * h->ldf));
+  A(dalloc(&h->D, (size_t)h->r_cap * h->ldf));
+  A(dalloc(&h->Sk, (size_t)h->r_cap * h->ldf));
   A(dalloc(&h->partial, (size_t)h->partial_cap));
   A(dalloc(&h->scal, kScalars));
   if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
@@ -1454,8 +1637,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (e == hipSuccess && h->yT) e = hipMemsetAsync(h->yT, 0, (size_t)m * n * es, h->stream);
   // factor buffers start at zero: the fused update reads whole 16-byte vectors of a factor row and
   // multiplies the columns beyond k by zeros, which then must be finite
-  if (e == hipSuccess) e = hipMemsetAsync(h->Ut, 0, (size_t)m * kEigMax * es, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->Vt, 0, (size_t)n * kEigMax * es, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->Ut, 0, (size_t)m * h->ldf * es, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->Vt, 0, (size_t)n * h->ldf * es, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     g_init_err = std::string("upload failed: ") + hipGetErrorString(e);
@@ -1637,6 +1820,8 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   h->have_factors = false;
   h->ev_valid = 0;
   h->ev_rows = 0;
+  h->full_mode = false;
+  h->fe_rows = 0;
   h->k = 0;
   h->hist_ok = false;
   h->hist_r.clear();
@@ -1721,7 +1906,7 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
   if (!h->hist_ok || (int64_t)h->hist_r.size() < T)
     return fail(h, SVT_E_STATE, "svt_grad needs T iterations run by svt_iterate since svt_init");
   for (int i = 0; i < T; ++i)
-    if (h->hist_r[i] > kEigMax) return fail(h, SVT_E_LIMIT, "svt_grad supports bases of at most 96 columns");
+    if (h->hist_r[i] > kJgMaxOrder) return fail(h, SVT_E_LIMIT, "svt_grad: basis wider than the eigen-solver's order");
   h->spec_ready = false;  // the adjoint reuses the buffers the enqueued leading work wrote
   const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, dtau, ddelta, da);
   h->spec_ready = false;

@@ -120,13 +120,23 @@ struct Handle {
   int32_t eig_pred = 6;    // products with G before the first Rayleigh-Ritz test (adapted each iteration)
   int32_t eig_pass_streak = 0;  // consecutive iterations whose first test passed
 
-  // factors of X = Ut Vt^T
-  void* Ut = nullptr;      // (T) m x kEigMax, Q S_K diag(sigma - tau)
-  void* Vt = nullptr;      // (T) n x kEigMax, W S_K diag(1 / sigma)
-  void* Utmp = nullptr;    // (T) max(m, n) x kEigMax scratch
-  double* C = nullptr;     // r_cap x kEigMax
-  double* D = nullptr;     // r_cap x kEigMax
-  double* Sk = nullptr;    // r_cap x kEigMax, eigenvectors of the Gram for sigma > tau
+  // full eigen-decomposition of G (Jacobi over many workgroups, eigfull.hip), used once the count
+  // above tau outgrows the block solver; r_cap x r_cap matrices allocated on first use
+  bool full_mode = false;   // the projected SVD diagonalises all of G (sticky while k stays large)
+  int32_t fe_rows = 0;      // leading rows / columns of FEt, FEU that hold the last full solve's vectors
+  double *JA = nullptr, *JV = nullptr, *FM = nullptr;  // Jacobi matrix, its rotations (rows), product scratch
+  double *FEt = nullptr, *FEU = nullptr;              // eigenvectors of G as rows / as columns, descending
+  double *Fval = nullptr, *Jpin = nullptr, *Jtol = nullptr, *Jpart = nullptr;
+  int32_t *Jperm = nullptr, *Jflag = nullptr;
+
+  // factors of X = Ut Vt^T; ldf columns each (the most singular values above tau tracked)
+  int32_t ldf = 0;
+  void* Ut = nullptr;      // (T) m x ldf, Q S_K diag(sigma - tau)
+  void* Vt = nullptr;      // (T) n x ldf, W S_K diag(1 / sigma)
+  void* Utmp = nullptr;    // (T) max(m, n) x ldf scratch
+  double* C = nullptr;     // r_cap x ldf
+  double* D = nullptr;     // r_cap x ldf
+  double* Sk = nullptr;    // r_cap x ldf, eigenvectors of the Gram for sigma > tau
   int32_t k = 0;
   std::vector<double> sigma_k;  // host copy of the k singular values above tau
 
@@ -339,14 +349,42 @@ hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, in
                                 double tau, double* C, double* D, int ldc);
 
 // ---------------------------------------------------------------------------------------------
+// full eigen-decomposition (eigfull.hip), double: cyclic Jacobi over many workgroups, one launch
+// per round-robin round
+// ---------------------------------------------------------------------------------------------
+constexpr int kJgMaxOrder = 4096;  // largest matrix order (slots per workgroup stay <= 8)
+constexpr int kJgMaxWg = 256;      // workgroups per round before a workgroup takes several slots
+// Pads an odd n with a zero row and column (A, ld lda >= n + 1), sets Vt = I (nn x nn) when
+// vt_identity (otherwise only its padding), writes the rotation inputs of round 0 into pin (3 nn / 2
+// doubles) and the rotation threshold (1e-15 of the largest diagonal entry) into *tolp.
+hipError_t launch_jg_start(hipStream_t s, double* A, int lda, int n, double* Vt, int ldv, bool vt_identity,
+                           double* pin, double* tolp);
+// One round rd (0 <= rd < nn - 1, nn even) in place on A and the rows of Vt; pin_cur / pin_next:
+// this round's and the next round's rotation inputs; *flag = 1 when a pair rotates.
+hipError_t launch_jg_round(hipStream_t s, double* A, int lda, double* Vt, int ldv, int nn, int rd, const double* pin_cur,
+                           double* pin_next, const double* tolp, int32_t* flag);
+// out[0] = max_{i < j} |A_ij| (part: 256 doubles), out[1] = the threshold
+hipError_t launch_jg_offmax(hipStream_t s, const double* A, int lda, int nn, const double* tolp, double* part,
+                            double* out);
+// eigenvalues descending (ties by index) into eval, eigenvector c as row c of Et and column c of EU
+// (either may be NULL); perm: n ints
+hipError_t launch_jg_finish(hipStream_t s, const double* A, int lda, const double* Vt, int ldv, int n, int32_t* perm,
+                            double* eval, double* Et, int ldet, double* EU, int ldeu);
+// M[i][j] = delta_ij outside the leading r0 x r0 block of the r x r matrix M
+hipError_t launch_extend_identity(hipStream_t s, double* M, int ld, int r0, int r);
+// dst (cols x rows) = src^T (src rows x cols)
+hipError_t launch_transpose(hipStream_t s, const double* src, int lds_, int rows, int cols, double* dst, int ldd);
+
+// ---------------------------------------------------------------------------------------------
 // reverse sweep (adjoint.hip), double
 // ---------------------------------------------------------------------------------------------
 // Cmat = [U_K diag(f/s) | U_K Gamma + U_N Kappa | U_K Beta^T U^T] (r x (2k + r)) and scal[slot] =
-// tau_bar for one unrolled iteration; U, theta: full eigen-decomposition of G (r <= kEigMax),
-// Z1 = Bbar V_K (r x k), Z2 = Bbar B^T (r x r); scratch r x r
+// tau_bar for one unrolled iteration; U, theta: full eigen-decomposition of G, Z1 = Bbar V_K (r x k),
+// Z2 = Bbar B^T (r x r); scratch: adjoint_coeffs_scratch(r, k) doubles.  1 <= k <= r.
 hipError_t launch_adjoint_coeffs(hipStream_t s, int r, int k, const double* U, int ldu, const double* theta,
                                  const double* Z1, int ldz1, const double* Z2, int ldz2, double tau, double* Cmat,
                                  int ldc, double* scratch, double* scal, int slot);
+size_t adjoint_coeffs_scratch(int r, int k);
 // out[p] = <L[row(p), 0:w], R[col(p), 0:w]> on Lambda (CSC order)
 hipError_t launch_lambda_dot(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* L,
                              int ldl, const double* R, int ldr, int w, double* out);

@@ -72,7 +72,7 @@ GOOD = dict(tau=1.0, delta=1.0)
     ("tau", (3, 3, [0], [0], [1.0]), dict(tau=0.0, delta=1.0)),
     ("delta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=-2.0)),
     ("beta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, beta=1.0)),
-    ("kmax", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, kmax=97)),
+    ("eta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, eta=1.0)),
     ("npow", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, npow=-1)),
 ])
 def test_init_rejects_bad_arguments_on_host(case, args, kw):

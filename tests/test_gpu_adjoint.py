@@ -23,7 +23,10 @@ CASES = [
     (90, 70, 3, 0.4, 31, {}, 8),                   # a growth block and an annealing step at the end
     (80, 60, 6, 0.5, 73, {"t0": 40, "dt": 8}, 5),  # 40-column basis, k = 6
     (500, 400, 2, 0.04, 36, {"t0": 12}, 8),        # 4% observed, basis grows 12 -> 52
+    (120, 110, 5, 0.5, 74, {"t0": 90, "dt": 12, "eps_thr0": 1e-6}, 5),  # 120-column basis: many-workgroup Jacobi
 ]
+# bases wider than 96 columns with many singular values above tau: (m, n, rank, frac, seed, extra, T, tau/sqrt(mn))
+WIDE_K = [(140, 120, 40, 0.6, 75, {"t0": 100, "dt": 10}, 6, 1.2)]
 
 
 def rel_err(a, b):
@@ -31,8 +34,8 @@ def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def _setup(svt, m, n, rank, frac, seed, extra, T, nh=40):
-    w = W.tiny_dense(m, n, rank, frac, seed=seed)
+def _setup(svt, m, n, rank, frac, seed, extra, T, nh=40, tau=None):
+    w = W.tiny_dense(m, n, rank, frac, seed=seed, tau=tau)
     prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
     p = Params(tau=w.tau, delta=w.delta, seed=seed, **extra)
     rec = forward_record(prob, p, T)
@@ -53,6 +56,20 @@ def _setup(svt, m, n, rank, frac, seed, extra, T, nh=40):
 def test_grad_matches_oracle(gpu_lib, m, n, rank, frac, seed, extra, T):
     w, prob, p, rec, hr, hc, g, h = _setup(gpu_lib, m, n, rank, frac, seed, extra, T)
     print(f"case m={m} n={n} T={T} r={[q.shape[1] for q in rec['Qs']]}", flush=True)
+    tb, db, ab = grad(prob, p, rec, hr, hc, g)
+    gt, gd, ga = h.grad(T, 0, hr, hc, g)
+    assert abs(gt - tb) <= TOL * max(abs(tb), 1e-12), ("dtau", gt, tb)
+    assert abs(gd - db) <= TOL * max(abs(db), 1e-12), ("ddelta", gd, db)
+    assert rel_err(ga, ab) <= TOL, ("da", rel_err(ga, ab))
+
+
+@pytest.mark.parametrize("m,n,rank,frac,seed,extra,T,c", WIDE_K)
+def test_grad_wide_basis_many_values_above_tau(gpu_lib, m, n, rank, frac, seed, extra, T, c):
+    """A 100-column basis with 74 singular values above tau: every Gram is diagonalised by the
+    many-workgroup Jacobi, and the coefficient block spans 2 k + r = 248 columns."""
+    w, prob, p, rec, hr, hc, g, h = _setup(gpu_lib, m, n, rank, frac, seed, extra, T,
+                                           tau=c * np.sqrt(m * n))
+    print(f"case m={m} n={n} T={T} r={[q.shape[1] for q in rec['Qs']]} k={rec['final_info'].k}", flush=True)
     tb, db, ab = grad(prob, p, rec, hr, hc, g)
     gt, gd, ga = h.grad(T, 0, hr, hc, g)
     assert abs(gt - tb) <= TOL * max(abs(tb), 1e-12), ("dtau", gt, tb)

@@ -79,6 +79,30 @@ def test_free_run_with_replayed_decisions(gpu_lib, m, n, rank, frac, seed, extra
     assert s["iter"] == infos[-1].it
 
 
+@pytest.mark.parametrize("m,n,rank,frac,c,seed", [(400, 320, 200, 0.6, 0.6, 91), (300, 260, 200, 0.7, 0.4, 92)])
+def test_counts_beyond_the_block_solver(gpu_lib, m, n, rank, frac, c, seed):
+    """A rank-200 planted matrix with a low threshold: k passes the 92 pairs the subspace solver's
+    96-column block can hold within four iterations and climbs to 242-284 of a 253-336 column
+    basis.  The projected SVD then diagonalises all of G (Jacobi over many workgroups, warm-started
+    from the previous iteration's eigenvectors).  30 iterations with replayed decisions at 1e-10."""
+    w = W.tiny_dense(m, n, rank, frac, seed=seed, tau=c * math.sqrt(m * n))
+    prob = _problem(w)
+    extra = {"dt": 40}
+    p = Params(tau=w.tau, delta=w.delta, seed=seed, maxit=30, **extra)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    assert max(i.k for i in infos) > 200
+    h = _gpu(gpu_lib, w, k0, seed=seed, maxit=30, **extra)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        print(f"iteration {info.it} r={info.r} k={info.k}", flush=True)
+        st = h.iterate(1)
+        assert not (st.flags & SVT_F_EIG_INEXACT), info.it
+        _compare_step(st, info, h, w, ("wide k", info.it))
+        if info.k > 0:
+            kk, s, U, V = h.factors(info.k)
+            assert rel_err(s, info.sigma[:info.k] - w.tau) <= TOL
+
+
 @pytest.mark.parametrize("extra", [{"t0": 20}, {"t0": 6, "dt": 4}])
 def test_heavy_columns_chunked_gather(gpu_lib, extra):
     """1% observed with three columns of 9000, 5000 and 2600 rows: Y^T Q takes the gather path
