@@ -746,24 +746,25 @@ struct Engine {
         k = 0;
         while (k < b && theta[k] > tau2) ++k;
         const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
+        if (b < r && 2 * nconv + 8 > h->b_cap) {
+          // the count needs a block of 2 k + 8 columns for a fast convergence ratio, wider than the
+          // subspace solver holds (narrower blocks converge slowly once the count nears the block
+          // width): diagonalise all of G
+          go_full = true;
+          break;
+        }
         if (nconv + 4 > b && b < r) {
-          if (b >= h->b_cap) {
-            // the count (with its four guard pairs) outgrows the widest block: diagonalise all of G
-            go_full = true;
-            break;
-          } else {
-            // widen the block with Gaussian columns and continue from the enlarged block: to the
-            // width the current count asks for (2 nconv + 8) at once, at least 16 more columns
-            const int nb = std::min(std::min(h->b_cap, r), std::max(b + 16, 2 * nconv + 8));
-            PhaseTimer tm(h, SVT_PH_EIG);
-            HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
-            b = nb;
-            CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
-            have_gv = false;
-            prev_k = -1;
-            target = powers + 2;
-            continue;
-          }
+          // widen the block with Gaussian columns and continue from the enlarged block: to the
+          // width the current count asks for (2 nconv + 8) at once, at least 16 more columns
+          const int nb = std::min(std::min(h->b_cap, r), std::max(b + 16, 2 * nconv + 8));
+          PhaseTimer tm(h, SVT_PH_EIG);
+          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
+          b = nb;
+          CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
+          have_gv = false;
+          prev_k = -1;
+          target = powers + 2;
+          continue;
         }
         // Accept when the pairs above tau^2 have converged, four guard pairs below it have Ritz
         // intervals below tau^2, and the count k agrees with the previous test (Ritz values rise
