@@ -206,11 +206,29 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
  * growth blocks and annealed[l] (0/1).  len = 0 clears the replay. */
 svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* annealed, int32_t len);
 
+/* Flags of svt_grad. */
+enum {
+  SVT_GRAD_FROZEN_BASIS = 1 /* hold every basis Q_i of the forward run fixed (see svt_grad) */
+};
+
 /* Derivative of a held-out loss through the first T unrolled iterations of
- * Alg. 4 (Eq. 4 with the kicking start), in the frozen-basis convention: the
- * kicking count, every growth and annealing decision and every basis Q_i of
- * the forward run are held fixed, so iteration i is the map
- * Y_i -> X_i = Q_i D_tau(Q_i^T Y_i) (Eq. 5) followed by the dual update.
+ * Alg. 4 (Eq. 4 with the kicking start).  The kicking count and every growth
+ * and annealing decision of the forward run are held fixed (they are discrete).
+ *
+ * Default (flags = 0): the exact derivative of the iteration as R4SVD computes
+ * it.  Iteration i maps Y_i to X_i = Q_i D_tau(Q_i^T Y_i) (Eq. 5) with the
+ * basis Q_i itself a function of the iterates: the recycled basis of iteration
+ * i - 1 (Alg. 3) followed by the sampled blocks orthonormalised against it
+ * (Alg. 2-3), each a function of Y_i Omega.  The reverse sweep carries the
+ * cotangent of the recycled basis from iteration to iteration.  It needs the
+ * R4SVD mode with every column recycled (recycle_extra < 0), npow = 0 and no
+ * column dropped by the orthonormalisation since svt_init.
+ *
+ * SVT_GRAD_FROZEN_BASIS: every basis Q_i is held fixed as well, so iteration i
+ * is the map Y_i -> Q_i D_tau(Q_i^T Y_i) of a constant Q_i.  This leaves out the
+ * basis's dependence on the iterates; it equals the exact derivative only when
+ * no block is sampled from an iterate that depends on the inputs.
+ *
  * The handle must have run at least T iterations since svt_init (svt_iterate,
  * no svt_set_state since), in the FP64 form.  Every eigenpair of each projected
  * Gram enters the derivative: bases up to 96 columns are diagonalised in one
@@ -224,12 +242,14 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
  * repeats add up; nh = 0 gives zero gradients).
  * Outputs: *dtau, *ddelta, and da (nnz, caller order) = dL/dA on Lambda.
  * The iteration state of the handle is left unchanged.
- * Errors: SVT_E_INVALID_ARG (T <= 0, NULL outputs, H index out of range),
- * SVT_E_STATE (fewer than T recorded iterations, state replaced, mixed form),
- * SVT_E_LIMIT (a basis wider than 4096 columns), SVT_E_NUMERIC (an eigen-
- * decomposition that did not converge). */
+ * Errors: SVT_E_INVALID_ARG (T <= 0, NULL outputs, H index out of range,
+ * unknown flags), SVT_E_STATE (fewer than T recorded iterations, state
+ * replaced, mixed form; for the exact derivative also another mode, truncated
+ * recycling, power iterations or a dropped column), SVT_E_LIMIT (a basis wider
+ * than 4096 columns), SVT_E_NUMERIC (an eigen-decomposition that did not
+ * converge). */
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
-                    const double* gx_h, double* dtau, double* ddelta, double* da);
+                    const double* gx_h, int32_t flags, double* dtau, double* ddelta, double* da);
 
 /* Instrumentation.  Phases of one iteration whose device time can be measured with hipEvents
  * recorded on the handle's stream around the launches of that phase. */

@@ -14,10 +14,20 @@ operator by Candes, Sing-Long and Trzasko, 2013): with M = U^T Bbar V in the ful
   Cbar_ii = f'(s_i) M_ii,   Cbar_ij = f(s_i)/s_i M_ij,  j > r,
   a_ij = (f_i - f_j)/(s_i - s_j),  b_ij = (f_i + f_j)/(s_i + s_j),
 and the adjoint is U Cbar V^T.  dX/dtau = -Q U_K V_K^T.  This module writes that out with a
-full numpy SVD (small problems only).
+full numpy SVD per iteration.
+
+grad_exact drops the frozen basis: it differentiates the unrolled iteration as R4SVD computes it
+(Alg. 2-3 with every discrete decision held fixed), including how the basis depends on the
+iterates.  With P_i the orthogonal projector onto span(Q_i), iteration i computes X_i =
+D_tau(P_i Y_i), and the projector is built by appending sampled blocks (Alg. 3): starting from the
+recycled P_{i-1} (the empty projector before the first iteration), each block gives
+Z = (I - P) Y_i Omega and P <- P + Z (Z^T Z)^{-1} Z^T.  The reverse sweep carries the cotangent of
+the recycled projector from iteration to iteration.  For Pz = Z (Z^T Z)^{-1} Z^T the adjoint in Z
+of <Pbar, Pz> is (I - Pz)(Pbar + Pbar^T) Z (Z^T Z)^{-1}.
 """
 import numpy as np
 
+from .philox import omega_block
 from .svt import Params, Problem, dense, initial_state, svt_step
 
 
@@ -58,35 +68,39 @@ def frozen_forward(prob, a, tau, delta, k0, Qs, hr, hc):
 
 def svt_vjp(Q, Y, tau, Xbar):
     """Adjoint of Y -> Q D_tau(Q^T Y) at Y (dense), applied to the cotangent Xbar (dense m x n).
-    Returns (Ybar dense, tau_bar)."""
+    Returns (Ybar dense, tau_bar).  The coefficients Cbar of the module docstring are formed for
+    all (i, j) at once (array expressions of the same case split)."""
     B = Q.T @ Y
     r, n = B.shape
     U, s, Vt = np.linalg.svd(B, full_matrices=True)  # U r x r, Vt n x n
     V = Vt.T
     ns = min(r, n)
-    sig = np.zeros(r)
-    sig[:ns] = s
+    sig = s[:ns]
     f = np.maximum(sig - tau, 0.0)
     fp = (sig > tau).astype(float)
     Bbar = Q.T @ Xbar
     M = U.T @ Bbar @ V  # r x n
     Cbar = np.zeros_like(M)
-    for i in range(r):
-        for j in range(n):
-            if i < ns and j < ns:
-                if i == j:
-                    Cbar[i, j] = fp[i] * M[i, j]
-                    continue
-                si, sj, fi, fj = sig[i], sig[j], f[i], f[j]
-                a = (fi - fj) / (si - sj) if si != sj else fp[i]
-                b = (fi + fj) / (si + sj) if si + sj > 0 else 0.0
-                Cbar[i, j] = 0.5 * (a + b) * M[i, j] + 0.5 * (a - b) * M[j, i]
-            elif i < ns:   # right complement of the row space (n > r)
-                Cbar[i, j] = f[i] / sig[i] * M[i, j] if sig[i] > 0 else 0.0
-            elif j < ns:   # left complement of the column space (r > n)
-                Cbar[i, j] = f[j] / sig[j] * M[i, j] if sig[j] > 0 else 0.0
+    # the leading ns x ns block: divided differences of f over the singular values
+    si, sj = sig[:, None], sig[None, :]
+    fi, fj = f[:, None], f[None, :]
+    same = si == sj
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = np.where(same, np.broadcast_to(fp[:, None], same.shape), (fi - fj) / np.where(same, 1.0, si - sj))
+        pos = (si + sj) > 0
+        b = np.where(pos, (fi + fj) / np.where(pos, si + sj, 1.0), 0.0)
+    Ms = M[:ns, :ns]
+    C = 0.5 * (a + b) * Ms + 0.5 * (a - b) * Ms.T
+    np.fill_diagonal(C, fp * np.diag(Ms))
+    Cbar[:ns, :ns] = C
+    with np.errstate(divide="ignore", invalid="ignore"):
+        fs = np.where(sig > 0, f / np.where(sig > 0, sig, 1.0), 0.0)
+    if n > ns:   # right complement of the row space (n > r)
+        Cbar[:ns, ns:] = fs[:, None] * M[:ns, ns:]
+    if r > ns:   # left complement of the column space (r > n)
+        Cbar[ns:, :ns] = fs[None, :] * M[ns:, :ns]
     Ybar = Q @ (U @ Cbar @ V.T)
-    tau_bar = -float(sum(M[i, i] for i in range(ns) if sig[i] > tau))
+    tau_bar = -float(np.sum(np.diag(Ms)[sig > tau]))
     return Ybar, tau_bar
 
 
@@ -126,3 +140,88 @@ def grad(prob, p, rec, hr, hc, gx_h):
     a_bar += k0 * delta * ybar
     d_bar += k0 * float(ybar @ a)
     return t_bar, d_bar, a_bar
+
+
+def _block_plan(prob, p, rec):
+    """(blk, width) of the sampled blocks appended in each iteration: the t-block (blk 0) in the
+    first one, then the growth blocks of Alg. 3 (width min(dt, r_max - r)).  Raises when the run
+    dropped columns (the basis widths then differ from the plan)."""
+    pr = p.resolved(prob.m, prob.n)
+    if pr.mode != "r4svd" or pr.npow != 0:
+        raise ValueError("grad_exact covers R4SVD without power iterations")
+    plan, r = [], 0
+    for i, (blocks, _) in enumerate(rec["decisions"]):
+        cur = []
+        if i == 0:
+            cur.append((0, pr.t0))
+            r = pr.t0
+        for b in range(1, blocks + 1):
+            w = min(pr.dt, pr.r_max - r)
+            cur.append((b, w))
+            r += w
+        if r != rec["Qs"][i].shape[1]:
+            raise ValueError(f"iteration {i + 1}: the basis width {rec['Qs'][i].shape[1]} differs from the plan {r}")
+        plan.append(cur)
+    return plan
+
+
+def grad_exact(prob, p, rec, hr, hc, gx_h):
+    """dL/dtau, dL/ddelta, dL/da through the unrolled R4SVD iteration itself (basis included), with
+    the decisions of the recorded run held fixed; dL/dX_T = gx_h on (hr, hc)."""
+    a, m, n = prob.a, prob.m, prob.n
+    tau, delta, k0 = p.tau, p.delta, rec["k0"]
+    T = len(rec["Qs"])
+    plan = _block_plan(prob, p, rec)
+    eye = np.eye(m)
+    # forward: iterates, projectors, and the blocks (Z, Omega, projector before the block)
+    ys, Ps, blocks, xs = [k0 * delta * a.copy()], [], [], []
+    P = np.zeros((m, m))
+    for i in range(T):
+        Yd = dense(m, n, prob.rows, prob.cols, ys[i])
+        cur = []
+        for blk, w in plan[i]:
+            Om = omega_block(p.seed, i + 1, blk, n, w)
+            Z = (eye - P) @ (Yd @ Om)
+            Qz, Rz = np.linalg.qr(Z)
+            cur.append((Om, Z, Qz, Rz, P.copy()))
+            P = P + Qz @ Qz.T
+        Ps.append(P.copy())
+        blocks.append(cur)
+        X = d_tau_dense(P @ Yd, tau)
+        xs.append(X[prob.rows, prob.cols])
+        if i + 1 < T:
+            ys.append(ys[i] + delta * (a - xs[i]))
+    # reverse
+    Xbar = np.zeros((m, n))
+    np.add.at(Xbar, (hr, hc), gx_h)
+    a_bar, d_bar, t_bar = np.zeros_like(a), 0.0, 0.0
+    Pbar = np.zeros((m, m))
+    ybar = None
+    for i in range(T - 1, -1, -1):
+        if i < T - 1:
+            a_bar += delta * ybar
+            d_bar += float(ybar @ (a - xs[i]))
+            Xbar = np.zeros((m, n))
+            Xbar[prob.rows, prob.cols] = -delta * ybar
+        Yd = dense(m, n, prob.rows, prob.cols, ys[i])
+        Mbar, tb = svt_vjp(eye, Ps[i] @ Yd, tau, Xbar)   # X_i = D_tau(M), M = P_i Y_i
+        t_bar += tb
+        Ybar = Ps[i] @ Mbar
+        Pbar = Pbar + Mbar @ Yd.T
+        for Om, Z, Qz, Rz, Pb in reversed(blocks[i]):
+            Pz = Qz @ Qz.T
+            Zbar = (eye - Pz) @ (Pbar + Pbar.T) @ np.linalg.solve(Rz, Qz.T).T   # (I - Pz)(Pbar + Pbar^T) Z (Z^T Z)^{-1}
+            Ybar = Ybar + ((eye - Pb) @ Zbar) @ Om.T
+            Pbar = Pbar - Zbar @ (Yd @ Om).T
+        yb_i = Ybar[prob.rows, prob.cols]
+        ybar = yb_i if i == T - 1 else ybar + yb_i
+    a_bar += k0 * delta * ybar
+    d_bar += k0 * float(ybar @ a)
+    return t_bar, d_bar, a_bar
+
+
+def d_tau_dense(M, tau):
+    """D_tau of a dense matrix (Eq. 5) by a full SVD."""
+    U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    K = s > tau
+    return (U[:, K] * (s[K] - tau)) @ Vt[K]

@@ -1,5 +1,6 @@
 """torch.autograd face of svt_grad: X_T on a held-out set as a differentiable function of the
-observed values, tau and delta (frozen-basis convention of the C-ABI's svt_grad).
+observed values, tau and delta (the exact derivative of the unrolled iteration by default, the
+frozen-basis one with frozen_basis=True).
 
     x_h = svt_heldout(a, tau, delta, m, n, rows, cols, hi, hj, T=20, seed=3)
     loss = ((x_h - target) ** 2).sum()
@@ -18,7 +19,7 @@ class SVTHeldOut(torch.autograd.Function):
     """(a, tau, delta) -> X_T(H) after T unrolled iterations, float64 on the host."""
 
     @staticmethod
-    def forward(ctx, a, tau, delta, m, n, rows, cols, hi, hj, T, ckpt, params):
+    def forward(ctx, a, tau, delta, m, n, rows, cols, hi, hj, T, ckpt, params, frozen_basis):
         h = SVT(m, n, rows, cols, a.detach().to("cpu", torch.float64).numpy(), tau=float(tau), delta=float(delta),
                 precision=0, **params)
         st = h.iterate(T)
@@ -28,26 +29,28 @@ class SVTHeldOut(torch.autograd.Function):
         hi = np.ascontiguousarray(hi, dtype=np.int32)
         hj = np.ascontiguousarray(hj, dtype=np.int32)
         x = h.sample(hi, hj)
-        ctx.h, ctx.T, ctx.ckpt, ctx.hi, ctx.hj = h, int(T), int(ckpt), hi, hj
+        ctx.h, ctx.T, ctx.ckpt, ctx.hi, ctx.hj, ctx.frozen = h, int(T), int(ckpt), hi, hj, bool(frozen_basis)
         ctx.a_dtype, ctx.a_device = a.dtype, a.device
         return torch.from_numpy(x)
 
     @staticmethod
     def backward(ctx, gx):
         h = ctx.h
-        dtau, ddelta, da = h.grad(ctx.T, ctx.ckpt, ctx.hi, ctx.hj, gx.detach().to("cpu", torch.float64).numpy())
+        dtau, ddelta, da = h.grad(ctx.T, ctx.ckpt, ctx.hi, ctx.hj, gx.detach().to("cpu", torch.float64).numpy(),
+                                  frozen_basis=ctx.frozen)
         h.close()
         need = ctx.needs_input_grad
         ga = torch.from_numpy(da).to(ctx.a_device, ctx.a_dtype) if need[0] else None
         gt = torch.tensor(dtau, dtype=torch.float64) if need[1] else None
         gd = torch.tensor(ddelta, dtype=torch.float64) if need[2] else None
-        return (ga, gt, gd, None, None, None, None, None, None, None, None, None)
+        return (ga, gt, gd, None, None, None, None, None, None, None, None, None, None)
 
 
-def svt_heldout(a, tau, delta, m, n, rows, cols, hi, hj, T, ckpt=0, **params):
+def svt_heldout(a, tau, delta, m, n, rows, cols, hi, hj, T, ckpt=0, frozen_basis=False, **params):
     """X_T on (hi, hj) after T iterations; differentiable in a (observed values), tau and delta.
     params go to svt_init (seed, t0, dt, k0, ...); maxit is raised to at least T."""
     params = dict(params)
     params["maxit"] = max(int(params.get("maxit", 0)), int(T))
     params["tol"] = params.get("tol", 0.0)
-    return SVTHeldOut.apply(a, tau, delta, int(m), int(n), rows, cols, hi, hj, int(T), int(ckpt), params)
+    return SVTHeldOut.apply(a, tau, delta, int(m), int(n), rows, cols, hi, hj, int(T), int(ckpt), params,
+                            bool(frozen_basis))

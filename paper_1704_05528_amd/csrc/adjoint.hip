@@ -153,6 +153,31 @@ __global__ void k_adj_sut(int r, int k, const double* __restrict__ U, int ldu, A
   Cmat[(int64_t)l * ldc + 2 * k + q] = v;
 }
 
+// C = copyltu(-M), RinvT = R^{-T}: one thread per column c of R^{-1}, by back substitution on the
+// upper triangle of Rm (z_i = (delta_ic - sum_{j > i} R_ij z_j) / R_ii for i = c .. 0).
+__global__ __launch_bounds__(64) void k_qr_adjoint_coeffs(int w, const double* __restrict__ Rm,
+                                                          const double* __restrict__ M, double* __restrict__ C,
+                                                          double* __restrict__ RinvT, int ld) {
+  __shared__ double R[64][65];
+  const int t = threadIdx.x;
+  for (int e = t; e < w * w; e += 64) {
+    const int i = e / w, j = e % w;
+    R[i][j] = (j >= i) ? Rm[i * ld + j] : 0.0;
+    const int a = max(i, j), b = min(i, j);
+    C[i * ld + j] = -M[a * ld + b];
+  }
+  __syncthreads();
+  if (t < w) {
+    double z[64];
+    for (int i = w - 1; i >= 0; --i) {
+      double v = (i == t) ? 1.0 : 0.0;
+      for (int j = i + 1; j < w; ++j) v -= R[i][j] * ((j <= t) ? z[j] : 0.0);
+      z[i] = (i <= t) ? v / R[i][i] : 0.0;
+    }
+    for (int i = 0; i < w; ++i) RinvT[t * ld + i] = z[i];
+  }
+}
+
 // out[p] = sum_l L[row(p), l] R[col(p), l] for the CSC positions p of Lambda (one thread each)
 __global__ void k_lambda_dot(int n, const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
                              const double* __restrict__ L, int ldl, const double* __restrict__ R, int ldr, int w,
@@ -223,6 +248,13 @@ hipError_t launch_adjoint_coeffs(hipStream_t s, int r, int k, const double* U, i
 }
 
 size_t adjoint_coeffs_scratch(int r, int k) { return (size_t)5 * r * k + (size_t)r * r; }
+
+hipError_t launch_qr_adjoint_coeffs(hipStream_t s, int w, const double* Rm, const double* M, double* C, double* RinvT,
+                                    int ld) {
+  if (w <= 0 || w > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_qr_adjoint_coeffs, dim3(1), dim3(64), 0, s, w, Rm, M, C, RinvT, ld);
+  return hipGetLastError();
+}
 
 hipError_t launch_lambda_dot(hipStream_t s, int n, const int32_t* colptr, const int32_t* rowidx, const double* L,
                              int ldl, const double* R, int ldr, int w, double* out) {

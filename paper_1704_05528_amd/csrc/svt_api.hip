@@ -386,6 +386,10 @@ struct Engine {
       }
       CHK(readback(h, S_NADD + 1));
       const int kept = (int)h->hscal[S_WK2];
+      if (kept == wc)
+        h->cur_chunks.push_back({it, blk, c0, wc, rq});
+      else
+        h->exact_ok = false;  // a dropped column: the basis is no longer the plain chain of sampled blocks
       *got += kept;
       *add += h->hscal[S_NADD];
     }
@@ -477,6 +481,7 @@ struct Engine {
   // ----------------------------------------------------------------------------------------
   svt_status r4svd_core(int it, int replay_blocks, svt_step_stats* st) {
     double normB = 0.0;
+    h->cur_chunks.clear();
     const bool pre = h->spec_ready && h->r > 0;  // leading work already enqueued (see iteration())
     h->spec_ready = false;
     if (h->yT && !pre) {
@@ -942,6 +947,7 @@ struct Engine {
     }
     CHK(r4svd_core(it, rb, st));
     h->hist_r.push_back(h->r);
+    h->hist_chunks.insert(h->hist_chunks.end(), h->cur_chunks.begin(), h->cur_chunks.end());
     CHK(projected_svd(st));
     int nbl = 0;
     {
@@ -1140,13 +1146,22 @@ svt_status dispatch(Handle* h, F&& f) {
 }
 
 // ==============================================================================================
-// Reverse sweep through T unrolled iterations of Alg. 4 (frozen-basis convention), FP64 form.
+// Reverse sweep through T unrolled iterations of Alg. 4, FP64 form.
 //
 // Iteration i (0-based) maps Y_i to X_i = Q_i D_tau(Q_i^T Y_i), Q_i the first hist_r[i] columns
 // of the append-only basis, then Y_{i+1} = Y_i + delta P(A - X_i) (Eq. 4); Y_0 = k0 delta P(A).
 // The Y_i are recomputed from checkpoints; per iteration the Gram of W_i = Y_i^T Q_i is
-// diagonalised in full (one-workgroup Jacobi), and the adjoint of the thresholding map becomes
-// one sampled product L R^T on Lambda whose small coefficient block comes from adjoint.hip.
+// diagonalised in full, and the adjoint of the thresholding map B -> F(B) becomes one sampled
+// product L R^T on Lambda (Bbar = Cmat R^T) whose coefficient block comes from adjoint.hip.
+//
+// Exact sweep (default): the basis is a function of the iterates too.  Q_i = [Q_{i-1}, chunks of
+// iteration i], each chunk Q' = orth((I - Qp Qp^T) Y_i Omega) (Qp: every column before it; CGS2 and
+// CholeskyQR2 compute this map).  With X_i = Q_i F(Q_i^T Y_i) the cotangent of Q_i collects
+// Xbar F^T + Y_i Bbar^T; each chunk, last first, passes its part back through the thin-QR adjoint
+// (Xpbar = (Qbar' + Q' copyltu(-Qbar'^T Q')) R^{-T}), the projection (Xbar = Xpbar - Qp Qp^T Xpbar,
+// Qpbar -= Xpbar T^T + X (Qp^T Xpbar)^T, T = Qp^T X) and X = Y Omega (Ybar += P(Xbar Omega^T)).  The
+// cotangent of the recycled columns carries over to iteration i - 1.  Frozen-basis sweep (flag):
+// the basis and its cotangent are ignored.
 // ==============================================================================================
 struct GradArena {
   hipStream_t s;
@@ -1165,7 +1180,7 @@ struct GradArena {
 };
 
 svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, const int32_t* hj, const double* gx,
-                     double* dtau, double* ddelta, double* da) {
+                     bool exact, double* dtau, double* ddelta, double* da) {
   Engine<double> eng(h);
   const hipStream_t s = h->stream;
   const int m = (int)h->m, n = (int)h->n;
@@ -1195,6 +1210,23 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
       hv[q] = gx[l];
     }
   }
+  // and in CSR order (the exact sweep's product Xbar V_K on the held-out entries)
+  std::vector<int32_t> hrp(m + 1, 0), hci(std::max<int64_t>(nh, 1));
+  std::vector<double> hvr(std::max<int64_t>(nh, 1));
+  int max_h_row = 0;
+  for (int64_t l = 0; l < nh; ++l) hrp[hi[l] + 1]++;
+  for (int i = 0; i < m; ++i) {
+    max_h_row = std::max(max_h_row, hrp[i + 1]);
+    hrp[i + 1] += hrp[i];
+  }
+  {
+    std::vector<int32_t> pos(hrp.begin(), hrp.end() - 1);
+    for (int64_t l = 0; l < nh; ++l) {
+      const int32_t q = pos[hi[l]]++;
+      hci[q] = hj[l];
+      hvr[q] = gx[l];
+    }
+  }
 
   GradArena ar(s);
   int32_t *d_hcp = nullptr, *d_hri = nullptr;
@@ -1202,6 +1234,13 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   double *xb = nullptr, *tmp = nullptr, *Wb = nullptr, *F = nullptr, *R = nullptr, *L = nullptr, *Cm = nullptr;
   double *Z1 = nullptr, *Z2 = nullptr, *scr = nullptr, *U = nullptr, *th = nullptr, *Cc = nullptr, *Dc = nullptr;
   double *Ut = nullptr, *Vt = nullptr;
+  // exact sweep: cotangent of the basis, products of the basis terms, and the chunk work blocks
+  int32_t *d_hrp = nullptr, *d_hci = nullptr;
+  double *d_hvr = nullptr, *Qbar = nullptr, *XV = nullptr, *CcT = nullptr, *CmT = nullptr, *tmp2 = nullptr;
+  double *Omc = nullptr, *Xc = nullptr, *Xpc = nullptr, *Vb = nullptr, *Xpb = nullptr, *Xb = nullptr;
+  double *Tq = nullptr, *Sq = nullptr, *Tt = nullptr, *St = nullptr, *Rq = nullptr, *Mq = nullptr, *Cq = nullptr,
+         *RiT = nullptr;
+  constexpr int kCh = 64;  // widest chunk (append_block works in 64-column chunks)
   JacobiWork jw;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) {
@@ -1223,6 +1262,21 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   for (double** p : {&Z1, &Z2, &U, &Cc, &Dc}) A(ar.get(p, (size_t)ldw * ldw));
   A(ar.get(&scr, adjoint_coeffs_scratch(ldw, ldw)));
   A(ar.get(&th, 2 * (size_t)ldw));
+  if (exact) {
+    A(ar.get(&d_hrp, m + 1));
+    A(ar.get(&d_hci, hci.size()));
+    A(ar.get(&d_hvr, hvr.size()));
+    A(ar.get(&Qbar, (size_t)m * ldw));
+    A(ar.get(&XV, (size_t)m * ldw));
+    A(ar.get(&CcT, (size_t)ldw * ldw));
+    A(ar.get(&CmT, (size_t)kW * ldw));
+    A(ar.get(&tmp2, nnz));
+    A(ar.get(&Omc, (size_t)n * kCh));
+    for (double** p : {&Xc, &Xpc, &Vb, &Xpb, &Xb}) A(ar.get(p, (size_t)m * kCh));
+    for (double** p : {&Tq, &Sq}) A(ar.get(p, (size_t)ldw * kCh));
+    for (double** p : {&Tt, &St}) A(ar.get(p, (size_t)kCh * ldw));
+    for (double** p : {&Rq, &Mq, &Cq, &RiT}) A(ar.get(p, (size_t)kCh * kCh));
+  }
   if (wide) {
     jw.ld = ldw;
     jw.pin_half = 3 * (ldw / 2 + 1);
@@ -1240,6 +1294,12 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   HIPCHK(hipMemcpyAsync(d_hcp, hcp.data(), hcp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d_hri, hri.data(), hri.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d_hv, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (exact) {
+    HIPCHK(hipMemcpyAsync(d_hrp, hrp.data(), hrp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_hci, hci.data(), hci.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_hvr, hvr.data(), hvr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(Qbar, 0, (size_t)m * ldw * sizeof(double), s));
+  }
 
   const double* Q = eng.Q();
   const double* a = eng.a();
@@ -1281,6 +1341,51 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
     return SVT_OK;
   };
 
+  // The chunks of iteration i (0-based) in the order they were appended.
+  std::vector<std::vector<Handle::ChunkRec>> chunks_of(T);
+  for (const auto& c : h->hist_chunks)
+    if (c.it >= 1 && c.it <= T) chunks_of[c.it - 1].push_back(c);
+
+  // Exact sweep, one chunk c of the iteration whose iterate is yi: pass the cotangent of the chunk's
+  // columns (Qbar[:, q0:q0+w]) back to Y_i (into ybar) and to the columns before it (Qbar[:, :q0]).
+  auto chunk_adjoint = [&](const Handle::ChunkRec& c, const double* yi) -> svt_status {
+    const int w = c.w, q0 = c.q0;
+    const double* Qc = Q + q0;
+    double* Qbc = Qbar + q0;
+    HIPCHK(launch_omega<double>(s, Omc, n, c.c0, w, kCh, h->p.seed, (uint64_t)c.blk, (uint64_t)c.it));
+    HIPCHK(launch_seg_spmm<double>(s, m, h->rowptr, h->colidx, h->csr2csc, yi, Omc, kCh, Xc, kCh, w, nnz,
+                                   h->max_row_nnz));  // X = Y Omega
+    HIPCHK((launch_copy_cols<double, double>(s, m, Xc, kCh, Xpc, kCh, w)));
+    if (q0 > 0) {  // T = Qp^T X, Xp = X - Qp T
+      HIPCHK((launch_tn_narrow<double, double>(s, m, Q, ldq, q0, Xc, kCh, w, Tq, kCh, h->partial, h->partial_cap)));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, q0, Q, ldq, Tq, kCh, Xpc, kCh, w, -1.0, 1.0)));
+    }
+    // R = Q'^T Xp, M = Qbar'^T Q', C = copyltu(-M), R^{-T}
+    HIPCHK((launch_tn_narrow<double, double>(s, m, Qc, ldq, w, Xpc, kCh, w, Rq, kCh, h->partial, h->partial_cap)));
+    HIPCHK((launch_tn_narrow<double, double>(s, m, Qbc, ldw, w, Qc, ldq, w, Mq, kCh, h->partial, h->partial_cap)));
+    HIPCHK(launch_qr_adjoint_coeffs(s, w, Rq, Mq, Cq, RiT, kCh));
+    // Xpbar = (Qbar' + Q' C) R^{-T}
+    HIPCHK((launch_copy_cols<double, double>(s, m, Qbc, ldw, Vb, kCh, w)));
+    HIPCHK((launch_rowmul<double, double, double>(s, m, w, Qc, ldq, Cq, kCh, Vb, kCh, w, 1.0, 1.0)));
+    HIPCHK((launch_rowmul<double, double, double>(s, m, w, Vb, kCh, RiT, kCh, Xpb, kCh, w, 1.0, 0.0)));
+    const double* xbar = Xpb;
+    if (q0 > 0) {
+      // S = Qp^T Xpbar; Xbar = Xpbar - Qp S; Qpbar -= Xpbar T^T + X S^T
+      HIPCHK((launch_tn_narrow<double, double>(s, m, Q, ldq, q0, Xpb, kCh, w, Sq, kCh, h->partial, h->partial_cap)));
+      HIPCHK((launch_copy_cols<double, double>(s, m, Xpb, kCh, Xb, kCh, w)));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, q0, Q, ldq, Sq, kCh, Xb, kCh, w, -1.0, 1.0)));
+      HIPCHK(launch_transpose(s, Tq, kCh, q0, w, Tt, ldw));
+      HIPCHK(launch_transpose(s, Sq, kCh, q0, w, St, ldw));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, w, Xpb, kCh, Tt, ldw, Qbar, ldw, q0, -1.0, 1.0)));
+      HIPCHK((launch_rowmul<double, double, double>(s, m, w, Xc, kCh, St, ldw, Qbar, ldw, q0, -1.0, 1.0)));
+      xbar = Xb;
+    }
+    // Ybar += P(Xbar Omega^T)
+    HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, xbar, kCh, Omc, kCh, w, tmp2));
+    HIPCHK(launch_axpby(s, nnz, 1.0, tmp2, 1.0, ybar));
+    return SVT_OK;
+  };
+
   // forward pass: Y_0 and the checkpoints Y_{c ckpt}
   HIPCHK((launch_scale_copy<double, double>(s, nnz, a, (double)h->k0 * delta, ycp)));
   for (int sg = 1; sg < nseg; ++sg) {
@@ -1311,6 +1416,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
       const int ri = h->hist_r[i];
       int k = 0;
       CHK(frozen_map(yi, ri, &k));
+      // Xbar_i: -delta Ybar_{i+1} on Lambda (tmp, CSC order), or the held-out cotangent at the end
+      bool xterms = false;
       if (i < T - 1) {
         // Y_{i+1} = Y_i + delta P(A - X_i): contributions to abar and dbar, cotangent of X_i
         CHK(dual_step(yi, k, res, tmp));
@@ -1318,29 +1425,49 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
         HIPCHK(launch_dot(s, nnz, ybar, res, h->partial, h->scal, S_DOT));
         CHK(readback(h, S_DOT + 1));
         d_bar += h->hscal[S_DOT];
-        if (k == 0) continue;
-        HIPCHK((launch_scale_copy<double, double>(s, nnz, ybar, -delta, tmp)));
-        HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, ldw, ri, h->nnz,
+        if (k > 0) {
+          HIPCHK((launch_scale_copy<double, double>(s, nnz, ybar, -delta, tmp)));
+          HIPCHK(launch_seg_spmm<double>(s, n, h->colptr, h->rowidx, nullptr, tmp, Q, ldq, F, ldw, ri, h->nnz,
                                          h->max_col_nnz));
-      } else {
-        if (k == 0 || nh == 0) continue;
+          if (exact)  // Xbar V_K over the rows of Lambda
+            HIPCHK(launch_seg_spmm<double>(s, m, h->rowptr, h->colidx, h->csr2csc, tmp, Vt, ldw, XV, ldw, k, nnz,
+                                           h->max_row_nnz));
+          xterms = true;
+        }
+      } else if (k > 0 && nh > 0) {
         HIPCHK(launch_seg_spmm<double>(s, n, d_hcp, d_hri, nullptr, d_hv, Q, ldq, F, ldw, ri, nh, 0));
+        if (exact)
+          HIPCHK(launch_seg_spmm<double>(s, m, d_hrp, d_hci, nullptr, d_hvr, Vt, ldw, XV, ldw, k, nh, max_h_row));
+        xterms = true;
       }
-      // F = Xbar^T Q_i = Bbar^T; Z1 = Bbar V_K, Z2 = Bbar W_i, R = [F U_K | V_K | W_i]
-      const int wl = 2 * k + ri;
-      HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Vt, ldw, k, Z1, ldw, h->partial,
-                                               h->partial_cap)));
-      HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Wb, ldw, ri, Z2, ldw, h->partial,
-                                               h->partial_cap)));
-      HIPCHK((launch_rowmul<double, double, double>(s, n, ri, F, ldw, U, ldw, R, kW, k, 1.0, 0.0)));
-      HIPCHK((launch_copy_cols<double, double>(s, n, Vt, ldw, R + k, kW, k)));
-      HIPCHK((launch_copy_cols<double, double>(s, n, Wb, ldw, R + 2 * k, kW, ri)));
-      HIPCHK(launch_adjoint_coeffs(s, ri, k, U, ldw, th, Z1, ldw, Z2, ldw, tau, Cm, kW, scr, h->scal, S_TBAR));
-      HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cm, kW, L, kW, wl, 1.0, 0.0)));
-      HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, L, kW, R, kW, wl, tmp));
-      HIPCHK(launch_axpby(s, nnz, 1.0, tmp, 1.0, ybar));
-      CHK(readback(h, S_TBAR + 1));
-      t_bar += h->hscal[S_TBAR];
+      if (xterms) {
+        // F = Xbar^T Q_i = Bbar^T; Z1 = Bbar V_K, Z2 = Bbar W_i, R = [F U_K | V_K | W_i]
+        const int wl = 2 * k + ri;
+        HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Vt, ldw, k, Z1, ldw, h->partial,
+                                                 h->partial_cap)));
+        HIPCHK((launch_tn_narrow<double, double>(s, n, F, ldw, ri, Wb, ldw, ri, Z2, ldw, h->partial,
+                                                 h->partial_cap)));
+        HIPCHK((launch_rowmul<double, double, double>(s, n, ri, F, ldw, U, ldw, R, kW, k, 1.0, 0.0)));
+        HIPCHK((launch_copy_cols<double, double>(s, n, Vt, ldw, R + k, kW, k)));
+        HIPCHK((launch_copy_cols<double, double>(s, n, Wb, ldw, R + 2 * k, kW, ri)));
+        HIPCHK(launch_adjoint_coeffs(s, ri, k, U, ldw, th, Z1, ldw, Z2, ldw, tau, Cm, kW, scr, h->scal, S_TBAR));
+        HIPCHK((launch_rowmul<double, double, double>(s, m, ri, Q, ldq, Cm, kW, L, kW, wl, 1.0, 0.0)));
+        HIPCHK(launch_lambda_dot(s, n, h->colptr, h->rowidx, L, kW, R, kW, wl, tmp));
+        HIPCHK(launch_axpby(s, nnz, 1.0, tmp, 1.0, ybar));
+        CHK(readback(h, S_TBAR + 1));
+        t_bar += h->hscal[S_TBAR];
+        if (exact) {
+          // Qbar_i += Xbar F^T + Y_i Bbar^T = (Xbar V_K) C^T + (Y_i R) Cmat^T  (C = U_K diag(s - tau))
+          HIPCHK(launch_transpose(s, Cc, ldw, ri, k, CcT, ldw));
+          HIPCHK((launch_rowmul<double, double, double>(s, m, k, XV, ldw, CcT, ldw, Qbar, ldw, ri, 1.0, 1.0)));
+          HIPCHK(launch_seg_spmm<double>(s, m, h->rowptr, h->colidx, h->csr2csc, yi, R, kW, L, kW, wl, nnz,
+                                         h->max_row_nnz));
+          HIPCHK(launch_transpose(s, Cm, kW, ri, wl, CmT, ldw));
+          HIPCHK((launch_rowmul<double, double, double>(s, m, wl, L, kW, CmT, ldw, Qbar, ldw, ri, 1.0, 1.0)));
+        }
+      }
+      if (exact)
+        for (auto it = chunks_of[i].rbegin(); it != chunks_of[i].rend(); ++it) CHK(chunk_adjoint(*it, yi));
     }
   }
   // Y_0 = k0 delta P(A)
@@ -1669,6 +1796,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   }
   h->r = 0;
   h->iter = 0;
+  h->exact_ok = (h->p.npow == 0);
   h->eps_thr_set = false;
   h->eps_min = std::numeric_limits<double>::infinity();
   *out = h;
@@ -1826,6 +1954,7 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   h->k = 0;
   h->hist_ok = false;
   h->hist_r.clear();
+  h->hist_chunks.clear();
   return SVT_OK;
 }
 
@@ -1892,10 +2021,11 @@ svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* fl
 }
 
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
-                    const double* gx_h, double* dtau, double* ddelta, double* da) {
+                    const double* gx_h, int32_t flags, double* dtau, double* ddelta, double* da) {
   if (!h) return SVT_E_INVALID_ARG;
   if (T <= 0) return fail(h, SVT_E_INVALID_ARG, "T must be positive");
   if (!dtau || !ddelta || !da) return fail(h, SVT_E_INVALID_ARG, "NULL output pointer");
+  if (flags & ~SVT_GRAD_FROZEN_BASIS) return fail(h, SVT_E_INVALID_ARG, "unknown svt_grad flags");
   if (nh < 0 || (nh > 0 && (!hi || !hj || !gx_h))) return fail(h, SVT_E_INVALID_ARG, "bad held-out arrays");
   if (nh >= ((int64_t)1 << 31)) return fail(h, SVT_E_INVALID_ARG, "nh must be below 2^31");
   for (int64_t l = 0; l < nh; ++l) {
@@ -1908,8 +2038,13 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
     return fail(h, SVT_E_STATE, "svt_grad needs T iterations run by svt_iterate since svt_init");
   for (int i = 0; i < T; ++i)
     if (h->hist_r[i] > kJgMaxOrder) return fail(h, SVT_E_LIMIT, "svt_grad: basis wider than the eigen-solver's order");
+  const bool exact = !(flags & SVT_GRAD_FROZEN_BASIS);
+  if (exact && (!h->exact_ok || h->p.mode != SVT_MODE_R4SVD || h->p.recycle_extra >= 0))
+    return fail(h, SVT_E_STATE,
+                "the exact reverse sweep needs R4SVD with full recycling, no power iterations and no dropped "
+                "columns; SVT_GRAD_FROZEN_BASIS gives the frozen-basis derivative");
   h->spec_ready = false;  // the adjoint reuses the buffers the enqueued leading work wrote
-  const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, dtau, ddelta, da);
+  const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, exact, dtau, ddelta, da);
   h->spec_ready = false;
   return gs;
 }

@@ -169,6 +169,15 @@ struct Handle {
   // iteration i is the first hist_r[i] columns of Q); svt_set_state invalidates it
   std::vector<int32_t> hist_r;
   bool hist_ok = true;
+  // every sampled chunk appended to the basis since svt_init, in order: SVT iteration (1-based),
+  // Omega block, its first column and width, and the basis column it starts at.  exact_ok: no chunk
+  // lost a column and no power iteration ran, so the basis is the plain chain the exact reverse
+  // sweep differentiates.
+  struct ChunkRec {
+    int32_t it, blk, c0, w, q0;
+  };
+  std::vector<ChunkRec> hist_chunks, cur_chunks;
+  bool exact_ok = true;
 
   // instrumentation: hipEvent pairs per phase, resolved at the next host synchronisation
   struct Pending {
@@ -381,6 +390,11 @@ hipError_t launch_transpose(hipStream_t s, const double* src, int lds_, int rows
 // Cmat = [U_K diag(f/s) | U_K Gamma + U_N Kappa | U_K Beta^T U^T] (r x (2k + r)) and scal[slot] =
 // tau_bar for one unrolled iteration; U, theta: full eigen-decomposition of G, Z1 = Bbar V_K (r x k),
 // Z2 = Bbar B^T (r x r); scratch: adjoint_coeffs_scratch(r, k) doubles.  1 <= k <= r.
+// Adjoint of a thin QR with R of positive diagonal, for one w x w block (w <= 64, one workgroup):
+// C = copyltu(-M) (the symmetric matrix with the lower triangle of -M) and RinvT = R^{-T} (R the
+// upper triangle of Rm).  All w x w with row stride ld.
+hipError_t launch_qr_adjoint_coeffs(hipStream_t s, int w, const double* Rm, const double* M, double* C, double* RinvT,
+                                    int ld);
 hipError_t launch_adjoint_coeffs(hipStream_t s, int r, int k, const double* U, int ldu, const double* theta,
                                  const double* Z1, int ldz1, const double* Z2, int ldz2, double tau, double* Cmat,
                                  int ldc, double* scratch, double* scal, int slot);

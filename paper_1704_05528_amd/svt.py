@@ -183,14 +183,17 @@ class SVT:
               self._h)
         return ms.value, by.value, fl.value
 
-    def grad(self, T, ckpt, hi, hj, gx_h):
+    def grad(self, T, ckpt, hi, hj, gx_h, frozen_basis=False):
+        """dL/dtau, dL/ddelta, dL/da through T unrolled iterations (exact, or with frozen bases)."""
+        from ._capi import SVT_GRAD_FROZEN_BASIS
         hi, ip = _i32(hi)
         hj, jp = _i32(hj)
         g, gp = _f64(gx_h)
         dtau, ddelta = C.c_double(), C.c_double()
         da = np.zeros(self.nnz)
-        check(load().svt_grad(self._h, int(T), int(ckpt), hi.size, ip, jp, gp, C.byref(dtau), C.byref(ddelta),
-                              da.ctypes.data_as(_f64p)), self._h)
+        flags = SVT_GRAD_FROZEN_BASIS if frozen_basis else 0
+        check(load().svt_grad(self._h, int(T), int(ckpt), hi.size, ip, jp, gp, flags, C.byref(dtau),
+                              C.byref(ddelta), da.ctypes.data_as(_f64p)), self._h)
         return dtau.value, ddelta.value, da
 
 
@@ -207,5 +210,5 @@ def svt_iterate(h, max_steps=1):
     return h.iterate(max_steps)
 
 
-def svt_grad(h, T, ckpt, hi, hj, gx_h):
-    return h.grad(T, ckpt, hi, hj, gx_h)
+def svt_grad(h, T, ckpt, hi, hj, gx_h, frozen_basis=False):
+    return h.grad(T, ckpt, hi, hj, gx_h, frozen_basis=frozen_basis)

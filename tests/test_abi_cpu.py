@@ -86,6 +86,6 @@ def test_null_handles_are_rejected():
     L = svt.load()
     assert L.svt_iterate(None, 1, None) == _capi.SVT_E_INVALID_ARG
     assert L.r4svd_step(None, None) == _capi.SVT_E_INVALID_ARG
-    assert L.svt_grad(None, 1, 1, 0, None, None, None, None, None, None) == _capi.SVT_E_INVALID_ARG
+    assert L.svt_grad(None, 1, 1, 0, None, None, None, 0, None, None, None) == _capi.SVT_E_INVALID_ARG
     assert L.svt_history(None, 0, 0, None, None) == _capi.SVT_E_INVALID_ARG
     L.svt_destroy(None)
