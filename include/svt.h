@@ -189,6 +189,19 @@ svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_
  * (all m n entries for the overall error, a held-out set for a test error).  nq >= 1. */
 svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref, double* mae);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): svt_mae with DEVICE pointers and no allocation, host
+ * copy or host synchronisation.  qi, qj (int32) and ref (float64) hold nq entries in device memory;
+ * mae points to one float64 in device memory that receives (1/nq) sum_l |ref[l] - X(qi[l], qj[l])|,
+ * the same value svt_mae returns.  The work is enqueued on the handle's stream and the call returns
+ * without waiting.  The reduction keeps its partial sums in a fixed library scratch array of 1032
+ * doubles in each GPU's memory (held until the process ends); every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other handles, other streams) race.  An index out
+ * of range gives a NaN result (the kernel checks every index before reading).
+ * Errors: SVT_E_INVALID_ARG (nq outside [1, 2^31 - 1], a NULL pointer), SVT_E_STATE (no factors). */
+svt_status svt_mae_device(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref,
+                          double* mae);
+
 /* Current state: y (nnz, caller order), basis Q (m x r row-major; pass
  * qcap >= r columns, or NULL), r, eps_threshold (NaN before the first
  * iteration), eps_min, iterations completed. */

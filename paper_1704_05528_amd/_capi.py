@@ -16,7 +16,7 @@ _STATUS = {0: "SVT_OK", -1: "SVT_E_INVALID_ARG", -2: "SVT_E_OOM", -3: "SVT_E_HIP
 
 # Names of every symbol include/svt.h declares (checked by the CPU tests).
 EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample",
-           "svt_mae", "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile",
+           "svt_mae", "svt_mae_device", "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile",
            "svt_profile_phases", "svt_profile_read", "svt_time_phase", "svt_last_error", "svt_destroy"]
 PHASES = ["spmm_t", "grow", "gram", "eig", "factors", "sddmm", "reduce", "densify"]
 
@@ -86,11 +86,14 @@ def load():
     L.svt_profile_phases.argtypes = [_vp, C.c_uint32]
     L.svt_profile_read.argtypes = [_vp, _f64p, _f64p, _f64p, _P(C.c_int64)]
     L.svt_time_phase.argtypes = [_vp, C.c_int32, C.c_int32, _f64p, _f64p, _f64p]
+    # device pointers (integers, e.g. torch.Tensor.data_ptr())
+    L.svt_mae_device.argtypes = [_vp, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.svt_last_error.argtypes = [_vp]
     L.svt_last_error.restype = C.c_char_p
     L.svt_destroy.argtypes = [_vp]
     L.svt_destroy.restype = None
-    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample", "svt_mae", "svt_get_state",
+    for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample", "svt_mae",
+                 "svt_mae_device", "svt_get_state",
                  "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_phases",
                  "svt_profile_read", "svt_time_phase"]:
         getattr(L, name).restype = C.c_int

@@ -1237,6 +1237,38 @@ __global__ void k_sample(int64_t nq, const int32_t* __restrict__ qi, const int32
   out[t] = (double)x;
 }
 
+// Per-block sums of |ref - X(qi, qj)| over a grid-stride loop: X as k_sample computes it and the
+// sum in the order of k_absdiff, so the total equals sample-then-absdiff bit for bit.  An index out
+// of range contributes NaN (no read happens), which makes the result NaN.
+template <class T>
+__global__ __launch_bounds__(256) void k_sample_absdiff(int64_t nq, const int32_t* __restrict__ qi,
+                                                        const int32_t* __restrict__ qj, const T* __restrict__ Ut,
+                                                        const T* __restrict__ Vt, int ld, int k, int64_t m,
+                                                        int64_t n, const double* __restrict__ ref,
+                                                        double* __restrict__ partial) {
+  __shared__ double lds[4];
+  double v = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = qi[e], j = qj[e];
+    if (i < 0 || i >= m || j < 0 || j >= n) {
+      v += __builtin_nan("");
+      continue;
+    }
+    const T* u = Ut + (int64_t)i * ld;
+    const T* w = Vt + (int64_t)j * ld;
+    T x = (T)0;
+    for (int l = 0; l < k; ++l) x = fma(u[l], w[l], x);
+    v += fabs(ref[e] - (double)x);
+  }
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// dst[0] = src[0] / denom
+__global__ void k_div_store(const double* __restrict__ src, double denom, double* __restrict__ dst) {
+  if (threadIdx.x == 0) dst[0] = src[0] / denom;
+}
+
 template <class TS, class TD>
 __global__ void k_scale_copy(int64_t len, const TS* __restrict__ src, double alpha, TD* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1618,6 +1650,21 @@ hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_mae_fused(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
+                           int ld, int k, int64_t m, int64_t n, const double* ref, double* work, double* out) {
+  if (nq <= 0) return hipErrorInvalidValue;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kMaeFusedBlocks, (nq + 255) / 256));
+  hipLaunchKernelGGL(k_sample_absdiff<T>, dim3(nb), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, m, n, ref, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, work, nb, 1, 1, work, kMaeFusedBlocks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_div_store, dim3(1), dim3(64), 0, s, work + kMaeFusedBlocks, (double)nq, out);
+  return hipGetLastError();
+}
+
 template <class TS, class TD>
 hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst) {
   if (len == 0) return hipSuccess;
@@ -1656,6 +1703,8 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
                                              int*);                                                                   \
   template hipError_t launch_sample<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*, int, \
                                        int, double*);                                                                 \
+  template hipError_t launch_mae_fused<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*,    \
+                                          int, int, int64_t, int64_t, const double*, double*, double*);               \
   template hipError_t launch_scale_copy<T, T>(hipStream_t, int64_t, const T*, double, T*);                            \
   template hipError_t launch_copy_cols<T, T>(hipStream_t, int, const T*, int, T*, int, int);
 

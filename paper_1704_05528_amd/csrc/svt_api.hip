@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 
@@ -22,9 +23,34 @@ struct svt_handle : svt::Handle {};
 
 using namespace svt;
 
+// Device scratch of svt_mae_device, the allocation-free entry point: the partial sums of its fused
+// reduction and their total.  Every GPU the library runs on holds its own copy for the life of the
+// process.  Host code never passes `scratch` itself to a kernel (in host code the name stands for a
+// host-side placeholder): it fetches each device's address once with hipGetSymbolAddress.
+constexpr int kScratchDoubles = kMaeFusedBlocks + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
 
 thread_local std::string g_init_err;
+
+// Per-device address of `scratch`, fetched with the device current on the first svt_init there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 constexpr double kDropTol = 1e-10;    // a projected column this small relative to its norm before lies in span(Q)
 constexpr double kDepTol = 1e-6;      // a Cholesky pivot this small relative to the column norm means dependence
@@ -1738,6 +1764,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->hstage, kStageDoubles * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->spec_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = scratch_address(h->device, &h->scratch);
   if (e != hipSuccess) {
     g_init_err = std::string("device allocation failed: ") + hipGetErrorString(e);
     svt_destroy(h);
@@ -1906,6 +1933,20 @@ svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* 
   CHK(readback(h, S_MAE + 1));
   *mae = h->hscal[S_MAE] / (double)nq;
   return SVT_OK;
+}
+
+svt_status svt_mae_device(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref,
+                          double* mae) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (nq <= 0 || nq > INT32_MAX || !qi || !qj || !ref || !mae)
+    return fail(h, SVT_E_INVALID_ARG, "svt_mae_device: nq must lie in [1, 2^31 - 1] and every pointer be non-NULL");
+  if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
+  if (!h->scratch) return fail(h, SVT_E_STATE, "the device scratch address is not set");
+  return dispatch(h, [&](auto& eng) -> svt_status {
+    HIPCHK(launch_mae_fused(h->stream, nq, qi, qj, eng.Ut(), eng.Vt(), h->ldf, h->k, h->m, h->n, ref, h->scratch,
+                            mae));
+    return SVT_OK;
+  });
 }
 
 svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,

@@ -146,6 +146,7 @@ struct Handle {
   double* scal = nullptr;   // device scalars
   double* hscal = nullptr;  // pinned host mirror
   double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks
+  double* scratch = nullptr;  // this device's copy of the library's file-scope scratch array (svt_mae_device)
   hipEvent_t sync_ev = nullptr;  // timing-free event the host spins on at decision points
   // The next iteration's leading work (dense copy of Y, W = Y^T Q, ||W||^2) was enqueued at the end
   // of the previous iteration; ||W||^2 lands in hscal[kSpecSlot] when spec_ev completes.
@@ -326,6 +327,13 @@ hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int 
 // scal[slot] = sum |ref - x| over len entries (deterministic)
 hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const double* ref, double* partial,
                               double* scal, int slot);
+// MAE of X against ref on nq entries in one pass without storing X: work holds kMaeFusedBlocks
+// partial sums and their total (kMaeFusedBlocks + 1 doubles); out[0] = total / nq.  Same value as
+// launch_sample followed by launch_absdiff_sum.
+constexpr int kMaeFusedBlocks = 1024;
+template <class T>
+hipError_t launch_mae_fused(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
+                           int ld, int k, int64_t m, int64_t n, const double* ref, double* work, double* out);
 // X on arbitrary entries
 template <class T>
 hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
