@@ -80,8 +80,11 @@ enum {
   SVT_F_RMAX_HIT = 4,  /* growth stopped because the basis reached r_max */
   SVT_F_EXHAUSTED = 8, /* a growth block had no direction outside span(Q) */
   SVT_F_ANNEALED = 16, /* eps_threshold was multiplied by beta in this iteration */
-  SVT_F_EIG_INEXACT = 32 /* the eigen-solver stopped at its cap (products of the subspace solver, or
-                            sweeps of the full decomposition) */
+  SVT_F_EIG_INEXACT = 32, /* the eigen-solver stopped at its cap (products of the subspace solver, or
+                             sweeps of the full decomposition) */
+  SVT_F_DIVERGING = 64     /* the relative residual has stayed above 10 times its smallest value so far for
+                             5 iterations in a row (annealing, the paper's only response to a residual that
+                             stops decreasing, cannot correct a step size above the stable bound) */
 };
 
 /* Inputs of Alg. 4 plus the values the paper leaves open.  Fill with
@@ -113,6 +116,10 @@ typedef struct {
   int32_t oversample; /* SVT_MODE_RSVD: oversampling p >= 0 (default 10) */
   double mae_tol;  /* > 0: also stop when the sample MAE (1/|Lambda|) sum |A - X| on Lambda falls
                       below mae_tol (the stop rule of Sec. 3); <= 0: unused */
+  double wait_timeout_s; /* longest host wait for the device at one decision point; <= 0 => 600 s.  A
+                            wait that runs out returns SVT_E_HIP and marks the handle lost:
+                            svt_destroy then neither waits for its stream nor frees its device
+                            memory (a kernel may still be using it) */
 } svt_params;
 
 /* Per-iteration report. */
@@ -214,6 +221,21 @@ svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int3
  * next iteration draws the Omega blocks of iteration iter + 1. */
 svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_t r, double eps_thr,
                          double eps_min, int32_t iter);
+
+/* Checkpoint for restarts: everything the next iterations read, in one host blob (Y on Lambda,
+ * the basis, the thresholds and counters, the eigen-solvers' warm-start vectors, the factors of the
+ * last X, and the decision log: the step reports, the basis widths and sampled blocks of every
+ * iteration, and the replay queue).  A handle restored from it continues bit for bit as the
+ * checkpointed one would, and svt_grad works across the restore.  buf = NULL: *size receives the
+ * bytes needed; otherwise cap must be at least that.  The blob's layout is this library's own
+ * (host byte order), not a stable file format.
+ * Errors: SVT_E_INVALID_ARG (size NULL, cap too small). */
+svt_status svt_checkpoint(svt_handle* h, void* buf, int64_t cap, int64_t* size);
+
+/* Load a checkpoint into a handle created by svt_init for the same problem (m, n, observed set and
+ * values), precision form, r_max and kmax.  Errors: SVT_E_INVALID_ARG (not a checkpoint, another
+ * problem or form, malformed; the handle is then unchanged). */
+svt_status svt_restore(svt_handle* h, const void* buf, int64_t size);
 
 /* Force the two discrete decisions of the next len iterations: blocks[l]
  * growth blocks and annealed[l] (0/1).  len = 0 clears the replay. */

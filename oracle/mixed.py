@@ -8,7 +8,9 @@ the sampled product x, the residual and the updated Y.  Gram matrices, the
 Cholesky factors, the small SVD and all norms stay float64.  Products whose
 result is stored in float32 are formed in float64 and rounded once; the device
 accumulates some of them in float32, which differs from this by accumulation
-noise only.
+noise only.  The operator variants of svt.py are the same here: R3SVD from a
+fresh t-block in every iteration, the fixed-rank randomized SVD of Alg. 1 and
+truncated recycling.
 """
 import math
 
@@ -56,7 +58,7 @@ def r4svd_mixed(Y, normY, Q, eps_thr, p, it, replay_blocks=None, info=None):
     info.eps_thr_used = eps_thr
     info.eps_hist.append(eps)
     blk = 0
-    while True:
+    while p.mode != "rsvd":              # Alg. 1 takes one sample of fixed width, no growth
         r = Q.shape[1]
         room = min(p.dt, p.r_max - r)
         if replay_blocks is not None:
@@ -94,13 +96,16 @@ def svt_step_mixed(prob, p, state, replay=None):
     y = f32(state.y)
     Y = prob.sparse(y)
     normY = float(y @ y)
-    Q0 = None if state.Q is None else f32(state.Q)
+    # R3SVD / RSVD start every iteration from a fresh sample
+    Q0 = None if state.Q is None or p.mode != "r4svd" else f32(state.Q)
     Q, W, normB, eps, eps_thr = r4svd_mixed(Y, normY, Q0, state.eps_thr, p, it,
                                             replay_blocks=None if replay is None else replay[0], info=info)
     info.r, info.eps, info.normY, info.normB, info.Q, info.W = Q.shape[1], eps, normY, normB, Q, W
 
     U_B, s, VBt = np.linalg.svd(W.T, full_matrices=W.shape[1] > W.shape[0])
     K = np.flatnonzero(s > p.tau)
+    if p.mode == "rsvd":
+        K = K[K < p.rank]                          # Alg. 1 keeps the `rank` leading triplets
     info.sigma, info.k = s, int(K.size)
     # factors stored in float32: Ut = Q U_K diag(sigma - tau), Vt = W U_K diag(1 / sigma) = V_K
     Ut = f32(Q @ (U_B[:, K] * (s[K] - p.tau)))
@@ -110,6 +115,7 @@ def svt_step_mixed(prob, p, state, replay=None):
     res = f32(a - x)
     rel = float(np.linalg.norm(res)) / float(np.linalg.norm(a))
     info.x, info.rel = x, rel
+    info.mae = float(np.mean(np.abs(res)))
 
     eps_min = state.eps_min
     target = eps_min * (1.0 - p.eta)
@@ -121,8 +127,11 @@ def svt_step_mixed(prob, p, state, replay=None):
         eps_min = rel
     info.annealed = annealed
 
-    new = State(it=it, y=y.copy(), Q=f32(Q @ U_B), eps_thr=eps_thr, eps_min=eps_min)
-    if rel < p.tol:
+    # recycle U_L: all r columns, or the leading k + recycle_extra (truncated recycling)
+    U_L = f32(Q @ U_B)
+    keep = U_L.shape[1] if p.recycle_extra < 0 else min(U_L.shape[1], info.k + p.recycle_extra)
+    new = State(it=it, y=y.copy(), Q=U_L[:, :keep] if keep > 0 else None, eps_thr=eps_thr, eps_min=eps_min)
+    if rel < p.tol or (p.mae_tol > 0 and info.mae < p.mae_tol):
         info.stopped = True
         return new, info
     delta32 = float(np.float32(p.delta))

@@ -10,13 +10,15 @@ SVT_GRAD_FROZEN_BASIS = 1
 SVT_FP64, SVT_MIXED = 0, 1
 SVT_MODE_R4SVD, SVT_MODE_R3SVD, SVT_MODE_RSVD = 0, 1, 2
 SVT_F_CONVERGED, SVT_F_MAXIT, SVT_F_RMAX_HIT, SVT_F_EXHAUSTED, SVT_F_ANNEALED, SVT_F_EIG_INEXACT = 1, 2, 4, 8, 16, 32
+SVT_F_DIVERGING = 64
 
 _STATUS = {0: "SVT_OK", -1: "SVT_E_INVALID_ARG", -2: "SVT_E_OOM", -3: "SVT_E_HIP", -4: "SVT_E_NUMERIC",
            -5: "SVT_E_STATE", -6: "SVT_E_LIMIT"}
 
 # Names of every symbol include/svt.h declares (checked by the CPU tests).
 EXPORTS = ["svt_default_params", "svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample",
-           "svt_mae", "svt_mae_device", "svt_get_state", "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile",
+           "svt_mae", "svt_mae_device", "svt_get_state", "svt_set_state", "svt_checkpoint", "svt_restore",
+           "svt_set_replay", "svt_grad", "svt_profile",
            "svt_profile_phases", "svt_profile_read", "svt_time_phase", "svt_last_error", "svt_destroy"]
 PHASES = ["spmm_t", "grow", "gram", "eig", "factors", "sddmm", "reduce", "densify"]
 
@@ -33,7 +35,7 @@ class Params(C.Structure):
                 ("dt", C.c_int32), ("npow", C.c_int32), ("r_max", C.c_int32), ("k0", C.c_int32),
                 ("seed", C.c_uint64), ("precision", C.c_int32), ("kmax", C.c_int32), ("mode", C.c_int32),
                 ("recycle_extra", C.c_int32), ("rank", C.c_int32), ("oversample", C.c_int32),
-                ("mae_tol", C.c_double)]
+                ("mae_tol", C.c_double), ("wait_timeout_s", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -86,6 +88,8 @@ def load():
     L.svt_profile_phases.argtypes = [_vp, C.c_uint32]
     L.svt_profile_read.argtypes = [_vp, _f64p, _f64p, _f64p, _P(C.c_int64)]
     L.svt_time_phase.argtypes = [_vp, C.c_int32, C.c_int32, _f64p, _f64p, _f64p]
+    L.svt_checkpoint.argtypes = [_vp, C.c_void_p, C.c_int64, _P(C.c_int64)]
+    L.svt_restore.argtypes = [_vp, C.c_void_p, C.c_int64]
     # device pointers (integers, e.g. torch.Tensor.data_ptr())
     L.svt_mae_device.argtypes = [_vp, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.svt_last_error.argtypes = [_vp]
@@ -93,7 +97,7 @@ def load():
     L.svt_destroy.argtypes = [_vp]
     L.svt_destroy.restype = None
     for name in ["svt_init", "r4svd_step", "svt_iterate", "svt_history", "svt_factors", "svt_sample", "svt_mae",
-                 "svt_mae_device", "svt_get_state",
+                 "svt_mae_device", "svt_checkpoint", "svt_restore", "svt_get_state",
                  "svt_set_state", "svt_set_replay", "svt_grad", "svt_profile", "svt_profile_phases",
                  "svt_profile_read", "svt_time_phase"]:
         getattr(L, name).restype = C.c_int

@@ -90,13 +90,21 @@ __device__ inline double jg_wave_max(double v) {
   return v;
 }
 
-// Pad an odd order with a zero row and column (identity row of Vt), set Vt = I when asked, and
-// write the rotation inputs of round 0.  One thread per slot for the inputs; rows/columns by a
-// grid-stride loop.
+// Replace A by its symmetric part, pad an odd order with a zero row and column (identity row of
+// Vt) and set Vt = I when asked; grid-stride loops.
 __global__ void k_jg_init(double* __restrict__ A, int lda, int n, int nn, double* __restrict__ Vt, int ldv,
                           int vt_identity, double* __restrict__ pin) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // symmetric part (a product like U^T G U is symmetric only up to rounding): each pair i < j once
+  for (int64_t e = tid; e < (int64_t)n * n; e += stride) {
+    const int64_t i = e / n, j = e - (e / n) * n;
+    if (i < j) {
+      const double v = 0.5 * (A[i * lda + j] + A[j * lda + i]);
+      A[i * lda + j] = v;
+      A[j * lda + i] = v;
+    }
+  }
   if (nn != n) {
     for (int64_t i = tid; i < nn; i += stride) {
       A[(int64_t)n * lda + i] = 0.0;

@@ -10,6 +10,7 @@
 // double for SVT_FP64, float for SVT_MIXED.  Gram matrices, the eigensolver and reductions are
 // double in both forms.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -59,6 +60,8 @@ constexpr int kEigMaxProducts = 240;  // cap on products with G per SVT iteratio
 constexpr int kEigMaxPred = 32;       // cap on the predicted number of products before a Rayleigh-Ritz test
 constexpr double kEigDepTol = 1e-12;  // eigen-block CholeskyQR drops only numerically dependent columns
 constexpr int kDirect = 32;           // basis widths up to this are diagonalised directly
+constexpr int kDivergeRun = 5;        // iterations in a row with the residual above 10x its minimum
+constexpr double kInitWaitSeconds = 600.0;  // host wait limit inside svt_init (before the caller's applies)
 
 // scalar slots of the device readback buffer
 enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_SWEEPS = 6, S_NORMY = 7, S_A = 8, S_B = 9, S_TBAR = 10,
@@ -131,6 +134,13 @@ struct PhaseTimer {
   }
 };
 
+// Algorithmic work of launches inside a multi-kernel phase (counted while the phase is recorded).
+void add_work(Handle* h, int ph, double bytes, double flops) {
+  if (!((h->prof_mask >> ph) & 1u)) return;
+  h->ph_bytes[ph] += bytes;
+  h->ph_flops[ph] += flops;
+}
+
 // Event pairs wait unresolved until svt_profile_read (or until kMaxPending have piled up), so the
 // host does no event queries inside the iteration's synchronisation points.
 constexpr size_t kMaxPending = 4096;
@@ -146,6 +156,27 @@ void resolve_pending(Handle* h) {
   h->pending.clear();
 }
 
+// Spin until an event recorded earlier on the handle's stream has completed, for at most
+// p.wait_timeout_s seconds: a kernel that never finishes turns into SVT_E_HIP instead of a host
+// thread spinning forever (the handle is then marked lost; svt_destroy neither waits for its
+// stream nor frees its device memory).
+svt_status wait_event(Handle* h, hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t it = 0;; ++it) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) return SVT_OK;
+    if (e != hipErrorNotReady) HIPCHK(e);
+    if ((it & 1023u) == 0u) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      const double limit = h->ready ? h->p.wait_timeout_s : kInitWaitSeconds;
+      if (el > limit) {
+        h->lost = true;
+        return fail(h, SVT_E_HIP, "timed out after " + std::to_string(limit) + " s waiting for the device");
+      }
+    }
+  }
+}
+
 // Wait for the handle's stream at a host decision point.  The iteration waits for a handful of
 // scalars several times per step; a blocking wait would put the thread to sleep and add the
 // wake-up latency to every one of them, so the host spins on a timing-free event instead.
@@ -155,20 +186,7 @@ svt_status wait_stream(Handle* h) {
     return SVT_OK;
   }
   HIPCHK(hipEventRecord(h->sync_ev, h->stream));
-  for (;;) {
-    const hipError_t e = hipEventQuery(h->sync_ev);
-    if (e == hipSuccess) return SVT_OK;
-    if (e != hipErrorNotReady) HIPCHK(e);
-  }
-}
-
-// Spin until an event recorded earlier on the handle's stream has completed.
-svt_status wait_event(Handle* h, hipEvent_t ev) {
-  for (;;) {
-    const hipError_t e = hipEventQuery(ev);
-    if (e == hipSuccess) return SVT_OK;
-    if (e != hipErrorNotReady) HIPCHK(e);
-  }
+  return wait_event(h, h->sync_ev);
 }
 
 svt_status readback(Handle* h, int count) {
@@ -189,7 +207,7 @@ svt_status to_host(Handle* h, T* dst, const T* src, size_t count) {
     std::memcpy(dst, h->hstage, bytes);
   } else {
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    CHK(wait_stream(h));
   }
   if (h->pending.size() >= kMaxPending) resolve_pending(h);
   return SVT_OK;
@@ -319,6 +337,10 @@ struct Engine {
   // product that wrote In left them (k_rowmul's epilogue), else nullptr.
   svt_status eig_cholqr(int rows, const double* In, double* Tmp, double* Out, int ld, int wc, bool twice,
                         const double* gram, int splits) {
+    if (wc > kCholTrsmMaxCols) {
+      if (In != Out) HIPCHK((launch_copy_cols<double, double>(h->stream, rows, In, ld, Out, ld, wc)));
+      return wide_orth(rows, Out, Tmp, ld, wc);
+    }
     if (!fused_cholqr(rows, wc)) {
       if (!twice) return chol_orth(rows, In, Out, ld, wc);
       CHK(chol_orth(rows, In, Tmp, ld, wc));
@@ -337,6 +359,23 @@ struct Engine {
       if (!ep) CHK(pass_gram<double>(rows, Tmp, ld, wc, &gg, &s2));
       HIPCHK(launch_chol_trsm<double>(s, rows, Tmp, ld, wc, gg, s2, ss, nullptr, 0.0, kEigDepTol, -1, Out, ld, nullptr,
                                       h->scal, S_WK2));
+    }
+    return SVT_OK;
+  }
+
+  // Orthonormalisation of an eigensolver block wider than one CholeskyQR launch holds, in place:
+  // 64-column chunks, each projected twice against the chunks before it and then put through
+  // CholeskyQR2 (the span of every leading set of columns is kept, as a QR would keep it).
+  svt_status wide_orth(int rows, double* V, double* Tmp, int ld, int b) {
+    hipStream_t s = h->stream;
+    for (int c0 = 0; c0 < b; c0 += 64) {
+      const int wc = std::min(64, b - c0);
+      for (int pass = 0; c0 > 0 && pass < 2; ++pass) {
+        HIPCHK((launch_tn_narrow<double, double>(s, rows, V, ld, c0, V + c0, ld, wc, h->T, h->w_cap, h->partial,
+                                                 h->partial_cap)));
+        HIPCHK((launch_rowmul<double, double, double>(s, rows, c0, V, ld, h->T, h->w_cap, V + c0, ld, wc, -1.0, 1.0)));
+      }
+      CHK(eig_cholqr(rows, V + c0, Tmp + c0, V + c0, ld, wc, true, nullptr, 0));
     }
     return SVT_OK;
   }
@@ -389,6 +428,13 @@ struct Engine {
       const int wc = std::min(64, w - c0);
       const int rq = h->r + *got;
       {
+        // algorithmic work of the chunk: X = Y Omega, two projections against the rq columns, two
+        // CholeskyQR passes, the copy into Q, W' = Y^T Q' and its squared norm (operands once each)
+        const double nz = (double)h->nnz, dm = m, dn = n, w_ = wc, rr = rq;
+        add_work(h, SVT_PH_GROW,
+                 es * (dn * w_ + dm * w_) + nz * (es + 4.0) + 2.0 * es * (2.0 * dm * rr + 3.0 * dm * w_) +
+                     4.0 * es * dm * w_ + 2.0 * es * dm * w_ + nz * (es + 4.0) + es * (dm + 2.0 * dn) * w_,
+                 4.0 * nz * w_ + 8.0 * dm * rr * w_ + 4.0 * dm * w_ * w_);
         PhaseTimer tm(h, SVT_PH_GROW);
         HIPCHK(launch_omega<T>(s, Om(), n, c0, wc, ld, h->p.seed, (uint64_t)blk, (uint64_t)it));
         CHK(spmm_y(Om(), ld, X(), ld, wc));
@@ -636,6 +682,11 @@ struct Engine {
     bool inexact = false;
     CHK(jacobi_full(h, full_work(), r, h->Fval, r0 > 0 ? h->FM : h->FEt, ld, r0 > 0 ? nullptr : h->FEU, ld, &sweeps,
                     &inexact));
+    // warm-start transforms (two r^3 products and one after), and per sweep r - 1 rounds that rotate
+    // every row pair of the matrix and of the rotations (about 6 r^2 flops and 32 r^2 bytes each)
+    const double rr = r;
+    add_work(h, SVT_PH_EIG, (r0 > 0 ? 3.0 * 24.0 * rr * rr : 0.0) + sweeps * (rr - 1.0) * 32.0 * rr * rr,
+             (r0 > 0 ? 6.0 * rr * rr * rr : 0.0) + sweeps * (rr - 1.0) * 6.0 * rr * rr);
     if (r0 > 0) {
       // eigenvectors of G: (rotations of the warm basis, sorted) times the warm basis
       HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->FM, ld, h->FEt, ld, h->JA, ld));
@@ -659,9 +710,9 @@ struct Engine {
       PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
       CHK(run_gram());
     }
-    std::vector<double> theta(std::max(2 * kEigMax, r)), res(kEigMax);
+    std::vector<double> theta(std::max(2 * kEB, r)), res(kEB);
     const double* S = nullptr;       // eigenvectors of G as columns (descending)
-    int lds_ = kEigMax;              // their row stride
+    int lds_ = kEB;              // their row stride
     const double* dtheta = h->Eval;  // the eigenvalues on the device
     int k = 0;
     st->eig_iters = 0;
@@ -669,13 +720,14 @@ struct Engine {
     if (r <= kDirect) {
       {
         PhaseTimer tm(h, SVT_PH_EIG);
-        HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS));
+        HIPCHK(launch_jacobi(s, h->G, h->r_cap, r, h->Eval, h->ES, kEB, h->scal, S_SWEEPS));
+        add_work(h, SVT_PH_EIG, 16.0 * r * r, 10.0 * (double)r * r * r);  // a few sweeps of the r x r Jacobi
       }
       CHK(to_host<double>(h, theta.data(), h->Eval, r));
       while (k < r && theta[k] > tau2) ++k;
       S = h->ES;
       // keep the eigenvectors as the warm start of the block solver
-      HIPCHK((launch_copy_cols<double, double>(s, r, h->ES, kEigMax, h->EV, kEigMax, r)));
+      HIPCHK((launch_copy_cols<double, double>(s, r, h->ES, kEB, h->EV, kEB, r)));
       h->ev_valid = r;
       h->ev_rows = r;
       st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
@@ -693,12 +745,12 @@ struct Engine {
         PhaseTimer tm(h, SVT_PH_EIG);
         if (valid > 0 && h->ev_rows < r) {
           // new basis columns were appended: zero the new rows of the kept vectors
-          HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEigMax, kEigMax * sizeof(double), 0,
+          HIPCHK(hipMemset2DAsync(h->EV + (size_t)h->ev_rows * kEB, kEB * sizeof(double), 0,
                                   valid * sizeof(double), r - h->ev_rows, s));
         }
         // the Ritz columns are orthonormal and the Gaussian ones well conditioned: the CholeskyQR
         // after the first products orthonormalises the block
-        HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+        HIPCHK(launch_fill_random(s, h->EV, r, kEB, valid, b, h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
       }
       // truncated recycling keeps the k + e leading Ritz vectors, which then must converge too
       const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
@@ -728,7 +780,7 @@ struct Engine {
               z = h->EZ3;
               have_gv = false;
               if (step == 2) {
-                HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEigMax, h->EZ, kEigMax, b,
+                HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEB, h->EZ, kEB, b,
                                                               1.0, 0.0, zg)));
                 z = h->EZ;
                 have_zg = zg != nullptr;
@@ -737,43 +789,62 @@ struct Engine {
               if (!have_g2) {
                 // G^2 on the LDS-tiled matrix-core product (an r x r x r contraction)
                 HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap));
+                add_work(h, SVT_PH_EIG, 24.0 * r * r, 2.0 * (double)r * r * r);
                 have_g2 = true;
               }
-              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G2, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
+              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G2, h->r_cap, h->EV, kEB, h->EZ, kEB, b,
                                                             1.0, 0.0, zg)));
               z = h->EZ;
               have_zg = zg != nullptr;
             } else {
-              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ3, kEigMax, b,
+              HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEB, h->EZ3, kEB, b,
                                                             1.0, 0.0, zg)));
               z = h->EZ3;
               have_zg = zg != nullptr;
             }
-            CHK(eig_cholqr(r, z, h->EZ2, h->EV, kEigMax, b, last, have_zg ? zg : nullptr, zgs));
+            CHK(eig_cholqr(r, z, h->EZ2, h->EV, kEB, b, last, have_zg ? zg : nullptr, zgs));
+            // one product with G or G^2 (r x r times r x b) and one or two CholeskyQR passes
+            add_work(h, SVT_PH_EIG, 8.0 * ((double)r * r + 2.0 * r * b) + (last ? 32.0 : 16.0) * r * b,
+                     2.0 * r * r * b + (last ? 6.0 : 3.0) * r * b * b);
             powers += step;
           }
           // Rayleigh-Ritz: H = V^T G V = S Theta S^T; V <- V S; G V <- (G V) S; residual norms
-          HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEigMax, h->EZ, kEigMax, b,
+          HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, h->EV, kEB, h->EZ, kEB, b,
                                                         1.0, 0.0)));
-          int sp = 0;
-          HIPCHK((launch_tn_partial<double, double>(s, r, h->EV, kEigMax, b, h->EZ, kEigMax, b, h->partial,
-                                                    h->partial_cap, &sp)));
-          HIPCHK(launch_jacobi(s, h->partial, b, b, h->Eval, h->ES, kEigMax, h->scal, S_SWEEPS, 40, sp,
-                               (int64_t)b * b));
+          if (b <= kEigMax) {
+            int sp = 0;
+            HIPCHK((launch_tn_partial<double, double>(s, r, h->EV, kEB, b, h->EZ, kEB, b, h->partial,
+                                                      h->partial_cap, &sp)));
+            HIPCHK(launch_jacobi(s, h->partial, b, b, h->Eval, h->ES, kEB, h->scal, S_SWEEPS, 40, sp,
+                                 (int64_t)b * b));
+          } else {
+            // a block wider than the one-workgroup Jacobi: the b x b Rayleigh quotient on the
+            // many-workgroup one
+            CHK(ensure_full_work());
+            HIPCHK((launch_tn_narrow<double, double>(s, r, h->EV, kEB, b, h->EZ, kEB, b, h->JA, h->r_cap,
+                                                     h->partial, h->partial_cap)));
+            int sw = 0;
+            bool inexact = false;
+            CHK(jacobi_full(h, full_work(), b, h->Eval, nullptr, 0, h->ES, kEB, &sw, &inexact));
+            if (inexact) st->flags |= SVT_F_EIG_INEXACT;
+          }
           {  // V S and (G V) S in one launch
-            const RowmulProblem<double, double, double> pa{r, b, h->EV, kEigMax, h->ES, kEigMax, h->EZ2, kEigMax, b,
+            const RowmulProblem<double, double, double> pa{r, b, h->EV, kEB, h->ES, kEB, h->EZ2, kEB, b,
                                                           1.0, 0.0, nullptr};
-            const RowmulProblem<double, double, double> pb{r, b, h->EZ, kEigMax, h->ES, kEigMax, h->EZ3, kEigMax, b,
+            const RowmulProblem<double, double, double> pb{r, b, h->EZ, kEB, h->ES, kEB, h->EZ3, kEB, b,
                                                           1.0, 0.0, nullptr};
             HIPCHK((launch_rowmul_pair<double, double, double>(s, pa, pb)));
           }
           std::swap(h->EV, h->EZ2);
-          HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEigMax, b, h->Eval, h->partial, h->Eval + kEigMax));
+          HIPCHK(launch_ritz_residual(s, r, h->EZ3, h->EV, kEB, b, h->Eval, h->partial, h->Eval + kEB));
+          // Rayleigh-Ritz: G V, V^T (G V), the b x b Jacobi (about 10 b^3), the two rotations, residuals
+          add_work(h, SVT_PH_EIG, 8.0 * ((double)r * r + 8.0 * r * b + 3.0 * b * b),
+                   2.0 * r * r * b + 2.0 * r * b * b + 10.0 * b * b * b + 4.0 * r * b * b + 3.0 * r * b);
           have_gv = true;
         }
         ++tests;
-        CHK(to_host<double>(h, theta.data(), h->Eval, 2 * kEigMax));
-        for (int c = 0; c < b; ++c) res[c] = theta[kEigMax + c];
+        CHK(to_host<double>(h, theta.data(), h->Eval, 2 * kEB));
+        for (int c = 0; c < b; ++c) res[c] = theta[kEB + c];
         k = 0;
         while (k < b && theta[k] > tau2) ++k;
         const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
@@ -789,9 +860,12 @@ struct Engine {
           // width the current count asks for (2 nconv + 8) at once, at least 16 more columns
           const int nb = std::min(std::min(h->b_cap, r), std::max(b + 16, 2 * nconv + 8));
           PhaseTimer tm(h, SVT_PH_EIG);
-          HIPCHK(launch_fill_random(s, h->EV, r, kEigMax, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
+          HIPCHK(launch_fill_random(s, h->EV, r, kEB, b, nb, h->p.seed ^ 0xA5A5A5A5ull, (uint64_t)tests));
           b = nb;
-          CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEigMax, b, nullptr));
+          if (b <= kCholTrsmMaxCols)
+            CHK(orthonormalize_block<double>(r, h->EV, h->EZ2, kEB, b, nullptr));
+          else
+            CHK(wide_orth(r, h->EV, h->EZ2, kEB, b));
           have_gv = false;
           prev_k = -1;
           target = powers + 2;
@@ -856,10 +930,10 @@ struct Engine {
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
       const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
       const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
-      if (2 * std::max(nconv, 4) + 8 <= 64) {
+      if (2 * std::max(nconv, 4) + 8 <= h->b_cap / 2) {
         // the count is small again: the block solver takes over from the leading eigenvectors
-        const int b = std::min(kEigMax, r);
-        HIPCHK((launch_copy_cols<double, double>(h->stream, r, h->FEU, h->r_cap, h->EV, kEigMax, b)));
+        const int b = std::min(kEB, r);
+        HIPCHK((launch_copy_cols<double, double>(h->stream, r, h->FEU, h->r_cap, h->EV, kEB, b)));
         h->ev_valid = b;
         h->ev_rows = r;
         h->full_mode = false;
@@ -909,7 +983,7 @@ struct Engine {
     h->hist_ok = false;
     // the Ritz vectors of this iteration: the block solver's, or every eigenvector of G in full mode
     const double* S = h->full_mode ? h->FEU : h->EV;
-    const int lds_ = h->full_mode ? h->r_cap : kEigMax;
+    const int lds_ = h->full_mode ? h->r_cap : kEB;
     if (keep > 0) {
       HIPCHK((launch_rowmul<T, double, T>(s, (int)h->m, r, Q(), h->r_cap, S, lds_, Utmp(), h->ldf, keep, 1.0, 0.0)));
       HIPCHK((launch_copy_cols<T, T>(s, (int)h->m, Utmp(), h->ldf, Q(), h->r_cap, keep)));
@@ -918,7 +992,7 @@ struct Engine {
         HIPCHK(launch_set_unit(s, h->FEt, keep, h->r_cap, 0, keep, 0));
         HIPCHK(launch_set_unit(s, h->FEU, keep, h->r_cap, 0, keep, 0));
       } else {
-        HIPCHK(launch_set_unit(s, h->EV, keep, kEigMax, 0, keep, 0));
+        HIPCHK(launch_set_unit(s, h->EV, keep, kEB, 0, keep, 0));
       }
       if (h->k > 0) HIPCHK(launch_set_unit(s, h->Sk, keep, h->ldf, 0, h->k, 0));
     }
@@ -1007,6 +1081,9 @@ struct Engine {
     const double target = h->eps_min * (1.0 - h->p.eta);
     st->anneal_margin =
         std::isfinite(h->eps_min) ? (rel - target) / h->eps_min : -std::numeric_limits<double>::infinity();
+    // divergence: the residual more than 10 times its smallest value so far for 5 iterations in a row
+    h->div_run = (std::isfinite(h->eps_min) && rel > 10.0 * h->eps_min) ? h->div_run + 1 : 0;
+    if (h->div_run >= kDivergeRun) st->flags |= SVT_F_DIVERGING;
     const bool annealed = (ra >= 0) ? (ra != 0) : !(rel < target);
     if (annealed) {
       h->eps_thr *= h->p.beta;
@@ -1087,7 +1164,7 @@ struct Engine {
     std::vector<T> buf(h->nnz);
     for (int64_t u = 0; u < h->nnz; ++u) buf[h->user2csc[u]] = (T)src_user[u];
     HIPCHK(hipMemcpyAsync(dst, buf.data(), h->nnz * sizeof(T), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    CHK(wait_stream(h));
     return SVT_OK;
   }
 
@@ -1103,7 +1180,7 @@ struct Engine {
     for (size_t i = 0; i < buf.size(); ++i) buf[i] = (T)Qh[i];
     HIPCHK(hipMemcpy2DAsync(Q(), h->r_cap * sizeof(T), buf.data(), r * sizeof(T), r * sizeof(T), h->m,
                             hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    CHK(wait_stream(h));
     return SVT_OK;
   }
 
@@ -1111,9 +1188,47 @@ struct Engine {
     std::vector<T> buf((size_t)h->m * h->r);
     HIPCHK(hipMemcpy2DAsync(buf.data(), h->r * sizeof(T), Q(), h->r_cap * sizeof(T), h->r * sizeof(T), h->m,
                             hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    CHK(wait_stream(h));
     for (int64_t i = 0; i < h->m; ++i)
       for (int c = 0; c < h->r; ++c) Qh[i * qcap + c] = (double)buf[(size_t)i * h->r + c];
+    return SVT_OK;
+  }
+
+  // ---- checkpoint: the device arrays the next iterations read, in a host blob ----------------
+  // y (nnz), Q[:, 0:r] (m x r), EV (ev_rows x kEB), FEt (fe_rows x fe_rows), Ut (m x k),
+  // Vt (n x k), Sk (r x k); rows copied without their padding
+  template <class U_>
+  svt_status copy_rows(bool save, std::vector<char>& blob, size_t& pos, U_* dev, int64_t rows, int64_t cols,
+                       int64_t ld) {
+    const size_t bytes = (size_t)(rows * cols) * sizeof(U_);
+    if (rows <= 0 || cols <= 0) return SVT_OK;
+    if (save) {
+      blob.resize(pos + bytes);
+      HIPCHK(hipMemcpy2DAsync(blob.data() + pos, cols * sizeof(U_), dev, ld * sizeof(U_), cols * sizeof(U_), rows,
+                              hipMemcpyDeviceToHost, h->stream));
+    } else {
+      if (pos + bytes > blob.size()) return fail(h, SVT_E_INVALID_ARG, "checkpoint is truncated");
+      HIPCHK(hipMemcpy2DAsync(dev, ld * sizeof(U_), blob.data() + pos, cols * sizeof(U_), cols * sizeof(U_), rows,
+                              hipMemcpyHostToDevice, h->stream));
+    }
+    pos += bytes;
+    return SVT_OK;
+  }
+  svt_status device_state(bool save, std::vector<char>& blob, size_t& pos) {
+    CHK(copy_rows<T>(save, blob, pos, y(), 1, h->nnz, h->nnz));
+    CHK(copy_rows<T>(save, blob, pos, Q(), h->m, h->r, h->r_cap));
+    CHK(copy_rows<double>(save, blob, pos, h->EV, h->ev_rows, kEB, kEB));
+    if (h->fe_rows > 0) {
+      if (!save) CHK(ensure_full_work());
+      CHK(copy_rows<double>(save, blob, pos, h->FEt, h->fe_rows, h->fe_rows, h->r_cap));
+      if (!save) HIPCHK(launch_transpose(h->stream, h->FEt, h->r_cap, h->fe_rows, h->fe_rows, h->FEU, h->r_cap));
+    }
+    if (h->have_factors && h->k > 0) {
+      CHK(copy_rows<T>(save, blob, pos, Ut(), h->m, h->k, h->ldf));
+      CHK(copy_rows<T>(save, blob, pos, Vt(), h->n, h->k, h->ldf));
+      CHK(copy_rows<double>(save, blob, pos, h->Sk, h->r, h->k, h->ldf));
+    }
+    CHK(wait_stream(h));
     return SVT_OK;
   }
 
@@ -1508,6 +1623,8 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
 }
 
 void release(Handle* h) {
+  // a handle whose device work timed out may still have kernels running on its buffers: leave them
+  if (h->lost) return;
   // work may still be queued on the stream (svt_iterate returns with the next step's leading
   // kernels and their copy into pinned memory enqueued): let it finish before anything is freed
   (void)hipStreamSynchronize(h->stream);
@@ -1538,6 +1655,57 @@ void release(Handle* h) {
 // ==============================================================================================
 // C-ABI
 // ==============================================================================================
+namespace {
+constexpr char kCkptMagic[8] = {'S', 'V', 'T', 'C', 'K', 'P', 'T', '1'};
+
+template <class U_>
+void put(std::vector<char>& b, const U_& v) {
+  const char* p = reinterpret_cast<const char*>(&v);
+  b.insert(b.end(), p, p + sizeof(U_));
+}
+template <class U_>
+void put_vec(std::vector<char>& b, const std::vector<U_>& v) {
+  put<int64_t>(b, (int64_t)v.size());
+  const char* p = reinterpret_cast<const char*>(v.data());
+  b.insert(b.end(), p, p + v.size() * sizeof(U_));
+}
+template <class U_>
+bool get(const std::vector<char>& b, size_t& pos, U_* v) {
+  if (pos + sizeof(U_) > b.size()) return false;
+  std::memcpy(v, b.data() + pos, sizeof(U_));
+  pos += sizeof(U_);
+  return true;
+}
+template <class U_>
+bool get_vec(const std::vector<char>& b, size_t& pos, std::vector<U_>* v) {
+  int64_t n = 0;
+  if (!get(b, pos, &n) || n < 0 || pos + (size_t)n * sizeof(U_) > b.size()) return false;
+  v->resize((size_t)n);
+  if (n > 0) std::memcpy(v->data(), b.data() + pos, (size_t)n * sizeof(U_));
+  pos += (size_t)n * sizeof(U_);
+  return true;
+}
+
+// The host part of a checkpoint: problem identity, iteration scalars, decision log.
+void put_host_state(std::vector<char>& b, const Handle* h) {
+  b.insert(b.end(), kCkptMagic, kCkptMagic + 8);
+  for (int64_t v : {h->m, h->n, h->nnz}) put(b, v);
+  for (int32_t v : {h->p.precision, h->r_cap, h->ldf, h->r, h->iter, h->k, h->div_run, h->ev_valid, h->ev_rows,
+                    h->eig_pred, h->eig_pass_streak, h->fe_rows})
+    put(b, v);
+  for (double v : {h->eps_thr, h->eps_min, h->normY}) put(b, v);
+  for (bool v : {h->eps_thr_set, h->converged, h->have_factors, h->full_mode, h->hist_ok, h->exact_ok})
+    put<uint8_t>(b, v ? 1 : 0);
+  put<int64_t>(b, (int64_t)h->replay_pos);
+  put_vec(b, h->history);
+  put_vec(b, h->hist_r);
+  put_vec(b, h->hist_chunks);
+  put_vec(b, h->sigma_k);
+  put_vec(b, h->replay_blocks);
+  put_vec(b, h->replay_anneal);
+}
+}  // namespace
+
 extern "C" {
 
 void svt_default_params(svt_params* p) {
@@ -1561,6 +1729,7 @@ void svt_default_params(svt_params* p) {
   p->rank = 0;
   p->oversample = 10;
   p->mae_tol = 0.0;
+  p->wait_timeout_s = 0.0;
 }
 
 const char* svt_last_error(const svt_handle* h) { return h ? h->err.c_str() : g_init_err.c_str(); }
@@ -1600,6 +1769,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.mode == SVT_MODE_RSVD && p.rank <= 0) return bad("the RSVD mode needs rank > 0");
   if (p.mode == SVT_MODE_RSVD && p.oversample < 0) return bad("oversample must be non-negative");
   if (std::isnan(p.mae_tol)) return bad("mae_tol is NaN");
+  if (std::isnan(p.wait_timeout_s)) return bad("wait_timeout_s is NaN");
+  if (p.wait_timeout_s <= 0.0) p.wait_timeout_s = 600.0;
   const int64_t mn = std::min(m, n);
   if (p.t0 <= 0) p.t0 = (int32_t)std::max<int64_t>(1, (int64_t)std::floor(0.05 * (double)mn));
   if (p.mode == SVT_MODE_RSVD) p.t0 = (int32_t)std::min<int64_t>((int64_t)p.rank + p.oversample, 1 << 30);
@@ -1697,7 +1868,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
 
   h->r_cap = ((p.r_max + 64 + 7) / 8) * 8;
   h->w_cap = 64;
-  h->b_cap = kEigMax;
+  h->b_cap = kEB;
   h->ldf = std::max(kEigMax, ((p.kmax + 7) / 8) * 8);
   h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
   h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
@@ -1731,13 +1902,13 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->small, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->Minv, (size_t)kEigMax * kEigMax));
   A(dalloc(&h->prenorm, kEigMax));
-  A(dalloc(&h->EV, std::max<size_t>((size_t)h->r_cap * kEigMax, mx)));
-  A(dalloc(&h->EZ, (size_t)h->r_cap * kEigMax));
-  A(dalloc(&h->EZ2, std::max<size_t>((size_t)h->r_cap * kEigMax, mx)));
-  A(dalloc(&h->EZ3, (size_t)h->r_cap * kEigMax));
-  A(dalloc(&h->EH, (size_t)kEigMax * kEigMax));
-  A(dalloc(&h->ES, (size_t)kEigMax * kEigMax));
-  A(dalloc(&h->Eval, 2 * kEigMax));
+  A(dalloc(&h->EV, std::max<size_t>((size_t)h->r_cap * kEB, mx)));
+  A(dalloc(&h->EZ, (size_t)h->r_cap * kEB));
+  A(dalloc(&h->EZ2, std::max<size_t>((size_t)h->r_cap * kEB, mx)));
+  A(dalloc(&h->EZ3, (size_t)h->r_cap * kEB));
+  A(dalloc(&h->EH, (size_t)kEB * kEB));
+  A(dalloc(&h->ES, (size_t)kEB * kEB));
+  A(dalloc(&h->Eval, 2 * kEB));
   A(dalloc(&h->C, (size_t)h->r_cap * h->ldf));
   A(dalloc(&h->D, (size_t)h->r_cap * h->ldf));
   A(dalloc(&h->Sk, (size_t)h->r_cap * h->ldf));
@@ -1823,6 +1994,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   }
   h->r = 0;
   h->iter = 0;
+  h->ready = true;
   h->exact_ok = (h->p.npow == 0);
   h->eps_thr_set = false;
   h->eps_min = std::numeric_limits<double>::infinity();
@@ -1832,6 +2004,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
 
 svt_status r4svd_step(svt_handle* h, svt_step_stats* st) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   svt_step_stats local;
   if (!st) st = &local;
   return dispatch(h, [&](auto& eng) { return eng.operator_only(st); });
@@ -1839,6 +2012,7 @@ svt_status r4svd_step(svt_handle* h, svt_step_stats* st) {
 
 svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (max_steps < 0) return fail(h, SVT_E_INVALID_ARG, "max_steps must be non-negative");
   if (h->converged) return fail(h, SVT_E_STATE, "the iteration has already converged");
   svt_step_stats st;
@@ -1872,6 +2046,7 @@ svt_status svt_history(const svt_handle* h, int64_t first, int64_t count, svt_st
 
 svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   if (k) *k = h->k;
   const int kk = std::min<int>(std::max(kcap, 0), h->k);
@@ -1883,6 +2058,7 @@ svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, doubl
 
 svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (nq < 0 || (nq > 0 && (!qi || !qj || !x_out))) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   for (int64_t l = 0; l < nq; ++l)
@@ -1909,6 +2085,7 @@ svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_
 
 svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref, double* mae) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (nq <= 0 || !qi || !qj || !ref || !mae) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   for (int64_t l = 0; l < nq; ++l) {
@@ -1938,6 +2115,7 @@ svt_status svt_mae(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* 
 svt_status svt_mae_device(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, const double* ref,
                           double* mae) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (nq <= 0 || nq > INT32_MAX || !qi || !qj || !ref || !mae)
     return fail(h, SVT_E_INVALID_ARG, "svt_mae_device: nq must lie in [1, 2^31 - 1] and every pointer be non-NULL");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
@@ -1952,6 +2130,7 @@ svt_status svt_mae_device(svt_handle* h, int64_t nq, const int32_t* qi, const in
 svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int32_t* r, double* eps_thr,
                          double* eps_min, int32_t* iter) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (Q && h->r > 0 && qcap < h->r) return fail(h, SVT_E_INVALID_ARG, "qcap smaller than r");
   svt_status st = dispatch(h, [&](auto& eng) -> svt_status {
     using TT = std::remove_pointer_t<decltype(eng.a())>;
@@ -1970,6 +2149,7 @@ svt_status svt_get_state(svt_handle* h, double* y, double* Q, int32_t qcap, int3
 svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_t r, double eps_thr,
                          double eps_min, int32_t iter) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (!y) return fail(h, SVT_E_INVALID_ARG, "y is NULL");
   if (r < 0 || r > h->p.r_max || (r > 0 && !Q)) return fail(h, SVT_E_INVALID_ARG, "bad basis width");
   if (iter < 0) return fail(h, SVT_E_INVALID_ARG, "iter must be non-negative");
@@ -1993,6 +2173,7 @@ svt_status svt_set_state(svt_handle* h, const double* y, const double* Q, int32_
   h->full_mode = false;
   h->fe_rows = 0;
   h->k = 0;
+  h->div_run = 0;
   h->hist_ok = false;
   h->hist_r.clear();
   h->hist_chunks.clear();
@@ -2005,6 +2186,87 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
   h->replay_blocks.assign(blocks, blocks + len);
   h->replay_anneal.assign(annealed, annealed + len);
   h->replay_pos = 0;
+  return SVT_OK;
+}
+
+
+svt_status svt_checkpoint(svt_handle* h, void* buf, int64_t cap, int64_t* size) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
+  if (!size) return fail(h, SVT_E_INVALID_ARG, "size is NULL");
+  std::vector<char> blob;
+  put_host_state(blob, h);
+  size_t pos = blob.size();
+  CHK(dispatch(h, [&](auto& eng) { return eng.device_state(true, blob, pos); }));
+  *size = (int64_t)blob.size();
+  if (!buf) return SVT_OK;
+  if (cap < (int64_t)blob.size()) return fail(h, SVT_E_INVALID_ARG, "buffer smaller than the checkpoint");
+  std::memcpy(buf, blob.data(), blob.size());
+  return SVT_OK;
+}
+
+svt_status svt_restore(svt_handle* h, const void* buf, int64_t size) {
+  if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
+  if (!buf || size < 8) return fail(h, SVT_E_INVALID_ARG, "no checkpoint given");
+  std::vector<char> b((const char*)buf, (const char*)buf + size);
+  if (std::memcmp(b.data(), kCkptMagic, 8) != 0) return fail(h, SVT_E_INVALID_ARG, "not an svt checkpoint");
+  size_t pos = 8;
+  int64_t mm = 0, nn = 0, zz = 0;
+  int32_t prec = 0, rcap = 0, ldf = 0;
+  bool ok = get(b, pos, &mm) && get(b, pos, &nn) && get(b, pos, &zz) && get(b, pos, &prec) && get(b, pos, &rcap) &&
+            get(b, pos, &ldf);
+  if (!ok || mm != h->m || nn != h->n || zz != h->nnz || prec != h->p.precision || rcap != h->r_cap || ldf != h->ldf)
+    return fail(h, SVT_E_INVALID_ARG, "the checkpoint belongs to another problem, precision form or r_max / kmax");
+  Handle t;  // parse into a scratch copy first so that a bad blob leaves the handle unchanged
+  int64_t rp = 0;
+  uint8_t f[6] = {};
+  ok = get(b, pos, &t.r) && get(b, pos, &t.iter) && get(b, pos, &t.k) && get(b, pos, &t.div_run) &&
+       get(b, pos, &t.ev_valid) && get(b, pos, &t.ev_rows) && get(b, pos, &t.eig_pred) &&
+       get(b, pos, &t.eig_pass_streak) && get(b, pos, &t.fe_rows) && get(b, pos, &t.eps_thr) &&
+       get(b, pos, &t.eps_min) && get(b, pos, &t.normY);
+  for (int q = 0; ok && q < 6; ++q) ok = get(b, pos, &f[q]);
+  ok = ok && get(b, pos, &rp) && get_vec(b, pos, &t.history) && get_vec(b, pos, &t.hist_r) &&
+       get_vec(b, pos, &t.hist_chunks) && get_vec(b, pos, &t.sigma_k) && get_vec(b, pos, &t.replay_blocks) &&
+       get_vec(b, pos, &t.replay_anneal);
+  if (!ok || t.r < 0 || t.r > h->p.r_max || t.k < 0 || t.k > h->ldf || t.ev_rows < 0 || t.ev_rows > h->r_cap ||
+      t.ev_valid < 0 || t.ev_valid > kEB || t.fe_rows < 0 || t.fe_rows > h->r_cap || rp < 0 ||
+      (size_t)rp > t.replay_blocks.size() || t.replay_anneal.size() != t.replay_blocks.size())
+    return fail(h, SVT_E_INVALID_ARG, "malformed checkpoint");
+  h->spec_ready = false;
+  h->r = t.r;
+  h->iter = t.iter;
+  h->k = t.k;
+  h->div_run = t.div_run;
+  h->ev_valid = t.ev_valid;
+  h->ev_rows = t.ev_rows;
+  h->eig_pred = t.eig_pred;
+  h->eig_pass_streak = t.eig_pass_streak;
+  h->fe_rows = t.fe_rows;
+  h->eps_thr = t.eps_thr;
+  h->eps_min = t.eps_min;
+  h->normY = t.normY;
+  h->eps_thr_set = f[0];
+  h->converged = f[1];
+  h->have_factors = f[2];
+  h->full_mode = f[3];
+  h->hist_ok = f[4];
+  h->exact_ok = f[5];
+  h->replay_pos = (size_t)rp;
+  h->history = std::move(t.history);
+  h->hist_r = std::move(t.hist_r);
+  h->hist_chunks = std::move(t.hist_chunks);
+  h->sigma_k = std::move(t.sigma_k);
+  h->replay_blocks = std::move(t.replay_blocks);
+  h->replay_anneal = std::move(t.replay_anneal);
+  const svt_status st = dispatch(h, [&](auto& eng) { return eng.device_state(false, b, pos); });
+  if (st != SVT_OK) {
+    // the device arrays are partly written: the handle holds no usable state any more
+    h->have_factors = false;
+    h->hist_ok = false;
+    h->converged = true;
+    return st;
+  }
   return SVT_OK;
 }
 
@@ -2031,6 +2293,7 @@ svt_status svt_profile_phases(svt_handle* h, uint32_t mask) {
 
 svt_status svt_time_phase(svt_handle* h, int32_t phase, int32_t reps, double* ms, double* bytes, double* flops) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (phase != SVT_PH_SPMM_T && phase != SVT_PH_GRAM && phase != SVT_PH_SDDMM && phase != SVT_PH_DENSIFY)
     return fail(h, SVT_E_INVALID_ARG, "svt_time_phase times single-kernel phases only");
   if (reps < 1 || !ms) return fail(h, SVT_E_INVALID_ARG, "reps must be positive and ms non-NULL");
@@ -2064,6 +2327,7 @@ svt_status svt_profile_read(svt_handle* h, double* ms, double* bytes, double* fl
 svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const int32_t* hi, const int32_t* hj,
                     const double* gx_h, int32_t flags, double* dtau, double* ddelta, double* da) {
   if (!h) return SVT_E_INVALID_ARG;
+  if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (T <= 0) return fail(h, SVT_E_INVALID_ARG, "T must be positive");
   if (!dtau || !ddelta || !da) return fail(h, SVT_E_INVALID_ARG, "NULL output pointer");
   if (flags & ~SVT_GRAD_FROZEN_BASIS) return fail(h, SVT_E_INVALID_ARG, "unknown svt_grad flags");

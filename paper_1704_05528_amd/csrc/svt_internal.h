@@ -13,6 +13,7 @@ namespace svt {
 
 constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
+constexpr int kEB = 256;      // widest block of the subspace eigen-solver (columns of EV, EZ, ES)
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
 constexpr int kScalars = 64;  // doubles in the device->host readback buffer
 constexpr int kSpecSlot = 48;  // host slot of the next iteration's ||W||^2 (past every readback's range)
@@ -112,8 +113,8 @@ struct Handle {
   double* prenorm = nullptr;  // column norms before projection
 
   // eigensolver (double)
-  double *EV = nullptr, *EZ = nullptr, *EZ2 = nullptr, *EZ3 = nullptr;  // r_cap x kEigMax blocks
-  double *EH = nullptr, *ES = nullptr;                                   // kEigMax x kEigMax
+  double *EV = nullptr, *EZ = nullptr, *EZ2 = nullptr, *EZ3 = nullptr;  // r_cap x kEB blocks
+  double *EH = nullptr, *ES = nullptr;                                   // kEB x kEB
   double* Eval = nullptr;  // eigenvalues (descending) followed by Ritz residual norms
   int32_t ev_valid = 0;    // columns of EV that hold Ritz vectors of the previous iteration
   int32_t ev_rows = 0;     // basis width those vectors refer to
@@ -164,6 +165,9 @@ struct Handle {
   int32_t k0 = 0;
   bool converged = false;
   bool have_factors = false;
+  bool lost = false;      // a wait for the device timed out: its buffers may still be in use
+  bool ready = false;     // svt_init has finished (the caller's wait limit applies from then on)
+  int32_t div_run = 0;    // iterations in a row with the residual above 10 times its minimum
   std::vector<int32_t> replay_blocks, replay_anneal;
   size_t replay_pos = 0;
   // basis width used by every iteration since svt_init (the basis only grows, so the basis of

@@ -146,6 +146,18 @@ class SVT:
             r = Q.shape[1]
         check(load().svt_set_state(self._h, yp, qp, r, float(eps_thr), float(eps_min), int(iter)), self._h)
 
+    def checkpoint(self):
+        """bytes of svt_checkpoint (restart point with the decision log)"""
+        L = load()
+        size = C.c_int64()
+        check(L.svt_checkpoint(self._h, None, 0, C.byref(size)), self._h)
+        buf = C.create_string_buffer(size.value)
+        check(L.svt_checkpoint(self._h, buf, size.value, C.byref(size)), self._h)
+        return buf.raw[: size.value]
+
+    def restore(self, blob):
+        check(load().svt_restore(self._h, bytes(blob), len(blob)), self._h)
+
     def set_replay(self, blocks, annealed):
         b, bp = _i32(blocks)
         a, ap = _i32(annealed)

@@ -34,10 +34,32 @@ def test_library_exports_every_declared_symbol():
         assert C.cast(getattr(L, name), C.c_void_p).value
 
 
-def test_struct_layouts_match_header():
-    # svt_params: 6 doubles, 6 int32, uint64, 6 int32, double
-    assert C.sizeof(_capi.Params) == 6 * 8 + 6 * 4 + 8 + 6 * 4 + 8
-    assert C.sizeof(_capi.StepStats) == 8 * 4 + 10 * 8
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of svt_params and svt_step_stats against the header as a C compiler lays
+    it out: size and the offset of every field (gcc on include/svt.h)."""
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svt.h"', "int main(void) {"]
+    for cname, py in (("svt_params", _capi.Params), ("svt_step_stats", _capi.StepStats)):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                              text=True).stdout.split("\n") if line)
+    for cname, py in (("svt_params", _capi.Params), ("svt_step_stats", _capi.StepStats)):
+        assert int(out[cname]) == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert int(out[f"{cname}.{field}"]) == getattr(py, field).offset, (cname, field)
 
 
 def test_default_params():

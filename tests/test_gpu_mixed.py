@@ -161,3 +161,29 @@ def test_mixed_step_wide_basis_gram_32_tiles(gpu_lib):
     assert rel_err(x, info_emu.x) <= TOL_EMU, rel_err(x, info_emu.x)
     assert abs(st.rel_res - info_emu.rel) <= TOL_EMU * info_emu.rel
     assert rel_err(h.get_state()["y"], nxt_emu.y) <= TOL_EMU
+
+
+def test_mixed_form_image_size_over_the_benchmark_window(gpu_lib):
+    """The reduced-precision form at the image workload's full size (1024 x 1024, 524,288 observed)
+    over iterations 1-25, the window the default benchmark command times.  Step parity: each
+    iteration starts the device from the emulated oracle's state and replays its two decisions;
+    x on Lambda, the residual and the next Y agree at the emulated bar, integers exactly."""
+    w = W.image()
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=11, maxit=30)
+    s64, k0 = initial_state(prob, p)
+    s32 = State(it=0, y=f32(s64.y))
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, k0=k0, seed=11,
+                         precision=gpu_lib.SVT_MIXED, maxit=30)
+    for it in range(1, 26):
+        nxt, info = svt_step_mixed(prob, p, s32)
+        h.set_state(s32.y, s32.Q, math.nan if s32.eps_thr is None else s32.eps_thr, s32.eps_min, s32.it)
+        h.set_replay([info.blocks], [int(info.annealed)])
+        st = h.iterate(1)
+        x = h.sample(w.rows, w.cols)
+        print(f"iteration {it}: r={info.r} k={info.k} err={rel_err(x, info.x):.2e}", flush=True)
+        assert st.r == info.r and st.k == info.k and st.blocks == info.blocks, it
+        assert rel_err(x, info.x) <= TOL_EMU, (it, rel_err(x, info.x))
+        assert abs(st.rel_res - info.rel) <= TOL_EMU * info.rel, it
+        assert rel_err(h.get_state()["y"], nxt.y) <= TOL_EMU, it
+        s32 = nxt

@@ -152,3 +152,44 @@ def test_history_keeps_every_iteration_report(gpu_lib):
     for a, b in zip(hist, hist2):
         assert (a.iter, a.r, a.k, a.blocks) == (b.iter, b.r, b.k, b.blocks)
         assert a.rel_res == b.rel_res
+
+
+def test_diverging_flag_on_an_unstable_step(gpu_lib):
+    """Fully observed, so one step is Y <- Y + delta (A - D_tau(Y)): with delta = 5 the residual grows
+    geometrically (the FP64 oracle: 0.71 after one step, 1.8e5 after ten; delta = 3 only oscillates).
+    The step report carries SVT_F_DIVERGING once the residual has stayed above 10 times its minimum
+    for 5 iterations, long before the iterate overflows."""
+    from paper_1704_05528_amd._capi import SVT_F_DIVERGING
+    w = W.tiny_dense(60, 50, 3, 1.0, seed=97, delta=5.0)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=97, maxit=400, tol=1e-12)
+    flagged = None
+    for _ in range(400):
+        try:
+            st = h.iterate(1)
+        except gpu_lib.SVTError as e:
+            assert e.status == gpu_lib.SVT_E_NUMERIC
+            break
+        if st.flags & SVT_F_DIVERGING:
+            flagged = st
+            break
+    assert flagged is not None, "no divergence flag before the iterate left the float range"
+    hist = h.history()
+    rels = [x.rel_res for x in hist]
+    assert rels[-1] > 10 * min(rels) and all(not (x.flags & SVT_F_DIVERGING) for x in hist[:-1])
+
+
+def test_wait_timeout_marks_the_handle_lost(gpu_lib):
+    """A host wait limit far below any kernel's run time forces the timeout path from the host: the
+    call returns SVT_E_HIP, every later call refuses, and svt_destroy returns without waiting (the
+    kernels themselves run to completion)."""
+    import torch
+    w = W.tiny_dense(400, 300, 3, 0.5, seed=98)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=98, wait_timeout_s=1e-9)
+    with pytest.raises(gpu_lib.SVTError) as e:
+        h.iterate(3)
+    assert e.value.status == gpu_lib.SVT_E_HIP and "timed out" in str(e.value)
+    with pytest.raises(gpu_lib.SVTError) as e:
+        h.iterate(1)
+    assert e.value.status == gpu_lib.SVT_E_HIP
+    h.close()
+    torch.cuda.synchronize()

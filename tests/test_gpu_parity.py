@@ -403,3 +403,46 @@ def test_ratings_workload_first_iterations(gpu_lib):
     h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
     for info in infos:
         _compare_step(h.iterate(1), info, h, w, ("ratings", info.it))
+
+
+def test_planted_step_with_the_basis_filling_the_space(gpu_lib):
+    """The planted 1000 x 1000 rank-10 problem late in its run: the oracle's state once the basis
+    holds all m = 1000 columns (tests/golden/make_planted_late_state.py, oracle only).  The device
+    starts from it (basis = identity, the same span) and takes one step: a 1000-column Gram, its
+    eigenpairs above tau and the sampled update, against the oracle's next step at 1e-10."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "planted_late_state.npz"))
+    w = W.planted()
+    h = _gpu(gpu_lib, w, int(ref["k0"]), seed=int(ref["seed"]), maxit=2000)
+    h.set_state(ref["y"], np.eye(w.m), float(ref["eps_thr"]), float(ref["eps_min"]), int(ref["it"]))
+    h.set_replay([int(ref["blocks"])], [int(ref["annealed"])])
+    st = h.iterate(1)
+    print(f"late planted step: iteration {st.iter} r={st.r} k={st.k} rel={st.rel_res:.6e}", flush=True)
+    assert st.r == int(ref["r"]) == w.m and st.k == int(ref["k"])
+    assert abs(st.rel_res - float(ref["rel"])) <= TOL * float(ref["rel"])
+    x = h.sample(w.rows[ref["x_sample_pos"]], w.cols[ref["x_sample_pos"]])
+    assert rel_err(x, ref["x_sample"]) <= TOL
+    kk, s, U, V = h.factors()
+    assert rel_err(s + w.tau, ref["sigma_k"]) <= TOL
+    if not st.stopped:
+        assert rel_err(h.get_state()["y"][ref["x_sample_pos"]], ref["y_next_sample"]) <= TOL
+
+
+@pytest.mark.parametrize("name", ["planted", "ratings"])
+def test_device_kicking_count(gpu_lib, name):
+    """k0 = ceil(tau / (delta ||P_Lambda A||_2)) from the device's own power iteration, against the
+    oracle's spectral norm (dense SVD for the planted problem, ARPACK for the ratings shape)."""
+    w = W.planted() if name == "planted" else W.ratings()
+    if name == "ratings":
+        w.delta = 1.9
+    sig = spectral_norm(w.m, w.n, w.rows, w.cols, w.a)
+    ratio = w.tau / (w.delta * sig)
+    if abs(ratio - round(ratio)) < 1e-9:
+        pytest.skip("tau / (delta sigma_1) within 1e-9 of an integer")
+    k0 = kicking_k0(w.tau, w.delta, sig)
+    h = gpu_lib.svt_init(w.m, w.n, w.rows, w.cols, w.a, tau=w.tau, delta=w.delta, seed=1)
+    y0 = h.get_state()["y"]
+    nz = np.abs(w.a) > 0
+    k_dev = np.unique(np.rint(y0[nz] / (w.delta * w.a[nz])).astype(int))
+    print(f"{name}: ratio {ratio:.6f} oracle k0 {k0} device {k_dev}", flush=True)
+    assert k_dev.tolist() == [k0]

@@ -348,3 +348,55 @@ def test_mixed_oracle_rounds_at_storage_points_and_tracks_fp64():
     assert np.abs(new32.y - new64.y).max() <= 1e-5 * np.abs(new64.y).max()
     # and the float32 rounding is really applied: the two forms are not bit-identical
     assert np.abs(i32.x - i64.x).max() > 0
+
+
+@pytest.mark.parametrize("mode_kw", [dict(mode="r3svd"), dict(mode="rsvd", rank=4, oversample=6),
+                                     dict(recycle_extra=2)])
+def test_mixed_oracle_modes_track_fp64(mode_kw):
+    """The emulated mixed form's operator variants (R3SVD every iteration, the fixed-rank RSVD of
+    Alg. 1, truncated recycling) take the FP64 oracle's decisions and stay within float32 error of
+    it over several iterations; the widths are those the variant fixes (t0 per R3SVD iteration,
+    rank + oversample for RSVD, at most k + extra recycled)."""
+    from oracle.mixed import f32, svt_step_mixed
+    w = W.tiny_dense(80, 70, 4, 0.45, seed=23)
+    prob = Problem(w.m, w.n, w.rows, w.cols, w.a)
+    p = Params(tau=w.tau, delta=w.delta, seed=6, t0=8, **mode_kw)
+    s64, k0 = initial_state(prob, p)
+    s32 = State(it=0, y=f32(s64.y))
+    for _ in range(8):
+        s64n, i64 = svt_step(prob, p, s64)
+        s32, i32 = svt_step_mixed(prob, p, s32, replay=(i64.blocks, i64.annealed))
+        assert i32.r == i64.r and i32.k == i64.k
+        assert np.abs(i32.x - i64.x).max() <= 2e-5 * max(np.abs(i64.x).max(), 1e-300)
+        assert abs(i32.rel - i64.rel) <= 2e-5 * i64.rel
+        assert np.array_equal(i32.x, f32(i32.x))
+        if p.mode == "rsvd":
+            assert i64.r == 10 and i64.k <= 4
+        if p.mode == "r3svd":
+            assert i64.blocks > 0 or i64.r == 8
+        if p.recycle_extra >= 0 and s32.Q is not None:
+            assert s32.Q.shape[1] <= i64.k + 2
+        s64 = s64n
+
+
+def test_spectral_norm_sparse_branch_matches_dense_svd():
+    """||P_Lambda A||_2 of the kicking start on problems above 4e6 entries comes from ARPACK
+    (scipy svds); on a 2100 x 2000 pattern (1% observed, the branch taken) it must equal the largest
+    singular value of the dense matrix from LAPACK's full SVD (np.linalg.norm(., 2)), and the
+    power-law shape of the ratings workload must not change that."""
+    from oracle.svt import dense, spectral_norm
+    rng = np.random.default_rng(29)
+    m, n = 2100, 2000
+    assert m * n > 4_000_000
+    for heavy in (False, True):
+        if heavy:   # a few dense columns and rows dominate, as with power-law degrees
+            lin = np.concatenate([rng.choice(m * n, 40_000, replace=False),
+                                  np.arange(m) * n + 3, 7 * n + np.arange(n)])
+        else:
+            lin = rng.choice(m * n, 42_000, replace=False)
+        lin = np.unique(lin)
+        rows, cols = lin // n, lin % n
+        vals = rng.standard_normal(lin.size)
+        s_sparse = spectral_norm(m, n, rows, cols, vals)
+        s_dense = float(np.linalg.svd(dense(m, n, rows, cols, vals), compute_uv=False)[0])
+        assert abs(s_sparse - s_dense) <= 1e-12 * s_dense, (heavy, s_sparse, s_dense)
