@@ -20,8 +20,12 @@
  * decrease (Sec. 2.5, Eq. 13-14, Alg. 4).
  *
  * Conventions
- *  - All pointers in these calls are HOST pointers unless a parameter says
- *    otherwise.  Inputs are copied; the library keeps no caller pointer.
+ *  - All pointers in these calls are HOST pointers unless a parameter or flag
+ *    says otherwise (svt_init's ptr_is_device, svt_factors's out_is_device,
+ *    svt_sample's ptr_is_device, SVT_GRAD_DEVICE_POINTERS, svt_mae_device).
+ *    Device pointers must be memory of the handle's device; work on them is
+ *    ordered on the handle's stream.  Inputs are copied; the library keeps no
+ *    caller pointer.
  *  - Index arrays are 0-based int32.  Lambda is given as COO (rows[p], cols[p]),
  *    p = 0..nnz-1, in any order, without duplicates.  Vectors "on Lambda"
  *    (values, y, x, residuals) are in that caller order.
@@ -148,17 +152,28 @@ typedef struct {
 /* Fill *p with defaults (tau and delta are set to 0 and must be given). */
 void svt_default_params(svt_params* p);
 
-/* Create a handle for the problem (Alg. 4 inputs).  Copies the COO triplets to
- * the device, builds the column-major (CSC) and row-major (CSR) orders,
+/* Element types of the observed values given to svt_init. */
+enum {
+  SVT_DTYPE_F64 = 0, /* double */
+  SVT_DTYPE_F32 = 1  /* float; widened to double on input */
+};
+
+/* Create a handle for the problem (Alg. 4 inputs).  Copies the COO triplets
+ * (rows, cols: int32; vals: nnz values of type vals_dtype) to the device, builds the column-major (CSC) and row-major (CSR) orders,
  * computes ||P_Lambda A||_F and, when p->k0 < 0, ||P_Lambda A||_2 by power
  * iteration, and sets Y^(0) = k0 * delta * P_Lambda(A) (kicking, Alg. 4
  * initialisation).  stream: a hipStream_t, or NULL for the default stream; every
  * later call on the handle works on it, so it must stay valid until svt_destroy.
+ * ptr_is_device = 1: rows, cols and vals are device pointers; they are read
+ * once, on the given stream, before the call returns (the orders of Lambda and
+ * the checks are built on the host either way).
  * Errors: SVT_E_INVALID_ARG for m, n, nnz <= 0, indices out of range,
  * duplicate (row, col), tau <= 0, delta <= 0, beta outside (0, 1), eta outside
- * [0, 1), npow < 0, non-finite values. */
+ * [0, 1), npow < 0, non-finite values, an unknown vals_dtype, ptr_is_device
+ * other than 0 or 1; SVT_E_HIP when the device inputs cannot be read. */
 svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows,
-                    const int32_t* cols, const double* vals, const svt_params* p, void* stream);
+                    const int32_t* cols, const void* vals, int32_t vals_dtype, int32_t ptr_is_device,
+                    const svt_params* p, void* stream);
 
 /* One R4SVD (Alg. 3; Alg. 2 when no basis exists yet) on the current iterate
  * Y, followed by the thresholded factors of D_tau(Y) (Eq. 5).  The iteration
@@ -184,12 +199,22 @@ svt_status svt_iterate(svt_handle* h, int32_t max_steps, svt_step_stats* last);
 svt_status svt_history(const svt_handle* h, int64_t first, int64_t count, svt_step_stats* out, int64_t* total);
 
 /* Thresholded factors of the last X = U diag(s) V^T (s = sigma - tau > 0):
- * k receives their count; U (m x kcap), V (n x kcap) row-major and s (kcap)
- * receive min(k, kcap) columns.  Any output pointer may be NULL. */
-svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V);
+ * k (host) receives their count; U (m x kcap), V (n x kcap) row-major and s
+ * (kcap) receive min(k, kcap) columns; columns kcap beyond that are left as
+ * they were.  Any output pointer may be NULL.  out_is_device = 1: s, U and V
+ * are device pointers, written on the handle's stream (the call returns once
+ * s has been copied; U and V are ordered before later work on that stream). */
+svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V,
+                       int32_t out_is_device);
 
-/* X of the last iteration sampled on nq arbitrary entries (qi[l], qj[l]). */
-svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out);
+/* X of the last iteration sampled on nq arbitrary entries (qi[l], qj[l]).
+ * ptr_is_device = 0: host arrays; an index outside m x n is SVT_E_INVALID_ARG
+ * and nothing is written.  ptr_is_device = 1: device arrays; nothing is
+ * allocated, the call only enqueues one kernel on the handle's stream and
+ * returns, and an index outside m x n gives NaN at its place (the other
+ * entries are computed). */
+svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out,
+                      int32_t ptr_is_device);
 
 /* Mean absolute error of the last X against reference values ref on nq entries (qi[l], qj[l]):
  * *mae = (1/nq) sum_l |ref[l] - X(qi[l], qj[l])|, the MAE of Eq. 15 restricted to the given entries
@@ -243,7 +268,8 @@ svt_status svt_set_replay(svt_handle* h, const int32_t* blocks, const int32_t* a
 
 /* Flags of svt_grad. */
 enum {
-  SVT_GRAD_FROZEN_BASIS = 1 /* hold every basis Q_i of the forward run fixed (see svt_grad) */
+  SVT_GRAD_FROZEN_BASIS = 1,   /* hold every basis Q_i of the forward run fixed (see svt_grad) */
+  SVT_GRAD_DEVICE_POINTERS = 2 /* hi, hj, gx_h and da are device pointers (dtau, ddelta stay host) */
 };
 
 /* Derivative of a held-out loss through the first T unrolled iterations of
@@ -276,6 +302,8 @@ enum {
  * Input: gx_h[l] = dL/dX_T(hi[l], hj[l]) on the held-out set H (nh entries,
  * repeats add up; nh = 0 gives zero gradients).
  * Outputs: *dtau, *ddelta, and da (nnz, caller order) = dL/dA on Lambda.
+ * With SVT_GRAD_DEVICE_POINTERS the held-out arrays are read from the device
+ * and da is written there; the call returns when da is complete.
  * The iteration state of the handle is left unchanged.
  * Errors: SVT_E_INVALID_ARG (T <= 0, NULL outputs, H index out of range,
  * unknown flags), SVT_E_STATE (fewer than T recorded iterations, state

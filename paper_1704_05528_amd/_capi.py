@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 SVT_OK = 0
 SVT_E_INVALID_ARG, SVT_E_OOM, SVT_E_HIP, SVT_E_NUMERIC, SVT_E_STATE, SVT_E_LIMIT = -1, -2, -3, -4, -5, -6
-SVT_GRAD_FROZEN_BASIS = 1
+SVT_GRAD_FROZEN_BASIS, SVT_GRAD_DEVICE_POINTERS = 1, 2
+SVT_DTYPE_F64, SVT_DTYPE_F32 = 0, 1
 SVT_FP64, SVT_MIXED = 0, 1
 SVT_MODE_R4SVD, SVT_MODE_R3SVD, SVT_MODE_RSVD = 0, 1, 2
 SVT_F_CONVERGED, SVT_F_MAXIT, SVT_F_RMAX_HIT, SVT_F_EXHAUSTED, SVT_F_ANNEALED, SVT_F_EIG_INEXACT = 1, 2, 4, 8, 16, 32
@@ -73,17 +74,19 @@ def load():
     L = C.CDLL(path)
     L.svt_default_params.argtypes = [_P(Params)]
     L.svt_default_params.restype = None
-    L.svt_init.argtypes = [_P(_vp), C.c_int64, C.c_int64, C.c_int64, _i32p, _i32p, _f64p, _P(Params), _vp]
+    # pointers that may be host or device memory (by a flag of the call) are declared void*
+    L.svt_init.argtypes = [_P(_vp), C.c_int64, C.c_int64, C.c_int64, _vp, _vp, _vp, C.c_int32, C.c_int32,
+                           _P(Params), _vp]
     L.r4svd_step.argtypes = [_vp, _P(StepStats)]
     L.svt_iterate.argtypes = [_vp, C.c_int32, _P(StepStats)]
     L.svt_history.argtypes = [_vp, C.c_int64, C.c_int64, _P(StepStats), _P(C.c_int64)]
-    L.svt_factors.argtypes = [_vp, C.c_int32, _i32p, _f64p, _f64p, _f64p]
-    L.svt_sample.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p]
+    L.svt_factors.argtypes = [_vp, C.c_int32, _i32p, _vp, _vp, _vp, C.c_int32]
+    L.svt_sample.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.c_int32]
     L.svt_mae.argtypes = [_vp, C.c_int64, _i32p, _i32p, _f64p, _f64p]
     L.svt_get_state.argtypes = [_vp, _f64p, _f64p, C.c_int32, _i32p, _f64p, _f64p, _i32p]
     L.svt_set_state.argtypes = [_vp, _f64p, _f64p, C.c_int32, C.c_double, C.c_double, C.c_int32]
     L.svt_set_replay.argtypes = [_vp, _i32p, _i32p, C.c_int32]
-    L.svt_grad.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_int32, _f64p, _f64p, _f64p]
+    L.svt_grad.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64, _vp, _vp, _vp, C.c_int32, _f64p, _f64p, _vp]
     L.svt_profile.argtypes = [_vp, C.c_int32]
     L.svt_profile_phases.argtypes = [_vp, C.c_uint32]
     L.svt_profile_read.argtypes = [_vp, _f64p, _f64p, _f64p, _P(C.c_int64)]

@@ -1227,11 +1227,17 @@ __global__ __launch_bounds__(256) void k_absdiff(int64_t len, const double* __re
 
 template <class T>
 __global__ void k_sample(int64_t nq, const int32_t* __restrict__ qi, const int32_t* __restrict__ qj,
-                         const T* __restrict__ Ut, const T* __restrict__ Vt, int ld, int k, double* __restrict__ out) {
+                         const T* __restrict__ Ut, const T* __restrict__ Vt, int ld, int k, int64_t m, int64_t n,
+                         double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq) return;
-  const T* u = Ut + (int64_t)qi[t] * ld;
-  const T* v = Vt + (int64_t)qj[t] * ld;
+  const int32_t i = qi[t], j = qj[t];
+  if (i < 0 || i >= m || j < 0 || j >= n) {  // an index outside the matrix reads nothing and yields NaN
+    out[t] = __builtin_nan("");
+    return;
+  }
+  const T* u = Ut + (int64_t)i * ld;
+  const T* v = Vt + (int64_t)j * ld;
   T x = (T)0;
   for (int l = 0; l < k; ++l) x = fma(u[l], v[l], x);
   out[t] = (double)x;
@@ -1273,6 +1279,13 @@ template <class TS, class TD>
 __global__ void k_scale_copy(int64_t len, const TS* __restrict__ src, double alpha, TD* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < len) dst[t] = (TD)(alpha * (double)src[t]);
+}
+
+// dst[t] = src[perm[t]]: a vector on Lambda from the library's CSC order back to the caller's order
+__global__ void k_gather_perm(int64_t len, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) dst[t] = src[perm[t]];
 }
 
 template <class TS, class TD>
@@ -1644,9 +1657,9 @@ hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int 
 
 template <class T>
 hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
-                         int ld, int k, double* out) {
+                         int ld, int k, int64_t m, int64_t n, double* out) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sample<T>, dim3(grid1(nq)), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, out);
+  hipLaunchKernelGGL(k_sample<T>, dim3(grid1(nq)), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, m, n, out);
   return hipGetLastError();
 }
 
@@ -1669,6 +1682,12 @@ template <class TS, class TD>
 hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst) {
   if (len == 0) return hipSuccess;
   hipLaunchKernelGGL((k_scale_copy<TS, TD>), dim3(grid1(len)), dim3(256), 0, s, len, src, alpha, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_perm(hipStream_t s, int64_t len, const int32_t* perm, const double* src, double* dst) {
+  if (len == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_perm, dim3(grid1(len)), dim3(256), 0, s, len, perm, src, dst);
   return hipGetLastError();
 }
 
@@ -1702,7 +1721,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
                                              const T*, const T*, T*, const T*, const T*, int, int, double, double*,   \
                                              int*);                                                                   \
   template hipError_t launch_sample<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*, int, \
-                                       int, double*);                                                                 \
+                                       int, int64_t, int64_t, double*);                                               \
   template hipError_t launch_mae_fused<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*,    \
                                           int, int, int64_t, int64_t, const double*, double*, double*);               \
   template hipError_t launch_scale_copy<T, T>(hipStream_t, int64_t, const T*, double, T*);                            \

@@ -1232,8 +1232,17 @@ struct Engine {
     return SVT_OK;
   }
 
-  svt_status factors(int kk, int kcap, double* U, double* V) {
+  svt_status factors(int kk, int kcap, double* U, double* V, bool dev) {
     std::vector<T> buf;
+    if (dev) {  // straight into the caller's device matrices (row-major, kcap columns, float64)
+      if (U) {
+        HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
+                                            kk, 1.0, 0.0)));
+        HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->m, Utmp(), h->ldf, U, kcap, kk)));
+      }
+      if (V) HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->n, Vt(), h->ldf, V, kcap, kk)));
+      return SVT_OK;
+    }
     if (U) {
       HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
                                           kk, 1.0, 0.0)));
@@ -1252,7 +1261,7 @@ struct Engine {
   }
 
   svt_status sample(int64_t nq, const int32_t* di, const int32_t* dj, double* dx) {
-    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), h->ldf, h->k, dx));
+    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), h->ldf, h->k, h->m, h->n, dx));
     return SVT_OK;
   }
 
@@ -1321,7 +1330,7 @@ struct GradArena {
 };
 
 svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, const int32_t* hj, const double* gx,
-                     bool exact, double* dtau, double* ddelta, double* da) {
+                     bool exact, bool da_device, double* dtau, double* ddelta, double* da) {
   Engine<double> eng(h);
   const hipStream_t s = h->stream;
   const int m = (int)h->m, n = (int)h->n;
@@ -1616,7 +1625,17 @@ svt_status grad_fp64(Handle* h, int T, int ckpt, int64_t nh, const int32_t* hi, 
   HIPCHK(launch_dot(s, nnz, ybar, a, h->partial, h->scal, S_DOT));
   CHK(readback(h, S_DOT + 1));
   d_bar += (double)h->k0 * h->hscal[S_DOT];
-  CHK(eng.download_lambda(da, abar));
+  if (da_device) {  // gathered into the caller's order on the device (res is free by now)
+    std::vector<int32_t> perm(nnz);
+    for (int64_t u = 0; u < nnz; ++u) perm[u] = (int32_t)h->user2csc[u];
+    int32_t* d_perm = nullptr;
+    HIPCHK(ar.get(&d_perm, nnz));
+    HIPCHK(hipMemcpyAsync(d_perm, perm.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gather_perm(s, nnz, d_perm, abar, da));
+    CHK(wait_stream(h));  // the host permutation goes out of scope
+  } else {
+    CHK(eng.download_lambda(da, abar));
+  }
   *dtau = t_bar;
   *ddelta = d_bar;
   return SVT_OK;
@@ -1740,8 +1759,9 @@ void svt_destroy(svt_handle* h) {
   delete h;
 }
 
-svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows, const int32_t* cols,
-                    const double* vals, const svt_params* pin, void* stream) {
+svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const int32_t* rows_in,
+                    const int32_t* cols_in, const void* vals_in, int32_t vals_dtype, int32_t ptr_is_device,
+                    const svt_params* pin, void* stream) {
   if (!out) {
     g_init_err = "out is NULL";
     return SVT_E_INVALID_ARG;
@@ -1751,10 +1771,45 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     g_init_err = msg;
     return SVT_E_INVALID_ARG;
   };
-  if (!rows || !cols || !vals || !pin) return bad("NULL input pointer");
+  if (!rows_in || !cols_in || !vals_in || !pin) return bad("NULL input pointer");
+  if (vals_dtype != SVT_DTYPE_F64 && vals_dtype != SVT_DTYPE_F32) return bad("unknown vals_dtype");
+  if (ptr_is_device != 0 && ptr_is_device != 1) return bad("ptr_is_device must be 0 or 1");
   if (m <= 0 || n <= 0 || nnz <= 0) return bad("m, n and nnz must be positive");
   if (m >= (1ll << 31) || n >= (1ll << 31) || nnz >= (1ll << 31)) return bad("m, n, nnz must be below 2^31");
   if (nnz > m * n) return bad("nnz exceeds m * n");
+  // The orders of Lambda are built on the host: device inputs are copied over once, on the
+  // caller's stream; values of either type are taken as float64.
+  std::vector<int32_t> rows_h, cols_h;
+  std::vector<double> vals_h;
+  const int32_t *rows = rows_in, *cols = cols_in;
+  const double* vals = (const double*)vals_in;
+  if (ptr_is_device || vals_dtype != SVT_DTYPE_F64) {
+    const size_t es_in = vals_dtype == SVT_DTYPE_F64 ? sizeof(double) : sizeof(float);
+    std::vector<char> raw((size_t)nnz * es_in);
+    if (ptr_is_device) {
+      rows_h.resize(nnz);
+      cols_h.resize(nnz);
+      hipStream_t cs = (hipStream_t)stream;
+      hipError_t e = hipMemcpyAsync(rows_h.data(), rows_in, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipMemcpyAsync(cols_h.data(), cols_in, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipMemcpyAsync(raw.data(), vals_in, raw.size(), hipMemcpyDeviceToHost, cs);
+      if (e == hipSuccess) e = hipStreamSynchronize(cs);
+      if (e != hipSuccess) {
+        g_init_err = std::string("copy of the device inputs failed: ") + hipGetErrorString(e);
+        return SVT_E_HIP;
+      }
+      rows = rows_h.data();
+      cols = cols_h.data();
+    } else {
+      std::memcpy(raw.data(), vals_in, raw.size());
+    }
+    vals_h.resize(nnz);
+    if (vals_dtype == SVT_DTYPE_F64)
+      std::memcpy(vals_h.data(), raw.data(), raw.size());
+    else
+      for (int64_t q = 0; q < nnz; ++q) vals_h[q] = (double)reinterpret_cast<const float*>(raw.data())[q];
+    vals = vals_h.data();
+  }
   svt_params p = *pin;
   if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return bad("tau must be positive and finite");
   if (!(p.delta > 0.0) || !std::isfinite(p.delta)) return bad("delta must be positive and finite");
@@ -2044,23 +2099,37 @@ svt_status svt_history(const svt_handle* h, int64_t first, int64_t count, svt_st
   return SVT_OK;
 }
 
-svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V) {
+svt_status svt_factors(svt_handle* h, int32_t kcap, int32_t* k, double* s, double* U, double* V,
+                       int32_t out_is_device) {
   if (!h) return SVT_E_INVALID_ARG;
   if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
+  if (out_is_device != 0 && out_is_device != 1) return fail(h, SVT_E_INVALID_ARG, "out_is_device must be 0 or 1");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   if (k) *k = h->k;
   const int kk = std::min<int>(std::max(kcap, 0), h->k);
   if (kk == 0) return SVT_OK;
-  if (s)
-    for (int c = 0; c < kk; ++c) s[c] = h->sigma_k[c] - h->p.tau;
-  return dispatch(h, [&](auto& eng) { return eng.factors(kk, kcap, U, V); });
+  std::vector<double> sv(kk);
+  for (int c = 0; c < kk; ++c) sv[c] = h->sigma_k[c] - h->p.tau;
+  if (s && !out_is_device) std::copy(sv.begin(), sv.end(), s);
+  if (s && out_is_device) {
+    HIPCHK(hipMemcpyAsync(s, sv.data(), kk * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    CHK(wait_stream(h));  // the host vector goes out of scope
+  }
+  return dispatch(h, [&](auto& eng) { return eng.factors(kk, kcap, U, V, out_is_device != 0); });
 }
 
-svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out) {
+svt_status svt_sample(svt_handle* h, int64_t nq, const int32_t* qi, const int32_t* qj, double* x_out,
+                      int32_t ptr_is_device) {
   if (!h) return SVT_E_INVALID_ARG;
   if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (nq < 0 || (nq > 0 && (!qi || !qj || !x_out))) return fail(h, SVT_E_INVALID_ARG, "bad query arrays");
+  if (ptr_is_device != 0 && ptr_is_device != 1) return fail(h, SVT_E_INVALID_ARG, "ptr_is_device must be 0 or 1");
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
+  if (ptr_is_device) {
+    // device queries and output: enqueued on the handle's stream, indices checked by the kernel
+    if (nq == 0) return SVT_OK;
+    return dispatch(h, [&](auto& eng) { return eng.sample(nq, qi, qj, x_out); });
+  }
   for (int64_t l = 0; l < nq; ++l)
     if (qi[l] < 0 || qi[l] >= h->m || qj[l] < 0 || qj[l] >= h->n)
       return fail(h, SVT_E_INVALID_ARG, "query out of range");
@@ -2330,9 +2399,26 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
   if (h->lost) return fail(h, SVT_E_HIP, "the handle's device work timed out; destroy the handle");
   if (T <= 0) return fail(h, SVT_E_INVALID_ARG, "T must be positive");
   if (!dtau || !ddelta || !da) return fail(h, SVT_E_INVALID_ARG, "NULL output pointer");
-  if (flags & ~SVT_GRAD_FROZEN_BASIS) return fail(h, SVT_E_INVALID_ARG, "unknown svt_grad flags");
+  if (flags & ~(SVT_GRAD_FROZEN_BASIS | SVT_GRAD_DEVICE_POINTERS))
+    return fail(h, SVT_E_INVALID_ARG, "unknown svt_grad flags");
   if (nh < 0 || (nh > 0 && (!hi || !hj || !gx_h))) return fail(h, SVT_E_INVALID_ARG, "bad held-out arrays");
   if (nh >= ((int64_t)1 << 31)) return fail(h, SVT_E_INVALID_ARG, "nh must be below 2^31");
+  const bool dev = (flags & SVT_GRAD_DEVICE_POINTERS) != 0;
+  // device held-out arrays: copied to the host once, where the column and row orders of H are built
+  std::vector<int32_t> hi_h, hj_h;
+  std::vector<double> gx_v;
+  if (dev && nh > 0) {
+    hi_h.resize(nh);
+    hj_h.resize(nh);
+    gx_v.resize(nh);
+    HIPCHK(hipMemcpyAsync(hi_h.data(), hi, nh * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(hj_h.data(), hj, nh * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(gx_v.data(), gx_h, nh * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CHK(wait_stream(h));
+    hi = hi_h.data();
+    hj = hj_h.data();
+    gx_h = gx_v.data();
+  }
   for (int64_t l = 0; l < nh; ++l) {
     if (hi[l] < 0 || hi[l] >= h->m || hj[l] < 0 || hj[l] >= h->n)
       return fail(h, SVT_E_INVALID_ARG, "held-out index out of range");
@@ -2349,7 +2435,7 @@ svt_status svt_grad(svt_handle* h, int32_t T, int32_t ckpt, int64_t nh, const in
                 "the exact reverse sweep needs R4SVD with full recycling, no power iterations and no dropped "
                 "columns; SVT_GRAD_FROZEN_BASIS gives the frozen-basis derivative");
   h->spec_ready = false;  // the adjoint reuses the buffers the enqueued leading work wrote
-  const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, exact, dtau, ddelta, da);
+  const svt_status gs = grad_fp64(h, T, ckpt, nh, hi, hj, gx_h, exact, dev, dtau, ddelta, da);
   h->spec_ready = false;
   return gs;
 }

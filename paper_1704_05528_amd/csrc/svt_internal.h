@@ -338,15 +338,17 @@ constexpr int kMaeFusedBlocks = 1024;
 template <class T>
 hipError_t launch_mae_fused(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
                            int ld, int k, int64_t m, int64_t n, const double* ref, double* work, double* out);
-// X on arbitrary entries
+// X on arbitrary entries; an index outside m x n gives NaN
 template <class T>
 hipError_t launch_sample(hipStream_t s, int64_t nq, const int32_t* qi, const int32_t* qj, const T* Ut, const T* Vt,
-                         int ld, int k, double* out);
+                         int ld, int k, int64_t m, int64_t n, double* out);
 
 template <class TS, class TD>
 hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst);
 template <class TS, class TD>
 hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds, TD* dst, int ldd, int w);
+// dst[t] = src[perm[t]], t < len
+hipError_t launch_gather_perm(hipStream_t s, int64_t len, const int32_t* perm, const double* src, double* dst);
 
 // columns c0 .. c0+count-1 of a rows x ld block set to e_{row0}, e_{row0+1}, ...
 hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, int count, int row0);

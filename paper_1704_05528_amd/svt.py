@@ -4,15 +4,18 @@
     stats = svt_iterate(h, 100)
     k, s, U, V = h.factors()
 
-Only argument marshalling happens here; every step of the iteration runs in
-libsvt.so on the GPU that is current when the handle is created.
+Inputs may also be torch tensors on the GPU (int32 indices, float64 or float32 values): they are
+then handed to the library as device pointers, and sample(), grad() and factors(device=True)
+answer with GPU tensors written on the handle's stream.  Only argument marshalling happens here;
+every step of the iteration runs in libsvt.so on the GPU that is current when the handle is created.
 """
 import ctypes as C
 import math
 
 import numpy as np
 
-from ._capi import SVTError, StepStats, check, default_params, load, SVT_E_INVALID_ARG
+from ._capi import (SVTError, StepStats, check, default_params, load, SVT_E_INVALID_ARG, SVT_DTYPE_F32,
+                    SVT_DTYPE_F64, SVT_GRAD_DEVICE_POINTERS, SVT_GRAD_FROZEN_BASIS)
 
 _i32p, _f64p = C.POINTER(C.c_int32), C.POINTER(C.c_double)
 
@@ -25,6 +28,22 @@ def _i32(a):
 def _f64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(_f64p)
+
+
+def _is_device(x):
+    """True for a torch tensor in GPU memory (torch is imported by load() already)."""
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+def _dev(t, dtypes, name):
+    """Device pointer of a contiguous GPU tensor of one of the given torch dtypes."""
+    if not _is_device(t):
+        raise SVTError(SVT_E_INVALID_ARG, f"{name}: expected a GPU tensor like the other device arguments")
+    if t.dtype not in dtypes:
+        raise SVTError(SVT_E_INVALID_ARG, f"{name}: dtype {t.dtype} is not one of {dtypes}")
+    if not t.is_contiguous():
+        raise SVTError(SVT_E_INVALID_ARG, f"{name}: the tensor must be contiguous")
+    return t.data_ptr()
 
 
 def _stream_handle(stream):
@@ -41,15 +60,27 @@ class SVT:
     def __init__(self, m, n, rows, cols, vals, stream=None, **params):
         L = load()
         self.m, self.n = int(m), int(n)
-        rows, rp = _i32(rows)
-        cols, cp = _i32(cols)
-        vals, vp = _f64(vals)
-        if not (rows.size == cols.size == vals.size):
+        if _is_device(vals):
+            import torch
+            rp = _dev(rows, (torch.int32,), "rows")
+            cp = _dev(cols, (torch.int32,), "cols")
+            vp = _dev(vals, (torch.float64, torch.float32), "vals")
+            sizes = (rows.numel(), cols.numel(), vals.numel())
+            dtype, on_dev = (SVT_DTYPE_F64 if vals.dtype == torch.float64 else SVT_DTYPE_F32), 1
+            if stream is not None:  # the library reads them on its stream
+                torch.cuda.current_stream().synchronize()
+        else:
+            rows, rp = _i32(rows)
+            cols, cp = _i32(cols)
+            vals, vp = _f64(vals)
+            sizes = (rows.size, cols.size, vals.size)
+            dtype, on_dev = SVT_DTYPE_F64, 0
+        if not (sizes[0] == sizes[1] == sizes[2]):
             raise SVTError(SVT_E_INVALID_ARG, "rows, cols and vals differ in length")
-        self.nnz = int(rows.size)
+        self.nnz = int(sizes[0])
         self.params = default_params(**params)
         h = C.c_void_p()
-        check(L.svt_init(C.byref(h), self.m, self.n, self.nnz, rp, cp, vp, C.byref(self.params),
+        check(L.svt_init(C.byref(h), self.m, self.n, self.nnz, rp, cp, vp, dtype, on_dev, C.byref(self.params),
                          _stream_handle(stream)), None)
         self._h = h
         self._stream = stream  # the library works on this stream until close(): keep it alive
@@ -95,25 +126,62 @@ class SVT:
         return list(arr[:max(0, min(n, total.value - int(first)))])
 
     # -- outputs --------------------------------------------------------------------------------
-    def factors(self, kcap=None):
+    def factors(self, kcap=None, device=False):
+        """(k, s, U, V) of the last X; device=True: GPU tensors on the current device."""
         L = load()
         k = C.c_int32()
-        check(L.svt_factors(self._h, 0, C.byref(k), None, None, None), self._h)
+        check(L.svt_factors(self._h, 0, C.byref(k), None, None, None, 0), self._h)
         kc = k.value if kcap is None else int(kcap)
-        s = np.zeros(kc)
-        U = np.zeros((self.m, kc))
-        V = np.zeros((self.n, kc))
+        if device:
+            import torch
+            s, U, V = (torch.zeros(sh, dtype=torch.float64, device="cuda") for sh in (kc, (self.m, kc), (self.n, kc)))
+            ptrs = [t.data_ptr() for t in (s, U, V)]
+        else:
+            s, U, V = np.zeros(kc), np.zeros((self.m, kc)), np.zeros((self.n, kc))
+            ptrs = [t.ctypes.data for t in (s, U, V)]
         if kc > 0:
-            check(L.svt_factors(self._h, kc, C.byref(k), s.ctypes.data_as(_f64p), U.ctypes.data_as(_f64p),
-                                V.ctypes.data_as(_f64p)), self._h)
+            self._order_after_torch(device)
+            check(L.svt_factors(self._h, kc, C.byref(k), *ptrs, int(device)), self._h)
+            if device:
+                self._order_torch_after()
         return k.value, s, U, V
 
     def sample(self, qi, qj):
+        """X of the last iteration on (qi, qj): numpy in, numpy out; GPU int32 tensors in, a GPU
+        float64 tensor out (an index outside m x n gives NaN there)."""
+        if _is_device(qi):
+            import torch
+            ip = _dev(qi, (torch.int32,), "qi")
+            jp = _dev(qj, (torch.int32,), "qj")
+            if qi.numel() != qj.numel():
+                raise SVTError(SVT_E_INVALID_ARG, "qi and qj differ in length")
+            out = torch.empty(qi.numel(), dtype=torch.float64, device=qi.device)
+            self._order_after_torch(True)
+            check(load().svt_sample(self._h, qi.numel(), ip, jp, out.data_ptr(), 1), self._h)
+            self._order_torch_after()
+            return out
         qi, ip = _i32(qi)
         qj, jp = _i32(qj)
         out = np.zeros(qi.size)
-        check(load().svt_sample(self._h, qi.size, ip, jp, out.ctypes.data_as(_f64p)), self._h)
+        check(load().svt_sample(self._h, qi.size, ip, jp, out.ctypes.data, 0), self._h)
         return out
+
+    def _order_after_torch(self, device):
+        """Device arguments written by torch on its current stream are complete before the library
+        reads them on the handle's stream (torch's allocations and fills are asynchronous)."""
+        if device and self._stream is not None:
+            import torch
+            torch.cuda.current_stream().synchronize()
+
+    def _order_torch_after(self):
+        """torch's current stream waits for what the library enqueued on the handle's stream."""
+        if self._stream is None:
+            return  # the legacy default stream orders itself with every blocking stream
+        import torch
+        if isinstance(self._stream, torch.cuda.Stream):
+            torch.cuda.current_stream().wait_stream(self._stream)
+        else:
+            torch.cuda.synchronize()
 
     def mae(self, qi, qj, ref):
         """Mean |ref - X| over the entries (qi, qj) (the MAE of Eq. 15 on those entries)."""
@@ -196,16 +264,31 @@ class SVT:
         return ms.value, by.value, fl.value
 
     def grad(self, T, ckpt, hi, hj, gx_h, frozen_basis=False):
-        """dL/dtau, dL/ddelta, dL/da through T unrolled iterations (exact, or with frozen bases)."""
-        from ._capi import SVT_GRAD_FROZEN_BASIS
-        hi, ip = _i32(hi)
-        hj, jp = _i32(hj)
-        g, gp = _f64(gx_h)
-        dtau, ddelta = C.c_double(), C.c_double()
-        da = np.zeros(self.nnz)
+        """dL/dtau, dL/ddelta, dL/da through T unrolled iterations (exact, or with frozen bases).
+        GPU tensors for hi, hj (int32) and gx_h (float64) give da as a GPU tensor."""
         flags = SVT_GRAD_FROZEN_BASIS if frozen_basis else 0
-        check(load().svt_grad(self._h, int(T), int(ckpt), hi.size, ip, jp, gp, flags, C.byref(dtau),
-                              C.byref(ddelta), da.ctypes.data_as(_f64p)), self._h)
+        dtau, ddelta = C.c_double(), C.c_double()
+        if _is_device(gx_h):
+            import torch
+            ip = _dev(hi, (torch.int32,), "hi")
+            jp = _dev(hj, (torch.int32,), "hj")
+            gp = _dev(gx_h, (torch.float64,), "gx_h")
+            if not (hi.numel() == hj.numel() == gx_h.numel()):
+                raise SVTError(SVT_E_INVALID_ARG, "hi, hj and gx_h differ in length")
+            nh = hi.numel()
+            da = torch.empty(self.nnz, dtype=torch.float64, device=gx_h.device)
+            dp = da.data_ptr()
+            flags |= SVT_GRAD_DEVICE_POINTERS
+            self._order_after_torch(True)
+        else:
+            hi, ip = _i32(hi)
+            hj, jp = _i32(hj)
+            g, gp = _f64(gx_h)
+            nh = hi.size
+            da = np.zeros(self.nnz)
+            dp = da.ctypes.data
+        check(load().svt_grad(self._h, int(T), int(ckpt), nh, ip, jp, gp, flags, C.byref(dtau), C.byref(ddelta), dp),
+              self._h)
         return dtau.value, ddelta.value, da
 
 

@@ -69,15 +69,14 @@ def test_default_params():
     assert p.mode == svt.SVT_MODE_R4SVD and p.recycle_extra == -1 and p.oversample == 10 and p.mae_tol == 0.0
 
 
-def _init(m, n, rows, cols, vals, **kw):
+def _init(m, n, rows, cols, vals, vals_dtype=_capi.SVT_DTYPE_F64, ptr_is_device=0, **kw):
     params = svt.default_params(**kw)
     h = C.c_void_p()
     r = np.ascontiguousarray(rows, dtype=np.int32)
     c = np.ascontiguousarray(cols, dtype=np.int32)
-    v = np.ascontiguousarray(vals, dtype=np.float64)
+    v = np.ascontiguousarray(vals, dtype=np.float32 if vals_dtype == _capi.SVT_DTYPE_F32 else np.float64)
     L = svt.load()
-    st = L.svt_init(C.byref(h), m, n, r.size, r.ctypes.data_as(C.POINTER(C.c_int32)),
-                    c.ctypes.data_as(C.POINTER(C.c_int32)), v.ctypes.data_as(C.POINTER(C.c_double)),
+    st = L.svt_init(C.byref(h), m, n, r.size, r.ctypes.data, c.ctypes.data, v.ctypes.data, vals_dtype, ptr_is_device,
                     C.byref(params), None)
     return st, h, L.svt_last_error(None).decode()
 
@@ -96,6 +95,11 @@ GOOD = dict(tau=1.0, delta=1.0)
     ("beta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, beta=1.0)),
     ("eta", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, eta=1.0)),
     ("npow", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, npow=-1)),
+    ("vals_dtype", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, vals_dtype=7)),
+    ("ptr_is_device", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, ptr_is_device=2)),
+    ("nan float32 value", (3, 3, [0, 1], [0, 1], [1.0, float("nan")]),
+     dict(tau=1.0, delta=1.0, vals_dtype=_capi.SVT_DTYPE_F32)),
+    ("float32 duplicate", (3, 3, [1, 1], [2, 2], [1.0, 2.0]), dict(tau=1.0, delta=1.0, vals_dtype=_capi.SVT_DTYPE_F32)),
 ])
 def test_init_rejects_bad_arguments_on_host(case, args, kw):
     st, h, msg = _init(*args, **kw)
@@ -109,5 +113,7 @@ def test_null_handles_are_rejected():
     assert L.svt_iterate(None, 1, None) == _capi.SVT_E_INVALID_ARG
     assert L.r4svd_step(None, None) == _capi.SVT_E_INVALID_ARG
     assert L.svt_grad(None, 1, 1, 0, None, None, None, 0, None, None, None) == _capi.SVT_E_INVALID_ARG
+    assert L.svt_factors(None, 0, None, None, None, None, 0) == _capi.SVT_E_INVALID_ARG
+    assert L.svt_sample(None, 0, None, None, None, 1) == _capi.SVT_E_INVALID_ARG
     assert L.svt_history(None, 0, 0, None, None) == _capi.SVT_E_INVALID_ARG
     L.svt_destroy(None)

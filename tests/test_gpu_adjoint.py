@@ -158,7 +158,7 @@ def test_grad_error_paths(gpu_lib):
     import ctypes as C
     from paper_1704_05528_amd import _capi
     out = (C.c_double(), C.c_double(), np.zeros(w.nnz))
-    st = svt.load().svt_grad(h._h, 6, 0, 0, None, None, None, 2, C.byref(out[0]), C.byref(out[1]),
+    st = svt.load().svt_grad(h._h, 6, 0, 0, None, None, None, 4, C.byref(out[0]), C.byref(out[1]),
                              out[2].ctypes.data_as(C.POINTER(C.c_double)))
     assert st == _capi.SVT_E_INVALID_ARG
 
