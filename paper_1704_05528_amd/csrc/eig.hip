@@ -73,10 +73,11 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
   const double tol = 1e-15 * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   const int nb1 = bb - 1;
   const int totA = half * half, totV = bb * half;
-  int sweep = 0;
+  int sweep = 0, seq = 0;  // seq: rounds since the start; its parity picks the flag, so a wave
+                           // that sets the next round's flag never overwrites one still being read
   for (; sweep < max_sweeps; ++sweep) {
     int sweep_any = 0;
-    for (int round = 0; round < nb1; ++round) {
+    for (int round = 0; round < nb1; ++round, ++seq) {
       int mine = 0;
       if (tid < half) {
         // round-robin pairing: slot 0 fixed, the others rotate by one position per round
@@ -106,10 +107,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
       }
       if (tid < kWave) {
         const unsigned long long bal = __ballot(mine);
-        if (tid == 0) flag[round & 1] = (bal != 0ull);
+        if (tid == 0) flag[seq & 1] = (bal != 0ull);
       }
       __syncthreads();
-      if (!flag[round & 1]) continue;  // uniform: nothing rotates, nothing to update this round
+      if (!flag[seq & 1]) continue;  // uniform: nothing rotates, nothing to update this round
       sweep_any = 1;
       for (int base = 0; base < totA; base += CA * 256) {
         double a0[CA], a1[CA], a2[CA], a3[CA], c1v[CA], s1v[CA], c2v[CA], s2v[CA];
