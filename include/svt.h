@@ -64,9 +64,16 @@ typedef enum {
 /* Precision forms. */
 enum {
   SVT_FP64 = 0,  /* every stored value and every accumulation in float64 */
-  SVT_MIXED = 1  /* float32 storage of y, a, Q, W, sampled blocks and factors, float32 accumulation in
+  SVT_MIXED = 1, /* float32 storage of y, a, Q, W, sampled blocks and factors, float32 accumulation in
                     the sparse products and the sampled update; float64 Gram matrices, Cholesky,
                     eigen-solver and every norm and reduction */
+  SVT_BF16 = 2   /* SVT_MIXED with the basis Q stored in bfloat16 (each sampled block orthonormalised
+                    in float32, then rounded to nearest even).  The rounded basis is not orthonormal,
+                    so the projection of Alg. 3 is taken on the exact orthogonal projector onto its
+                    span: with Q^T Q = L L^T (float64 Cholesky, bordered as blocks are appended),
+                    ||B||_F^2 of Eq. 10-11 is trace(L^-1 W^T W L^-T) and svd(B) is taken through the
+                    eigenpairs of L^-1 W^T W L^-T.  The whole stored basis is recycled (no truncated
+                    recycling); svt_grad is not available */
 };
 
 /* Operator variants (svt_params.mode). */
@@ -108,7 +115,7 @@ typedef struct {
   int32_t r_max;   /* basis width cap; <= 0 => m */
   int32_t k0;      /* kicking count; < 0 => ceil(tau / (delta ||P_Lambda A||_2)) */
   uint64_t seed;   /* key of the Philox4x64-10 Omega stream */
-  int32_t precision; /* SVT_FP64 or SVT_MIXED */
+  int32_t precision; /* SVT_FP64, SVT_MIXED or SVT_BF16 */
   int32_t kmax;    /* most singular values above tau tracked (the factor buffers hold this many
                       columns); <= 0 => r_max, i.e. every singular value the basis can hold.  Counts
                       that need a wider block than the subspace solver's 96 columns are found by a full

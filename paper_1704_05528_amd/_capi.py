@@ -8,7 +8,7 @@ SVT_OK = 0
 SVT_E_INVALID_ARG, SVT_E_OOM, SVT_E_HIP, SVT_E_NUMERIC, SVT_E_STATE, SVT_E_LIMIT = -1, -2, -3, -4, -5, -6
 SVT_GRAD_FROZEN_BASIS, SVT_GRAD_DEVICE_POINTERS = 1, 2
 SVT_DTYPE_F64, SVT_DTYPE_F32 = 0, 1
-SVT_FP64, SVT_MIXED = 0, 1
+SVT_FP64, SVT_MIXED, SVT_BF16 = 0, 1, 2
 SVT_MODE_R4SVD, SVT_MODE_R3SVD, SVT_MODE_RSVD = 0, 1, 2
 SVT_F_CONVERGED, SVT_F_MAXIT, SVT_F_RMAX_HIT, SVT_F_EXHAUSTED, SVT_F_ANNEALED, SVT_F_EIG_INEXACT = 1, 2, 4, 8, 16, 32
 SVT_F_DIVERGING = 64

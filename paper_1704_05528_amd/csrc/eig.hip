@@ -8,6 +8,8 @@
 // kernel diagonalises.
 #include "svt_internal.h"
 
+#include <algorithm>
+
 namespace svt {
 
 namespace {
@@ -236,7 +238,120 @@ __global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int 
   D[(int64_t)i * ldc + c] = v / sg;
 }
 
+// ------------------------------------------------------------------------------------------
+// Bordering step of the inverse Cholesky factor of the stored basis's Gram, BF16 form.  With
+// G_Q = Q^T Q = L L^T for the stored (rounded, not orthonormal) basis Q and Linv = L^{-1} lower
+// triangular, appending w columns Q' gives the new block row [Linv21, Linv22] of Linv:
+//   L21 = (Linv11 Q^T Q')^T, L22 = chol(Q'^T Q' - L21 L21^T), Linv22 = L22^{-1},
+//   Linv21 = -Linv22 L21 Linv11.
+// Workgroup 0 factors S = Q'^T Q' - L21 L21^T (w <= 64, symmetrised, in LDS), inverts L22 (one
+// thread per column) and writes Linv22 into Linv and its transpose into LinvT; a pivot that is
+// not positive sets scal[slot] = 1 (else 0).  The other workgroups clear the strips
+// Linv[0:rq, rq:rq+w] and LinvT[rq:rq+w, 0:rq], which an earlier basis of other block widths may
+// have written.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_border_chol(const double* __restrict__ Gq22, int ldg,
+                                                     const double* __restrict__ P, int ldp, int w, int rq,
+                                                     double* __restrict__ Linv, double* __restrict__ LinvT, int ld,
+                                                     double* scal, int slot) {
+  if (blockIdx.x > 0) {
+    const int64_t total = (int64_t)rq * w;
+    for (int64_t e = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)(gridDim.x - 1) * blockDim.x) {
+      const int i = (int)(e / w), j = (int)(e % w);
+      Linv[(int64_t)i * ld + rq + j] = 0.0;
+      LinvT[(int64_t)(rq + j) * ld + i] = 0.0;
+    }
+    return;
+  }
+  __shared__ double A[64][65];
+  __shared__ double B[64][65];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double sij = 0.5 * (Gq22[(int64_t)i * ldg + j] + Gq22[(int64_t)j * ldg + i]);
+    if (P) sij -= 0.5 * (P[(int64_t)i * ldp + j] + P[(int64_t)j * ldp + i]);
+    A[i][j] = sij;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // right-looking Cholesky, lower triangle: column c scaled by its pivot's root, then the
+  // trailing lower triangle updated
+  for (int c = 0; c < w; ++c) {
+    const double d = A[c][c];
+    if (!(d > 0.0)) {  // uniform: every thread read the same pivot
+      if (tid == 0) bad = 1;
+      break;
+    }
+    const double lc = sqrt(d);
+    __syncthreads();  // every thread has read the pivot
+    for (int i = c + tid; i < w; i += blockDim.x) A[i][c] = (i == c) ? lc : A[i][c] / lc;
+    __syncthreads();
+    const int n1 = w - c - 1;
+    for (int e = tid; e < n1 * n1; e += blockDim.x) {
+      const int i = c + 1 + e / n1, j = c + 1 + e % n1;
+      if (j <= i) A[i][j] -= A[i][c] * A[j][c];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) scal[slot] = (double)bad;
+  if (bad) return;  // uniform
+  // inverse of the lower-triangular factor, one column per thread: L x = e_j
+  if (tid < w) {
+    const int j = tid;
+    for (int i = 0; i < w; ++i) {
+      double x = 0.0;
+      if (i == j) {
+        x = 1.0 / A[j][j];
+      } else if (i > j) {
+        double sacc = 0.0;
+        for (int l = j; l < i; ++l) sacc = fma(A[i][l], B[l][j], sacc);
+        x = -sacc / A[i][i];
+      }
+      B[i][j] = x;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    const double v = B[i][j];
+    Linv[(int64_t)(rq + i) * ld + rq + j] = v;
+    LinvT[(int64_t)(rq + j) * ld + rq + i] = v;
+  }
+}
+
+// scal[slot] = sum_i G[i][i] (fixed order: strided per-thread sums, then a tree)
+__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ G, int ld, int r, double* scal, int slot) {
+  __shared__ double red[256];
+  double sacc = 0.0;
+  for (int i = threadIdx.x; i < r; i += 256) sacc += G[(int64_t)i * ld + i];
+  red[threadIdx.x] = sacc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scal[slot] = red[0];
+}
+
 }  // namespace
+
+hipError_t launch_border_chol(hipStream_t s, const double* Gq22, int ldg, const double* P, int ldp, int w, int rq,
+                              double* Linv, double* LinvT, int ld, double* scal, int slot) {
+  if (w <= 0 || w > 64 || rq < 0) return hipErrorInvalidValue;
+  const int64_t strip = (int64_t)rq * w;
+  const unsigned extra = (unsigned)std::min<int64_t>(256, (strip + 255) / 256);
+  hipLaunchKernelGGL(k_border_chol, dim3(1 + extra), dim3(256), 0, s, Gq22, ldg, P, ldp, w, rq, Linv, LinvT, ld, scal,
+                     slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(hipStream_t s, const double* G, int ld, int r, double* scal, int slot) {
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, G, ld, r, scal, slot);
+  return hipGetLastError();
+}
 
 hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double* eval, double* evec, int ldv,
                          double* scal, int slot, int max_sweeps, int splits, int64_t sstride) {

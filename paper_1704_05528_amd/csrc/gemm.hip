@@ -66,9 +66,9 @@ __device__ inline int xcd_tile(int id, int total) {
   return x * per + min(x, rem) + slot;
 }
 
-template <class T, int GN>
+template <class T, int GN, class TB>
 __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A,
-                                                                     int lda, const T* __restrict__ B, int ldb,
+                                                                     int lda, const TB* __restrict__ B, int ldb,
                                                                      T* __restrict__ C, int ldc, int tiles_n) {
   using MM = Mfma16<T>;
   constexpr int KG = gemm_kgroups<T>(), DEPTH = gemm_depth<T>();
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
     for (int u = 0; u < BL; ++u) {
       const int e = tid + u * 256, kk = e / GN, j = e % GN;
       const int gk = k0 + kk, gj = n0 + j;
-      rb[p][u] = (gk < K && gj < N) ? B[(int64_t)gk * ldb + gj] : (T)0;
+      rb[p][u] = (gk < K && gj < N) ? (T)B[(int64_t)gk * ldb + gj] : (T)0;
     }
   };
   auto store_chunk = [&](auto P) {
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* _
 
 }  // namespace
 
-template <class T>
-hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc) {
+template <class T, class TB>
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc) {
   if (M == 0 || N == 0) return hipSuccess;
   if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
   const int tm = (M + kGM - 1) / kGM;
@@ -197,11 +197,11 @@ hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int ld
   auto load = [&](int gn) { return (int64_t)((tm * ((N + gn - 1) / gn) + 255) / 256) * gn; };
   if (load(48) < load(32)) {
     const int tn = (N + 47) / 48;
-    hipLaunchKernelGGL((k_gemm_nn<T, 48>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+    hipLaunchKernelGGL((k_gemm_nn<T, 48, TB>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
                        C, ldc, tn);
   } else {
     const int tn = (N + 31) / 32;
-    hipLaunchKernelGGL((k_gemm_nn<T, 32>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+    hipLaunchKernelGGL((k_gemm_nn<T, 32, TB>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
                        C, ldc, tn);
   }
   return hipGetLastError();
@@ -216,11 +216,13 @@ hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, c
 }
 
 #define SVT_GEMM_INST(T)                                                                                       \
-  template hipError_t launch_gemm_nn<T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int);   \
+  template hipError_t launch_gemm_nn<T, T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int); \
   template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*, \
                                                 int64_t);
 
 SVT_GEMM_INST(double)
 SVT_GEMM_INST(float)
+template hipError_t launch_gemm_nn<float, bf16>(hipStream_t, int, int, int, const float*, int, const bf16*, int, float*,
+                                                int);
 
 }  // namespace svt

@@ -9,6 +9,8 @@
 // then one workgroup adds the partials in index order.  No floating-point atomics are used.
 #include "svt_internal.h"
 
+#include <type_traits>
+
 #include <algorithm>
 
 namespace svt {
@@ -113,17 +115,64 @@ __global__ void k_set_unit(double* __restrict__ V, int rows, int ld, int c0, int
 // (idx = column indices, vperm = CSR->CSC map, D = Omega) it is X = Y Omega.
 // ------------------------------------------------------------------------------------------
 
+// Four consecutive entries of a row of D (float, double or bfloat16) as T, entries from `valid`
+// on as zero.  With vec (the four are in range and 16-byte aligned for float and double, 8-byte
+// aligned for bfloat16) they come as one or two vector loads.
+template <class T, class TD>
+__device__ inline void load_row4(const TD* src, bool vec, int valid, T (&d)[4]) {
+  if constexpr (std::is_same<TD, float>::value) {
+    if (vec) {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const f4 x = *reinterpret_cast<const f4*>(src);
+      d[0] = x.x;
+      d[1] = x.y;
+      d[2] = x.z;
+      d[3] = x.w;
+      return;
+    }
+  } else if constexpr (std::is_same<TD, double>::value) {
+    if (vec) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 v0 = reinterpret_cast<const d2*>(src)[0], v1 = reinterpret_cast<const d2*>(src)[1];
+      d[0] = v0.x;
+      d[1] = v0.y;
+      d[2] = v1.x;
+      d[3] = v1.y;
+      return;
+    }
+  } else {
+    static_assert(std::is_same<TD, bf16>::value, "float, double or bf16 rows");
+    if (vec) {
+      const uint2 x = *reinterpret_cast<const uint2*>(src);  // entries 0, 1 in x.x (low half first)
+      d[0] = (T)__builtin_bit_cast(float, x.x << 16);
+      d[1] = (T)__builtin_bit_cast(float, x.x & 0xffff0000u);
+      d[2] = (T)__builtin_bit_cast(float, x.y << 16);
+      d[3] = (T)__builtin_bit_cast(float, x.y & 0xffff0000u);
+      return;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) d[c] = (c < valid) ? (T)src[c] : (T)0;
+}
+
+// rows of D may be loaded four entries at a time: 16-byte (float, double) or 8-byte (bf16) alignment
+template <class TD>
+inline bool rows_vec4(const TD* D, int ldd) {
+  const uintptr_t align = sizeof(TD) == 2 ? 7u : 15u;
+  return (ldd % 4 == 0) && ((reinterpret_cast<uintptr_t>(D) & align) == 0);
+}
+
 // Narrow blocks (w <= 16): a segment is shared by SPLIT waves (1: one segment per wave; 4: one
 // per workgroup, for long segments); their lanes form 16 SPLIT groups of four, group gg takes the
 // nonzeros p0 + gg, p0 + gg + 16 SPLIT, ..., and lane q of a group the columns 4q .. 4q + 3 of D's
 // row (one 16-byte load for float when the row is aligned).  Each lane keeps four partial sums;
 // a wave adds its 16 groups with four butterfly steps, and the SPLIT waves' sums are added in
 // wave order (fixed order, deterministic).
-template <int WN, int SPLIT, class T>
+template <int WN, int SPLIT, class T, class TD>
 __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const int32_t* __restrict__ vperm, const T* __restrict__ val,
-                                                         const T* __restrict__ D, int ldd, T* __restrict__ out,
+                                                         const TD* __restrict__ D, int ldd, T* __restrict__ out,
                                                          int ldo, int w, const int32_t* __restrict__ seg_lo,
                                                          const int32_t* __restrict__ seg_hi,
                                                          const int32_t* __restrict__ skip) {
@@ -137,8 +186,9 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
   if (row >= nrows) return;                         // uniform over the waves of a segment
   if (skip != nullptr && skip[row] != 0) return;  // uniform over the waves of a segment
   const int gg = sub * 16 + (lane >> 2), c0 = (lane & 3) * 4;
-  const bool vec = (sizeof(T) == 4) && (c0 + 4 <= w) && (ldd % 4 == 0) &&
-                   ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
+  const uintptr_t align = sizeof(TD) == 2 ? 7u : 15u;
+  const bool vec = (sizeof(T) == 4 || sizeof(TD) == 2) && (c0 + 4 <= w) && (ldd % 4 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(D) & align) == 0);
   T acc[4] = {(T)0, (T)0, (T)0, (T)0};
   const int p0 = seg_lo ? seg_lo[row] : ptr[row], p1 = seg_lo ? seg_hi[row] : ptr[row + 1];
   for (int base = p0 + gg; base < p1; base += kG * kU) {
@@ -149,18 +199,7 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
       const bool ok = p < p1;
       const int pc = ok ? p : p0;  // a valid position (the segment is not empty here)
       v[u] = ok ? val[vperm ? vperm[pc] : pc] : (T)0;
-      const T* src = D + (int64_t)idx[pc] * ldd + c0;
-      if (vec) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 x = *reinterpret_cast<const f4*>(src);
-        d[u][0] = x.x;
-        d[u][1] = x.y;
-        d[u][2] = x.z;
-        d[u][3] = x.w;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) d[u][c] = (c0 + c < w) ? src[c] : (T)0;
-      }
+      load_row4<T, TD>(D + (int64_t)idx[pc] * ldd + c0, vec, w - c0, d[u]);
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
@@ -200,11 +239,11 @@ __global__ __launch_bounds__(256) void k_seg_spmm_narrow(int nrows, const int32_
 // Segment forms: with seg_lo / seg_hi, "row" s is the position range [seg_lo[s], seg_hi[s]) and
 // writes out row s (the chunk partials of long segments); with skip, rows whose flag is set are
 // left to that chunked form.
-template <int CPL, bool VEC, class T>
+template <int CPL, bool VEC, class T, class TD>
 __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ vperm, const T* __restrict__ val,
-                                                       const T* __restrict__ D, int ldd, T* __restrict__ out, int ldo,
+                                                       const TD* __restrict__ D, int ldd, T* __restrict__ out, int ldo,
                                                        int w, const int32_t* __restrict__ seg_lo,
                                                        const int32_t* __restrict__ seg_hi,
                                                        const int32_t* __restrict__ skip) {
@@ -218,29 +257,7 @@ __global__ __launch_bounds__(256) void k_seg_spmm_wide(int nrows, const int32_t*
   T acc[CPL];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = (T)0;
-  auto load4 = [&](int ii, T (&d)[CPL]) {
-    const T* src = D + (int64_t)ii * ldd + c0;
-    if (vec) {
-      if constexpr (sizeof(T) == 4) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 v = *reinterpret_cast<const f4*>(src);
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
-      } else {
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        const d2 v0 = reinterpret_cast<const d2*>(src)[0], v1 = reinterpret_cast<const d2*>(src)[1];
-        d[0] = v0.x;
-        d[1] = v0.y;
-        d[2] = v1.x;
-        d[3] = v1.y;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) d[c] = (c0 + c < w) ? src[c] : (T)0;
-    }
-  };
+  auto load4 = [&](int ii, T (&d)[CPL]) { load_row4<T, TD>(D + (int64_t)ii * ldd + c0, vec, w - c0, d); };
   const int p0 = seg_lo ? seg_lo[row] : ptr[row], p1 = seg_lo ? seg_hi[row] : ptr[row + 1];
   for (int base = p0; base < p1; base += kWave) {
     const int p = base + lane;
@@ -305,10 +322,10 @@ __global__ __launch_bounds__(256) void k_seg_chunk_sum(const int32_t* __restrict
 // ------------------------------------------------------------------------------------------
 constexpr int kTR = 32, kTJ = 64, kTC = 64;
 
-template <class T>
+template <class T, class TQ>
 __global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_t* __restrict__ rowidx,
                                                       const int32_t* __restrict__ tstart, int nt,
-                                                      const T* __restrict__ val, const T* __restrict__ Q, int ldq,
+                                                      const T* __restrict__ val, const TQ* __restrict__ Q, int ldq,
                                                       int r, T* __restrict__ out, int ldo, int tiles_per_split,
                                                       int64_t split_stride) {
   __shared__ T Ys[kTR][kTJ + 2];
@@ -330,7 +347,7 @@ __global__ __launch_bounds__(256) void k_spmm_t_tiled(int m, int n, const int32_
     for (int e = tid; e < kTR * kTJ; e += 256) Ys[e / kTJ][e % kTJ] = (T)0;
     for (int e = tid; e < kTR * kTC; e += 256) {
       const int i = e / kTC, c = e % kTC;
-      Qs[i][c] = (i0 + i < m && c0 + c < r) ? Q[(int64_t)(i0 + i) * ldq + c0 + c] : (T)0;
+      Qs[i][c] = (i0 + i < m && c0 + c < r) ? (T)Q[(int64_t)(i0 + i) * ldq + c0 + c] : (T)0;
     }
     __syncthreads();
     if (gj < n) {
@@ -1329,30 +1346,30 @@ hipError_t launch_set_unit(hipStream_t s, double* V, int rows, int ld, int c0, i
   return hipGetLastError();
 }
 
-template <class T>
+template <class T, class TD>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
+                           const T* val, const TD* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
                            const SegChunks* ch) {
   if (nrows == 0 || w == 0) return hipSuccess;
   constexpr int CPL = 4;
   const unsigned gy = (unsigned)((w + kWave * CPL - 1) / (kWave * CPL));
-  const bool vec = (ldd % CPL == 0) && ((reinterpret_cast<uintptr_t>(D) & 15u) == 0);
+  const bool vec = rows_vec4(D, ldd);
   // one wave per segment: segments [ptr[q], ptr[q+1]) or, with lo given, [lo[q], hi[q]); narrow
   // blocks give a whole workgroup to each segment when segments average 256 positions or more
   auto segments = [&](int nseg, T* o, int ldo_, const int32_t* lo, const int32_t* hi, const int32_t* skip,
                       bool long_segments) {
     const unsigned gx = (unsigned)((nseg + 3) / 4);
     if (w <= kNarrow && long_segments)
-      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 4, T>), dim3(nseg), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 4, T, TD>), dim3(nseg), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
                          D, ldd, o, ldo_, w, lo, hi, skip);
     else if (w <= kNarrow)
-      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 1, T>), dim3(gx), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+      hipLaunchKernelGGL((k_seg_spmm_narrow<kNarrow, 1, T, TD>), dim3(gx), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
                          D, ldd, o, ldo_, w, lo, hi, skip);
     else if (vec)
-      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, true, T, TD>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
                          D, ldd, o, ldo_, w, lo, hi, skip);
     else
-      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, false, T>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
+      hipLaunchKernelGGL((k_seg_spmm_wide<CPL, false, T, TD>), dim3(gx, gy), dim3(256), 0, s, nseg, ptr, idx, vperm, val,
                          D, ldd, o, ldo_, w, lo, hi, skip);
     return hipGetLastError();
   };
@@ -1370,9 +1387,9 @@ hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const i
   return hipGetLastError();
 }
 
-template <class T>
+template <class T, class TQ>
 hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
-                               const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
+                               const T* val, const TQ* Q, int ldq, int r, T* W, int ldw, double* partial,
                                int64_t partial_cap) {
   if (n == 0 || r == 0) return hipSuccess;
   const int nt = tiled_row_tiles(m);
@@ -1382,13 +1399,13 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
   const int tps = (nt + splits - 1) / splits;
   splits = (nt + tps - 1) / tps;
   if (splits == 1) {
-    hipLaunchKernelGGL(k_spmm_t_tiled<T>, dim3(gx, gy, 1), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
+    hipLaunchKernelGGL((k_spmm_t_tiled<T, TQ>), dim3(gx, gy, 1), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq, r,
                        W, ldw, tps, (int64_t)0);
     return hipGetLastError();
   }
   T* part = reinterpret_cast<T*>(partial);
   const int64_t stride = (int64_t)n * r;
-  hipLaunchKernelGGL(k_spmm_t_tiled<T>, dim3(gx, gy, splits), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq,
+  hipLaunchKernelGGL((k_spmm_t_tiled<T, TQ>), dim3(gx, gy, splits), dim3(256), 0, s, m, n, rowidx, tstart, nt, val, Q, ldq,
                      r, part, r, tps, stride);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1702,10 +1719,10 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
 // explicit instantiations for the two storage types
 #define SVT_INST(T)                                                                                                   \
   template hipError_t launch_omega<T>(hipStream_t, T*, int, int, int, int, uint64_t, uint64_t, uint64_t);             \
-  template hipError_t launch_seg_spmm<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*, const T*,  \
-                                         const T*, int, T*, int, int, int64_t, int, const SegChunks*);                \
-  template hipError_t launch_spmm_t_tiled<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,         \
-                                             const T*, int, int, T*, int, double*, int64_t);                          \
+  template hipError_t launch_seg_spmm<T, T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*,        \
+                                            const T*, const T*, int, T*, int, int, int64_t, int, const SegChunks*);   \
+  template hipError_t launch_spmm_t_tiled<T, T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,      \
+                                                const T*, int, int, T*, int, double*, int64_t);                       \
   template hipError_t launch_tn_narrow<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*, int,  \
                                              double*, int64_t);                                                       \
   template hipError_t launch_tn_partial<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*,      \
@@ -1748,5 +1765,20 @@ template hipError_t launch_tn_narrow<float, double>(hipStream_t, int, const floa
 template hipError_t launch_copy_cols<float, double>(hipStream_t, int, const float*, int, double*, int, int);
 template hipError_t launch_copy_cols<double, float>(hipStream_t, int, const double*, int, float*, int, int);
 template hipError_t launch_scale_copy<double, float>(hipStream_t, int64_t, const double*, double, float*);
+
+// the BF16 form: a bfloat16 basis with float32 iterate, projections and factors
+template hipError_t launch_seg_spmm<float, bf16>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*,
+                                                 const float*, const bf16*, int, float*, int, int, int64_t, int,
+                                                 const SegChunks*);
+template hipError_t launch_spmm_t_tiled<float, bf16>(hipStream_t, int, int, const int32_t*, const int32_t*,
+                                                     const float*, const bf16*, int, int, float*, int, double*,
+                                                     int64_t);
+template hipError_t launch_tn_narrow<bf16, float>(hipStream_t, int, const bf16*, int, int, const float*, int, int,
+                                                  double*, int, double*, int64_t);
+template hipError_t launch_tn_narrow<bf16, bf16>(hipStream_t, int, const bf16*, int, int, const bf16*, int, int,
+                                                 double*, int, double*, int64_t);
+template hipError_t launch_rowmul<bf16, double, float>(hipStream_t, int, int, const bf16*, int, const double*, int,
+                                                       float*, int, int, double, double, double*);
+template hipError_t launch_copy_cols<float, bf16>(hipStream_t, int, const float*, int, bf16*, int, int);
 
 }  // namespace svt

@@ -64,7 +64,7 @@ constexpr int kDivergeRun = 5;        // iterations in a row with the residual a
 constexpr double kInitWaitSeconds = 600.0;  // host wait limit inside svt_init (before the caller's applies)
 
 // scalar slots of the device readback buffer
-enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_SWEEPS = 6, S_NORMY = 7, S_A = 8, S_B = 9, S_TBAR = 10,
+enum { S_NORMB = 0, S_WK1 = 1, S_WK2 = 2, S_NADD = 3, S_BORDER = 4, S_SWEEPS = 6, S_NORMY = 7, S_A = 8, S_B = 9, S_TBAR = 10,
        S_DOT = 11, S_RES2 = 12, S_YN2 = 13, S_ABS = 14, S_MAE = 15, S_JOFF = 16 /* and 17 */ };
 
 #define HIPCHK(expr)                                                     \
@@ -256,17 +256,20 @@ svt_status jacobi_full(Handle* h, const JacobiWork& w, int n, double* eval, doub
 }
 
 // ==============================================================================================
-// The engine, templated on the storage type
+// The engine, templated on the storage type T and the storage type TQ of the basis (T, or
+// bfloat16 in the BF16 form, whose projected SVD goes through the exact projector onto the span
+// of the stored basis: see border() and correct_gram())
 // ==============================================================================================
-template <class T>
+template <class T, class TQ = T>
 struct Engine {
+  static constexpr bool kBF16 = std::is_same<TQ, bf16>::value;
   Handle* h;
   explicit Engine(Handle* hh) : h(hh) {}
 
   T* a() const { return (T*)h->a; }
   T* y() const { return (T*)h->y; }
   T* y_next() const { return (T*)h->y_next; }
-  T* Q() const { return (T*)h->Q; }
+  TQ* Q() const { return (TQ*)h->Q; }
   T* W() const { return (T*)h->W; }
   T* X() const { return (T*)h->X; }
   T* X2() const { return (T*)h->X2; }
@@ -401,13 +404,72 @@ struct Engine {
   // out = Y^T D: a matrix-core product with the dense copy of Y when at least a quarter of the
   // entries are observed and D has 32 columns or more (the copy is refreshed at the start of
   // every R4SVD call), else the CSC gather kernel
-  svt_status spmm_yt(const T* D, int ldd, T* out, int ldo, int w) {
+  template <class TD>
+  svt_status spmm_yt(const TD* D, int ldd, T* out, int ldo, int w) {
     if (h->yT && w >= 32) {  // narrow blocks stay on the sparse kernel (too few output tiles)
       HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo));
       return SVT_OK;
     }
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w,
                               h->nnz, h->max_col_nnz, &h->csc_long));
+    return SVT_OK;
+  }
+
+  // ----------------------------------------------------------------------------------------
+  // BF16 form.  The stored basis Q (bfloat16) is not orthonormal; with G_Q = Q^T Q = L L^T the
+  // basis Q_o = Q L^{-T} is, and it spans the same space, so the projection of Alg. 3 is taken
+  // on Q_o: B_o = Q_o^T Y = L^{-1} W^T (W = Y^T Q).  Linv = L^{-1} (lower) and its transpose
+  // LinvT are kept for the current basis and bordered whenever columns are appended.
+  // border(): extend Linv by the w columns appended at rq (see launch_border_chol); with
+  // energy, scal[S_NADD] = ||Y^T Q_o'||_F^2 for the new orthonormal directions Q_o' =
+  // Q Linv[rq:rq+w, :]^T, the energy they add to ||B_o||_F^2 (Eq. 11).
+  // ----------------------------------------------------------------------------------------
+  svt_status border(int rq, int w, bool energy) {
+    if constexpr (kBF16) {
+      hipStream_t s = h->stream;
+      const int m = (int)h->m, n = (int)h->n, ld = h->r_cap, lw = h->w_cap;
+      // Gq = Q[:, 0:rq+w]^T Q[:, rq:rq+w], (rq + w) x w
+      HIPCHK((launch_tn_narrow<TQ, TQ>(s, m, Q(), ld, rq + w, Q() + rq, ld, w, h->T, lw, h->partial,
+                                       h->partial_cap)));
+      const double* P = nullptr;
+      if (rq > 0) {
+        // L21^T = Linv11 Gq[0:rq, :] and P = L21 L21^T
+        HIPCHK((launch_rowmul<double, double, double>(s, rq, rq, h->Linv, ld, h->T, lw, h->Lw, lw, w, 1.0, 0.0)));
+        HIPCHK((launch_tn_narrow<double, double>(s, rq, h->Lw, lw, w, h->Lw, lw, w, h->small, w, h->partial,
+                                                 h->partial_cap)));
+        P = h->small;
+      }
+      HIPCHK(launch_border_chol(s, h->T + (size_t)rq * lw, lw, P, w, w, rq, h->Linv, h->LinvT, ld, h->scal,
+                                S_BORDER));
+      if (rq > 0) {
+        // Linv21^T = -(LinvT11 L21^T) Linv22^T into LinvT[0:rq, rq:rq+w], and its transpose into Linv
+        HIPCHK((launch_rowmul<double, double, double>(s, rq, rq, h->LinvT, ld, h->Lw, lw, h->Lw2, lw, w, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<double, double, double>(s, rq, w, h->Lw2, lw, h->LinvT + (size_t)rq * ld + rq, ld,
+                                                      h->LinvT + rq, ld, w, -1.0, 0.0)));
+        HIPCHK(launch_transpose(s, h->LinvT + rq, ld, rq, w, h->Linv + (size_t)rq * ld, ld));
+      }
+      if (energy) {
+        // Y^T Q_o' = W[:, 0:rq+w] LinvT[0:rq+w, rq:rq+w]
+        HIPCHK((launch_rowmul<T, double, T>(s, n, rq + w, W(), ld, h->LinvT + rq, ld, Om(), lw, w, 1.0, 0.0)));
+        HIPCHK(launch_sumsq_cols<T>(s, n, Om(), lw, 0, w, h->partial, h->scal, S_NADD));
+      }
+      const double rq_ = rq, w_ = w, mm = m;
+      add_work(h, SVT_PH_GROW, 2.0 * mm * (rq_ + 2.0 * w_) + 8.0 * (2.0 * rq_ * rq_ + 4.0 * rq_ * w_),
+               2.0 * mm * (rq_ + w_) * w_ + 4.0 * rq_ * rq_ * w_ + (energy ? 2.0 * n * (rq_ + w_) * w_ : 0.0));
+    }
+    return SVT_OK;
+  }
+
+  // BF16 form: G <- Linv G Linv^T, the Gram B_o B_o^T of the projection on the orthonormal basis
+  // Q_o (its eigenpairs are those of svd(B_o)); with slot >= 0 its trace ||B_o||_F^2 goes to
+  // scal[slot].  G2 serves as scratch (the eigensolver forms G^2 afresh when it needs it).
+  svt_status correct_gram(int r, int slot) {
+    hipStream_t s = h->stream;
+    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->Linv, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap));
+    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G2, h->r_cap, h->LinvT, h->r_cap, h->G, h->r_cap));
+    if (slot >= 0) HIPCHK(launch_trace(s, h->G, h->r_cap, r, h->scal, slot));
+    const double rr = r;
+    add_work(h, SVT_PH_GRAM, 8.0 * 4.0 * rr * rr, 4.0 * rr * rr * rr);
     return SVT_OK;
   }
 
@@ -446,17 +508,29 @@ struct Engine {
         HIPCHK(launch_colnorms<T>(s, m, X(), ld, wc, h->small, h->partial, h->partial_cap, h->prenorm));
         if (rq > 0) {
           for (int pass = 0; pass < 2; ++pass) {
-            HIPCHK((launch_tn_narrow<T, T>(s, m, Q(), h->r_cap, rq, X(), ld, wc, h->T, ld, h->partial,
-                                           h->partial_cap)));
-            HIPCHK((launch_rowmul<T, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0)));
+            HIPCHK((launch_tn_narrow<TQ, T>(s, m, Q(), h->r_cap, rq, X(), ld, wc, h->T, ld, h->partial,
+                                            h->partial_cap)));
+            HIPCHK((launch_rowmul<TQ, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0)));
           }
         }
         CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm));
-        HIPCHK((launch_copy_cols<T, T>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
+        HIPCHK((launch_copy_cols<T, TQ>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
         CHK(spmm_yt(Q() + rq, h->r_cap, W() + rq, h->r_cap, wc));
-        HIPCHK(launch_sumsq_cols<T>(s, n, W(), h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
+        if constexpr (!kBF16)
+          HIPCHK(launch_sumsq_cols<T>(s, n, W(), h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
       }
-      CHK(readback(h, S_NADD + 1));
+      if constexpr (kBF16) {
+        // the kept columns are rounded to bfloat16 in Q: extend the inverse Cholesky factor of the
+        // stored basis's Gram by them; the new orthonormal directions carry the added energy
+        CHK(readback(h, S_WK2 + 1));
+        const int kept = (int)h->hscal[S_WK2];
+        PhaseTimer tm(h, SVT_PH_GROW);
+        if (kept > 0) CHK(border(rq, kept, true));
+        else HIPCHK(hipMemsetAsync(h->scal + S_NADD, 0, 2 * sizeof(double), s));
+      }
+      CHK(readback(h, S_BORDER + 1));
+      if (kBF16 && h->hscal[S_BORDER] != 0.0)
+        return fail(h, SVT_E_NUMERIC, "the Gram of the bfloat16 basis lost positive definiteness");
       const int kept = (int)h->hscal[S_WK2];
       if (kept == wc)
         h->cur_chunks.push_back({it, blk, c0, wc, rq});
@@ -556,6 +630,10 @@ struct Engine {
     h->cur_chunks.clear();
     const bool pre = h->spec_ready && h->r > 0;  // leading work already enqueued (see iteration())
     h->spec_ready = false;
+    // BF16 form: G holds the corrected Gram of the current basis when the leading work or the
+    // recycled-basis branch below formed it and no block has been appended since
+    h->gp_now = pre && h->gp_valid;
+    h->gp_valid = false;
     if (h->yT && !pre) {
       PhaseTimer tm(h, SVT_PH_DENSIFY, work_bytes(SVT_PH_DENSIFY));
       CHK(run_densify());
@@ -570,12 +648,19 @@ struct Engine {
       if (got == 0) return fail(h, SVT_E_NUMERIC, "the first sampled block has no nonzero direction (Y = 0?)");
       h->r = got;
       normB = add;
+      h->gp_now = false;
     } else {
       {
         PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
         CHK(run_spmm_t());
       }
-      {
+      if constexpr (kBF16) {
+        // ||B_o||_F^2 = trace(Linv W^T W Linv^T): the corrected Gram, kept for the projected SVD
+        PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
+        CHK(run_gram());
+        CHK(correct_gram(h->r, S_NORMB));
+        h->gp_now = true;
+      } else {
         PhaseTimer tm(h, SVT_PH_REDUCE);
         HIPCHK(launch_sumsq_cols<T>(h->stream, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
       }
@@ -610,6 +695,7 @@ struct Engine {
       int got = 0;
       double add = 0.0;
       CHK(append_block(it, blk, room, &got, &add));
+      h->gp_now = false;
       if (got == 0) {
         st->flags |= SVT_F_EXHAUSTED;
         break;
@@ -708,7 +794,11 @@ struct Engine {
     const double tau2 = h->p.tau * h->p.tau;
     {
       PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
-      CHK(run_gram());
+      if (!(kBF16 && h->gp_now)) {
+        CHK(run_gram());
+        if constexpr (kBF16) CHK(correct_gram(r, -1));
+      }
+      h->gp_now = false;
     }
     std::vector<double> theta(std::max(2 * kEB, r)), res(kEB);
     const double* S = nullptr;       // eigenvectors of G as columns (descending)
@@ -958,12 +1048,24 @@ struct Engine {
                     2.0 * (double)(h->m + h->n) * r * k);
       HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf));
       HIPCHK((launch_copy_cols<double, double>(s, r, S, lds_, h->Sk, h->ldf, k)));
-      // Ut = Q C and Vt = W D side by side in one launch
-      const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0,
-                                           nullptr};
-      const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0, 0.0,
-                                           nullptr};
-      HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
+      if constexpr (kBF16) {
+        // U_L = Q_o U_B = Q (Linv^T U_B) and V_L = B_o^T U_B diag(1/sigma) = W (Linv^T U_B) diag(1/sigma):
+        // C, D and the kept eigenvectors taken from the left by Linv^T
+        for (double* Mx : {h->C, h->D, h->Sk}) {
+          HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->LinvT, h->r_cap, Mx, h->ldf, h->Ctmp, h->ldf, k,
+                                                        1.0, 0.0)));
+          HIPCHK((launch_copy_cols<double, double>(s, r, h->Ctmp, h->ldf, Mx, h->ldf, k)));
+        }
+        HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0, 0.0)));
+      } else {
+        // Ut = Q C and Vt = W D side by side in one launch
+        const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0,
+                                             0.0, nullptr};
+        const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0,
+                                             0.0, nullptr};
+        HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
+      }
     }
     h->have_factors = true;
     return SVT_OK;
@@ -976,6 +1078,9 @@ struct Engine {
   // ----------------------------------------------------------------------------------------
   svt_status recycle_truncated() {
     if (h->p.mode != SVT_MODE_R4SVD || h->p.recycle_extra < 0) return SVT_OK;
+    if constexpr (kBF16) {
+      return fail(h, SVT_E_STATE, "the BF16 form recycles the whole stored basis");
+    } else {
     const int r = h->r, keep = std::min(r, h->k + h->p.recycle_extra);
     if (keep >= r) return SVT_OK;
     if (keep > h->ldf) return fail(h, SVT_E_LIMIT, "truncated recycling keeps more vectors than kmax");
@@ -1001,6 +1106,7 @@ struct Engine {
     h->ev_rows = keep;
     h->fe_rows = h->full_mode ? keep : 0;
     return SVT_OK;
+    }
   }
 
   // The leading work of an R4SVD call on the current Y and basis: the dense copy of Y, W = Y^T Q and
@@ -1015,7 +1121,12 @@ struct Engine {
       PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
       CHK(run_spmm_t());
     }
-    {
+    if constexpr (kBF16) {
+      PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
+      CHK(run_gram());
+      CHK(correct_gram(h->r, S_NORMB));
+      h->gp_valid = true;
+    } else {
       PhaseTimer tm(h, SVT_PH_REDUCE);
       HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
     }
@@ -1175,18 +1286,27 @@ struct Engine {
     return SVT_OK;
   }
 
+  // the basis is stored as TQ (rounded to bfloat16 in the BF16 form, whose inverse Cholesky factor
+  // is then rebuilt by bordering in 64-column steps)
   svt_status set_basis(const double* Qh, int r) {
-    std::vector<T> buf((size_t)h->m * r);
-    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (T)Qh[i];
-    HIPCHK(hipMemcpy2DAsync(Q(), h->r_cap * sizeof(T), buf.data(), r * sizeof(T), r * sizeof(T), h->m,
+    std::vector<TQ> buf((size_t)h->m * r);
+    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (TQ)Qh[i];
+    HIPCHK(hipMemcpy2DAsync(Q(), h->r_cap * sizeof(TQ), buf.data(), r * sizeof(TQ), r * sizeof(TQ), h->m,
                             hipMemcpyHostToDevice, h->stream));
+    if constexpr (kBF16) {
+      for (int c0 = 0; c0 < r; c0 += h->w_cap) {
+        CHK(border(c0, std::min(h->w_cap, r - c0), false));
+        CHK(readback(h, S_BORDER + 1));
+        if (h->hscal[S_BORDER] != 0.0) return fail(h, SVT_E_INVALID_ARG, "the basis is (numerically) rank deficient");
+      }
+    }
     CHK(wait_stream(h));
     return SVT_OK;
   }
 
   svt_status get_basis(double* Qh, int qcap) {
-    std::vector<T> buf((size_t)h->m * h->r);
-    HIPCHK(hipMemcpy2DAsync(buf.data(), h->r * sizeof(T), Q(), h->r_cap * sizeof(T), h->r * sizeof(T), h->m,
+    std::vector<TQ> buf((size_t)h->m * h->r);
+    HIPCHK(hipMemcpy2DAsync(buf.data(), h->r * sizeof(TQ), Q(), h->r_cap * sizeof(TQ), h->r * sizeof(TQ), h->m,
                             hipMemcpyDeviceToHost, h->stream));
     CHK(wait_stream(h));
     for (int64_t i = 0; i < h->m; ++i)
@@ -1216,7 +1336,11 @@ struct Engine {
   }
   svt_status device_state(bool save, std::vector<char>& blob, size_t& pos) {
     CHK(copy_rows<T>(save, blob, pos, y(), 1, h->nnz, h->nnz));
-    CHK(copy_rows<T>(save, blob, pos, Q(), h->m, h->r, h->r_cap));
+    CHK(copy_rows<TQ>(save, blob, pos, Q(), h->m, h->r, h->r_cap));
+    if constexpr (kBF16) {
+      CHK(copy_rows<double>(save, blob, pos, h->Linv, h->r, h->r, h->r_cap));
+      CHK(copy_rows<double>(save, blob, pos, h->LinvT, h->r, h->r, h->r_cap));
+    }
     CHK(copy_rows<double>(save, blob, pos, h->EV, h->ev_rows, kEB, kEB));
     if (h->fe_rows > 0) {
       if (!save) CHK(ensure_full_work());
@@ -1236,7 +1360,7 @@ struct Engine {
     std::vector<T> buf;
     if (dev) {  // straight into the caller's device matrices (row-major, kcap columns, float64)
       if (U) {
-        HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
+        HIPCHK((launch_rowmul<TQ, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
                                             kk, 1.0, 0.0)));
         HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->m, Utmp(), h->ldf, U, kcap, kk)));
       }
@@ -1244,7 +1368,7 @@ struct Engine {
       return SVT_OK;
     }
     if (U) {
-      HIPCHK((launch_rowmul<T, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
+      HIPCHK((launch_rowmul<TQ, double, T>(h->stream, (int)h->m, h->r, Q(), h->r_cap, h->Sk, h->ldf, Utmp(), h->ldf,
                                           kk, 1.0, 0.0)));
       buf.resize((size_t)h->m * h->ldf);
       CHK(to_host<T>(h, buf.data(), Utmp(), buf.size()));
@@ -1289,6 +1413,10 @@ template <class F>
 svt_status dispatch(Handle* h, F&& f) {
   if (h->p.precision == SVT_MIXED) {
     Engine<float> e(h);
+    return f(e);
+  }
+  if (h->p.precision == SVT_BF16) {
+    Engine<float, bf16> e(h);
     return f(e);
   }
   Engine<double> e(h);
@@ -1655,7 +1783,7 @@ void release(Handle* h) {
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal,
                   h->JA, h->JV, h->FM, h->FEt, h->FEU, h->Fval, h->Jpin, h->Jtol, h->Jpart, h->Jperm, h->Jflag,
                   h->csc_long.lo, h->csc_long.hi, h->csc_long.lcol, h->csc_long.lfirst, h->csc_long.skip,
-                  h->csc_long.P};
+                  h->csc_long.P, h->Linv, h->LinvT, h->Lw, h->Lw2, h->Ctmp};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
@@ -1819,7 +1947,9 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   if (p.dt <= 0) p.dt = 10;
   if (p.maxit <= 0) p.maxit = 500;
   if (p.npow < 0) return bad("npow must be non-negative");
-  if (p.precision != SVT_FP64 && p.precision != SVT_MIXED) return bad("unknown precision form");
+  if (p.precision != SVT_FP64 && p.precision != SVT_MIXED && p.precision != SVT_BF16) return bad("unknown precision form");
+  if (p.precision == SVT_BF16 && p.recycle_extra >= 0)
+    return bad("the BF16 form recycles the whole stored basis: truncated recycling is not available");
   if (p.mode != SVT_MODE_R4SVD && p.mode != SVT_MODE_R3SVD && p.mode != SVT_MODE_RSVD) return bad("unknown mode");
   if (p.mode == SVT_MODE_RSVD && p.rank <= 0) return bad("the RSVD mode needs rank > 0");
   if (p.mode == SVT_MODE_RSVD && p.oversample < 0) return bad("oversample must be non-negative");
@@ -1928,7 +2058,8 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   h->partial_cap = std::max<int64_t>((int64_t)h->r_cap * h->r_cap, (int64_t)1 << 22);
   h->partial_cap = std::max<int64_t>(h->partial_cap, (int64_t)h->r_cap * kEigMax * 4);
   h->partial_cap = std::max<int64_t>(h->partial_cap, 3 * ((int64_t)ccol.size() / 4 + 2));  // fused-update sums
-  const size_t es = (p.precision == SVT_MIXED) ? sizeof(float) : sizeof(double);
+  const size_t es = (p.precision == SVT_FP64) ? sizeof(double) : sizeof(float);
+  const size_t esq = (p.precision == SVT_BF16) ? sizeof(bf16) : es;  // the basis
   const size_t mx = (size_t)std::max(m, n);
 
   hipError_t e = hipSuccess;
@@ -1943,7 +2074,14 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc_bytes(&h->a, nnz * es));
   A(dalloc_bytes(&h->y, nnz * es));
   A(dalloc_bytes(&h->y_next, nnz * es));
-  A(dalloc_bytes(&h->Q, (size_t)m * h->r_cap * es));
+  A(dalloc_bytes(&h->Q, (size_t)m * h->r_cap * esq));
+  if (p.precision == SVT_BF16) {
+    A(dalloc(&h->Linv, (size_t)h->r_cap * h->r_cap));
+    A(dalloc(&h->LinvT, (size_t)h->r_cap * h->r_cap));
+    A(dalloc(&h->Lw, (size_t)h->r_cap * h->w_cap));
+    A(dalloc(&h->Lw2, (size_t)h->r_cap * h->w_cap));
+    A(dalloc(&h->Ctmp, (size_t)h->r_cap * h->ldf));
+  }
   A(dalloc_bytes(&h->W, (size_t)n * h->r_cap * es));
   A(dalloc_bytes(&h->X, (size_t)m * h->w_cap * es));
   A(dalloc_bytes(&h->X2, (size_t)m * h->w_cap * es));
@@ -2014,7 +2152,9 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     up(h->csc_long.lfirst, lfirst.data(), lfirst.size() * sizeof(int32_t));
     up(h->csc_long.skip, lskip.data(), lskip.size() * sizeof(int32_t));
   }
-  if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * es, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->Q, 0, (size_t)m * h->r_cap * esq, h->stream);
+  if (e == hipSuccess && h->Linv) e = hipMemsetAsync(h->Linv, 0, (size_t)h->r_cap * h->r_cap * sizeof(double), h->stream);
+  if (e == hipSuccess && h->LinvT) e = hipMemsetAsync(h->LinvT, 0, (size_t)h->r_cap * h->r_cap * sizeof(double), h->stream);
   if (e == hipSuccess && h->yT) e = hipMemsetAsync(h->yT, 0, (size_t)m * n * es, h->stream);
   // factor buffers start at zero: the fused update reads whole 16-byte vectors of a factor row and
   // multiplies the columns beyond k by zeros, which then must be finite

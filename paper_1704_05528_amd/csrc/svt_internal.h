@@ -20,6 +20,23 @@ constexpr int kSpecSlot = 48;  // host slot of the next iteration's ||W||^2 (pas
 constexpr int kStageDoubles = 4096;  // pinned staging doubles for small device->host copies
 constexpr int kSddmmChunk = 256;  // most CSC positions one wave of the fused sampled update takes
 
+// bfloat16 storage (the basis of the BF16 form): the upper half of a float32.  Conversion from
+// float rounds to nearest, ties to even; conversion to float is exact.
+struct bf16 {
+  uint16_t bits;
+  bf16() = default;
+  __host__ __device__ explicit bf16(float f) : bits(round(f)) {}
+  __host__ __device__ explicit bf16(double d) : bits(round((float)d)) {}
+  __host__ __device__ explicit bf16(int i) : bits(round((float)i)) {}
+  __host__ __device__ operator float() const { return __builtin_bit_cast(float, (uint32_t)bits << 16); }
+  __host__ __device__ static uint16_t round(float f) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays a (quiet) NaN
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+};
+static_assert(sizeof(bf16) == 2, "bf16 is two bytes");
+
 // Newton-Raphson refinement (two steps each, quadratic convergence from the hardware estimates)
 // of the double reciprocal and reciprocal square root: short dependent chains for the small
 // one-workgroup factorisations, where an IEEE division sits on the critical path.
@@ -138,6 +155,12 @@ struct Handle {
   double* C = nullptr;     // r_cap x ldf
   double* D = nullptr;     // r_cap x ldf
   double* Sk = nullptr;    // r_cap x ldf, eigenvectors of the Gram for sigma > tau
+
+  // BF16 form: inverse Cholesky factor of the stored basis's Gram Q^T Q (lower, r_cap x r_cap), its
+  // transpose, and scratch for the bordering steps and the factor coefficients
+  double *Linv = nullptr, *LinvT = nullptr, *Lw = nullptr, *Lw2 = nullptr, *Ctmp = nullptr;
+  bool gp_valid = false;  // the leading work left the corrected Gram of the current basis in G
+  bool gp_now = false;    // G holds it within the current R4SVD call
   int32_t k = 0;
   std::vector<double> sigma_k;  // host copy of the k singular values above tau
 
@@ -216,17 +239,17 @@ hipError_t launch_omega(hipStream_t s, T* om, int n, int c0, int w, int ld, uint
 // sums in ch->P, instead of on one wave each.
 constexpr int kNarrowSplitLen = 256;   // narrow blocks: a workgroup per segment from this mean length on,
 constexpr int kNarrowSplitMax = 1024;  // or from this longest segment on
-template <class T>
+template <class T, class TD>
 hipError_t launch_seg_spmm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* vperm,
-                           const T* val, const T* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
+                           const T* val, const TD* D, int ldd, T* out, int ldo, int w, int64_t total, int max_len,
                            const SegChunks* ch = nullptr);
 
 // LDS-tiled W = Y^T Q for densely sampled patterns; tstart holds, for every column j, the CSC
 // position of its first entry in each row tile (n x (tiled_row_tiles(m) + 1) int32)
 int tiled_row_tiles(int64_t m);
-template <class T>
+template <class T, class TQ>
 hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowidx, const int32_t* tstart,
-                               const T* val, const T* Q, int ldq, int r, T* W, int ldw, double* partial,
+                               const T* val, const TQ* Q, int ldq, int r, T* W, int ldw, double* partial,
                                int64_t partial_cap);
 
 // One product of launch_rowmul / launch_rowmul_pair (see below)
@@ -260,9 +283,10 @@ template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
                             double* out, int ldo, double* partial, int64_t partial_cap);
 
-// dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation)
-template <class T>
-hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc);
+// dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation);
+// B may be stored in bfloat16 for float (widened on load)
+template <class T, class TB>
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc);
 // G = A^T A (A rows x na row-major, G na x na double) from 64 x 64 tiles staged in LDS on the
 // matrix cores; gram_tn_tiles(na) is the number of workgroups it launches.  launch_gram takes it
 // from rows * na >= kGramTiledMin on.
@@ -347,6 +371,15 @@ template <class TS, class TD>
 hipError_t launch_scale_copy(hipStream_t s, int64_t len, const TS* src, double alpha, TD* dst);
 template <class TS, class TD>
 hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds, TD* dst, int ldd, int w);
+// BF16 form: the bordering step of the inverse Cholesky factor Linv of the stored basis's Gram
+// (w <= 64 appended columns at rq; Gq22 = Q'^T Q', P = L21 L21^T or nullptr when rq = 0); writes
+// Linv22 and its transpose, clears the strips above / left of them, scal[slot] = 1 on a pivot
+// that is not positive
+hipError_t launch_border_chol(hipStream_t s, const double* Gq22, int ldg, const double* P, int ldp, int w, int rq,
+                              double* Linv, double* LinvT, int ld, double* scal, int slot);
+// scal[slot] = trace(G[0:r, 0:r])
+hipError_t launch_trace(hipStream_t s, const double* G, int ld, int r, double* scal, int slot);
+
 // dst[t] = src[perm[t]], t < len
 hipError_t launch_gather_perm(hipStream_t s, int64_t len, const int32_t* perm, const double* src, double* dst);
 

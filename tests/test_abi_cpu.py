@@ -100,6 +100,9 @@ GOOD = dict(tau=1.0, delta=1.0)
     ("nan float32 value", (3, 3, [0, 1], [0, 1], [1.0, float("nan")]),
      dict(tau=1.0, delta=1.0, vals_dtype=_capi.SVT_DTYPE_F32)),
     ("float32 duplicate", (3, 3, [1, 1], [2, 2], [1.0, 2.0]), dict(tau=1.0, delta=1.0, vals_dtype=_capi.SVT_DTYPE_F32)),
+    ("precision", (3, 3, [0], [0], [1.0]), dict(tau=1.0, delta=1.0, precision=3)),
+    ("bf16 truncated recycling", (3, 3, [0], [0], [1.0]),
+     dict(tau=1.0, delta=1.0, precision=_capi.SVT_BF16, recycle_extra=2)),
 ])
 def test_init_rejects_bad_arguments_on_host(case, args, kw):
     st, h, msg = _init(*args, **kw)
