@@ -26,9 +26,11 @@ namespace {
 // waiting on memory latency.  The launcher takes the tile width that puts the fewest tile
 // columns on the busiest CU (one round of 256 tiles of 48 rather than two of 32, say).
 //
-// Tiles are numbered row-block major and dealt to the eight XCDs in contiguous ranges (the
-// hardware deals consecutive workgroups round-robin over the XCDs), so the workgroups that
-// share a row block of A share one L2.
+// The tile grid is split into ga x gb rectangles (ga gb = 8, chosen by the launcher to balance the
+// tiles and then to minimise the operand bytes each XCD reads), one per XCD: the hardware deals
+// consecutive workgroups round-robin over the eight XCDs, so workgroup id goes to XCD id % 8 and
+// takes tile id / 8 of that XCD's rectangle.  Each XCD's L2 then fetches only its rectangle's
+// row blocks of A and column blocks of B, instead of every column block of B.
 // ------------------------------------------------------------------------------------------
 constexpr int kGM = 64, kGK = 32;
 constexpr int kXcd = 8;
@@ -59,17 +61,18 @@ constexpr int gemm_depth() {
   return sizeof(T) == 4 ? 2 : 1;
 }
 
-// Tile of workgroup id when `total` tiles are dealt round-robin over the XCDs: XCD x receives the
-// contiguous range of tiles starting at x * (total / 8) + min(x, total % 8).
-__device__ inline int xcd_tile(int id, int total) {
-  const int x = id % kXcd, slot = id / kXcd, per = total / kXcd, rem = total % kXcd;
-  return x * per + min(x, rem) + slot;
+// part i of n items cut into g nearly equal contiguous parts: first item and count
+__host__ __device__ inline void split_range(int n, int g, int i, int* first, int* count) {
+  const int base = n / g, rem = n % g;
+  *first = i * base + (i < rem ? i : rem);
+  *count = base + (i < rem ? 1 : 0);
 }
 
 template <class T, int GN, class TB>
 __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A,
                                                                      int lda, const TB* __restrict__ B, int ldb,
-                                                                     T* __restrict__ C, int ldc, int tiles_n) {
+                                                                     T* __restrict__ C, int ldc, int tiles_m,
+                                                                     int tiles_n, int ga, int tri) {
   using MM = Mfma16<T>;
   constexpr int KG = gemm_kgroups<T>(), DEPTH = gemm_depth<T>();
   constexpr int NT = GN / 16, BL = kGK * GN / 256;  // column blocks; B elements per thread and chunk
@@ -77,8 +80,14 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
   static_assert((KG - 1) * 4 * NT * 256 <= KG * (kAS + kBS), "the reduction area must fit in the staging area");
   __shared__ T smem[KG * (kAS + kBS)];
   const int tid = threadIdx.x & 255, kg = threadIdx.x >> 8, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int m0 = (tile / tiles_n) * kGM, n0 = (tile % tiles_n) * GN;
+  // this XCD's rectangle of the tile grid, and this workgroup's tile in it (workgroups past the
+  // rectangle's tiles exit; uniform over the workgroup)
+  const int xcd = blockIdx.x % kXcd, slot = blockIdx.x / kXcd, gb = kXcd / ga;
+  int ra0, rac, cb0, cbc;
+  split_range(tiles_m, ga, xcd / gb, &ra0, &rac);
+  split_range(tiles_n, gb, xcd % gb, &cb0, &cbc);
+  if (slot >= rac * cbc) return;
+  const int m0 = (ra0 + slot / cbc) * kGM, n0 = (cb0 + slot % cbc) * GN;
   T* As = smem + kg * (kAS + kBS);  // [kGM][kGK + 1]
   T* Bs = As + kAS;                  // [kGK][GN + 1]
   // global -> register staging, DEPTH chunks: A chunk 64 x 32 (8 per thread), B chunk 32 x GN
@@ -115,7 +124,10 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = typename MM::acc_t{0, 0, 0, 0};
   const int ar = wv * 16 + (lane & 15), kl = lane >> 4, bc = lane & 15;
-  const int nchunk = (K + kGK - 1) / kGK, rounds = (nchunk + KG - 1) / KG;
+  // a lower-triangular A (tri 1) or upper-triangular B (tri 2) holds zeros past the tile's diagonal: the
+  // K chunks beyond it are skipped (the sums over the others are unchanged)
+  const int Keff = tri == 1 ? min(K, m0 + kGM) : (tri == 2 ? min(K, n0 + GN) : K);
+  const int nchunk = (Keff + kGK - 1) / kGK, rounds = (nchunk + KG - 1) / KG;
   // one round: stage chunk c from register buffer P, refill P with chunk c + DEPTH KG, multiply
   auto round = [&](auto P, int c) {
     __syncthreads();  // the previous chunk has been consumed
@@ -188,22 +200,39 @@ __global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* _
 }  // namespace
 
 template <class T, class TB>
-hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc) {
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
+                          int tri) {
   if (M == 0 || N == 0) return hipSuccess;
   if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
   const int tm = (M + kGM - 1) / kGM;
   // tile columns on the busiest of the 256 CUs, rounds of 256 tiles: 48-wide tiles when that is
   // fewer than with 32-wide ones
   auto load = [&](int gn) { return (int64_t)((tm * ((N + gn - 1) / gn) + 255) / 256) * gn; };
-  if (load(48) < load(32)) {
-    const int tn = (N + 47) / 48;
-    hipLaunchKernelGGL((k_gemm_nn<T, 48, TB>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
-                       C, ldc, tn);
-  } else {
-    const int tn = (N + 31) / 32;
-    hipLaunchKernelGGL((k_gemm_nn<T, 32, TB>), dim3(tm * tn), dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
-                       C, ldc, tn);
+  const int gn = load(48) < load(32) ? 48 : 32;
+  const int tn = (N + gn - 1) / gn;
+  // the XCD rectangles: fewest tiles on the busiest XCD, then fewest operand bytes per XCD.  With a
+  // triangular operand the work of a tile grows with its row block (tri 1) or column block (tri 2):
+  // every XCD then takes all of those blocks, so the heavy tiles are spread over the eight
+  int ga = 1;
+  int64_t best_tiles = -1, best_bytes = 0;
+  for (int g = 1; g <= kXcd; g *= 2) {
+    if ((tri == 1 && g != 1) || (tri == 2 && g != kXcd)) continue;
+    const int rows = (tm + g - 1) / g, cols = (tn + kXcd / g - 1) / (kXcd / g);
+    const int64_t tiles = (int64_t)rows * cols;
+    const int64_t bytes = (int64_t)rows * kGM * sizeof(T) + (int64_t)cols * gn * sizeof(TB);
+    if (best_tiles < 0 || tiles < best_tiles || (tiles == best_tiles && bytes < best_bytes)) {
+      best_tiles = tiles;
+      best_bytes = bytes;
+      ga = g;
+    }
   }
+  const dim3 grid((unsigned)(best_tiles * kXcd));
+  if (gn == 48)
+    hipLaunchKernelGGL((k_gemm_nn<T, 48, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, tm, tn, ga, tri);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, 32, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, tm, tn, ga, tri);
   return hipGetLastError();
 }
 
@@ -216,13 +245,14 @@ hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, c
 }
 
 #define SVT_GEMM_INST(T)                                                                                       \
-  template hipError_t launch_gemm_nn<T, T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int); \
+  template hipError_t launch_gemm_nn<T, T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int,   \
+                                           int);                                                                \
   template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*, \
                                                 int64_t);
 
 SVT_GEMM_INST(double)
 SVT_GEMM_INST(float)
 template hipError_t launch_gemm_nn<float, bf16>(hipStream_t, int, int, int, const float*, int, const bf16*, int, float*,
-                                                int);
+                                                int, int);
 
 }  // namespace svt

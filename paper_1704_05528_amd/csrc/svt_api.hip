@@ -465,11 +465,11 @@ struct Engine {
   // scal[slot].  G2 serves as scratch (the eigensolver forms G^2 afresh when it needs it).
   svt_status correct_gram(int r, int slot) {
     hipStream_t s = h->stream;
-    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->Linv, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap));
-    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G2, h->r_cap, h->LinvT, h->r_cap, h->G, h->r_cap));
+    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->Linv, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap, 1));
+    HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G2, h->r_cap, h->LinvT, h->r_cap, h->G, h->r_cap, 2));
     if (slot >= 0) HIPCHK(launch_trace(s, h->G, h->r_cap, r, h->scal, slot));
     const double rr = r;
-    add_work(h, SVT_PH_GRAM, 8.0 * 4.0 * rr * rr, 4.0 * rr * rr * rr);
+    add_work(h, SVT_PH_GRAM, 8.0 * 4.0 * rr * rr, 2.0 * rr * rr * rr);  // triangular factors: half the flops
     return SVT_OK;
   }
 
@@ -1046,16 +1046,17 @@ struct Engine {
     if (k > 0) {
       PhaseTimer tm(h, SVT_PH_FACTORS, es * (double)(h->m + h->n) * (r + k) + 16.0 * r * k,
                     2.0 * (double)(h->m + h->n) * r * k);
-      HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf));
-      HIPCHK((launch_copy_cols<double, double>(s, r, S, lds_, h->Sk, h->ldf, k)));
       if constexpr (kBF16) {
-        // U_L = Q_o U_B = Q (Linv^T U_B) and V_L = B_o^T U_B diag(1/sigma) = W (Linv^T U_B) diag(1/sigma):
-        // C, D and the kept eigenvectors taken from the left by Linv^T
-        for (double* Mx : {h->C, h->D, h->Sk}) {
-          HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->LinvT, h->r_cap, Mx, h->ldf, h->Ctmp, h->ldf, k,
-                                                        1.0, 0.0)));
-          HIPCHK((launch_copy_cols<double, double>(s, r, h->Ctmp, h->ldf, Mx, h->ldf, k)));
-        }
+        // U_L = Q_o U_B = Q (Linv^T U_B) and V_L = B_o^T U_B diag(1/sigma) = W (Linv^T U_B) diag(1/sigma): the
+        // kept eigenvectors taken from the left by Linv^T once, then scaled into C and D as below
+        HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->LinvT, h->r_cap, S, lds_, h->Sk, h->ldf, k, 1.0,
+                                                      0.0)));
+        HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf));
+      } else {
+        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf));
+        HIPCHK((launch_copy_cols<double, double>(s, r, S, lds_, h->Sk, h->ldf, k)));
+      }
+      if constexpr (kBF16) {
         HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0)));
         HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0, 0.0)));
       } else {
@@ -1783,7 +1784,7 @@ void release(Handle* h) {
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal,
                   h->JA, h->JV, h->FM, h->FEt, h->FEU, h->Fval, h->Jpin, h->Jtol, h->Jpart, h->Jperm, h->Jflag,
                   h->csc_long.lo, h->csc_long.hi, h->csc_long.lcol, h->csc_long.lfirst, h->csc_long.skip,
-                  h->csc_long.P, h->Linv, h->LinvT, h->Lw, h->Lw2, h->Ctmp};
+                  h->csc_long.P, h->Linv, h->LinvT, h->Lw, h->Lw2};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
@@ -2080,7 +2081,6 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
     A(dalloc(&h->LinvT, (size_t)h->r_cap * h->r_cap));
     A(dalloc(&h->Lw, (size_t)h->r_cap * h->w_cap));
     A(dalloc(&h->Lw2, (size_t)h->r_cap * h->w_cap));
-    A(dalloc(&h->Ctmp, (size_t)h->r_cap * h->ldf));
   }
   A(dalloc_bytes(&h->W, (size_t)n * h->r_cap * es));
   A(dalloc_bytes(&h->X, (size_t)m * h->w_cap * es));

@@ -157,8 +157,8 @@ struct Handle {
   double* Sk = nullptr;    // r_cap x ldf, eigenvectors of the Gram for sigma > tau
 
   // BF16 form: inverse Cholesky factor of the stored basis's Gram Q^T Q (lower, r_cap x r_cap), its
-  // transpose, and scratch for the bordering steps and the factor coefficients
-  double *Linv = nullptr, *LinvT = nullptr, *Lw = nullptr, *Lw2 = nullptr, *Ctmp = nullptr;
+  // transpose, and scratch for the bordering steps
+  double *Linv = nullptr, *LinvT = nullptr, *Lw = nullptr, *Lw2 = nullptr;
   bool gp_valid = false;  // the leading work left the corrected Gram of the current basis in G
   bool gp_now = false;    // G holds it within the current R4SVD call
   int32_t k = 0;
@@ -284,9 +284,11 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
                             double* out, int ldo, double* partial, int64_t partial_cap);
 
 // dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation);
-// B may be stored in bfloat16 for float (widened on load)
+// B may be stored in bfloat16 for float (widened on load).  tri = 1: A is lower triangular, tri = 2: B is
+// upper triangular (the zero parts are not read)
 template <class T, class TB>
-hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc);
+hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
+                          int tri = 0);
 // G = A^T A (A rows x na row-major, G na x na double) from 64 x 64 tiles staged in LDS on the
 // matrix cores; gram_tn_tiles(na) is the number of workgroups it launches.  launch_gram takes it
 // from rows * na >= kGramTiledMin on.
