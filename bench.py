@@ -100,9 +100,11 @@ def committed_traffic(phase, form, workload, r):
                 sha = hashlib.sha256(f.read()).hexdigest()
         except (OSError, ValueError, KeyError):
             continue
-        if (sha == t.get("source_sha256") and t.get("phase") == phase and t.get("form") == form
-                and t.get("workload") == workload and t.get("r") == r):
-            return float(t["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+        if sha != t.get("source_sha256"):
+            continue
+        for e in t.get("entries", [t]):
+            if e.get("phase") == phase and e.get("form") == form and e.get("workload") == workload and e.get("r") == r:
+                return float(e["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
 
 
