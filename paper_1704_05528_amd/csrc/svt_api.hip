@@ -788,6 +788,14 @@ struct Engine {
   // ----------------------------------------------------------------------------------------
   // svd(B) through eig(W^T W): eigenpairs with sigma > tau, factor matrices Ut = Q C, Vt = W D.
   // ----------------------------------------------------------------------------------------
+  // Widest block the subspace solver takes for a basis of r columns: 256, or up to a third of the
+  // basis (at most b_cap) for wider bases.  A wider count goes to the full decomposition.  A
+  // Rayleigh-Ritz step on a block of b columns takes about b / r of the Jacobi rounds of a sweep over
+  // G, and an iteration usually needs one or two such steps besides the products and the wide
+  // CholeskyQR passes; measured on the recommendation shape (r up to 2048), blocks of up to half the
+  // basis lost time against the full decomposition once they passed about a third.
+  int block_limit(int r) const { return std::max(256, std::min(h->b_cap, r / 3)); }
+
   svt_status projected_svd(svt_step_stats* st) {
     hipStream_t s = h->stream;
     const int r = h->r;
@@ -938,7 +946,7 @@ struct Engine {
         k = 0;
         while (k < b && theta[k] > tau2) ++k;
         const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
-        if (b < r && 2 * nconv + 8 > h->b_cap) {
+        if (b < r && 2 * nconv + 8 > block_limit(r)) {
           // the count needs a block of 2 k + 8 columns for a fast convergence ratio, wider than the
           // subspace solver holds (narrower blocks converge slowly once the count nears the block
           // width): diagonalise all of G
@@ -1020,7 +1028,7 @@ struct Engine {
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
       const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
       const int nconv = (extra >= 0) ? std::min(r, k + extra) : k;
-      if (2 * std::max(nconv, 4) + 8 <= h->b_cap / 2) {
+      if (2 * std::max(nconv, 4) + 8 <= block_limit(r) / 2) {
         // the count is small again: the block solver takes over from the leading eigenvectors
         const int b = std::min(kEB, r);
         HIPCHK((launch_copy_cols<double, double>(h->stream, r, h->FEU, h->r_cap, h->EV, kEB, b)));

@@ -13,7 +13,7 @@ namespace svt {
 
 constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
-constexpr int kEB = 256;      // widest block of the subspace eigen-solver (columns of EV, EZ, ES)
+constexpr int kEB = 1024;     // widest block of the subspace eigen-solver (columns of EV, EZ, ES)
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
 constexpr int kScalars = 64;  // doubles in the device->host readback buffer
 constexpr int kSpecSlot = 48;  // host slot of the next iteration's ||W||^2 (past every readback's range)

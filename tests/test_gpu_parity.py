@@ -103,6 +103,26 @@ def test_counts_beyond_the_block_solver(gpu_lib, m, n, rank, frac, c, seed):
             assert rel_err(s, info.sigma[:info.k] - w.tau) <= TOL
 
 
+def test_subspace_blocks_wider_than_256_on_a_wide_basis(gpu_lib):
+    """A 1000-column basis with 144-161 values above tau: the subspace solver holds blocks of up to a
+    third of the basis there, so iterations 3-6 run it with blocks of 292 and 324 columns (Rayleigh
+    quotients on the many-workgroup Jacobi) instead of the full decomposition.  Six iterations with
+    replayed decisions at 1e-10."""
+    w = W.tiny_dense(1100, 1000, 160, 0.6, seed=93, tau=2.5 * math.sqrt(1100 * 1000))
+    prob = _problem(w)
+    extra = {"t0": 1000}
+    p = Params(tau=w.tau, delta=w.delta, seed=93, maxit=6, **extra)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    assert [i.r for i in infos] == [1000] * 6 and 127 <= infos[2].k <= 162
+    h = _gpu(gpu_lib, w, k0, seed=93, maxit=6, **extra)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        print(f"iteration {info.it} r={info.r} k={info.k}", flush=True)
+        st = h.iterate(1)
+        assert not (st.flags & SVT_F_EIG_INEXACT), info.it
+        _compare_step(st, info, h, w, ("wide blocks", info.it))
+
+
 @pytest.mark.parametrize("extra", [{"t0": 20}, {"t0": 6, "dt": 4}])
 def test_heavy_columns_chunked_gather(gpu_lib, extra):
     """1% observed with three columns of 9000, 5000 and 2600 rows: Y^T Q takes the gather path
