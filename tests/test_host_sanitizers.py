@@ -90,7 +90,7 @@ def test_host_validation_under_asan_and_ubsan(tmp_path):
     rt = _asan_runtime()
     if rt is None:
         pytest.skip("the clang ASan runtime is not installed")
-    from paper_1704_05528_amd.build import build_host_sanitized
+    from host_sanitized_build import build_host_sanitized
     lib = build_host_sanitized(str(tmp_path / "libsvt_host_sanitized.so"))
     syms = subprocess.run(["nm", "-D", "--undefined-only", lib], stdout=subprocess.PIPE).stdout.decode()
     assert "__asan_" in syms and "__ubsan_" in syms  # the host code really is instrumented
