@@ -76,6 +76,8 @@ def parse():
                     help="iterations after the timed ones with every phase timed (per-phase breakdown)")
     ap.add_argument("--replay-reps", type=int, default=50,
                     help="back-to-back launches per single-kernel phase for the per-launch roofline time")
+    ap.add_argument("--grad", action="store_true",
+                    help="also time the derivative workload (image, 50 iterations, checkpoints every 10)")
     ap.add_argument("--ratings-run", action="store_true",
                     help="with --workload ratings: also run every form to the paper's train-MAE stop rule")
     ap.add_argument("--image-maxit", type=int, default=1500,
@@ -211,6 +213,42 @@ def whole_run(svt, w, stream, seed, precision, maxit, chunk=25, **kw):
     out = {"seconds": el, "iterations": st.iter, "iters_per_s": st.iter / el, "stopped": bool(st.stopped),
            "rel_res": st.rel_res, "sample_mae_255": 255.0 * st.mae, "r_final": st.r, "k_final": st.k,
            "rel_res_below": below}
+    h.close()
+    return out
+
+
+def grad_workload(svt, W, stream, seed, T=50, ckpt=10):
+    """The derivative workload: the image, T unrolled iterations (FP64 form) and the gradient of the
+    held-out RMSE with respect to tau, delta and every observed value, checkpoints every ckpt
+    iterations; GPU tensors across the boundary.  Wall time of the forward iterations and of each
+    reverse sweep (exact and frozen-basis)."""
+    import numpy as np
+    import torch
+    w = W.image_adjoint()
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")  # noqa: E731
+    rows, cols, vals = dev(w.rows, torch.int32), dev(w.cols, torch.int32), dev(w.a, torch.float64)
+    hi, hj = dev(w.held_rows, torch.int32), dev(w.held_cols, torch.int32)
+    ref = dev(w.held_a, torch.float64)
+    h = svt.svt_init(w.m, w.n, rows, cols, vals, stream=stream, tau=w.tau, delta=w.delta, seed=seed, maxit=T + 5,
+                     tol=0.0, precision=svt.SVT_FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = h.iterate(T)
+    x = h.sample(hi, hj)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    rmse = torch.sqrt(torch.mean((x - ref) ** 2))
+    g = ((x - ref) / (x.numel() * rmse)).contiguous()
+    out = {"workload": f"image 1024x1024, {T} iterations (FP64), gradient of the RMSE on {w.held_rows.size} held-out "
+                       f"pixels w.r.t. tau, delta and the {w.nnz} observed values, checkpoints every {ckpt}",
+           "forward_seconds": t_fwd, "r_final": st.r, "k_final": st.k, "rmse": float(rmse)}
+    for name, frozen in (("exact", False), ("frozen_basis", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dtau, ddelta, da = h.grad(T, ckpt, hi, hj, g, frozen_basis=frozen)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "dtau": dtau, "ddelta": ddelta,
+                     "da_norm": float(torch.linalg.norm(da))}
     h.close()
     return out
 
@@ -474,6 +512,8 @@ def main():
                      "k_final": st.k}
             h.close()
         out["ratings_whole_runs"] = {"stop": "train MAE < 0.1 (Sec. 3.2), at most 600 iterations", **rr}
+    if args.grad:
+        out["derivative_workload"] = grad_workload(svt, W, stream, args.seed)
     if args.ablation_steps > 0:
         out["recycling_ablation"] = {"workload": "image 1024x1024 (as above), first iterations from Y^(0), FP64",
                                      **ablation(svt, w, stream, args.ablation_steps, args.seed)}
