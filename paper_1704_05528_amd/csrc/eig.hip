@@ -114,33 +114,6 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
       __syncthreads();
       if (!flag[seq & 1]) continue;  // uniform: nothing rotates, nothing to update this round
       sweep_any = 1;
-      if (bb <= 32) {
-        // small blocks: one pass over the 2 x 2 blocks of A and the row pairs of V, no chunking
-        // (at these sizes the gather-then-update chunks below cost more than they save)
-        for (int e = tid; e < totA + totV; e += blockDim.x) {
-          if (e < totA) {
-            const int P = e / half, R = e - (e / half) * half;
-            const int p1 = pp[P], q1 = qq[P], p2 = pp[R], q2 = qq[R];
-            const double c1 = cs[P], s1 = sn[P], c2 = cs[R], s2 = sn[R];
-            const double a0 = A[p1 * ld + p2], a1 = A[p1 * ld + q2], a2 = A[q1 * ld + p2], a3 = A[q1 * ld + q2];
-            const double r00 = c1 * a0 - s1 * a2, r01 = c1 * a1 - s1 * a3;
-            const double r10 = s1 * a0 + c1 * a2, r11 = s1 * a1 + c1 * a3;
-            A[p1 * ld + p2] = c2 * r00 - s2 * r01;
-            A[p1 * ld + q2] = s2 * r00 + c2 * r01;
-            A[q1 * ld + p2] = c2 * r10 - s2 * r11;
-            A[q1 * ld + q2] = s2 * r10 + c2 * r11;
-          } else {
-            const int e2 = e - totA, i = e2 / half, R = e2 - (e2 / half) * half;
-            const int p = pp[R], q = qq[R];
-            const double c = cs[R], s = sn[R];
-            const double v0 = V[i * ld + p], v1 = V[i * ld + q];
-            V[i * ld + p] = c * v0 - s * v1;
-            V[i * ld + q] = s * v0 + c * v1;
-          }
-        }
-        __syncthreads();
-        continue;
-      }
       for (int base = 0; base < totA; base += CA * 256) {
         double a0[CA], a1[CA], a2[CA], a3[CA], c1v[CA], s1v[CA], c2v[CA], s2v[CA];
         int o0[CA], o1[CA], o2[CA], o3[CA];
@@ -213,6 +186,16 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
       __syncthreads();
     }
     if (!sweep_any) break;
+    // as in k_jacobi_wave: stop when the next sweep would rotate nothing
+    bool big = false;
+    for (int e = tid; e < bb * bb; e += blockDim.x) {
+      const int i = e / bb, j = e - (e / bb) * bb;
+      big = big || (i < j && fabs(A[i * ld + j]) > tol);
+    }
+    if (!__syncthreads_or(big)) {
+      ++sweep;
+      break;
+    }
   }
 
   // descending order by a parallel rank count (ties by index); the padding index of odd b is excluded
@@ -232,6 +215,450 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
     const int i = e / b, c = e - (e / b) * b;
     evec[(int64_t)i * ldv + c] = V[i * ld + rank_of[c]];
   }
+}
+
+// The same cyclic Jacobi for blocks of at most kJacWaveMax columns, in one wave.  At these sizes a
+// round is a short chain of LDS round trips, and with four waves their barriers and the flag
+// exchange took most of it.  Here the ballot of the rotating lanes decides a round directly, the
+// pair indices are recomputed from the round number instead of read from a table, and each lane's
+// blocks of A and row pairs of V (fixed for the whole solve) are gathered before any is updated,
+// so a round costs one LDS trip for the rotation inputs and one for the operands.  The rotations,
+// the tolerance and the output are those of k_jacobi.
+constexpr int kJacWaveMax = 32;
+
+// Indices (p < q) of pair slot t in a round of the round-robin ordering over bb indices: slot 0
+// keeps index 0, the other indices move one position per round.
+__device__ inline void rr_pair(int t, int round, int bb, int& p, int& q) {
+  const int nb1 = bb - 1;
+  int x = t - 1 + round;
+  x = (x >= nb1) ? x - nb1 : x;
+  int y = bb - 2 - t + round;
+  y = (y >= nb1) ? y - nb1 : y;
+  const int pa = (t == 0) ? 0 : 1 + x;
+  const int pb = 1 + y;
+  p = min(pa, pb);
+  q = max(pa, pb);
+}
+
+// Orders the LDS accesses of one wave around this point (a wave's LDS instructions execute in
+// order; the wait and the clobber keep the compiler from moving loads or stores across it).
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Cyclic Jacobi on the b x b symmetric A (LDS, row stride NB + 1, padded to even order bb with a zero
+// row and column), accumulating the rotations into V (LDS, same layout, the identity on entry), by one
+// whole wave with no barrier: the rotations, the tolerance test and the stopping rule of k_jacobi.  A
+// round first loads every operand this lane updates (blocks (P, R) of A, e = P half + R, and row pairs
+// (i, R) of V, e = i half + R; the indices come from the round number), then the rotating lanes
+// compute their (c, s) from the pivots and publish them through cs / sn, and the update follows: the
+// operand loads overlap the rotation arithmetic, which is the round's longest chain.  Slot counts are
+// wave-uniform, so slots a small block does not need are skipped by scalar branches.  Returns the
+// number of sweeps.
+template <int NB>
+__device__ int jacobi_wave_core(double* A, double* V, double* cs, double* sn, int b, double tol, int max_sweeps,
+                                int lane) {
+  constexpr int LD = NB + 1, NH = NB / 2;
+  constexpr int NA = (NH * NH + kWave - 1) / kWave;  // blocks of A per lane
+  constexpr int NV = (NB * NH + kWave - 1) / kWave;  // row pairs of V per lane
+  const int bb = b + (b & 1), half = bb / 2, nb1 = bb - 1;
+  const int totA = half * half, totV = bb * half;
+  const int nA = (totA + kWave - 1) / kWave, nV = (totV + kWave - 1) / kWave;
+  int aP[NA], aR[NA], vI[NV], vR[NV];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const int e = lane + j * kWave;
+    aP[j] = (e < totA) ? e / half : -1;
+    aR[j] = (e < totA) ? e - (e / half) * half : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int e = lane + j * kWave;
+    vI[j] = (e < totV) ? e / half : -1;
+    vR[j] = (e < totV) ? e - (e / half) * half : 0;
+  }
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    bool sweep_any = false;
+    for (int round = 0; round < nb1; ++round) {
+      // operands of this lane's updates (unused slots read clamped, valid addresses)
+      double a0[NA], a1[NA], a2[NA], a3[NA], v0[NV], v1[NV];
+      int o0[NA], o1[NA], o2[NA], o3[NA], w0[NV], w1[NV];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        if (j >= nA) break;
+        int p1, q1, p2, q2;
+        rr_pair(aP[j] < 0 ? 0 : aP[j], round, bb, p1, q1);
+        rr_pair(aR[j], round, bb, p2, q2);
+        o0[j] = p1 * LD + p2;
+        o1[j] = p1 * LD + q2;
+        o2[j] = q1 * LD + p2;
+        o3[j] = q1 * LD + q2;
+        a0[j] = A[o0[j]];
+        a1[j] = A[o1[j]];
+        a2[j] = A[o2[j]];
+        a3[j] = A[o3[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        if (j >= nV) break;
+        int p, q;
+        rr_pair(vR[j], round, bb, p, q);
+        const int i = vI[j] < 0 ? 0 : vI[j];
+        w0[j] = i * LD + p;
+        w1[j] = i * LD + q;
+        v0[j] = V[w0[j]];
+        v1[j] = V[w1[j]];
+      }
+      bool mine = false;
+      if (lane < half) {
+        int p, q;
+        rr_pair(lane, round, bb, p, q);
+        const double apq = A[p * LD + q], app = A[p * LD + p], aqq = A[q * LD + q];
+        // computed on every rotating lane and selected, so the three loads go out together
+        const double dd = aqq - app;
+        const double den = fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq));
+        const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq * rcp_nr(den);
+        const double cr = rsq_nr(fma(tt, tt, 1.0));
+        mine = fabs(apq) > tol;
+        cs[lane] = mine ? cr : 1.0;
+        sn[lane] = mine ? tt * cr : 0.0;
+      }
+      if (__ballot(mine) == 0ull) continue;  // wave-uniform: nothing rotates this round
+      sweep_any = true;
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        if (j >= nA) break;
+        const int P = aP[j] < 0 ? 0 : aP[j], R = aR[j];
+        const double c1 = cs[P], s1 = sn[P], c2 = cs[R], s2 = sn[R];
+        if (aP[j] >= 0) {
+          const double r00 = c1 * a0[j] - s1 * a2[j], r01 = c1 * a1[j] - s1 * a3[j];
+          const double r10 = s1 * a0[j] + c1 * a2[j], r11 = s1 * a1[j] + c1 * a3[j];
+          A[o0[j]] = c2 * r00 - s2 * r01;
+          A[o1[j]] = s2 * r00 + c2 * r01;
+          A[o2[j]] = c2 * r10 - s2 * r11;
+          A[o3[j]] = s2 * r10 + c2 * r11;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        if (j >= nV) break;
+        const double c = cs[vR[j]], s = sn[vR[j]];
+        if (vI[j] >= 0) {
+          V[w0[j]] = c * v0[j] - s * v1[j];
+          V[w1[j]] = s * v0[j] + c * v1[j];
+        }
+      }
+      wave_lds_sync();
+    }
+    if (!sweep_any) break;
+    // the sweep that would follow rotates nothing when every off-diagonal entry is at or below the
+    // tolerance (no rotation changes A then): stop here with the count it would have ended with
+    bool big = false;
+    if (lane < bb)
+      for (int i = 0; i < lane; ++i) big = big || fabs(A[i * LD + lane]) > tol;
+    if (__ballot(big) == 0ull) {
+      ++sweep;
+      break;
+    }
+  }
+  return sweep;
+}
+
+// The same cyclic Jacobi for blocks of at most kJacWaveMax columns, in one wave (jacobi_wave_core).
+// At these sizes a round is a short chain of LDS round trips, and with four waves their barriers and
+// the flag exchange took most of it.  The output is that of k_jacobi.
+__global__ __launch_bounds__(kWave) void k_jacobi_wave(const double* __restrict__ H, int ldh, int splits,
+                                                       int64_t sstride, int b, double* __restrict__ eval,
+                                                       double* __restrict__ evec, int ldv, double* scal, int slot,
+                                                       int max_sweeps) {
+  constexpr int NB = kJacWaveMax, LD = NB + 1;
+  __shared__ double A[NB * LD], V[NB * LD];
+  __shared__ double cs[NB / 2], sn[NB / 2];
+  __shared__ int rank_of[NB];
+  const int lane = threadIdx.x;
+  const int bb = b + (b & 1);
+  for (int e = lane; e < bb * bb; e += kWave) {
+    const int i = e / bb, j = e - (e / bb) * bb;
+    double hij = 0.0, hji = 0.0;
+    if (i < b && j < b) {
+      hij = split_sum(H + (int64_t)i * ldh + j, splits, sstride);
+      hji = split_sum(H + (int64_t)j * ldh + i, splits, sstride);
+    }
+    A[i * LD + j] = 0.5 * (hij + hji);
+    V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+  }
+  wave_lds_sync();
+  double dm = 0.0;
+  for (int i = lane; i < b; i += kWave) dm = fmax(dm, fabs(A[i * LD + i]));
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, kWave));
+  const int sweep = jacobi_wave_core<NB>(A, V, cs, sn, b, 1e-15 * dm, max_sweeps, lane);
+  wave_lds_sync();
+  // descending order by a parallel rank count (ties by index); the padding index of odd b is excluded
+  for (int i = lane; i < b; i += kWave) {
+    const double di = A[i * LD + i];
+    int rk = 0;
+    for (int j = 0; j < b; ++j) {
+      const double dj = A[j * LD + j];
+      rk += (dj > di) || (dj == di && j < i);
+    }
+    rank_of[rk] = i;
+  }
+  wave_lds_sync();
+  if (lane == 0) scal[slot] = (double)sweep;
+  for (int c = lane; c < b; c += kWave) eval[c] = A[rank_of[c] * LD + rank_of[c]];
+  for (int e = lane; e < b * b; e += kWave) {
+    const int i = e / b, c = e - (e / b) * b;
+    evec[(int64_t)i * ldv + c] = V[i * LD + rank_of[c]];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// The subspace iteration of the block eigensolver for a small basis, one workgroup, nothing
+// leaving LDS: G (r <= kSmallR) and the block (b <= kSmallB columns) are loaded once, then npairs
+// double steps V <- CholeskyQR(p(G) V) (the last CholeskyQR twice), then the Rayleigh-Ritz step:
+// H = V^T G V, its Jacobi eigenpairs (one wave, jacobi_wave_core), V <- V S, G V <- (G V) S and the
+// residual norms.  p(G) V is alpha G (G V) + beta G V + V (the Chebyshev filter) or G (G V).  The
+// products run on the FP64 matrix cores, one 16-row tile per wave; the CholeskyQR follows the rules
+// of k_chol_trsm (a column whose pivot falls to dep_tol^2 of its Gram diagonal is dropped and the
+// kept columns are packed to the left).  At these sizes every launch of the multi-kernel chain is a
+// few microseconds of latency around a few hundred cycles of work; here the chain is one launch.
+// Outputs: EV (Ritz vectors), GV (G times them), eval[0..b) (Ritz values, descending),
+// eval[ldres + c] (residual norms), scal[slot] (Jacobi sweeps).
+// ------------------------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+__device__ inline dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kSmallThreads = 512;
+constexpr int kSGL = kSmallR + 1;  // row stride of G in LDS (odd: the A operand's 16 rows fall on distinct banks)
+constexpr int kJL = kSmallB + 1;   // row stride of the b x b blocks
+
+__global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double* __restrict__ G, int ldg,
+                                                             double* __restrict__ EV, double* __restrict__ GV, int ldv,
+                                                             int b, int npairs, int filt, double alpha, double beta,
+                                                             double dep_tol, double* __restrict__ eval, int ldres,
+                                                             double* scal, int slot, int max_sweeps) {
+  __shared__ double Gs[kSmallR * kSGL];            // G; after the Rayleigh-Ritz products, (G V) S
+  __shared__ double Vs[kSmallR * kSmallB];         // the block
+  __shared__ double Ts[kSmallR * kSmallB];         // G V
+  __shared__ double Zs[kSmallR * kSmallB];         // p(G) V; after the Rayleigh-Ritz products, V S
+  __shared__ double Red[2 * 256];                  // the two waves' halves of a 16 x 16 product
+  __shared__ double Cg[kSmallB * kJL];             // Gram, Cholesky factor, then the rows of R; later S
+  __shared__ double JA[kSmallB * kJL], JV[kSmallB * kJL];
+  __shared__ double cs[kSmallB / 2], sn[kSmallB / 2];
+  __shared__ double gdiag[kSmallB], rinv[kSmallB], theta[kSmallB];
+  __shared__ int rank_of[kSmallB];
+  __shared__ int keepm[1];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int RP = (r + 15) & ~15, RT = RP / 16;
+  const int kl = lane >> 4, cl = lane & 15;
+
+  for (int e = tid; e < RP * RP; e += kSmallThreads) {
+    const int i = e / RP, k = e - (e / RP) * RP;
+    Gs[i * kSGL + k] = (i < r && k < r) ? G[(int64_t)i * ldg + k] : 0.0;
+  }
+  for (int e = tid; e < RP * kSmallB; e += kSmallThreads) {
+    const int i = e / kSmallB, c = e % kSmallB;
+    Vs[e] = (i < r && c < b) ? EV[(int64_t)i * ldv + c] : 0.0;
+  }
+  __syncthreads();
+
+  // Out = G In (RP x 16) on waves 0 .. RT - 1, then Out = alpha Out' + beta T + V when `mix`
+  auto gprod = [&](const double* In, double* Out, bool mix) {
+    if (wv < RT) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      const double* ga = Gs + (wv * 16 + cl) * kSGL;
+      for (int k0 = 0; k0 < RP; k0 += 4) acc = mfma16x16x4(ga[k0 + kl], In[(k0 + kl) * kSmallB + cl], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = (wv * 16 + kl + 4 * v) * kSmallB + cl;
+        Out[o] = mix ? fma(alpha, acc[v], fma(beta, Ts[o], Vs[o])) : acc[v];
+      }
+    }
+    __syncthreads();
+  };
+  // Red = X^T Y (16 x 16) over the RP rows, two waves taking half each; returns nothing (read Red)
+  auto tprod = [&](const double* X, const double* Y) {
+    if (wv < 2) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      const int h0 = wv * (RP / 2), h1 = h0 + RP / 2;
+      for (int k0 = h0; k0 < h1; k0 += 4)
+        acc = mfma16x16x4(X[(k0 + kl) * kSmallB + cl], Y[(k0 + kl) * kSmallB + cl], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Red[wv * 256 + (kl + 4 * v) * 16 + cl] = acc[v];
+    }
+    __syncthreads();
+  };
+  // Vs <- Zs R^{-1}, Zs^T Zs = R^T R (CholeskyQR, the rules of k_chol_trsm)
+  auto cholqr = [&]() {
+    tprod(Zs, Zs);
+    if (wv == 0) {
+      for (int e = lane; e < 256; e += kWave) {
+        const int i = e >> 4, j = e & 15;
+        Cg[i * kJL + j] = (i < b && j < b) ? Red[e] + Red[256 + e] : 0.0;
+      }
+      wave_lds_sync();
+      unsigned keep = 0;
+      for (int c = 0; c < b; ++c) {
+        const double g = fmax(Cg[c * kJL + c], 0.0);
+        if (lane == c) gdiag[c] = g;
+        if (sqrt(g) > 0.0) keep |= 1u << c;
+      }
+      wave_lds_sync();
+      // right-looking Cholesky on the upper triangle; keep is wave-uniform
+      for (int c = 0; c < b; ++c) {
+        if (!(keep >> c & 1u)) continue;
+        const double d = Cg[c * kJL + c];
+        const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
+        if (ok) {
+          const double inv = rcp_nr(d);
+          for (int e = lane; e < 256; e += kWave) {
+            const int i = e >> 4, j = e & 15;
+            if (i > c && i <= j && j < b) Cg[i * kJL + j] -= Cg[c * kJL + i] * Cg[c * kJL + j] * inv;
+          }
+        } else {
+          keep &= ~(1u << c);
+        }
+        wave_lds_sync();
+      }
+      // rows of R in place (zero rows and columns for the dropped indices)
+      if (lane < kSmallB) {
+        const bool kc = lane < b && (keep >> lane & 1u);
+        const double ri = kc ? rsq_nr(Cg[lane * kJL + lane]) : 0.0;
+        rinv[lane] = ri;
+        gdiag[lane] = kc ? Cg[lane * kJL + lane] * ri : 0.0;  // now the diagonal of R
+      }
+      wave_lds_sync();
+      for (int e = lane; e < 256; e += kWave) {
+        const int c = e >> 4, j = e & 15;
+        double v = 0.0;
+        if (j >= c && gdiag[c] != 0.0 && gdiag[j] != 0.0) v = (j == c) ? gdiag[c] : Cg[c * kJL + j] * rinv[c];
+        Cg[c * kJL + j] = v;
+      }
+      if (lane == 0) keepm[0] = (int)keep;
+    }
+    __syncthreads();
+    // forward substitution, one row per thread; kept columns packed to the left
+    if (tid < RP) {
+      double z[kSmallB];
+#pragma unroll
+      for (int c = 0; c < kSmallB; ++c) z[c] = Zs[tid * kSmallB + c];
+#pragma unroll
+      for (int c = 0; c < kSmallB; ++c) {
+        if (c < b) {
+          double v = z[c];
+#pragma unroll
+          for (int l = 0; l < c; ++l) v = fma(-z[l], Cg[l * kJL + c], v);
+          z[c] = v * rinv[c];
+        }
+      }
+      const unsigned keep = (unsigned)keepm[0];
+      int q = 0;
+#pragma unroll
+      for (int c = 0; c < kSmallB; ++c)
+        if (c < b && (keep >> c & 1u)) Vs[tid * kSmallB + q++] = (tid < r) ? z[c] : 0.0;
+      for (int c = q; c < kSmallB; ++c) Vs[tid * kSmallB + c] = 0.0;
+    }
+    __syncthreads();
+  };
+
+  for (int pr = 0; pr < npairs; ++pr) {
+    gprod(Vs, Ts, false);           // T = G V
+    gprod(Ts, Zs, filt != 0);       // Z = alpha G T + beta T + V, or G T
+    cholqr();
+    if (pr + 1 == npairs) {         // the last pass before the Rayleigh-Ritz step runs twice
+      for (int e = tid; e < RP * kSmallB; e += kSmallThreads) Zs[e] = Vs[e];
+      __syncthreads();
+      cholqr();
+    }
+  }
+
+  // Rayleigh-Ritz: H = V^T G V (symmetrised), S Theta S^T = H
+  gprod(Vs, Ts, false);
+  tprod(Vs, Ts);
+  if (wv == 0) {
+    const int bb = b + (b & 1);
+    for (int e = lane; e < kSmallB * kSmallB; e += kWave) {
+      const int i = e >> 4, j = e & 15;
+      double h = 0.0;
+      if (i < b && j < b) h = 0.5 * ((Red[i * 16 + j] + Red[256 + i * 16 + j]) + (Red[j * 16 + i] + Red[256 + j * 16 + i]));
+      if (i < bb && j < bb) {
+        JA[i * kJL + j] = h;
+        JV[i * kJL + j] = (i == j) ? 1.0 : 0.0;
+      }
+    }
+    wave_lds_sync();
+    double dm = 0.0;
+    if (lane < b) dm = fabs(JA[lane * kJL + lane]);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, kWave));
+    const int sweeps = jacobi_wave_core<kSmallB>(JA, JV, cs, sn, b, 1e-15 * dm, max_sweeps, lane);
+    wave_lds_sync();
+    if (lane < b) {
+      const double di = JA[lane * kJL + lane];
+      int rk = 0;
+      for (int j = 0; j < b; ++j) {
+        const double dj = JA[j * kJL + j];
+        rk += (dj > di) || (dj == di && j < lane);
+      }
+      rank_of[rk] = lane;
+    }
+    wave_lds_sync();
+    if (lane < b) theta[lane] = JA[rank_of[lane] * kJL + rank_of[lane]];
+    for (int e = lane; e < kSmallB * kSmallB; e += kWave) {  // S (b x b, descending), zero elsewhere
+      const int k = e >> 4, c = e & 15;
+      Cg[k * kJL + c] = (k < b && c < b) ? JV[k * kJL + rank_of[c]] : 0.0;
+    }
+    if (lane == 0) scal[slot] = (double)sweeps;
+  }
+  __syncthreads();
+  // V S -> Zs, (G V) S -> Gs (G is no longer needed)
+  for (int e = tid; e < RP * kSmallB; e += kSmallThreads) {
+    const int i = e / kSmallB, c = e % kSmallB;
+    double zv = 0.0, zt = 0.0;
+    for (int k = 0; k < b; ++k) {
+      const double sk = Cg[k * kJL + c];
+      zv = fma(Vs[i * kSmallB + k], sk, zv);
+      zt = fma(Ts[i * kSmallB + k], sk, zt);
+    }
+    Zs[e] = zv;
+    Gs[e] = zt;
+  }
+  __syncthreads();
+  // residual norms || (G V S)_c - theta_c (V S)_c ||, wave w taking columns 2 w and 2 w + 1
+  for (int c = 2 * wv; c < 2 * wv + 2 && c < b; ++c) {
+    double acc = 0.0;
+    for (int i = lane; i < r; i += kWave) {
+      const double d = Gs[i * kSmallB + c] - theta[c] * Zs[i * kSmallB + c];
+      acc = fma(d, d, acc);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (lane == 0) {
+      eval[c] = theta[c];
+      eval[ldres + c] = sqrt(acc);
+    }
+  }
+  for (int e = tid; e < r * kSmallB; e += kSmallThreads) {
+    const int i = e / kSmallB, c = e % kSmallB;
+    if (c < b) {
+      EV[(int64_t)i * ldv + c] = Zs[e];
+      GV[(int64_t)i * ldv + c] = Gs[e];
+    }
+  }
+}
+
+// P = alpha P + beta G + I (r x r, row stride ld): with P = G^2 on entry, the second-degree
+// Chebyshev filter of the block eigensolver
+__global__ __launch_bounds__(256) void k_cheb2(int r, double* __restrict__ P, const double* __restrict__ G, int ld,
+                                               double alpha, double beta) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e / r), j = (int)(e - (e / r) * r);
+  const int64_t o = (int64_t)i * ld + j;
+  P[o] = fma(alpha, P[o], fma(beta, G[o], i == j ? 1.0 : 0.0));
 }
 
 // res[c] = || Z[:, c] - theta[c] V[:, c] ||_2, one workgroup per column (deterministic).
@@ -385,6 +812,11 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
   if (b <= 0 || b > kEigMax || splits <= 0) return hipErrorInvalidValue;
   const int bb = b + (b & 1);
   const size_t lds = (size_t)2 * bb * (bb + 1) * sizeof(double);
+  if (b <= kJacWaveMax) {
+    hipLaunchKernelGGL(k_jacobi_wave, dim3(1), dim3(kWave), 0, s, H, ldh, splits, sstride, b, eval, evec, ldv, scal,
+                       slot, max_sweeps);
+    return hipGetLastError();
+  }
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -394,6 +826,22 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
   }
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, H, ldh, splits, sstride, b, eval, evec, ldv, scal, slot,
                      max_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
+                            int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
+                            double* scal, int slot, int max_sweeps) {
+  if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_eig_small, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV, GV, ldv, b, npairs, filt ? 1 : 0,
+                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb2(hipStream_t s, int r, double* P, const double* G, int ld, double alpha, double beta) {
+  if (r <= 0) return hipSuccess;
+  const int64_t n = (int64_t)r * r;
+  hipLaunchKernelGGL(k_cheb2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, P, G, ld, alpha, beta);
   return hipGetLastError();
 }
 

@@ -26,6 +26,11 @@ namespace {
 // waiting on memory latency.  The launcher takes the tile width that puts the fewest tile
 // columns on the busiest CU (one round of 256 tiles of 48 rather than two of 32, say).
 //
+// With few tiles (a basis of a hundred columns gives 64 over 1024 rows) the K range is also cut
+// into ks contiguous parts, each a workgroup of its own on the same XCD as the tile's others; the
+// parts write their partial tiles to a workspace and k_split_sum adds them in part order
+// (deterministic), so four times the compute units share the loads.
+//
 // The tile grid is split into ga x gb rectangles (ga gb = 8, chosen by the launcher to balance the
 // tiles and then to minimise the operand bytes each XCD reads), one per XCD: the hardware deals
 // consecutive workgroups round-robin over the eight XCDs, so workgroup id goes to XCD id % 8 and
@@ -72,7 +77,7 @@ template <class T, int GN, class TB>
 __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int N, int K, const T* __restrict__ A,
                                                                      int lda, const TB* __restrict__ B, int ldb,
                                                                      T* __restrict__ C, int ldc, int tiles_m,
-                                                                     int tiles_n, int ga, int tri) {
+                                                                     int tiles_n, int ga, int tri, int ks) {
   using MM = Mfma16<T>;
   constexpr int KG = gemm_kgroups<T>(), DEPTH = gemm_depth<T>();
   constexpr int NT = GN / 16, BL = kGK * GN / 256;  // column blocks; B elements per thread and chunk
@@ -82,11 +87,16 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
   const int tid = threadIdx.x & 255, kg = threadIdx.x >> 8, lane = tid & (kWave - 1), wv = tid / kWave;
   // this XCD's rectangle of the tile grid, and this workgroup's tile in it (workgroups past the
   // rectangle's tiles exit; uniform over the workgroup)
-  const int xcd = blockIdx.x % kXcd, slot = blockIdx.x / kXcd, gb = kXcd / ga;
+  const int xcd = blockIdx.x % kXcd, slot = (blockIdx.x / kXcd) / ks, part = (blockIdx.x / kXcd) % ks;
+  const int gb = kXcd / ga;
   int ra0, rac, cb0, cbc;
   split_range(tiles_m, ga, xcd / gb, &ra0, &rac);
   split_range(tiles_n, gb, xcd % gb, &cb0, &cbc);
   if (slot >= rac * cbc) return;
+  if (ks > 1) {  // part `part` of the K range writes its partial tile to its own M x N slice of C (ld N)
+    C += (int64_t)part * M * N;
+    ldc = N;
+  }
   const int m0 = (ra0 + slot / cbc) * kGM, n0 = (cb0 + slot % cbc) * GN;
   T* As = smem + kg * (kAS + kBS);  // [kGM][kGK + 1]
   T* Bs = As + kAS;                  // [kGK][GN + 1]
@@ -127,7 +137,13 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
   // a lower-triangular A (tri 1) or upper-triangular B (tri 2) holds zeros past the tile's diagonal: the
   // K chunks beyond it are skipped (the sums over the others are unchanged)
   const int Keff = tri == 1 ? min(K, m0 + kGM) : (tri == 2 ? min(K, n0 + GN) : K);
-  const int nchunk = (Keff + kGK - 1) / kGK, rounds = (nchunk + KG - 1) / KG;
+  int c_first = 0, nchunk = (Keff + kGK - 1) / kGK;
+  if (ks > 1) {  // this part's chunks [c_first, nchunk)
+    int cnt;
+    split_range(nchunk, ks, part, &c_first, &cnt);
+    nchunk = c_first + cnt;
+  }
+  const int rounds = (nchunk - c_first + KG - 1) / KG;
   // one round: stage chunk c from register buffer P, refill P with chunk c + DEPTH KG, multiply
   auto round = [&](auto P, int c) {
     __syncthreads();  // the previous chunk has been consumed
@@ -145,7 +161,7 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
   };
   using B0 = std::integral_constant<int, 0>;
   using B1 = std::integral_constant<int, DEPTH - 1>;
-  int c = kg;
+  int c = c_first + kg;
   if (c < nchunk) load_chunk(B0{}, c * kGK);
   if constexpr (DEPTH == 2) {
     if (c + KG < nchunk) load_chunk(B1{}, (c + KG) * kGK);
@@ -185,6 +201,17 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
   }
 }
 
+// C[i][j] = sum over the ks partial products (M x N slices of P, in part order)
+template <class T>
+__global__ __launch_bounds__(256) void k_split_sum(int M, int N, int ks, const T* __restrict__ P, T* __restrict__ C,
+                                                   int ldc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x, mn = (int64_t)M * N;
+  if (e >= mn) return;
+  T sum = P[e];
+  for (int q = 1; q < ks; ++q) sum += P[q * mn + e];
+  C[(e / N) * ldc + e % N] = sum;
+}
+
 // yT[j * ldy + i] = y at CSC position p = (i, j): the dense transposed copy of Y on Lambda (the
 // entries outside Lambda stay zero from set-up); one wave per column
 template <class T>
@@ -201,7 +228,7 @@ __global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* _
 
 template <class T, class TB>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
-                          int tri) {
+                          int tri, T* work, int64_t work_elems) {
   if (M == 0 || N == 0) return hipSuccess;
   if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
   const int tm = (M + kGM - 1) / kGM;
@@ -226,13 +253,26 @@ hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int ld
       ga = g;
     }
   }
-  const dim3 grid((unsigned)(best_tiles * kXcd));
+  // K parts: as many (up to four) as keep the grid within one round of 256 workgroups while every
+  // K group of a part still gets two chunks, when the workspace holds the partial products
+  int ks = 1;
+  const int64_t nchunk = (K + kGK - 1) / kGK, mn = (int64_t)M * N;
+  while (tri == 0 && ks < 4 && (int64_t)tm * tn * ks * 2 <= 256 && nchunk >= (int64_t)ks * 2 * 2 * gemm_kgroups<T>() &&
+         work != nullptr && mn * ks * 2 <= work_elems)
+    ks *= 2;
+  T* out = ks > 1 ? work : C;
+  const dim3 grid((unsigned)(best_tiles * kXcd * ks));
   if (gn == 48)
-    hipLaunchKernelGGL((k_gemm_nn<T, 48, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C,
-                       ldc, tm, tn, ga, tri);
+    hipLaunchKernelGGL((k_gemm_nn<T, 48, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+                       out, ldc, tm, tn, ga, tri, ks);
   else
-    hipLaunchKernelGGL((k_gemm_nn<T, 32, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb, C,
-                       ldc, tm, tn, ga, tri);
+    hipLaunchKernelGGL((k_gemm_nn<T, 32, TB>), grid, dim3(256 * gemm_kgroups<T>()), 0, s, M, N, K, A, lda, B, ldb,
+                       out, ldc, tm, tn, ga, tri, ks);
+  if (ks > 1) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_sum<T>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, N, ks, work, C, ldc);
+  }
   return hipGetLastError();
 }
 
@@ -246,13 +286,13 @@ hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, c
 
 #define SVT_GEMM_INST(T)                                                                                       \
   template hipError_t launch_gemm_nn<T, T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int,   \
-                                           int);                                                                \
+                                           int, T*, int64_t);                                                   \
   template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*, \
                                                 int64_t);
 
 SVT_GEMM_INST(double)
 SVT_GEMM_INST(float)
 template hipError_t launch_gemm_nn<float, bf16>(hipStream_t, int, int, int, const float*, int, const bf16*, int, float*,
-                                                int, int);
+                                                int, int, float*, int64_t);
 
 }  // namespace svt

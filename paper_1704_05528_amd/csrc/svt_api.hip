@@ -407,7 +407,8 @@ struct Engine {
   template <class TD>
   svt_status spmm_yt(const TD* D, int ldd, T* out, int ldo, int w) {
     if (h->yT && w >= 32) {  // narrow blocks stay on the sparse kernel (too few output tiles)
-      HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo));
+      HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo, 0,
+                               (T*)h->kpart, kKPartElems * (int64_t)(sizeof(double) / sizeof(T))));
       return SVT_OK;
     }
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w,
@@ -828,6 +829,7 @@ struct Engine {
       HIPCHK((launch_copy_cols<double, double>(s, r, h->ES, kEB, h->EV, kEB, r)));
       h->ev_valid = r;
       h->ev_rows = r;
+      h->cheb_c = 0.0;
       st->sigma1 = r > 0 ? std::sqrt(std::max(theta[0], 0.0)) : 0.0;
     } else if (!go_full) {
       // Warm-started subspace iteration on G.  Start block: the previous iteration's Ritz vectors
@@ -852,6 +854,15 @@ struct Engine {
       }
       // truncated recycling keeps the k + e leading Ritz vectors, which then must converge too
       const int extra = (h->p.mode == SVT_MODE_R4SVD) ? h->p.recycle_extra : -1;
+      // Double steps take the second-degree Chebyshev filter p(G) = T_2(2 G / c - I) in place of G^2 when
+      // the previous solve left the lower end c of its block's Ritz values (the interval [0, c] maps into
+      // [-1, 1], everything above grows like the square of its distance from c / 2), capped at tau^2: every
+      // eigenvalue above tau^2, the ones the thresholding keeps, then has |p| > 1 and still dominates the
+      // near-null directions (p(0) = 1).  The damping of the components below c against the kept ones is
+      // 1 / p(lambda) instead of (lambda' / lambda)^2; the Rayleigh-Ritz steps and the acceptance test
+      // use G itself, so only the convergence speed depends on the filter.
+      const double cf = std::min(h->cheb_c, tau2);
+      const bool filt = warm && cf > 1e-10 * tau2 && std::isfinite(cf);
       bool done = false, have_gv = false, have_g2 = false;
       int powers = 0, tests = 0, prev_k = -1;
       int target = std::max(2, h->eig_pred);
@@ -860,7 +871,21 @@ struct Engine {
           st->flags |= SVT_F_EIG_INEXACT;
           break;
         }
-        {
+        if (r <= kSmallR && b <= kSmallB) {
+          // a small basis: the double steps and the Rayleigh-Ritz step in one workgroup (G in LDS),
+          // leaving the Ritz vectors in EV, G times them in EZ3, and the Ritz values and residuals
+          PhaseTimer tm(h, SVT_PH_EIG);
+          const int npairs = std::max(1, (target - powers + 1) / 2);
+          HIPCHK(launch_eig_small(s, r, h->G, h->r_cap, h->EV, h->EZ3, kEB, b, npairs, filt, 8.0 / (cf * cf), -8.0 / cf,
+                                  kEigDepTol, h->Eval, kEB, h->scal, S_SWEEPS, 40));
+          // per double step two products with G and one or two CholeskyQR passes; then G V, V^T G V,
+          // the b x b Jacobi, the two rotations and the residuals
+          add_work(h, SVT_PH_EIG, 8.0 * ((double)r * r + 4.0 * r * b + 2.0 * kEB),
+                   npairs * (4.0 * r * r * b + 3.0 * r * b * b) + 3.0 * r * b * b + 2.0 * r * r * b + 2.0 * r * b * b +
+                       10.0 * b * b * b + 4.0 * r * b * b + 3.0 * r * b);
+          powers += 2 * npairs;
+          have_gv = true;
+        } else {
           PhaseTimer tm(h, SVT_PH_EIG);
           while (powers < target) {
             const int step = (target - powers >= 2) ? 2 : 1;
@@ -874,9 +899,10 @@ struct Engine {
             double* zg = (b <= 16) ? h->partial : nullptr;
             const int zgs = (r + 15) / 16;
             bool have_zg = false;
-            if (have_gv) {
+            const bool use_gv = have_gv && !(filt && step == 2);
+            have_gv = false;
+            if (use_gv) {
               z = h->EZ3;
-              have_gv = false;
               if (step == 2) {
                 HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G, h->r_cap, z, kEB, h->EZ, kEB, b,
                                                               1.0, 0.0, zg)));
@@ -885,9 +911,13 @@ struct Engine {
               }
             } else if (step == 2) {
               if (!have_g2) {
-                // G^2 on the LDS-tiled matrix-core product (an r x r x r contraction)
+                // G^2 on the LDS-tiled matrix-core product (an r x r x r contraction), then the filter
                 HIPCHK(launch_gemm_nn<double>(s, r, r, r, h->G, h->r_cap, h->G, h->r_cap, h->G2, h->r_cap));
                 add_work(h, SVT_PH_EIG, 24.0 * r * r, 2.0 * (double)r * r * r);
+                if (filt) {
+                  HIPCHK(launch_cheb2(s, r, h->G2, h->G, h->r_cap, 8.0 / (cf * cf), -8.0 / cf));
+                  add_work(h, SVT_PH_EIG, 24.0 * r * r, 4.0 * (double)r * r);
+                }
                 have_g2 = true;
               }
               HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->G2, h->r_cap, h->EV, kEB, h->EZ, kEB, b,
@@ -1009,6 +1039,7 @@ struct Engine {
       S = h->EV;
       h->ev_valid = b;
       h->ev_rows = r;
+      h->cheb_c = (b < r) ? std::max(theta[b - 1], 0.0) : 0.0;
       st->sigma1 = std::sqrt(std::max(theta[0], 0.0));
       }
     }
@@ -1034,6 +1065,7 @@ struct Engine {
         HIPCHK((launch_copy_cols<double, double>(h->stream, r, h->FEU, h->r_cap, h->EV, kEB, b)));
         h->ev_valid = b;
         h->ev_rows = r;
+        h->cheb_c = 0.0;
         h->full_mode = false;
         h->fe_rows = 0;
       } else {
@@ -1792,7 +1824,7 @@ void release(Handle* h) {
                   h->EZ3, h->EH, h->ES, h->Eval, h->Ut, h->Vt, h->Utmp, h->C, h->D, h->Sk, h->partial, h->scal,
                   h->JA, h->JV, h->FM, h->FEt, h->FEU, h->Fval, h->Jpin, h->Jtol, h->Jpart, h->Jperm, h->Jflag,
                   h->csc_long.lo, h->csc_long.hi, h->csc_long.lcol, h->csc_long.lfirst, h->csc_long.skip,
-                  h->csc_long.P, h->Linv, h->LinvT, h->Lw, h->Lw2};
+                  h->csc_long.P, h->Linv, h->LinvT, h->Lw, h->Lw2, h->kpart};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (h->hscal) (void)hipHostFree(h->hscal);
@@ -1849,7 +1881,7 @@ void put_host_state(std::vector<char>& b, const Handle* h) {
   for (int32_t v : {h->p.precision, h->r_cap, h->ldf, h->r, h->iter, h->k, h->div_run, h->ev_valid, h->ev_rows,
                     h->eig_pred, h->eig_pass_streak, h->fe_rows})
     put(b, v);
-  for (double v : {h->eps_thr, h->eps_min, h->normY}) put(b, v);
+  for (double v : {h->eps_thr, h->eps_min, h->normY, h->cheb_c}) put(b, v);
   for (bool v : {h->eps_thr_set, h->converged, h->have_factors, h->full_mode, h->hist_ok, h->exact_ok})
     put<uint8_t>(b, v ? 1 : 0);
   put<int64_t>(b, (int64_t)h->replay_pos);
@@ -2117,6 +2149,7 @@ svt_status svt_init(svt_handle** out, int64_t m, int64_t n, int64_t nnz, const i
   A(dalloc(&h->scal, kScalars));
   if (!tstart.empty()) A(dalloc(&h->tstart, tstart.size()));
   if (dense_y) A(dalloc_bytes(&h->yT, (size_t)m * n * es));
+  if (dense_y) A(dalloc(&h->kpart, (size_t)kKPartElems));
   h->nchunks = (int32_t)ccol.size();
   if (!lcol.empty()) {
     SegChunks& L = h->csc_long;
@@ -2441,7 +2474,7 @@ svt_status svt_restore(svt_handle* h, const void* buf, int64_t size) {
   ok = get(b, pos, &t.r) && get(b, pos, &t.iter) && get(b, pos, &t.k) && get(b, pos, &t.div_run) &&
        get(b, pos, &t.ev_valid) && get(b, pos, &t.ev_rows) && get(b, pos, &t.eig_pred) &&
        get(b, pos, &t.eig_pass_streak) && get(b, pos, &t.fe_rows) && get(b, pos, &t.eps_thr) &&
-       get(b, pos, &t.eps_min) && get(b, pos, &t.normY);
+       get(b, pos, &t.eps_min) && get(b, pos, &t.normY) && get(b, pos, &t.cheb_c);
   for (int q = 0; ok && q < 6; ++q) ok = get(b, pos, &f[q]);
   ok = ok && get(b, pos, &rp) && get_vec(b, pos, &t.history) && get_vec(b, pos, &t.hist_r) &&
        get_vec(b, pos, &t.hist_chunks) && get_vec(b, pos, &t.sigma_k) && get_vec(b, pos, &t.replay_blocks) &&
@@ -2463,6 +2496,7 @@ svt_status svt_restore(svt_handle* h, const void* buf, int64_t size) {
   h->eps_thr = t.eps_thr;
   h->eps_min = t.eps_min;
   h->normY = t.normY;
+  h->cheb_c = t.cheb_c;
   h->eps_thr_set = f[0];
   h->converged = f[1];
   h->have_factors = f[2];

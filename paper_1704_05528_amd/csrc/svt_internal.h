@@ -12,6 +12,7 @@
 namespace svt {
 
 constexpr int kWave = 64;     // CDNA wavefront width
+constexpr int64_t kKPartElems = (int64_t)256 * 64 * 48;  // a product split over K: at most 256 tiles of 64 x 48
 constexpr int kEigMax = 96;   // largest block the in-LDS Jacobi / Cholesky kernels hold
 constexpr int kEB = 1024;     // widest block of the subspace eigen-solver (columns of EV, EZ, ES)
 constexpr int kNarrow = 16;   // widest block handled by the lanes-over-nonzeros SpMM
@@ -137,6 +138,7 @@ struct Handle {
   int32_t ev_rows = 0;     // basis width those vectors refer to
   int32_t eig_pred = 6;    // products with G before the first Rayleigh-Ritz test (adapted each iteration)
   int32_t eig_pass_streak = 0;  // consecutive iterations whose first test passed
+  double cheb_c = 0.0;  // smallest Ritz value of the last accepted block (0: none): the damped interval of the filter
 
   // full eigen-decomposition of G (Jacobi over many workgroups, eigfull.hip), used once the count
   // above tau outgrows the block solver; r_cap x r_cap matrices allocated on first use
@@ -167,6 +169,7 @@ struct Handle {
   // reductions
   double* partial = nullptr;
   int64_t partial_cap = 0;
+  double* kpart = nullptr;  // K-split partial products of the dense W = Y^T Q (kKPartElems doubles)
   double* scal = nullptr;   // device scalars
   double* hscal = nullptr;  // pinned host mirror
   double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks
@@ -285,10 +288,11 @@ hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int n
 
 // dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation);
 // B may be stored in bfloat16 for float (widened on load).  tri = 1: A is lower triangular, tri = 2: B is
-// upper triangular (the zero parts are not read)
+// upper triangular (the zero parts are not read).  With a workspace of work_elems elements a product
+// with few output tiles is also split over K (partial products there, then added in a fixed order).
 template <class T, class TB>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
-                          int tri = 0);
+                          int tri = 0, T* work = nullptr, int64_t work_elems = 0);
 // G = A^T A (A rows x na row-major, G na x na double) from 64 x 64 tiles staged in LDS on the
 // matrix cores; gram_tn_tiles(na) is the number of workgroups it launches.  launch_gram takes it
 // from rows * na >= kGramTiledMin on.
@@ -394,6 +398,18 @@ hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0
 // ---------------------------------------------------------------------------------------------
 // eigensolver (eig.hip), double
 // ---------------------------------------------------------------------------------------------
+// The block subspace iteration (npairs double steps with CholeskyQR) and its Rayleigh-Ritz step for a
+// basis of r <= kSmallR columns and a block of b <= kSmallB, in one workgroup (G and the block in LDS).
+// EV (r x b, ld ldv) holds the start block on entry and the Ritz vectors on exit, GV gets G times them,
+// eval[0..b) the Ritz values (descending) and eval[ldres + c] the residual norms.
+constexpr int kSmallR = 112, kSmallB = 16;
+hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
+                            int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
+                            double* scal, int slot, int max_sweeps);
+
+// P = alpha P + beta G + I on the leading r x r blocks (ld) of two symmetric matrices
+hipError_t launch_cheb2(hipStream_t s, int r, double* P, const double* G, int ld, double alpha, double beta);
+
 // Jacobi eigen-decomposition of a b x b symmetric matrix (b <= kEigMax) in one workgroup.
 // Eigenvalues descending into eval, eigenvectors as columns of evec (row-major, ld = ldv).
 // H may be given as the sum of `splits` matrices sstride doubles apart (split partial products).
