@@ -244,6 +244,13 @@ __device__ inline void rr_pair(int t, int round, int bb, int& p, int& q) {
 // order; the wait and the clobber keep the compiler from moving loads or stores across it).
 __device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// x of lane l (wave-uniform l), as a scalar broadcast
+__device__ inline double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
 // Cyclic Jacobi on the b x b symmetric A (LDS, row stride NB + 1, padded to even order bb with a zero
 // row and column), accumulating the rotations into V (LDS, same layout, the identity on entry), by one
 // whole wave with no barrier: the rotations, the tolerance test and the stopping rule of k_jacobi.  A
@@ -448,16 +455,26 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   __shared__ double Cg[kSmallB * kJL];             // Gram, Cholesky factor, then the rows of R; later S
   __shared__ double JA[kSmallB * kJL], JV[kSmallB * kJL];
   __shared__ double cs[kSmallB / 2], sn[kSmallB / 2];
-  __shared__ double gdiag[kSmallB], rinv[kSmallB], theta[kSmallB];
+  __shared__ double rinv[kSmallB], theta[kSmallB];
   __shared__ int rank_of[kSmallB];
   __shared__ int keepm[1];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int RP = (r + 15) & ~15, RT = RP / 16;
   const int kl = lane >> 4, cl = lane & 15;
 
-  for (int e = tid; e < RP * RP; e += kSmallThreads) {
-    const int i = e / RP, k = e - (e / RP) * RP;
-    Gs[i * kSGL + k] = (i < r && k < r) ? G[(int64_t)i * ldg + k] : 0.0;
+  // G in batches of eight loads per thread in flight (clamped, valid addresses; masked on store)
+  for (int e0 = 0; e0 < RP * RP; e0 += 8 * kSmallThreads) {
+    double gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + tid + u * kSmallThreads, i = e / RP, k = e - (e / RP) * RP;
+      gv[u] = G[(int64_t)min(i, r - 1) * ldg + min(k, r - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + tid + u * kSmallThreads, i = e / RP, k = e - (e / RP) * RP;
+      if (e < RP * RP) Gs[i * kSGL + k] = (i < r && k < r) ? gv[u] : 0.0;
+    }
   }
   for (int e = tid; e < RP * kSmallB; e += kSmallThreads) {
     const int i = e / kSmallB, c = e % kSmallB;
@@ -468,9 +485,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   // Out = G In (RP x 16) on waves 0 .. RT - 1, then Out = alpha Out' + beta T + V when `mix`
   auto gprod = [&](const double* In, double* Out, bool mix) {
     if (wv < RT) {
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      // four independent accumulator chains over interleaved k-steps, added in a fixed order
+      dbl4 a4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = dbl4{0.0, 0.0, 0.0, 0.0};
       const double* ga = Gs + (wv * 16 + cl) * kSGL;
-      for (int k0 = 0; k0 < RP; k0 += 4) acc = mfma16x16x4(ga[k0 + kl], In[(k0 + kl) * kSmallB + cl], acc);
+      for (int k0 = 0; k0 < RP; k0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + kl;
+          a4[u] = mfma16x16x4(ga[k], In[k * kSmallB + cl], a4[u]);
+        }
+      }
+      const dbl4 acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int o = (wv * 16 + kl + 4 * v) * kSmallB + cl;
@@ -482,10 +509,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   // Red = X^T Y (16 x 16) over the RP rows, two waves taking half each; returns nothing (read Red)
   auto tprod = [&](const double* X, const double* Y) {
     if (wv < 2) {
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      const int h0 = wv * (RP / 2), h1 = h0 + RP / 2;
-      for (int k0 = h0; k0 < h1; k0 += 4)
-        acc = mfma16x16x4(X[(k0 + kl) * kSmallB + cl], Y[(k0 + kl) * kSmallB + cl], acc);
+      dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+      const int h0 = wv * (RP / 2), h1 = h0 + RP / 2;  // RP / 2 is a multiple of 8
+      for (int k0 = h0; k0 < h1; k0 += 8) {
+        a0 = mfma16x16x4(X[(k0 + kl) * kSmallB + cl], Y[(k0 + kl) * kSmallB + cl], a0);
+        a1 = mfma16x16x4(X[(k0 + 4 + kl) * kSmallB + cl], Y[(k0 + 4 + kl) * kSmallB + cl], a1);
+      }
+      const dbl4 acc = a0 + a1;
 #pragma unroll
       for (int v = 0; v < 4; ++v) Red[wv * 256 + (kl + 4 * v) * 16 + cl] = acc[v];
     }
@@ -495,47 +525,48 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   auto cholqr = [&]() {
     tprod(Zs, Zs);
     if (wv == 0) {
-      for (int e = lane; e < 256; e += kWave) {
-        const int i = e >> 4, j = e & 15;
-        Cg[i * kJL + j] = (i < b && j < b) ? Red[e] + Red[256 + e] : 0.0;
-      }
-      wave_lds_sync();
+      // right-looking Cholesky in registers: lane i < 16 holds row i of the symmetric Gram (both
+      // triangles, updated alike, so it stays symmetric); step c reads the pivot and row c from lane c
+      // (v_readlane, no LDS round trip) and lane i > c updates its entries past c with its own A[i][c]
+      double a[kSmallB];
+      const int li = lane < kSmallB ? lane : 0;
+#pragma unroll
+      for (int j = 0; j < kSmallB; ++j)
+        a[j] = (li < b && j < b) ? Red[li * 16 + j] + Red[256 + li * 16 + j] : 0.0;
       unsigned keep = 0;
-      for (int c = 0; c < b; ++c) {
-        const double g = fmax(Cg[c * kJL + c], 0.0);
-        if (lane == c) gdiag[c] = g;
-        if (sqrt(g) > 0.0) keep |= 1u << c;
+      double gd[kSmallB];
+#pragma unroll
+      for (int c = 0; c < kSmallB; ++c) {
+        gd[c] = fmax(readlane_d(a[c], c), 0.0);
+        if (c < b && gd[c] > 0.0) keep |= 1u << c;
       }
-      wave_lds_sync();
-      // right-looking Cholesky on the upper triangle; keep is wave-uniform
-      for (int c = 0; c < b; ++c) {
-        if (!(keep >> c & 1u)) continue;
-        const double d = Cg[c * kJL + c];
-        const bool ok = (d > dep_tol * dep_tol * gdiag[c]) && (d > 0.0);
-        if (ok) {
-          const double inv = rcp_nr(d);
-          for (int e = lane; e < 256; e += kWave) {
-            const int i = e >> 4, j = e & 15;
-            if (i > c && i <= j && j < b) Cg[i * kJL + j] -= Cg[c * kJL + i] * Cg[c * kJL + j] * inv;
-          }
-        } else {
+#pragma unroll
+      for (int c = 0; c < kSmallB; ++c) {
+        if (c >= b || !(keep >> c & 1u)) continue;  // uniform
+        const double d = readlane_d(a[c], c);
+        if (!((d > dep_tol * dep_tol * gd[c]) && (d > 0.0))) {
           keep &= ~(1u << c);
+          continue;
         }
-        wave_lds_sync();
+        const double inv = rcp_nr(d), aic = a[c];
+#pragma unroll
+        for (int j = c + 1; j < kSmallB; ++j) {
+          const double rcj = readlane_d(a[j], c);
+          if (lane > c) a[j] = a[j] - aic * rcj * inv;
+        }
       }
-      // rows of R in place (zero rows and columns for the dropped indices)
+      // rows of R (row c on lane c): R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c]; zero rows and
+      // columns for the dropped and inactive indices
+      const bool kc = lane < b && (keep >> li & 1u);
+      const double ri = kc ? rsq_nr(a[li]) : 0.0;
       if (lane < kSmallB) {
-        const bool kc = lane < b && (keep >> lane & 1u);
-        const double ri = kc ? rsq_nr(Cg[lane * kJL + lane]) : 0.0;
         rinv[lane] = ri;
-        gdiag[lane] = kc ? Cg[lane * kJL + lane] * ri : 0.0;  // now the diagonal of R
-      }
-      wave_lds_sync();
-      for (int e = lane; e < 256; e += kWave) {
-        const int c = e >> 4, j = e & 15;
-        double v = 0.0;
-        if (j >= c && gdiag[c] != 0.0 && gdiag[j] != 0.0) v = (j == c) ? gdiag[c] : Cg[c * kJL + j] * rinv[c];
-        Cg[c * kJL + j] = v;
+#pragma unroll
+        for (int j = 0; j < kSmallB; ++j) {
+          double v = 0.0;
+          if (kc && j >= lane && (keep >> j & 1u)) v = a[j] * ri;  // j == lane: sqrt(pivot)
+          Cg[lane * kJL + j] = v;
+        }
       }
       if (lane == 0) keepm[0] = (int)keep;
     }

@@ -863,7 +863,7 @@ struct Engine {
       // use G itself, so only the convergence speed depends on the filter.
       const double cf = std::min(h->cheb_c, tau2);
       const bool filt = warm && cf > 1e-10 * tau2 && std::isfinite(cf);
-      bool done = false, have_gv = false, have_g2 = false;
+      bool done = false, have_gv = false, have_g2 = false, used_small = false;
       int powers = 0, tests = 0, prev_k = -1;
       int target = std::max(2, h->eig_pred);
       while (!done) {
@@ -885,6 +885,7 @@ struct Engine {
                        10.0 * b * b * b + 4.0 * r * b * b + 3.0 * r * b);
           powers += 2 * npairs;
           have_gv = true;
+          used_small = true;
         } else {
           PhaseTimer tm(h, SVT_PH_EIG);
           while (powers < target) {
@@ -1022,10 +1023,11 @@ struct Engine {
       }
       if (!go_full) {
       // a failed first test costs a Rayleigh-Ritz step and a readback, far more than one product:
-      // keep the count after a first-test pass, and probe one lower only after four in a row
+      // keep the count after a first-test pass, and probe one lower only after four in a row (one
+      // double step lower for the one-workgroup solver, which only takes double steps)
       if (tests == 1) {
         if (++h->eig_pass_streak >= 4) {
-          h->eig_pred = std::max(2, powers - 1);
+          h->eig_pred = std::max(2, powers - (used_small ? 2 : 1));
           h->eig_pass_streak = 0;
         } else {
           h->eig_pred = std::max(2, powers);
