@@ -1666,6 +1666,26 @@ hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const
   return launch_finish(s, partial, nb, 1, 1, scal, slot);
 }
 
+// dst[0..count) = src[0..count) in host memory mapped into the device, then *flag = seq once every
+// value is visible to the host (each thread's system-scope fence, the barrier, then thread 0's)
+__global__ __launch_bounds__(256) void k_post(const double* __restrict__ src, int count, double* dst,
+                                              unsigned* flag, unsigned seq) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *(volatile unsigned*)flag = seq;
+  }
+}
+
+hipError_t launch_post(hipStream_t s, const double* src, int count, double* dst_mapped, unsigned* flag_mapped,
+                       unsigned seq) {
+  if (count < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(256), 0, s, src, count, dst_mapped, flag_mapped, seq);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal,
                          int slot) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nblocks, stride, nq, scal, slot);

@@ -171,12 +171,19 @@ struct Handle {
   int64_t partial_cap = 0;
   double* kpart = nullptr;  // K-split partial products of the dense W = Y^T Q (kKPartElems doubles)
   double* scal = nullptr;   // device scalars
-  double* hscal = nullptr;  // pinned host mirror
-  double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks
+  double* hscal = nullptr;  // pinned host mirror (mapped into the device: hscal_d)
+  double* hstage = nullptr; // pinned staging area of kStageDoubles doubles for small readbacks (hstage_d)
+  double* hscal_d = nullptr;
+  double* hstage_d = nullptr;
+  unsigned* hflag = nullptr;    // mapped host word: the sequence number of the last completed post
+  unsigned* hflag_d = nullptr;
+  unsigned post_seq = 0;        // sequence number of the last post enqueued
+  unsigned spec_seq = 0;        // the post that carries the next iteration's ||W||^2
+  unsigned sync_seq = 0;        // the post that carries an iteration's sums
   double* scratch = nullptr;  // this device's copy of the library's file-scope scratch array (svt_mae_device)
   hipEvent_t sync_ev = nullptr;  // timing-free event the host spins on at decision points
   // The next iteration's leading work (dense copy of Y, W = Y^T Q, ||W||^2) was enqueued at the end
-  // of the previous iteration; ||W||^2 lands in hscal[kSpecSlot] when spec_ev completes.
+  // of the previous iteration; ||W||^2 lands in hscal[kSpecSlot] when post spec_seq completes.
   bool spec_ready = false;
   hipEvent_t spec_ev = nullptr;
 
@@ -358,6 +365,10 @@ hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart
                                int ld, int k, double delta, double* partial, int* nblocks);
 // scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
+// Copies count doubles to host memory mapped into the device (dst_mapped: its device address) and then
+// sets the mapped flag to seq: the host polls the flag instead of waiting for a copy and an event.
+hipError_t launch_post(hipStream_t s, const double* src, int count, double* dst_mapped, unsigned* flag_mapped,
+                       unsigned seq);
 // scal[slot] = sum |ref - x| over len entries (deterministic)
 hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const double* ref, double* partial,
                               double* scal, int slot);
