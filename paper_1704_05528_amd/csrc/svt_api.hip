@@ -872,7 +872,11 @@ struct Engine {
       // predicted number of products is done.  The prediction is the count the previous SVT
       // iteration needed, lowered by one when its first test already passed.
       const bool warm = h->ev_valid > 0 && h->ev_rows <= r;
-      int b = std::min(std::min(h->b_cap, r), std::max(12, 2 * std::max(h->k, 4) + 4));
+      // block width: the count k, its four guard pairs and two more for a small count (simulated on the
+      // image workload's Gram matrices, iterations 6-80, the double steps needed were those of blocks of
+      // max(12, 2 k + 4)); 2 k + 4 for larger counts, whose eigenvalues near the threshold cluster more
+      const int kb = h->k;
+      int b = std::min(std::min(h->b_cap, r), kb <= 8 ? std::max(8, kb + 6) : 2 * kb + 4);
       int valid = warm ? std::max(0, std::min(h->ev_valid, b - 4)) : 0;
       {
         PhaseTimer tm(h, SVT_PH_EIG);
