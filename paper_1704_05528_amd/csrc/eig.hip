@@ -446,7 +446,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
                                                              double* __restrict__ EV, double* __restrict__ GV, int ldv,
                                                              int b, int npairs, int filt, double alpha, double beta,
                                                              double dep_tol, double* __restrict__ eval, int ldres,
-                                                             double* scal, int slot, int max_sweeps) {
+                                                             double* scal, int slot, int max_sweeps, int valid,
+                                                             int ev_rows, uint64_t seed, uint64_t tag) {
   __shared__ double Gs[kSmallR * kSGL];            // G; after the Rayleigh-Ritz products, (G V) S
   __shared__ double Vs[kSmallR * kSmallB];         // the block
   __shared__ double Ts[kSmallR * kSmallB];         // G V
@@ -476,9 +477,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
       if (e < RP * RP) Gs[i * kSGL + k] = (i < r && k < r) ? gv[u] : 0.0;
     }
   }
+  // the start block: the kept columns (rows past ev_rows zero) and Gaussian columns valid .. b-1
   for (int e = tid; e < RP * kSmallB; e += kSmallThreads) {
     const int i = e / kSmallB, c = e % kSmallB;
-    Vs[e] = (i < r && c < b) ? EV[(int64_t)i * ldv + c] : 0.0;
+    double v = 0.0;
+    if (i < r && c < valid) {
+      v = (i < ev_rows) ? EV[(int64_t)i * ldv + c] : 0.0;
+    } else if (i < r && c < b) {
+      double z[4];
+      gaussian4((uint64_t)i, (uint64_t)c, tag, 0xFFFFFFFFull, seed, z);
+      v = z[0];
+    }
+    Vs[e] = v;
   }
   __syncthreads();
 
@@ -713,7 +723,8 @@ __global__ __launch_bounds__(256) void k_ritz_residual(int rows, const double* _
 
 // C[:, c] = S[:, c] (sigma_c - tau), D[:, c] = S[:, c] / sigma_c, sigma_c = sqrt(theta_c), c < k.
 __global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int lds_, const double* __restrict__ theta,
-                                double tau, double* __restrict__ C, double* __restrict__ D, int ldc) {
+                                double tau, double* __restrict__ C, double* __restrict__ D, int ldc,
+                                double* __restrict__ Sk) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)r * k) return;
   const int i = (int)(t / k), c = (int)(t % k);
@@ -721,6 +732,7 @@ __global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int 
   const double v = S[(int64_t)i * lds_ + c];
   C[(int64_t)i * ldc + c] = v * (sg - tau);
   D[(int64_t)i * ldc + c] = v / sg;
+  if (Sk) Sk[(int64_t)i * ldc + c] = v;  // the kept eigenvectors themselves, when asked for
 }
 
 // ------------------------------------------------------------------------------------------
@@ -862,10 +874,11 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
 
 hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
                             int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
-                            double* scal, int slot, int max_sweeps) {
-  if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1) return hipErrorInvalidValue;
+                            double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
+                            uint64_t tag) {
+  if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1 || valid < 0 || valid > b) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eig_small, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV, GV, ldv, b, npairs, filt ? 1 : 0,
-                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps);
+                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid, ev_rows, seed, tag);
   return hipGetLastError();
 }
 
@@ -885,11 +898,11 @@ hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const 
 }
 
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds_, const double* theta,
-                                double tau, double* C, double* D, int ldc) {
+                                double tau, double* C, double* D, int ldc, double* Sk) {
   const int64_t work = (int64_t)r * k;
   if (work == 0) return hipSuccess;
   hipLaunchKernelGGL(k_factor_coeffs, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, r, k, S, lds_, theta,
-                     tau, C, D, ldc);
+                     tau, C, D, ldc, Sk);
   return hipGetLastError();
 }
 

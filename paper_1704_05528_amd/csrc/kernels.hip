@@ -42,40 +42,6 @@ __device__ inline double block_sum(double v, double* lds) {
   return t;
 }
 
-// ------------------------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: the Gaussian sampling matrix Omega of
-// Alg. 2 / Alg. 3.  Counter = (row j, 4-column group q, block, iteration), key = (seed, 0).
-// ------------------------------------------------------------------------------------------
-__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    k0 += W0; k1 += W1;
-  }
-}
-
-__device__ inline double word_to_uniform(uint64_t w) {
-  return ((double)(w >> 11) + 0.5) * 0x1p-53;
-}
-
-__device__ inline void gaussian4(uint64_t j, uint64_t q, uint64_t blk, uint64_t it, uint64_t seed, double z[4]) {
-  uint64_t c[4] = {j, q, blk, it};
-  philox4x64_10(c, seed, 0ull);
-#pragma unroll
-  for (int pr = 0; pr < 2; ++pr) {
-    const double ur = word_to_uniform(c[2 * pr]), ua = word_to_uniform(c[2 * pr + 1]);
-    const double rad = sqrt(-2.0 * log(ur));
-    const double ang = 2.0 * M_PI * ua;
-    z[2 * pr] = rad * cos(ang);
-    z[2 * pr + 1] = rad * sin(ang);
-  }
-}
-
 // om[j, c] for rows j < n and block columns c0 <= c < c0 + w (c0 a multiple of 4), stored at om[j*ld + c - c0].
 template <class T>
 __global__ void k_omega(T* __restrict__ om, int n, int c0, int w, int ld, uint64_t seed, uint64_t blk, uint64_t it) {

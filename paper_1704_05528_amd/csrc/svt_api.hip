@@ -878,7 +878,13 @@ struct Engine {
       const int kb = h->k;
       int b = std::min(std::min(h->b_cap, r), kb <= 8 ? std::max(8, kb + 6) : 2 * kb + 4);
       int valid = warm ? std::max(0, std::min(h->ev_valid, b - 4)) : 0;
-      {
+      // the one-workgroup solver sets up its start block itself (fill_valid columns kept, rows past
+      // fill_rows zero, the others drawn with the same seed and tag)
+      int fill_valid = b, fill_rows = r;
+      if (r <= kSmallR && b <= kSmallB) {
+        fill_valid = valid;
+        fill_rows = (valid > 0) ? h->ev_rows : r;
+      } else {
         PhaseTimer tm(h, SVT_PH_EIG);
         if (valid > 0 && h->ev_rows < r) {
           // new basis columns were appended: zero the new rows of the kept vectors
@@ -914,7 +920,10 @@ struct Engine {
           PhaseTimer tm(h, SVT_PH_EIG);
           const int npairs = std::max(1, (target - powers + 1) / 2);
           HIPCHK(launch_eig_small(s, r, h->G, h->r_cap, h->EV, h->EZ3, kEB, b, npairs, filt, 8.0 / (cf * cf), -8.0 / cf,
-                                  kEigDepTol, h->Eval, kEB, h->scal, S_SWEEPS, 40));
+                                  kEigDepTol, h->Eval, kEB, h->scal, S_SWEEPS, 40, fill_valid, fill_rows,
+                                  h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+          fill_valid = b;  // EV holds the whole block from here on
+          fill_rows = r;
           // per double step two products with G and one or two CholeskyQR passes; then G V, V^T G V,
           // the b x b Jacobi, the two rotations and the residuals
           add_work(h, SVT_PH_EIG, 8.0 * ((double)r * r + 4.0 * r * b + 2.0 * kEB),
@@ -1141,8 +1150,7 @@ struct Engine {
                                                       0.0)));
         HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf));
       } else {
-        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf));
-        HIPCHK((launch_copy_cols<double, double>(s, r, S, lds_, h->Sk, h->ldf, k)));
+        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf, h->Sk));
       }
       if constexpr (kBF16) {
         HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0)));

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include <string>
 #include <vector>
 
@@ -52,6 +54,40 @@ __device__ inline double rsq_nr(double x) {
   y = y * fma(-0.5 * x * y, y, 1.5);
   y = y * fma(-0.5 * x * y, y, 1.5);
   return y;
+}
+
+// ------------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: the Gaussian sampling matrix Omega of
+// Alg. 2 / Alg. 3.  Counter = (row j, 4-column group q, block, iteration), key = (seed, 0).
+// ------------------------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+__device__ inline double word_to_uniform(uint64_t w) {
+  return ((double)(w >> 11) + 0.5) * 0x1p-53;
+}
+
+__device__ inline void gaussian4(uint64_t j, uint64_t q, uint64_t blk, uint64_t it, uint64_t seed, double z[4]) {
+  uint64_t c[4] = {j, q, blk, it};
+  philox4x64_10(c, seed, 0ull);
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const double ur = word_to_uniform(c[2 * pr]), ua = word_to_uniform(c[2 * pr + 1]);
+    const double rad = sqrt(-2.0 * log(ur));
+    const double ang = 2.0 * M_PI * ua;
+    z[2 * pr] = rad * cos(ang);
+    z[2 * pr + 1] = rad * sin(ang);
+  }
 }
 
 // sum_{t < n} p[t * stride] in a fixed order (16 interleaved partial sums, then a fixed tree),
@@ -414,9 +450,12 @@ hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0
 // EV (r x b, ld ldv) holds the start block on entry and the Ritz vectors on exit, GV gets G times them,
 // eval[0..b) the Ritz values (descending) and eval[ldres + c] the residual norms.
 constexpr int kSmallR = 112, kSmallB = 16;
+// Columns valid .. b-1 of the start block are drawn in the kernel (launch_fill_random's values for seed and
+// tag) and rows ev_rows .. r-1 of the first valid columns read as zero, so the block needs no set-up launch.
 hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
                             int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
-                            double* scal, int slot, int max_sweeps);
+                            double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
+                            uint64_t tag);
 
 // P = alpha P + beta G + I on the leading r x r blocks (ld) of two symmetric matrices
 hipError_t launch_cheb2(hipStream_t s, int r, double* P, const double* G, int ld, double alpha, double beta);
@@ -431,7 +470,7 @@ hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const 
                                 const double* theta, double* partial, double* out);
 // factor matrices C = S[:, :k] diag(sigma - tau), D = S[:, :k] diag(1/sigma) from eigenpairs of the Gram
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds, const double* theta,
-                                double tau, double* C, double* D, int ldc);
+                                double tau, double* C, double* D, int ldc, double* Sk = nullptr);
 
 // ---------------------------------------------------------------------------------------------
 // full eigen-decomposition (eigfull.hip), double: cyclic Jacobi over many workgroups, one launch
