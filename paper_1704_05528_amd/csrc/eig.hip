@@ -447,7 +447,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
                                                              int b, int npairs, int filt, double alpha, double beta,
                                                              double dep_tol, double* __restrict__ eval, int ldres,
                                                              double* scal, int slot, int max_sweeps, int valid,
-                                                             int ev_rows, uint64_t seed, uint64_t tag) {
+                                                             int ev_rows, uint64_t seed, uint64_t tag,
+                                                             double* post_dst, unsigned* post_flag, unsigned post_seq) {
   __shared__ double Gs[kSmallR * kSGL];            // G; after the Rayleigh-Ritz products, (G V) S
   __shared__ double Vs[kSmallR * kSmallB];         // the block
   __shared__ double Ts[kSmallR * kSmallB];         // G V
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   __shared__ double Cg[kSmallB * kJL];             // Gram, Cholesky factor, then the rows of R; later S
   __shared__ double JA[kSmallB * kJL], JV[kSmallB * kJL];
   __shared__ double cs[kSmallB / 2], sn[kSmallB / 2];
-  __shared__ double rinv[kSmallB], theta[kSmallB];
+  __shared__ double rinv[kSmallB], theta[kSmallB], resid[2 * kSmallB];
   __shared__ int rank_of[kSmallB];
   __shared__ int keepm[1];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -680,6 +681,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
     if (lane == 0) {
       eval[c] = theta[c];
       eval[ldres + c] = sqrt(acc);
+      resid[c] = theta[c];
+      resid[b + c] = sqrt(acc);
     }
   }
   for (int e = tid; e < r * kSmallB; e += kSmallThreads) {
@@ -687,6 +690,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
     if (c < b) {
       EV[(int64_t)i * ldv + c] = Zs[e];
       GV[(int64_t)i * ldv + c] = Gs[e];
+    }
+  }
+  // the Ritz values and residual norms to the host: the device copies above complete before the host
+  // can act on them (it only enqueues work behind this kernel)
+  if (post_dst != nullptr) {  // uniform
+    __syncthreads();
+    if (tid < 2 * b) post_dst[tid] = resid[tid];
+    __threadfence_system();
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence_system();
+      *(volatile unsigned*)post_flag = post_seq;
     }
   }
 }
@@ -875,10 +890,11 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
 hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
                             int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
                             double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
-                            uint64_t tag) {
+                            uint64_t tag, double* post_dst, unsigned* post_flag, unsigned post_seq) {
   if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1 || valid < 0 || valid > b) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eig_small, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV, GV, ldv, b, npairs, filt ? 1 : 0,
-                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid, ev_rows, seed, tag);
+                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid, ev_rows, seed, tag, post_dst,
+                     post_flag, post_seq);
   return hipGetLastError();
 }
 

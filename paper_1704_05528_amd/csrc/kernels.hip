@@ -731,7 +731,8 @@ __global__ __launch_bounds__(256) void k_sumsq(int64_t len, const T* __restrict_
 // scal[slot + q] = sum_b partial[b * stride + q] for q < nq: one workgroup, each thread sums a
 // fixed strided subset, then a fixed butterfly and wave order (deterministic).
 __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int nblocks, int stride, int nq,
-                                                double* scal, int slot) {
+                                                double* scal, int slot, const double* post_src, int post_count,
+                                                double* post_dst, unsigned* post_flag, unsigned post_seq) {
   __shared__ double lds[4];
   for (int q = 0; q < nq; ++q) {
     double v = 0.0;
@@ -739,6 +740,7 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ parti
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) scal[slot + q] = t;
   }
+  if (post_dst != nullptr) post_to_host(post_src, post_count, post_dst, post_flag, post_seq);  // uniform
 }
 
 __global__ void k_diag_sqrt(const double* __restrict__ G, int ldg, int w, double* __restrict__ out) {
@@ -1474,14 +1476,13 @@ hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, dou
 
 template <class T>
 hipError_t launch_sumsq_cols(hipStream_t s, int rows, const T* A, int lda, int c0, int w, double* partial,
-                             double* scal, int slot) {
+                             double* scal, int slot, const PostReq* post) {
   const int64_t total = (int64_t)rows * w;
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (total + 255) / 256));
   hipLaunchKernelGGL(k_sumsq_cols<T>, dim3(nb), dim3(256), 0, s, rows, A, lda, c0, w, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
-  return hipGetLastError();
+  return launch_finish(s, partial, nb, 1, 1, scal, slot, post);
 }
 
 template <class T>
@@ -1490,7 +1491,7 @@ hipError_t launch_sumsq(hipStream_t s, int64_t len, const T* v, double* partial,
   hipLaunchKernelGGL(k_sumsq<T>, dim3(nb), dim3(256), 0, s, len, v, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nb, 1, 1, scal, slot, nullptr, 0, nullptr, nullptr, 0u);
   return hipGetLastError();
 }
 
@@ -1636,13 +1637,7 @@ hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const
 // value is visible to the host (each thread's system-scope fence, the barrier, then thread 0's)
 __global__ __launch_bounds__(256) void k_post(const double* __restrict__ src, int count, double* dst,
                                               unsigned* flag, unsigned seq) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
-  __threadfence_system();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence_system();
-    *(volatile unsigned*)flag = seq;
-  }
+  post_to_host(src, count, dst, flag, seq);
 }
 
 hipError_t launch_post(hipStream_t s, const double* src, int count, double* dst_mapped, unsigned* flag_mapped,
@@ -1653,8 +1648,11 @@ hipError_t launch_post(hipStream_t s, const double* src, int count, double* dst_
 }
 
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal,
-                         int slot) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nblocks, stride, nq, scal, slot);
+                         int slot, const PostReq* post) {
+  const PostReq none;
+  const PostReq& p = post ? *post : none;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partial, nblocks, stride, nq, scal, slot, p.src, p.count, p.dst,
+                     p.flag, p.seq);
   return hipGetLastError();
 }
 
@@ -1674,7 +1672,8 @@ hipError_t launch_mae_fused(hipStream_t s, int64_t nq, const int32_t* qi, const 
   hipLaunchKernelGGL(k_sample_absdiff<T>, dim3(nb), dim3(256), 0, s, nq, qi, qj, Ut, Vt, ld, k, m, n, ref, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, work, nb, 1, 1, work, kMaeFusedBlocks);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, work, nb, 1, 1, work, kMaeFusedBlocks, nullptr, 0, nullptr,
+                     nullptr, 0u);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_div_store, dim3(1), dim3(64), 0, s, work + kMaeFusedBlocks, (double)nq, out);
@@ -1714,7 +1713,8 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
   template hipError_t launch_tn_partial<T, T>(hipStream_t, int, const T*, int, int, const T*, int, int, double*,      \
                                               int64_t, int*);                                                         \
   template hipError_t launch_gram<T>(hipStream_t, int, const T*, int, int, double*, int, double*, int64_t);           \
-  template hipError_t launch_sumsq_cols<T>(hipStream_t, int, const T*, int, int, int, double*, double*, int);         \
+  template hipError_t launch_sumsq_cols<T>(hipStream_t, int, const T*, int, int, int, double*, double*, int,          \
+                                           const PostReq*);                                                            \
   template hipError_t launch_sumsq<T>(hipStream_t, int64_t, const T*, double*, double*, int);                         \
   template hipError_t launch_colnorms<T>(hipStream_t, int, const T*, int, int, double*, double*, int64_t, double*);   \
   template hipError_t launch_trsm_rows<T>(hipStream_t, int, const T*, int, int, const double*, int, T*, int);         \

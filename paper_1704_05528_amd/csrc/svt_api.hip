@@ -907,6 +907,7 @@ struct Engine {
       const double cf = std::min(h->cheb_c, tau2);
       const bool filt = warm && cf > 1e-10 * tau2 && std::isfinite(cf);
       bool done = false, have_gv = false, have_g2 = false, used_small = false;
+      unsigned small_seq = 0;  // the one-workgroup solver's post of this test (0: none)
       int powers = 0, tests = 0, prev_k = -1;
       int target = std::max(2, h->eig_pred);
       while (!done) {
@@ -919,9 +920,10 @@ struct Engine {
           // leaving the Ritz vectors in EV, G times them in EZ3, and the Ritz values and residuals
           PhaseTimer tm(h, SVT_PH_EIG);
           const int npairs = std::max(1, (target - powers + 1) / 2);
+          small_seq = ++h->post_seq;
           HIPCHK(launch_eig_small(s, r, h->G, h->r_cap, h->EV, h->EZ3, kEB, b, npairs, filt, 8.0 / (cf * cf), -8.0 / cf,
                                   kEigDepTol, h->Eval, kEB, h->scal, S_SWEEPS, 40, fill_valid, fill_rows,
-                                  h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter));
+                                  h->p.seed ^ 0x5A5A5A5Aull, (uint64_t)h->iter, h->hstage_d, h->hflag_d, small_seq));
           fill_valid = b;  // EV holds the whole block from here on
           fill_rows = r;
           // per double step two products with G and one or two CholeskyQR passes; then G V, V^T G V,
@@ -1018,12 +1020,16 @@ struct Engine {
           have_gv = true;
         }
         ++tests;
-        {  // the b Ritz values and the b residual norms, posted together
-          hipError_t e = hipSuccess;
-          (void)post(h, h->hstage_d, h->Eval, b, &e);
-          HIPCHK(e);
-          const unsigned seq = post(h, h->hstage_d + b, h->Eval + kEB, b, &e);
-          HIPCHK(e);
+        {  // the b Ritz values and the b residual norms (posted by the one-workgroup solver itself)
+          unsigned seq = small_seq;
+          if (seq == 0) {
+            hipError_t e = hipSuccess;
+            (void)post(h, h->hstage_d, h->Eval, b, &e);
+            HIPCHK(e);
+            seq = post(h, h->hstage_d + b, h->Eval + kEB, b, &e);
+            HIPCHK(e);
+          }
+          small_seq = 0;
           CHK(wait_post(h, seq));
           std::memcpy(theta.data(), h->hstage, (size_t)b * sizeof(double));
           std::memcpy(res.data(), h->hstage + b, (size_t)b * sizeof(double));
@@ -1224,8 +1230,12 @@ struct Engine {
       CHK(correct_gram(h->r, S_NORMB));
       h->gp_valid = true;
     } else {
+      // ||W||^2 and its post to the host in one launch sequence
       PhaseTimer tm(h, SVT_PH_REDUCE);
-      HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+      const PostReq pr{h->scal + S_NORMB, 1, h->hscal_d + kSpecSlot, h->hflag_d, ++h->post_seq};
+      HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB, &pr));
+      h->spec_seq = pr.seq;
+      return SVT_OK;
     }
     hipError_t e = hipSuccess;
     h->spec_seq = post(h, h->hscal_d + kSpecSlot, h->scal + S_NORMB, 1, &e);
@@ -1265,18 +1275,16 @@ struct Engine {
     }
     {
       PhaseTimer tm(h, SVT_PH_REDUCE);
-      HIPCHK(launch_finish(h->stream, h->partial, nbl, 3, 3, h->scal, S_RES2));
+      // the sums, and with them every scalar up to S_ABS, go to the host from the same kernel
+      const PostReq pr{h->scal, S_ABS + 1, h->hscal_d, h->hflag_d, ++h->post_seq};
+      HIPCHK(launch_finish(h->stream, h->partial, nbl, 3, 3, h->scal, S_RES2, &pr));
+      h->sync_seq = pr.seq;
     }
     CHK(recycle_truncated());
     // This iteration's sums go to the host first.  In R4SVD mode the next iteration's leading work
     // (dense copy, W = Y^T Q, ||W||^2 on the updated iterate and the recycled basis) is enqueued
     // behind them, so the GPU runs it while the host waits for the sums and takes this iteration's
     // decisions: none of them changes its inputs, and a stop leaves it unused.
-    {
-      hipError_t e = hipSuccess;
-      h->sync_seq = post(h, h->hscal_d, h->scal, S_ABS + 1, &e);
-      HIPCHK(e);
-    }
     if (h->p.mode == SVT_MODE_R4SVD && h->r > 0) {
       std::swap(h->y, h->y_next);
       const svt_status ls = lead_work();

@@ -90,6 +90,21 @@ __device__ inline void gaussian4(uint64_t j, uint64_t q, uint64_t blk, uint64_t 
   }
 }
 
+// Copies src[0..count) to mapped host memory and then sets *flag = seq, with every value visible to
+// the host first (each thread's system-scope fence, the barrier, then thread 0's); one workgroup.
+// The source may have been written by this workgroup before the call.
+__device__ inline void post_to_host(const double* src, int count, double* dst, unsigned* flag, unsigned seq) {
+  __threadfence_block();
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *(volatile unsigned*)flag = seq;
+  }
+}
+
 // sum_{t < n} p[t * stride] in a fixed order (16 interleaved partial sums, then a fixed tree),
 // with 16 independent loads in flight: the split sums of the tall products are latency bound
 // when each load waits for the previous add.
@@ -352,10 +367,20 @@ template <class T>
 hipError_t launch_gram(hipStream_t s, int rows, const T* A, int lda, int na, double* G, int ldg, double* partial,
                        int64_t partial_cap);
 
-// scal[slot] = sum of squares over the columns c0..c0+w-1 of a rows x ld matrix
+// A device -> host post attached to the kernel that produces the values (see launch_post): after its
+// own work the kernel copies src[0..count) to dst (mapped host memory) and sets *flag = seq.
+struct PostReq {
+  const double* src = nullptr;
+  int count = 0;
+  double* dst = nullptr;
+  unsigned* flag = nullptr;
+  unsigned seq = 0;
+};
+
+// scal[slot] = sum of squares over the columns c0..c0+w-1 of a rows x ld matrix (then the post, if any)
 template <class T>
 hipError_t launch_sumsq_cols(hipStream_t s, int rows, const T* A, int lda, int c0, int w, double* partial,
-                             double* scal, int slot);
+                             double* scal, int slot, const PostReq* post = nullptr);
 // scal[slot] = sum v[i]^2
 template <class T>
 hipError_t launch_sumsq(hipStream_t s, int64_t len, const T* v, double* partial, double* scal, int slot);
@@ -399,8 +424,9 @@ template <class T>
 hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
                                const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
                                int ld, int k, double delta, double* partial, int* nblocks);
-// scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order
-hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot);
+// scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order (then the post, if any)
+hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot,
+                         const PostReq* post = nullptr);
 // Copies count doubles to host memory mapped into the device (dst_mapped: its device address) and then
 // sets the mapped flag to seq: the host polls the flag instead of waiting for a copy and an event.
 hipError_t launch_post(hipStream_t s, const double* src, int count, double* dst_mapped, unsigned* flag_mapped,
@@ -452,10 +478,13 @@ hipError_t launch_fill_random(hipStream_t s, double* V, int rows, int ld, int c0
 constexpr int kSmallR = 112, kSmallB = 16;
 // Columns valid .. b-1 of the start block are drawn in the kernel (launch_fill_random's values for seed and
 // tag) and rows ev_rows .. r-1 of the first valid columns read as zero, so the block needs no set-up launch.
+// With post_dst given, the b Ritz values and then the b residual norms are also written there (mapped
+// host memory) and *post_flag set to post_seq.
 hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, double* EV, double* GV, int ldv, int b,
                             int npairs, bool filt, double alpha, double beta, double dep_tol, double* eval, int ldres,
                             double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
-                            uint64_t tag);
+                            uint64_t tag, double* post_dst = nullptr, unsigned* post_flag = nullptr,
+                            unsigned post_seq = 0);
 
 // P = alpha P + beta G + I on the leading r x r blocks (ld) of two symmetric matrices
 hipError_t launch_cheb2(hipStream_t s, int r, double* P, const double* G, int ld, double alpha, double beta);
