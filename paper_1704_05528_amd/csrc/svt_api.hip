@@ -315,7 +315,13 @@ struct Engine {
   // Block orthonormalisation (CholeskyQR2 with the column-drop rule) of X (rows x wc, ld).
   // prenorm == nullptr: no span rule.  Orthonormal columns packed left; scal[S_WK2] = count.
   template <class U>
-  svt_status orthonormalize_block(int rows, U* X, U* X2, int ld, int wc, const double* prenorm) {
+  svt_status orthonormalize_block(int rows, U* X, U* X2, int ld, int wc, const double* prenorm, U* out = nullptr,
+                                  int ldo = 0) {
+    // the result goes to out (row stride ldo) when given, else back into X
+    if (out == nullptr) {
+      out = X;
+      ldo = ld;
+    }
     hipStream_t s = h->stream;
     const int64_t ss = (int64_t)wc * wc;  // stride of the split partial Grams
     int sp = 0;
@@ -331,7 +337,7 @@ struct Engine {
       const double* gg = g2;
       int s2 = row_groups(rows);
       if (!ep) CHK(pass_gram<U>(rows, X2, ld, wc, &gg, &s2));
-      HIPCHK(launch_chol_trsm<U>(s, rows, X2, ld, wc, gg, s2, ss, nullptr, 0.0, kDepTol, S_WK1, X, ld, nullptr,
+      HIPCHK(launch_chol_trsm<U>(s, rows, X2, ld, wc, gg, s2, ss, nullptr, 0.0, kDepTol, S_WK1, out, ldo, nullptr,
                                  h->scal, S_WK2));
       return SVT_OK;
     }
@@ -342,7 +348,7 @@ struct Engine {
     HIPCHK((launch_tn_partial<U, U>(s, rows, X2, ld, wc, X2, ld, wc, h->partial, h->partial_cap, &sp)));
     HIPCHK(launch_block_chol(s, h->partial, wc, wc, nullptr, 0.0, kDepTol, h->Minv, kEigMax, h->scal, S_WK2, S_WK1,
                              sp, ss));
-    HIPCHK(launch_trsm_rows<U>(s, rows, X2, ld, wc, h->Minv, kEigMax, X, ld));
+    HIPCHK(launch_trsm_rows<U>(s, rows, X2, ld, wc, h->Minv, kEigMax, out, ldo));
     return SVT_OK;
   }
 
@@ -520,6 +526,7 @@ struct Engine {
     const int ld = h->w_cap;
     *got = 0;
     *add = 0.0;
+    PostReq post_pr;
     for (int c0 = 0; c0 < w; c0 += 64) {
       const int wc = std::min(64, w - c0);
       const int rq = h->r + *got;
@@ -547,11 +554,19 @@ struct Engine {
             HIPCHK((launch_rowmul<TQ, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0)));
           }
         }
-        CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm));
-        HIPCHK((launch_copy_cols<T, TQ>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
+        if constexpr (kBF16) {
+          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm));
+          HIPCHK((launch_copy_cols<T, TQ>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
+        } else {
+          // the second CholeskyQR pass writes the new columns straight into the basis
+          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm, (T*)Q() + rq, (int)h->r_cap));
+        }
         CHK(spmm_yt(Q() + rq, h->r_cap, W() + rq, h->r_cap, wc));
-        if constexpr (!kBF16)
-          HIPCHK(launch_sumsq_cols<T>(s, n, W(), h->r_cap, rq, wc, h->partial, h->scal, S_NADD));
+        if constexpr (!kBF16) {
+          // ||W'||^2, posted to the host with the kept-column count and the other scalars
+          post_pr = PostReq{h->scal, S_BORDER + 1, h->hscal_d, h->hflag_d, ++h->post_seq};
+          HIPCHK(launch_sumsq_cols<T>(s, n, W(), h->r_cap, rq, wc, h->partial, h->scal, S_NADD, &post_pr));
+        }
       }
       if constexpr (kBF16) {
         // the kept columns are rounded to bfloat16 in Q: extend the inverse Cholesky factor of the
@@ -562,7 +577,12 @@ struct Engine {
         if (kept > 0) CHK(border(rq, kept, true));
         else HIPCHK(hipMemsetAsync(h->scal + S_NADD, 0, 2 * sizeof(double), s));
       }
-      CHK(readback(h, S_BORDER + 1));
+      if constexpr (kBF16) {
+        CHK(readback(h, S_BORDER + 1));
+      } else {
+        CHK(wait_post(h, post_pr.seq));
+        if (h->pending.size() >= kMaxPending) resolve_pending(h);
+      }
       if (kBF16 && h->hscal[S_BORDER] != 0.0)
         return fail(h, SVT_E_NUMERIC, "the Gram of the bfloat16 basis lost positive definiteness");
       const int kept = (int)h->hscal[S_WK2];
