@@ -225,6 +225,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
 // so a round costs one LDS trip for the rotation inputs and one for the operands.  The rotations,
 // the tolerance and the output are those of k_jacobi.
 constexpr int kJacWaveMax = 32;
+// blocks up to this width go to the one-wave kernel: measured on warm starts, 32.2 against 41.4 us at 12
+// columns and 43.6 against 60.4 at 16, but 150 against 119 at 24 and 272 against 170 at 32, where the
+// lanes' four A blocks and eight V row pairs per round outweigh the barriers of four waves
+constexpr int kJacWaveSmall = 16;
 
 // Indices (p < q) of pair slot t in a round of the round-robin ordering over bb indices: slot 0
 // keeps index 0, the other indices move one position per round.
@@ -320,9 +324,12 @@ __device__ int jacobi_wave_core(double* A, double* V, double* cs, double* sn, in
         int p, q;
         rr_pair(lane, round, bb, p, q);
         const double apq = A[p * LD + q], app = A[p * LD + p], aqq = A[q * LD + q];
-        // computed on every rotating lane and selected, so the three loads go out together
+        // computed on every rotating lane and selected, so the three loads go out together.  The square
+        // root is x rsq(x) with the refined reciprocal root (a few ulps, where the IEEE root is a longer
+        // chain): the angle only needs to be close, the rotation is orthogonal through c = rsq(1 + t^2)
         const double dd = aqq - app;
-        const double den = fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq));
+        const double x = fma(dd, dd, 4.0 * apq * apq);
+        const double den = fabs(dd) + x * rsq_nr(x);
         const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq * rcp_nr(den);
         const double cr = rsq_nr(fma(tt, tt, 1.0));
         mine = fabs(apq) > tol;
@@ -870,7 +877,7 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
   if (b <= 0 || b > kEigMax || splits <= 0) return hipErrorInvalidValue;
   const int bb = b + (b & 1);
   const size_t lds = (size_t)2 * bb * (bb + 1) * sizeof(double);
-  if (b <= kJacWaveMax) {
+  if (b <= kJacWaveSmall) {
     hipLaunchKernelGGL(k_jacobi_wave, dim3(1), dim3(kWave), 0, s, H, ldh, splits, sstride, b, eval, evec, ldv, scal,
                        slot, max_sweeps);
     return hipGetLastError();
