@@ -97,7 +97,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
           mine = 1;
           // tangent of the smaller rotation angle that annihilates a_pq
           const double dd = aqq - app;
-          const double den = fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq));
+          const double x = fma(dd, dd, 4.0 * apq * apq);  // x > 0 here (|a_pq| above the tolerance)
+          const double den = fabs(dd) + x * rsq_nr(x);
           const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq * rcp_nr(den);
           c = rsq_nr(fma(tt, tt, 1.0));
           s = tt * c;
@@ -114,6 +115,33 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ H, in
       __syncthreads();
       if (!flag[seq & 1]) continue;  // uniform: nothing rotates, nothing to update this round
       sweep_any = 1;
+      if (bb <= 32) {
+        // up to 32 columns: one pass over the 2 x 2 blocks of A and the row pairs of V, no chunking
+        // (at these sizes the gather-then-update chunks below cost more than they save)
+        for (int e = tid; e < totA + totV; e += blockDim.x) {
+          if (e < totA) {
+            const int P = e / half, R = e - (e / half) * half;
+            const int p1 = pp[P], q1 = qq[P], p2 = pp[R], q2 = qq[R];
+            const double c1 = cs[P], s1 = sn[P], c2 = cs[R], s2 = sn[R];
+            const double a0 = A[p1 * ld + p2], a1 = A[p1 * ld + q2], a2 = A[q1 * ld + p2], a3 = A[q1 * ld + q2];
+            const double r00 = c1 * a0 - s1 * a2, r01 = c1 * a1 - s1 * a3;
+            const double r10 = s1 * a0 + c1 * a2, r11 = s1 * a1 + c1 * a3;
+            A[p1 * ld + p2] = c2 * r00 - s2 * r01;
+            A[p1 * ld + q2] = s2 * r00 + c2 * r01;
+            A[q1 * ld + p2] = c2 * r10 - s2 * r11;
+            A[q1 * ld + q2] = s2 * r10 + c2 * r11;
+          } else {
+            const int e2 = e - totA, i = e2 / half, R = e2 - (e2 / half) * half;
+            const int p = pp[R], q = qq[R];
+            const double c = cs[R], s = sn[R];
+            const double v0 = V[i * ld + p], v1 = V[i * ld + q];
+            V[i * ld + p] = c * v0 - s * v1;
+            V[i * ld + q] = s * v0 + c * v1;
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       for (int base = 0; base < totA; base += CA * 256) {
         double a0[CA], a1[CA], a2[CA], a3[CA], c1v[CA], s1v[CA], c2v[CA], s2v[CA];
         int o0[CA], o1[CA], o2[CA], o3[CA];
