@@ -316,7 +316,7 @@ struct Engine {
   // prenorm == nullptr: no span rule.  Orthonormal columns packed left; scal[S_WK2] = count.
   template <class U>
   svt_status orthonormalize_block(int rows, U* X, U* X2, int ld, int wc, const double* prenorm, U* out = nullptr,
-                                  int ldo = 0) {
+                                  int ldo = 0, const double* gram_in = nullptr, int gram_splits = 0) {
     // the result goes to out (row stride ldo) when given, else back into X
     if (out == nullptr) {
       out = X;
@@ -328,8 +328,10 @@ struct Engine {
     if (fused_cholqr(rows, wc)) {
       // Gram of X; pass 1 factors and solves into X2 (and, up to 32 columns, leaves the Gram
       // partials of X2); pass 2 factors the Gram of X2 and solves back into X
-      const double* g1 = nullptr;
-      CHK(pass_gram<U>(rows, X, ld, wc, &g1, &sp));
+      // the Gram partials of X: left by the product that wrote X (gram_in), else formed here
+      const double* g1 = gram_in;
+      sp = gram_splits;
+      if (g1 == nullptr) CHK(pass_gram<U>(rows, X, ld, wc, &g1, &sp));
       const bool ep = wc <= kCholTrsmGoutCols;
       double* g2 = h->partial + h->partial_cap / 2;
       HIPCHK(launch_chol_trsm<U>(s, rows, X, ld, wc, g1, sp, ss, prenorm, kDropTol, kDepTol, -1, X2, ld,
@@ -547,19 +549,29 @@ struct Engine {
           CHK(spmm_y(Om(), ld, X(), ld, wc));
         }
         HIPCHK(launch_colnorms<T>(s, m, X(), ld, wc, h->small, h->partial, h->partial_cap, h->prenorm));
+        // the second projection's product also leaves the Gram partials of the projected block (one per
+        // 16-row tile) for the first CholeskyQR pass, when the block has at most 16 columns
+        const double* gram_x = nullptr;
+        int gram_xs = 0;
         if (rq > 0) {
           for (int pass = 0; pass < 2; ++pass) {
             HIPCHK((launch_tn_narrow<TQ, T>(s, m, Q(), h->r_cap, rq, X(), ld, wc, h->T, ld, h->partial,
                                             h->partial_cap)));
-            HIPCHK((launch_rowmul<TQ, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0)));
+            const bool gx = pass == 1 && wc <= 16 && fused_cholqr(m, wc);
+            HIPCHK((launch_rowmul<TQ, double, T>(s, m, rq, Q(), h->r_cap, h->T, ld, X(), ld, wc, -1.0, 1.0,
+                                                 gx ? h->partial : nullptr)));
+            if (gx) {
+              gram_x = h->partial;
+              gram_xs = (m + 15) / 16;
+            }
           }
         }
         if constexpr (kBF16) {
-          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm));
+          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm, nullptr, 0, gram_x, gram_xs));
           HIPCHK((launch_copy_cols<T, TQ>(s, m, X(), ld, Q() + rq, h->r_cap, wc)));
         } else {
           // the second CholeskyQR pass writes the new columns straight into the basis
-          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm, (T*)Q() + rq, (int)h->r_cap));
+          CHK(orthonormalize_block<T>(m, X(), X2(), ld, wc, h->prenorm, (T*)Q() + rq, (int)h->r_cap, gram_x, gram_xs));
         }
         CHK(spmm_yt(Q() + rq, h->r_cap, W() + rq, h->r_cap, wc));
         if constexpr (!kBF16) {
