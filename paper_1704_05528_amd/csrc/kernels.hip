@@ -1132,7 +1132,8 @@ __device__ inline double dot16(Vec16<double>::type a, Vec16<double>::type b, dou
 // Work comes in chunks of at most kSddmmChunk consecutive CSC positions of one column (the chunk
 // table is built once at set-up), one wave per chunk, so power-law columns do not serialise on
 // one wave.  Vt[j, :] is staged in LDS.  The dot product and the update run in T; the sums
-// accumulate in double.
+// accumulate in double.  With yT set, y_next also goes to the dense transposed copy of the
+// iterate (yT[j * ldy + i]), which the next R4SVD call's products then read as they are.
 // ------------------------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t* __restrict__ cstart,
@@ -1140,7 +1141,8 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
                                                       const int32_t* __restrict__ rowidx, const T* __restrict__ a,
                                                       const T* __restrict__ y, T* __restrict__ y_next,
                                                       const T* __restrict__ Ut, const T* __restrict__ Vt, int ld,
-                                                      int k, T delta, double* __restrict__ partial) {
+                                                      int k, T delta, double* __restrict__ partial,
+                                                      T* __restrict__ yT, int64_t ldy) {
   using V = typename Vec16<T>::type;  // 16-byte vector of T
   constexpr int E = Vec16<T>::n;
   extern __shared__ __align__(16) unsigned char sdd_lds[];
@@ -1150,21 +1152,23 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
   const int kv = (k + E - 1) / E;  // 16-byte vectors per factor row (ld is a multiple of E)
   T* vsw = reinterpret_cast<T*>(sdd_lds) + (size_t)wid * kv * E;  // this wave's row of Vt
   double s_res = 0.0, s_y = 0.0, s_abs = 0.0;
-  int p0 = 0, p1 = 0;
+  int p0 = 0, p1 = 0, j = 0;
   if (c < nchunks) {
     p0 = cstart[c];
     p1 = cstart[c + 1];
-    const int j = ccol[c];
+    j = ccol[c];
     // Vt[j, :k] and zeros up to the vector boundary (the factor buffers are zero-initialised, so
     // the padded products are exact zeros)
     for (int l = lane; l < kv * E; l += kWave) vsw[l] = (l < k) ? Vt[(int64_t)j * ld + l] : (T)0;
   }
   __syncthreads();
   const V* vv = reinterpret_cast<const V*>(vsw);
-  auto update = [&](int p, T x) {
+  T* ycol = yT ? yT + (int64_t)j * ldy : nullptr;
+  auto update = [&](int p, int i, T x) {
     const T res = a[p] - x;
     const T yn = fma(delta, res, y[p]);
     y_next[p] = yn;
+    if (ycol) ycol[i] = yn;
     s_res = fma((double)res, (double)res, s_res);
     s_y = fma((double)yn, (double)yn, s_y);
     s_abs += fabs((double)res);
@@ -1172,22 +1176,24 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
   // two entries per lane and step: both factor rows are in flight before the products
   int p = p0 + lane;
   for (; p + kWave < p1; p += 2 * kWave) {
-    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p] * ld);
-    const V* u1 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p + kWave] * ld);
+    const int i0 = rowidx[p], i1 = rowidx[p + kWave];
+    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)i0 * ld);
+    const V* u1 = reinterpret_cast<const V*>(Ut + (int64_t)i1 * ld);
     T x0 = (T)0, x1 = (T)0;
     for (int l = 0; l < kv; ++l) {
       const V a0 = u0[l], a1 = u1[l], b = vv[l];
       x0 = dot16(a0, b, x0);
       x1 = dot16(a1, b, x1);
     }
-    update(p, x0);
-    update(p + kWave, x1);
+    update(p, i0, x0);
+    update(p + kWave, i1, x1);
   }
   if (p < p1) {
-    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)rowidx[p] * ld);
+    const int i0 = rowidx[p];
+    const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)i0 * ld);
     T x0 = (T)0;
     for (int l = 0; l < kv; ++l) x0 = dot16(u0[l], vv[l], x0);
-    update(p, x0);
+    update(p, i0, x0);
   }
   const double t0 = block_sum(s_res, lds);
   const double t1 = block_sum(s_y, lds);
@@ -1604,7 +1610,7 @@ hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w,
 template <class T>
 hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
                                const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
-                               int ld, int k, double delta, double* partial, int* nblocks) {
+                               int ld, int k, double delta, double* partial, int* nblocks, T* yT, int64_t ldy) {
   const int nb = std::max(1, (nchunks + 3) / 4);
   *nblocks = nb;
   constexpr int E = (int)(16 / sizeof(T));
@@ -1620,7 +1626,7 @@ hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart
     if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), lds, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut,
-                     Vt, ld, k, (T)delta, partial);
+                     Vt, ld, k, (T)delta, partial, yT, ldy);
   return hipGetLastError();
 }
 
@@ -1722,7 +1728,7 @@ hipError_t launch_copy_cols(hipStream_t s, int rows, const TS* src, int lds_, TD
                                           const double*, double, double, int, T*, int, double*, double*, int);        \
   template hipError_t launch_sddmm_update<T>(hipStream_t, int, const int32_t*, const int32_t*, const int32_t*,       \
                                              const T*, const T*, T*, const T*, const T*, int, int, double, double*,   \
-                                             int*);                                                                   \
+                                             int*, T*, int64_t);                                                      \
   template hipError_t launch_sample<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*, int, \
                                        int, int64_t, int64_t, double*);                                               \
   template hipError_t launch_mae_fused<T>(hipStream_t, int64_t, const int32_t*, const int32_t*, const T*, const T*,    \

@@ -443,8 +443,8 @@ struct Engine {
   }
 
   // out = Y^T D: a matrix-core product with the dense copy of Y when at least a quarter of the
-  // entries are observed and D has 32 columns or more (the copy is refreshed at the start of
-  // every R4SVD call), else the CSC gather kernel
+  // entries are observed and D has 32 columns or more (the copy is written by the update that
+  // produced Y, or refreshed at the start of the R4SVD call), else the CSC gather kernel
   template <class TD>
   svt_status spmm_yt(const TD* D, int ldd, T* out, int ldo, int w) {
     if (h->yT && w >= 32) {  // narrow blocks stay on the sparse kernel (too few output tiles)
@@ -632,10 +632,11 @@ struct Engine {
     HIPCHK(launch_gram<T>(h->stream, (int)h->n, W(), h->r_cap, h->r, h->G, h->r_cap, h->partial, h->partial_cap));
     return SVT_OK;
   }
-  // y_next = y + delta P_Lambda(A - Ut Vt^T), with the residual sums in partial
+  // y_next = y + delta P_Lambda(A - Ut Vt^T), with the residual sums in partial; on the dense path
+  // y_next also goes to the dense copy yT (which then no longer holds y)
   svt_status run_sddmm(int* nbl) {
     HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
-                                  h->ldf, h->k, h->p.delta, h->partial, nbl));
+                                  h->ldf, h->k, h->p.delta, h->partial, nbl, (T*)h->yT, h->m));
     return SVT_OK;
   }
   double work_bytes(int ph) const {
@@ -644,7 +645,7 @@ struct Engine {
       case SVT_PH_DENSIFY: return nnz * (2.0 * es + 4.0) + 4.0 * (n + 1);
       case SVT_PH_SPMM_T: return nnz * (es + 4.0) + 4.0 * (n + 1) + es * r * (m + n);
       case SVT_PH_GRAM: return es * n * r + 8.0 * r * r;
-      case SVT_PH_SDDMM: return nnz * (3.0 * es + 4.0) + 4.0 * (n + 1) + es * k * (m + n);
+      case SVT_PH_SDDMM: return nnz * ((h->yT ? 4.0 : 3.0) * es + 4.0) + 4.0 * (n + 1) + es * k * (m + n);
       default: return 0.0;
     }
   }
@@ -1244,14 +1245,11 @@ struct Engine {
     }
   }
 
-  // The leading work of an R4SVD call on the current Y and basis: the dense copy of Y, W = Y^T Q and
-  // ||W||^2 (posted to hscal[kSpecSlot] as spec_seq).
+  // The leading work of an R4SVD call on the current Y and basis: W = Y^T Q and ||W||^2 (posted to
+  // hscal[kSpecSlot] as spec_seq).  It follows the update, which has already written the dense
+  // copy of this Y.
   svt_status lead_work() {
     hipStream_t s = h->stream;
-    if (h->yT) {
-      PhaseTimer tm(h, SVT_PH_DENSIFY, work_bytes(SVT_PH_DENSIFY));
-      CHK(run_densify());
-    }
     {
       PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
       CHK(run_spmm_t());
@@ -1314,7 +1312,7 @@ struct Engine {
     }
     CHK(recycle_truncated());
     // This iteration's sums go to the host first.  In R4SVD mode the next iteration's leading work
-    // (dense copy, W = Y^T Q, ||W||^2 on the updated iterate and the recycled basis) is enqueued
+    // (W = Y^T Q and ||W||^2 on the updated iterate and the recycled basis) is enqueued
     // behind them, so the GPU runs it while the host waits for the sums and takes this iteration's
     // decisions: none of them changes its inputs, and a stop leaves it unused.
     if (h->p.mode == SVT_MODE_R4SVD && h->r > 0) {

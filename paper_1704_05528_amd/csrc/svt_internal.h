@@ -419,11 +419,13 @@ hipError_t launch_chol_trsm(hipStream_t s, int rows, const T* X, int ldx, int w,
 // sampled product on Lambda (CSC order) with residual and dual update, one wave per chunk of at
 // most kSddmmChunk positions of one column (chunk c = [cstart[c], cstart[c+1]) in column ccol[c]);
 // per-block partial sums of res^2, y_next^2 and |res| land in partial[3 b], partial[3 b + 1],
-// partial[3 b + 2]; *nblocks receives the block count
+// partial[3 b + 2]; *nblocks receives the block count.  With yT non-null, y_next at position
+// (i, j) is also stored to yT[j * ldy + i] (the dense transposed copy; other entries untouched).
 template <class T>
 hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart, const int32_t* ccol,
                                const int32_t* rowidx, const T* a, const T* y, T* y_next, const T* Ut, const T* Vt,
-                               int ld, int k, double delta, double* partial, int* nblocks);
+                               int ld, int k, double delta, double* partial, int* nblocks, T* yT = nullptr,
+                               int64_t ldy = 0);
 // scal[slot + q] = sum_b partial[b * stride + q], q < nq, in block order (then the post, if any)
 hipError_t launch_finish(hipStream_t s, const double* partial, int nblocks, int stride, int nq, double* scal, int slot,
                          const PostReq* post = nullptr);
