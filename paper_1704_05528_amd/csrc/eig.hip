@@ -477,6 +477,9 @@ constexpr int kSmallThreads = 512;
 constexpr int kSGL = kSmallR + 1;  // row stride of G in LDS (odd: the A operand's 16 rows fall on distinct banks)
 constexpr int kJL = kSmallB + 1;   // row stride of the b x b blocks
 
+// NB (8 or 16, at least b) sizes the register arrays of the Cholesky factorisation and of the row
+// solve; the LDS layout keeps 16 columns for the matrix-core tiles either way.
+template <int NB>
 __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double* __restrict__ G, int ldg,
                                                              double* __restrict__ EV, double* __restrict__ GV, int ldv,
                                                              int b, int npairs, int filt, double alpha, double beta,
@@ -571,44 +574,46 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   auto cholqr = [&]() {
     tprod(Zs, Zs);
     if (wv == 0) {
-      // right-looking Cholesky in registers: lane i < 16 holds row i of the symmetric Gram (both
+      // right-looking Cholesky in registers: lane i < NB holds row i of the symmetric Gram (both
       // triangles, updated alike, so it stays symmetric); step c reads the pivot and row c from lane c
-      // (v_readlane, no LDS round trip) and lane i > c updates its entries past c with its own A[i][c]
-      double a[kSmallB];
-      const int li = lane < kSmallB ? lane : 0;
+      // (v_readlane, no LDS round trip) and lanes i > c subtract their multiple A[i][c] / A[c][c] of it
+      // (the other lanes subtract zero).  Step c of a kept column leaves the pivot in piv on lane c.
+      double a[NB];
+      const int li = lane < NB ? lane : 0;
 #pragma unroll
-      for (int j = 0; j < kSmallB; ++j)
-        a[j] = (li < b && j < b) ? Red[li * 16 + j] + Red[256 + li * 16 + j] : 0.0;
+      for (int j = 0; j < NB; ++j) {  // a product with 0 or 1, not a select: the loads stay unconditional
+        const double x = Red[li * 16 + j] + Red[256 + li * 16 + j];
+        a[j] = x * ((lane < b && j < b) ? 1.0 : 0.0);
+      }
       unsigned keep = 0;
-      double gd[kSmallB];
+      double gd[NB];
 #pragma unroll
-      for (int c = 0; c < kSmallB; ++c) {
+      for (int c = 0; c < NB; ++c) {
         gd[c] = fmax(readlane_d(a[c], c), 0.0);
         if (c < b && gd[c] > 0.0) keep |= 1u << c;
       }
+      double piv = 0.0;
 #pragma unroll
-      for (int c = 0; c < kSmallB; ++c) {
-        if (c >= b || !(keep >> c & 1u)) continue;  // uniform
+      for (int c = 0; c < NB; ++c) {
+        if (c >= b) break;  // uniform
         const double d = readlane_d(a[c], c);
-        if (!((d > dep_tol * dep_tol * gd[c]) && (d > 0.0))) {
+        if (!((keep >> c & 1u) && d > dep_tol * dep_tol * gd[c] && d > 0.0)) {  // uniform
           keep &= ~(1u << c);
           continue;
         }
-        const double inv = rcp_nr(d), aic = a[c];
+        piv = (lane == c) ? d : piv;
+        const double f = (lane > c) ? a[c] * rcp_nr(d) : 0.0;
 #pragma unroll
-        for (int j = c + 1; j < kSmallB; ++j) {
-          const double rcj = readlane_d(a[j], c);
-          if (lane > c) a[j] = a[j] - aic * rcj * inv;
-        }
+        for (int j = c + 1; j < NB; ++j) a[j] = fma(-f, readlane_d(a[j], c), a[j]);
       }
       // rows of R (row c on lane c): R[c][c] = sqrt(pivot), R[c][j] = A[c][j] / R[c][c]; zero rows and
       // columns for the dropped and inactive indices
       const bool kc = lane < b && (keep >> li & 1u);
-      const double ri = kc ? rsq_nr(a[li]) : 0.0;
+      const double ri = kc ? rsq_nr(piv) : 0.0;
       if (lane < kSmallB) {
         rinv[lane] = ri;
 #pragma unroll
-        for (int j = 0; j < kSmallB; ++j) {
+        for (int j = 0; j < NB; ++j) {
           double v = 0.0;
           if (kc && j >= lane && (keep >> j & 1u)) v = a[j] * ri;  // j == lane: sqrt(pivot)
           Cg[lane * kJL + j] = v;
@@ -619,11 +624,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
     __syncthreads();
     // forward substitution, one row per thread; kept columns packed to the left
     if (tid < RP) {
-      double z[kSmallB];
+      double z[NB];
 #pragma unroll
-      for (int c = 0; c < kSmallB; ++c) z[c] = Zs[tid * kSmallB + c];
+      for (int c = 0; c < NB; ++c) z[c] = Zs[tid * kSmallB + c];
 #pragma unroll
-      for (int c = 0; c < kSmallB; ++c) {
+      for (int c = 0; c < NB; ++c) {
         if (c < b) {
           double v = z[c];
 #pragma unroll
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
       const unsigned keep = (unsigned)keepm[0];
       int q = 0;
 #pragma unroll
-      for (int c = 0; c < kSmallB; ++c)
+      for (int c = 0; c < NB; ++c)
         if (c < b && (keep >> c & 1u)) Vs[tid * kSmallB + q++] = (tid < r) ? z[c] : 0.0;
       for (int c = q; c < kSmallB; ++c) Vs[tid * kSmallB + c] = 0.0;
     }
@@ -927,9 +932,9 @@ hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, doub
                             double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
                             uint64_t tag, double* post_dst, unsigned* post_flag, unsigned post_seq) {
   if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1 || valid < 0 || valid > b) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_eig_small, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV, GV, ldv, b, npairs, filt ? 1 : 0,
-                     alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid, ev_rows, seed, tag, post_dst,
-                     post_flag, post_seq);
+  hipLaunchKernelGGL(b <= 8 ? k_eig_small<8> : k_eig_small<kSmallB>, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV,
+                     GV, ldv, b, npairs, filt ? 1 : 0, alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid,
+                     ev_rows, seed, tag, post_dst, post_flag, post_seq);
   return hipGetLastError();
 }
 
