@@ -202,14 +202,26 @@ __global__ __launch_bounds__(256 * gemm_kgroups<T>()) void k_gemm_nn(int M, int 
 }
 
 // C[i][j] = sum over the ks partial products (M x N slices of P, in part order)
+// With npart, also this workgroup's sum of squares of C (a fixed shuffle tree, then the four waves in
+// order) in npart[blockIdx.x].
 template <class T>
 __global__ __launch_bounds__(256) void k_split_sum(int M, int N, int ks, const T* __restrict__ P, T* __restrict__ C,
-                                                   int ldc) {
+                                                   int ldc, double* __restrict__ npart) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x, mn = (int64_t)M * N;
-  if (e >= mn) return;
-  T sum = P[e];
-  for (int q = 1; q < ks; ++q) sum += P[q * mn + e];
-  C[(e / N) * ldc + e % N] = sum;
+  double sq = 0.0;
+  if (e < mn) {
+    T sum = P[e];
+    for (int q = 1; q < ks; ++q) sum += P[q * mn + e];
+    C[(e / N) * ldc + e % N] = sum;
+    sq = (double)sum * (double)sum;
+  }
+  if (npart == nullptr) return;  // uniform
+  __shared__ double red[4];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) npart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);  // 256 threads
 }
 
 // yT[j * ldy + i] = y at CSC position p = (i, j): the dense transposed copy of Y on Lambda (the
@@ -228,7 +240,8 @@ __global__ __launch_bounds__(256) void k_scatter_dense_t(int n, const int32_t* _
 
 template <class T, class TB>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
-                          int tri, T* work, int64_t work_elems) {
+                          int tri, T* work, int64_t work_elems, const NormReq* nrm, int* nparts) {
+  if (nparts) *nparts = 0;
   if (M == 0 || N == 0) return hipSuccess;
   if (M < 0 || N < 0 || K < 0) return hipErrorInvalidValue;
   const int tm = (M + kGM - 1) / kGM;
@@ -271,7 +284,11 @@ hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int ld
   if (ks > 1) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_sum<T>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, N, ks, work, C, ldc);
+    const int64_t nb = (mn + 255) / 256;
+    const bool fuse = nrm != nullptr && nparts != nullptr && nb <= nrm->cap;
+    hipLaunchKernelGGL(k_split_sum<T>, dim3((unsigned)nb), dim3(256), 0, s, M, N, ks, work, C, ldc,
+                       fuse ? nrm->partial : nullptr);
+    if (fuse) *nparts = (int)nb;
   }
   return hipGetLastError();
 }
@@ -286,13 +303,13 @@ hipError_t launch_scatter_dense_t(hipStream_t s, int n, const int32_t* colptr, c
 
 #define SVT_GEMM_INST(T)                                                                                       \
   template hipError_t launch_gemm_nn<T, T>(hipStream_t, int, int, int, const T*, int, const T*, int, T*, int,   \
-                                           int, T*, int64_t);                                                   \
+                                           int, T*, int64_t, const NormReq*, int*);                             \
   template hipError_t launch_scatter_dense_t<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*, T*, \
                                                 int64_t);
 
 SVT_GEMM_INST(double)
 SVT_GEMM_INST(float)
 template hipError_t launch_gemm_nn<float, bf16>(hipStream_t, int, int, int, const float*, int, const bf16*, int, float*,
-                                                int, int, float*, int64_t);
+                                                int, int, float*, int64_t, const NormReq*, int*);
 
 }  // namespace svt

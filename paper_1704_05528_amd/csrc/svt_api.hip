@@ -445,11 +445,15 @@ struct Engine {
   // out = Y^T D: a matrix-core product with the dense copy of Y when at least a quarter of the
   // entries are observed and D has 32 columns or more (the copy is written by the update that
   // produced Y, or refreshed at the start of the R4SVD call), else the CSC gather kernel
+  // With nrm, a product on the dense copy that is split over K also leaves the partial sums of squares
+  // of out (NormReq; *nparts of them, 0 if it did not).
   template <class TD>
-  svt_status spmm_yt(const TD* D, int ldd, T* out, int ldo, int w) {
+  svt_status spmm_yt(const TD* D, int ldd, T* out, int ldo, int w, const NormReq* nrm = nullptr,
+                     int* nparts = nullptr) {
+    if (nparts) *nparts = 0;
     if (h->yT && w >= 32) {  // narrow blocks stay on the sparse kernel (too few output tiles)
       HIPCHK(launch_gemm_nn<T>(h->stream, (int)h->n, w, (int)h->m, (const T*)h->yT, (int)h->m, D, ldd, out, ldo, 0,
-                               (T*)h->kpart, kKPartElems * (int64_t)(sizeof(double) / sizeof(T))));
+                               (T*)h->kpart, kKPartElems * (int64_t)(sizeof(double) / sizeof(T)), nrm, nparts));
       return SVT_OK;
     }
     HIPCHK(launch_seg_spmm<T>(h->stream, (int)h->n, h->colptr, h->rowidx, nullptr, y(), D, ldd, out, ldo, w,
@@ -617,9 +621,10 @@ struct Engine {
     HIPCHK(launch_scatter_dense_t<T>(h->stream, (int)h->n, h->colptr, h->rowidx, y(), (T*)h->yT, h->m));
     return SVT_OK;
   }
-  // W = Y^T Q[:, 0:r]
-  svt_status run_spmm_t() {
-    if (h->yT && h->r >= 32) return spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r);
+  // W = Y^T Q[:, 0:r] (with nrm, possibly also the partial sums of squares of W: see spmm_yt)
+  svt_status run_spmm_t(const NormReq* nrm = nullptr, int* nparts = nullptr) {
+    if (nparts) *nparts = 0;
+    if (h->yT && h->r >= 32) return spmm_yt(Q(), h->r_cap, W(), h->r_cap, h->r, nrm, nparts);
     if (h->tstart) {
       HIPCHK(launch_spmm_t_tiled<T>(h->stream, (int)h->m, (int)h->n, h->rowidx, h->tstart, y(), Q(), h->r_cap, h->r,
                                     W(), h->r_cap, h->partial, h->partial_cap));
@@ -1250,9 +1255,11 @@ struct Engine {
   // copy of this Y.
   svt_status lead_work() {
     hipStream_t s = h->stream;
+    int nparts = 0;  // partial sums of squares of W left by the product (0: none)
     {
       PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
-      CHK(run_spmm_t());
+      const NormReq nr{h->partial, h->partial_cap};
+      CHK(run_spmm_t(kBF16 ? nullptr : &nr, &nparts));
     }
     if constexpr (kBF16) {
       PhaseTimer tm(h, SVT_PH_GRAM, work_bytes(SVT_PH_GRAM), work_flops(SVT_PH_GRAM));
@@ -1263,7 +1270,10 @@ struct Engine {
       // ||W||^2 and its post to the host in one launch sequence
       PhaseTimer tm(h, SVT_PH_REDUCE);
       const PostReq pr{h->scal + S_NORMB, 1, h->hscal_d + kSpecSlot, h->hflag_d, ++h->post_seq};
-      HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB, &pr));
+      if (nparts > 0)  // the product's partials: only their sum and the post remain
+        HIPCHK(launch_finish(s, h->partial, nparts, 1, 1, h->scal, S_NORMB, &pr));
+      else
+        HIPCHK(launch_sumsq_cols<T>(s, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB, &pr));
       h->spec_seq = pr.seq;
       return SVT_OK;
     }

@@ -344,13 +344,23 @@ template <class TA, class TB>
 hipError_t launch_tn_narrow(hipStream_t s, int rows, const TA* A, int lda, int na, const TB* B, int ldb, int nb,
                             double* out, int ldo, double* partial, int64_t partial_cap);
 
+// The sum of squares of a product's output, taken by the kernel that writes it as per-workgroup
+// partials: partial[0..*nparts) (at most cap of them), to be added by launch_finish.
+struct NormReq {
+  double* partial = nullptr;
+  int64_t cap = 0;
+};
+
 // dense C = A B (row-major) on the matrix cores in the storage precision (float or double accumulation);
 // B may be stored in bfloat16 for float (widened on load).  tri = 1: A is lower triangular, tri = 2: B is
 // upper triangular (the zero parts are not read).  With a workspace of work_elems elements a product
 // with few output tiles is also split over K (partial products there, then added in a fixed order).
+// With nrm, a product split over K also leaves the partial sums of squares of C (see NormReq) from the
+// kernel that adds the parts, and *nparts is their count (0 when it did not: the caller takes them).
 template <class T, class TB>
 hipError_t launch_gemm_nn(hipStream_t s, int M, int N, int K, const T* A, int lda, const TB* B, int ldb, T* C, int ldc,
-                          int tri = 0, T* work = nullptr, int64_t work_elems = 0);
+                          int tri = 0, T* work = nullptr, int64_t work_elems = 0, const NormReq* nrm = nullptr,
+                          int* nparts = nullptr);
 // G = A^T A (A rows x na row-major, G na x na double) from 64 x 64 tiles staged in LDS on the
 // matrix cores; gram_tn_tiles(na) is the number of workgroups it launches.  launch_gram takes it
 // from rows * na >= kGramTiledMin on.
