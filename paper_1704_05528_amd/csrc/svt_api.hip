@@ -722,9 +722,11 @@ struct Engine {
       normB = add;
       h->gp_now = false;
     } else {
+      int nparts = 0;  // partial sums of squares of W left by the product (0: none), as in lead_work
       {
         PhaseTimer tm(h, SVT_PH_SPMM_T, work_bytes(SVT_PH_SPMM_T), work_flops(SVT_PH_SPMM_T));
-        CHK(run_spmm_t());
+        const NormReq nr{h->partial, h->partial_cap};
+        CHK(run_spmm_t(kBF16 ? nullptr : &nr, &nparts));
       }
       if constexpr (kBF16) {
         // ||B_o||_F^2 = trace(Linv W^T W Linv^T): the corrected Gram, kept for the projected SVD
@@ -733,8 +735,13 @@ struct Engine {
         CHK(correct_gram(h->r, S_NORMB));
         h->gp_now = true;
       } else {
+        // the same sums in the same order as the leading work's, so that a restored or replayed
+        // iteration reproduces the value bit for bit
         PhaseTimer tm(h, SVT_PH_REDUCE);
-        HIPCHK(launch_sumsq_cols<T>(h->stream, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
+        if (nparts > 0)
+          HIPCHK(launch_finish(h->stream, h->partial, nparts, 1, 1, h->scal, S_NORMB));
+        else
+          HIPCHK(launch_sumsq_cols<T>(h->stream, (int)h->n, W(), h->r_cap, 0, h->r, h->partial, h->scal, S_NORMB));
       }
       CHK(readback(h, S_NORMB + 1));
       normB = h->hscal[S_NORMB];
