@@ -502,32 +502,50 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
   const int RP = (r + 15) & ~15, RT = RP / 16;
   const int kl = lane >> 4, cl = lane & 15;
 
-  // G in batches of eight loads per thread in flight (clamped, valid addresses; masked on store)
-  for (int e0 = 0; e0 < RP * RP; e0 += 8 * kSmallThreads) {
-    double gv[8];
+  // G in batches of eight loads per thread in flight (clamped, valid addresses; masked on store).  The
+  // start block is drawn while the first batch is in flight: the kept columns (rows past ev_rows
+  // zero) and Gaussian columns valid .. b-1, one Philox draw per row and group of four columns
+  // (element (i, c) is z[c % 4] of the draw for (i, c / 4), as in k_fill_random).
+  static_assert(kSmallR * (kSmallB / 4) <= kSmallThreads, "one group of four columns per thread");
+  auto load_g = [&](int e0, double* gv) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + tid + u * kSmallThreads, i = e / RP, k = e - (e / RP) * RP;
       gv[u] = G[(int64_t)min(i, r - 1) * ldg + min(k, r - 1)];
     }
+  };
+  auto store_g = [&](int e0, const double* gv) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + tid + u * kSmallThreads, i = e / RP, k = e - (e / RP) * RP;
       if (e < RP * RP) Gs[i * kSGL + k] = (i < r && k < r) ? gv[u] : 0.0;
     }
-  }
-  // the start block: the kept columns (rows past ev_rows zero) and Gaussian columns valid .. b-1
-  for (int e = tid; e < RP * kSmallB; e += kSmallThreads) {
-    const int i = e / kSmallB, c = e % kSmallB;
-    double v = 0.0;
-    if (i < r && c < valid) {
-      v = (i < ev_rows) ? EV[(int64_t)i * ldv + c] : 0.0;
-    } else if (i < r && c < b) {
-      double z[4];
-      gaussian4((uint64_t)i, (uint64_t)c, tag, 0xFFFFFFFFull, seed, z);
-      v = z[0];
+  };
+  {
+    double gv[8];
+    load_g(0, gv);
+    if (tid < RP * (kSmallB / 4)) {
+      const int i = tid / (kSmallB / 4), c0 = 4 * (tid % (kSmallB / 4));
+      double z[4] = {0.0, 0.0, 0.0, 0.0};
+      if (i < r && c0 + 3 >= valid && c0 < b)  // a Gaussian column in this group
+        gaussian4((uint64_t)i, (uint64_t)(c0 / 4), tag, 0xFFFFFFFFull, seed, z);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u;
+        double v = 0.0;
+        if (i < r && c < valid)
+          v = (i < ev_rows) ? EV[(int64_t)i * ldv + c] : 0.0;
+        else if (i < r && c < b)
+          v = z[u];
+        Vs[i * kSmallB + c] = v;
+      }
     }
-    Vs[e] = v;
+    store_g(0, gv);
+  }
+  for (int e0 = 8 * kSmallThreads; e0 < RP * RP; e0 += 8 * kSmallThreads) {
+    double gv[8];
+    load_g(e0, gv);
+    store_g(e0, gv);
   }
   __syncthreads();
 

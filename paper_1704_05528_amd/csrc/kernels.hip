@@ -56,15 +56,16 @@ __global__ void k_omega(T* __restrict__ om, int n, int c0, int w, int ld, uint64
     if (4 * g + l < w) om[(int64_t)j * ld + 4 * g + l] = (T)z[l];
 }
 
-// Gaussian fill of columns [c0, c1) of a rows x ld block (eigensolver start vectors).
+// Gaussian fill of columns [c0, c1) of a rows x ld block (eigensolver start vectors): element (i, c)
+// is z[c % 4] of the Philox draw for row i and column group c / 4.
 __global__ void k_fill_random(double* __restrict__ V, int rows, int ld, int c0, int c1, uint64_t seed, uint64_t tag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = c1 - c0;
   if (t >= (int64_t)rows * w) return;
   const int i = (int)(t / w), c = c0 + (int)(t % w);
   double z[4];
-  gaussian4((uint64_t)i, (uint64_t)c, tag, 0xFFFFFFFFull, seed, z);
-  V[(int64_t)i * ld + c] = z[0];
+  gaussian4((uint64_t)i, (uint64_t)(c / 4), tag, 0xFFFFFFFFull, seed, z);
+  V[(int64_t)i * ld + c] = z[c % 4];
 }
 
 // columns c0 .. c0+count-1 of a rows x ld block set to the unit vectors e_{row0}, e_{row0+1}, ...
