@@ -645,13 +645,34 @@ __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double
       double z[NB];
 #pragma unroll
       for (int c = 0; c < NB; ++c) z[c] = Zs[tid * kSmallB + c];
+      if constexpr (NB <= 8) {
+        // every entry of R and every 1 / R[c][c] in registers first (all of them written, zeros past b),
+        // so the substitution chain waits on no LDS load; past b it leaves the zero columns zero
+        double rr[NB * (NB - 1) / 2 + 1], ri[NB];
+        int t = 0;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (c < b) {
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int l = 0; l < c; ++l) rr[t++] = Cg[l * kJL + c];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) ri[c] = rinv[c];
+        t = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
           double v = z[c];
 #pragma unroll
-          for (int l = 0; l < c; ++l) v = fma(-z[l], Cg[l * kJL + c], v);
-          z[c] = v * rinv[c];
+          for (int l = 0; l < c; ++l) v = fma(-z[l], rr[t++], v);
+          z[c] = v * ri[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c < b) {
+            double v = z[c];
+#pragma unroll
+            for (int l = 0; l < c; ++l) v = fma(-z[l], Cg[l * kJL + c], v);
+            z[c] = v * rinv[c];
+          }
         }
       }
       const unsigned keep = (unsigned)keepm[0];
