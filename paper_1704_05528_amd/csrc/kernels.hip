@@ -1135,8 +1135,9 @@ __device__ inline double dot16(Vec16<double>::type a, Vec16<double>::type b, dou
 // one wave.  Vt[j, :] is staged in LDS.  The dot product and the update run in T; the sums
 // accumulate in double.  With yT set, y_next also goes to the dense transposed copy of the
 // iterate (yT[j * ldy + i]), which the next R4SVD call's products then read as they are.
+// KB (1, 2, 4 or 8) is the batch of factor vectors per row whose loads are in flight together.
 // ------------------------------------------------------------------------------------------
-template <class T>
+template <class T, int KB>
 __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t* __restrict__ cstart,
                                                       const int32_t* __restrict__ ccol,
                                                       const int32_t* __restrict__ rowidx, const T* __restrict__ a,
@@ -1174,6 +1175,29 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
     s_y = fma((double)yn, (double)yn, s_y);
     s_abs += fabs((double)res);
   };
+  // The factor rows go in batches of kB vectors with every load of a batch in flight before its
+  // products: indices past kv are clamped to the row's last vector (a valid address) and meet a zero
+  // vector of Vt, so the products and their order are those of the plain loop over kv.  (A loop over
+  // kv unrolled by the compiler took one memory round trip per vector below its unroll width.)
+  constexpr int kB = KB;
+  const V vzero = {};
+  auto dots = [&](const V* u0, const V* u1, T& x0, T& x1, bool two) {
+    for (int l0 = 0; l0 < kv; l0 += kB) {
+      V a0[kB], a1[kB], bv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int l = min(l0 + u, kv - 1);
+        a0[u] = u0[l];
+        if (two) a1[u] = u1[l];  // uniform
+        bv[u] = (l0 + u < kv) ? vv[l] : vzero;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        x0 = dot16(a0[u], bv[u], x0);
+        if (two) x1 = dot16(a1[u], bv[u], x1);
+      }
+    }
+  };
   // two entries per lane and step: both factor rows are in flight before the products
   int p = p0 + lane;
   for (; p + kWave < p1; p += 2 * kWave) {
@@ -1181,19 +1205,15 @@ __global__ __launch_bounds__(256) void k_sddmm_update(int nchunks, const int32_t
     const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)i0 * ld);
     const V* u1 = reinterpret_cast<const V*>(Ut + (int64_t)i1 * ld);
     T x0 = (T)0, x1 = (T)0;
-    for (int l = 0; l < kv; ++l) {
-      const V a0 = u0[l], a1 = u1[l], b = vv[l];
-      x0 = dot16(a0, b, x0);
-      x1 = dot16(a1, b, x1);
-    }
+    dots(u0, u1, x0, x1, true);
     update(p, i0, x0);
     update(p + kWave, i1, x1);
   }
   if (p < p1) {
     const int i0 = rowidx[p];
     const V* u0 = reinterpret_cast<const V*>(Ut + (int64_t)i0 * ld);
-    T x0 = (T)0;
-    for (int l = 0; l < kv; ++l) x0 = dot16(u0[l], vv[l], x0);
+    T x0 = (T)0, x1 = (T)0;
+    dots(u0, u0, x0, x1, false);
     update(p, i0, x0);
   }
   const double t0 = block_sum(s_res, lds);
@@ -1615,20 +1635,24 @@ hipError_t launch_sddmm_update(hipStream_t s, int nchunks, const int32_t* cstart
   const int nb = std::max(1, (nchunks + 3) / 4);
   *nblocks = nb;
   constexpr int E = (int)(16 / sizeof(T));
-  const size_t lds = (size_t)4 * ((std::max(k, 1) + E - 1) / E) * E * sizeof(T);
-  if (lds > 64 * 1024) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      const hipError_t e = hipFuncSetAttribute((const void*)k_sddmm_update<T>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+  const int kv = (std::max(k, 1) + E - 1) / E;
+  const size_t lds = (size_t)4 * kv * E * sizeof(T);
+  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  // the batch: the factor row's vectors up to eight, no loads beyond them for short rows
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024 - 1024);
       if (e != hipSuccess) return e;
-      attr_set = true;
     }
-    if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
-  }
-  hipLaunchKernelGGL(k_sddmm_update<T>, dim3(nb), dim3(256), lds, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut,
-                     Vt, ld, k, (T)delta, partial, yT, ldy);
-  return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), lds, s, nchunks, cstart, ccol, rowidx, a, y, y_next, Ut, Vt, ld, k,
+                       (T)delta, partial, yT, ldy);
+    return hipGetLastError();
+  };
+  if (kv <= 1) return go(k_sddmm_update<T, 1>);
+  if (kv <= 2) return go(k_sddmm_update<T, 2>);
+  if (kv <= 4) return go(k_sddmm_update<T, 4>);
+  return go(k_sddmm_update<T, 8>);
 }
 
 hipError_t launch_absdiff_sum(hipStream_t s, int64_t len, const double* x, const double* ref, double* partial,
