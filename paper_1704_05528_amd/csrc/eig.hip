@@ -815,13 +815,19 @@ __global__ __launch_bounds__(256) void k_ritz_residual(int rows, const double* _
   if (threadIdx.x == 0) out[c] = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
 }
 
-// C[:, c] = S[:, c] (sigma_c - tau), D[:, c] = S[:, c] / sigma_c, sigma_c = sqrt(theta_c), c < k.
-__global__ void k_factor_coeffs(int r, int k, const double* __restrict__ S, int lds_, const double* __restrict__ theta,
-                                double tau, double* __restrict__ C, double* __restrict__ D, int ldc,
-                                double* __restrict__ Sk) {
+// C[:, c] = S[:, c] (sigma_c - tau), D[:, c] = S[:, c] / sigma_c, sigma_c = sqrt(theta_c), c < k; zeros for
+// k <= c < kpad.
+__global__ void k_factor_coeffs(int r, int k, int kpad, const double* __restrict__ S, int lds_,
+                                const double* __restrict__ theta, double tau, double* __restrict__ C,
+                                double* __restrict__ D, int ldc, double* __restrict__ Sk) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)r * k) return;
-  const int i = (int)(t / k), c = (int)(t % k);
+  if (t >= (int64_t)r * kpad) return;
+  const int i = (int)(t / kpad), c = (int)(t % kpad);
+  if (c >= k) {
+    C[(int64_t)i * ldc + c] = 0.0;
+    D[(int64_t)i * ldc + c] = 0.0;
+    return;
+  }
   const double sg = sqrt(theta[c]);
   const double v = S[(int64_t)i * lds_ + c];
   C[(int64_t)i * ldc + c] = v * (sg - tau);
@@ -993,11 +999,13 @@ hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const 
 }
 
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds_, const double* theta,
-                                double tau, double* C, double* D, int ldc, double* Sk) {
-  const int64_t work = (int64_t)r * k;
+                                double tau, double* C, double* D, int ldc, double* Sk, int kpad) {
+  kpad = std::max(kpad, k);
+  if (kpad > ldc) return hipErrorInvalidValue;
+  const int64_t work = (int64_t)r * kpad;
   if (work == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_factor_coeffs, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, r, k, S, lds_, theta,
-                     tau, C, D, ldc, Sk);
+  hipLaunchKernelGGL(k_factor_coeffs, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, r, k, kpad, S, lds_,
+                     theta, tau, C, D, ldc, Sk);
   return hipGetLastError();
 }
 

@@ -309,6 +309,13 @@ struct Engine {
   T* Om() const { return (T*)h->Om; }
   T* Ut() const { return (T*)h->Ut; }
   T* Vt() const { return (T*)h->Vt; }
+  // Row stride of Ut and Vt: the count k rounded up to a 128-byte line (columns k .. ldu-1 hold zeros),
+  // not ldf, so that the factor rows the fused update gathers lie close together however large kmax
+  // is, and each starts a line (the update loads a row in 128-byte batches).
+  int ldu() const {
+    constexpr int L = (int)(128 / sizeof(T));
+    return std::min(h->ldf, std::max(L, (h->k + L - 1) / L * L));
+  }
   T* Utmp() const { return (T*)h->Utmp; }
   static constexpr double es = (double)sizeof(T);
 
@@ -641,7 +648,7 @@ struct Engine {
   // y_next also goes to the dense copy yT (which then no longer holds y)
   svt_status run_sddmm(int* nbl) {
     HIPCHK(launch_sddmm_update<T>(h->stream, h->nchunks, h->cstart, h->ccol, h->rowidx, a(), y(), y_next(), Ut(), Vt(),
-                                  h->ldf, h->k, h->p.delta, h->partial, nbl, (T*)h->yT, h->m));
+                                  ldu(), h->k, h->p.delta, h->partial, nbl, (T*)h->yT, h->m));
     return SVT_OK;
   }
   double work_bytes(int ph) const {
@@ -1199,18 +1206,20 @@ struct Engine {
         // kept eigenvectors taken from the left by Linv^T once, then scaled into C and D as below
         HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->LinvT, h->r_cap, S, lds_, h->Sk, h->ldf, k, 1.0,
                                                       0.0)));
-        HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf));
+        HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf, nullptr, ldu()));
       } else {
-        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf, h->Sk));
+        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf, h->Sk, ldu()));
       }
+      // the factors with row stride ldu(), their columns k .. ldu-1 the products with zero columns of C, D
+      const int kp = ldu();
       if constexpr (kBF16) {
-        HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0, 0.0)));
-        HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), kp, kp, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), kp, kp, 1.0, 0.0)));
       } else {
         // Ut = Q C and Vt = W D side by side in one launch
-        const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), h->ldf, k, 1.0,
+        const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), kp, kp, 1.0,
                                              0.0, nullptr};
-        const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), h->ldf, k, 1.0,
+        const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), kp, kp, 1.0,
                                              0.0, nullptr};
         HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
       }
@@ -1504,8 +1513,8 @@ struct Engine {
       if (!save) HIPCHK(launch_transpose(h->stream, h->FEt, h->r_cap, h->fe_rows, h->fe_rows, h->FEU, h->r_cap));
     }
     if (h->have_factors && h->k > 0) {
-      CHK(copy_rows<T>(save, blob, pos, Ut(), h->m, h->k, h->ldf));
-      CHK(copy_rows<T>(save, blob, pos, Vt(), h->n, h->k, h->ldf));
+      CHK(copy_rows<T>(save, blob, pos, Ut(), h->m, ldu(), ldu()));
+      CHK(copy_rows<T>(save, blob, pos, Vt(), h->n, ldu(), ldu()));
       CHK(copy_rows<double>(save, blob, pos, h->Sk, h->r, h->k, h->ldf));
     }
     CHK(wait_stream(h));
@@ -1520,7 +1529,7 @@ struct Engine {
                                             kk, 1.0, 0.0)));
         HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->m, Utmp(), h->ldf, U, kcap, kk)));
       }
-      if (V) HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->n, Vt(), h->ldf, V, kcap, kk)));
+      if (V) HIPCHK((launch_copy_cols<T, double>(h->stream, (int)h->n, Vt(), ldu(), V, kcap, kk)));
       return SVT_OK;
     }
     if (U) {
@@ -1532,16 +1541,17 @@ struct Engine {
         for (int c = 0; c < kk; ++c) U[i * kcap + c] = (double)buf[i * h->ldf + c];
     }
     if (V) {
-      buf.resize((size_t)h->n * h->ldf);
+      const int lu = ldu();
+      buf.resize((size_t)h->n * lu);
       CHK(to_host<T>(h, buf.data(), Vt(), buf.size()));
       for (int64_t j = 0; j < h->n; ++j)
-        for (int c = 0; c < kk; ++c) V[j * kcap + c] = (double)buf[j * h->ldf + c];
+        for (int c = 0; c < kk; ++c) V[j * kcap + c] = (double)buf[j * lu + c];
     }
     return SVT_OK;
   }
 
   svt_status sample(int64_t nq, const int32_t* di, const int32_t* dj, double* dx) {
-    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), h->ldf, h->k, h->m, h->n, dx));
+    HIPCHK(launch_sample<T>(h->stream, nq, di, dj, Ut(), Vt(), ldu(), h->k, h->m, h->n, dx));
     return SVT_OK;
   }
 
@@ -2494,7 +2504,7 @@ svt_status svt_mae_device(svt_handle* h, int64_t nq, const int32_t* qi, const in
   if (!h->have_factors) return fail(h, SVT_E_STATE, "no factors yet: run an iteration first");
   if (!h->scratch) return fail(h, SVT_E_STATE, "the device scratch address is not set");
   return dispatch(h, [&](auto& eng) -> svt_status {
-    HIPCHK(launch_mae_fused(h->stream, nq, qi, qj, eng.Ut(), eng.Vt(), h->ldf, h->k, h->m, h->n, ref, h->scratch,
+    HIPCHK(launch_mae_fused(h->stream, nq, qi, qj, eng.Ut(), eng.Vt(), eng.ldu(), h->k, h->m, h->n, ref, h->scratch,
                             mae));
     return SVT_OK;
   });

@@ -509,9 +509,10 @@ hipError_t launch_jacobi(hipStream_t s, const double* H, int ldh, int b, double*
 // residual column norms ||Z[:, c] - theta_c V[:, c]|| for c < b
 hipError_t launch_ritz_residual(hipStream_t s, int rows, const double* Z, const double* V, int ld, int b,
                                 const double* theta, double* partial, double* out);
-// factor matrices C = S[:, :k] diag(sigma - tau), D = S[:, :k] diag(1/sigma) from eigenpairs of the Gram
+// factor matrices C = S[:, :k] diag(sigma - tau), D = S[:, :k] diag(1/sigma) from eigenpairs of the Gram,
+// and zeros in their columns k .. kpad-1 (kpad >= k; 0 means k)
 hipError_t launch_factor_coeffs(hipStream_t s, int r, int k, const double* S, int lds, const double* theta,
-                                double tau, double* C, double* D, int ldc, double* Sk = nullptr);
+                                double tau, double* C, double* D, int ldc, double* Sk = nullptr, int kpad = 0);
 
 // ---------------------------------------------------------------------------------------------
 // full eigen-decomposition (eigfull.hip), double: cyclic Jacobi over many workgroups, one launch
