@@ -316,6 +316,12 @@ struct Engine {
     constexpr int L = (int)(128 / sizeof(T));
     return std::min(h->ldf, std::max(L, (h->k + L - 1) / L * L));
   }
+  // Columns of Ut and Vt that are written: k rounded up to a 16-byte vector, the columns the fused
+  // update reads (those past k zero); the rest of each ldu() row is never read.
+  int kvec() const {
+    constexpr int E = (int)(16 / sizeof(T));
+    return std::min(ldu(), std::max(E, (h->k + E - 1) / E * E));
+  }
   T* Utmp() const { return (T*)h->Utmp; }
   static constexpr double es = (double)sizeof(T);
 
@@ -1206,20 +1212,20 @@ struct Engine {
         // kept eigenvectors taken from the left by Linv^T once, then scaled into C and D as below
         HIPCHK((launch_rowmul<double, double, double>(s, r, r, h->LinvT, h->r_cap, S, lds_, h->Sk, h->ldf, k, 1.0,
                                                       0.0)));
-        HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf, nullptr, ldu()));
+        HIPCHK(launch_factor_coeffs(s, r, k, h->Sk, h->ldf, dtheta, h->p.tau, h->C, h->D, h->ldf, nullptr, kvec()));
       } else {
-        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf, h->Sk, ldu()));
+        HIPCHK(launch_factor_coeffs(s, r, k, S, lds_, dtheta, h->p.tau, h->C, h->D, h->ldf, h->Sk, kvec()));
       }
-      // the factors with row stride ldu(), their columns k .. ldu-1 the products with zero columns of C, D
-      const int kp = ldu();
+      // the factors with row stride ldu(): columns k .. kvec()-1 are the products with zero columns of C, D
+      const int lu = ldu(), kw = kvec();
       if constexpr (kBF16) {
-        HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), kp, kp, 1.0, 0.0)));
-        HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), kp, kp, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<TQ, double, T>(s, (int)h->m, r, Q(), h->r_cap, h->C, h->ldf, Ut(), lu, kw, 1.0, 0.0)));
+        HIPCHK((launch_rowmul<T, double, T>(s, (int)h->n, r, W(), h->r_cap, h->D, h->ldf, Vt(), lu, kw, 1.0, 0.0)));
       } else {
         // Ut = Q C and Vt = W D side by side in one launch
-        const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), kp, kp, 1.0,
+        const RowmulProblem<T, double, T> pu{(int)h->m, r, Q(), (int)h->r_cap, h->C, h->ldf, Ut(), lu, kw, 1.0,
                                              0.0, nullptr};
-        const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), kp, kp, 1.0,
+        const RowmulProblem<T, double, T> pv{(int)h->n, r, W(), (int)h->r_cap, h->D, h->ldf, Vt(), lu, kw, 1.0,
                                              0.0, nullptr};
         HIPCHK((launch_rowmul_pair<T, double, T>(s, pu, pv)));
       }
@@ -1513,8 +1519,8 @@ struct Engine {
       if (!save) HIPCHK(launch_transpose(h->stream, h->FEt, h->r_cap, h->fe_rows, h->fe_rows, h->FEU, h->r_cap));
     }
     if (h->have_factors && h->k > 0) {
-      CHK(copy_rows<T>(save, blob, pos, Ut(), h->m, ldu(), ldu()));
-      CHK(copy_rows<T>(save, blob, pos, Vt(), h->n, ldu(), ldu()));
+      CHK(copy_rows<T>(save, blob, pos, Ut(), h->m, kvec(), ldu()));
+      CHK(copy_rows<T>(save, blob, pos, Vt(), h->n, kvec(), ldu()));
       CHK(copy_rows<double>(save, blob, pos, h->Sk, h->r, h->k, h->ldf));
     }
     CHK(wait_stream(h));
