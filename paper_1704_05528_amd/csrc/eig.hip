@@ -477,7 +477,7 @@ constexpr int kSmallThreads = 512;
 constexpr int kSGL = kSmallR + 1;  // row stride of G in LDS (odd: the A operand's 16 rows fall on distinct banks)
 constexpr int kJL = kSmallB + 1;   // row stride of the b x b blocks
 
-// NB (8 or 16, at least b) sizes the register arrays of the Cholesky factorisation and of the row
+// NB (8, 12 or 16, at least b) sizes the register arrays of the Cholesky factorisation and of the row
 // solve; the LDS layout keeps 16 columns for the matrix-core tiles either way.
 template <int NB>
 __global__ __launch_bounds__(kSmallThreads) void k_eig_small(int r, const double* __restrict__ G, int ldg,
@@ -977,7 +977,8 @@ hipError_t launch_eig_small(hipStream_t s, int r, const double* G, int ldg, doub
                             double* scal, int slot, int max_sweeps, int valid, int ev_rows, uint64_t seed,
                             uint64_t tag, double* post_dst, unsigned* post_flag, unsigned post_seq) {
   if (r <= 0 || r > kSmallR || b <= 0 || b > kSmallB || b > r || npairs < 1 || valid < 0 || valid > b) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(b <= 8 ? k_eig_small<8> : k_eig_small<kSmallB>, dim3(1), dim3(kSmallThreads), 0, s, r, G, ldg, EV,
+  hipLaunchKernelGGL(b <= 8 ? k_eig_small<8> : b <= 12 ? k_eig_small<12> : k_eig_small<kSmallB>, dim3(1),
+                     dim3(kSmallThreads), 0, s, r, G, ldg, EV,
                      GV, ldv, b, npairs, filt ? 1 : 0, alpha, beta, dep_tol, eval, ldres, scal, slot, max_sweeps, valid,
                      ev_rows, seed, tag, post_dst, post_flag, post_seq);
   return hipGetLastError();
