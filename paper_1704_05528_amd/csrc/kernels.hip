@@ -394,6 +394,73 @@ __device__ inline dbl4 reduce_waves(dbl4 acc, double (*red)[kWave][4]) {
 }
 
 // ------------------------------------------------------------------------------------------
+// The same product for tall operands with many tiles (the factor products of a large problem): a
+// workgroup of four waves takes 64 rows x 32 columns, wave v the rows 16 v .. 16 v + 15 over the
+// whole K range (no reduction) and both 16-column tiles, which share its loads of A; the four waves
+// read the same slices of M at about the same time, mostly from L1.  One 16 x 16 tile per workgroup
+// re-read its slice of M per 16 rows and the rows of A per 16 columns (about 50 GB from L2 for the
+// factors of a 150000-row problem at r = 4096, k = 105).  No Gram epilogue.
+// ------------------------------------------------------------------------------------------
+constexpr int kTallRows = 64, kTallCols = 32;
+
+template <class TA, class TM, class TO>
+__global__ __launch_bounds__(4 * kWave) void k_rowmul_tall(RowmulProblem<TA, TM, TO> pr0,
+                                                          RowmulProblem<TA, TM, TO> pr1) {
+  const RowmulProblem<TA, TM, TO>& pr = blockIdx.z == 0 ? pr0 : pr1;
+  const int rows = pr.rows, K = pr.K, lda = pr.lda, ldm = pr.ldm, ldo = pr.ldo, w = pr.w;
+  const TA* __restrict__ A = pr.A;
+  const TM* __restrict__ M = pr.M;
+  TO* __restrict__ out = pr.out;
+  const double alpha = pr.alpha, beta = pr.beta;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int i0 = blockIdx.x * kTallRows + 16 * wv, j0 = blockIdx.y * kTallCols;
+  if (i0 >= rows || j0 >= w) return;  // uniform over the wave; the waves share no barrier
+  const int ia = i0 + (lane & 15), jb0 = j0 + (lane & 15), jb1 = jb0 + 16, kl = lane >> 4;
+  const bool rowok = ia < rows, c0ok = jb0 < w, c1ok = jb1 < w;
+  // out-of-range operands are loaded from a clamped, valid address and replaced by zero
+  const TA* arow = A + (int64_t)min(ia, rows - 1) * lda;
+  const TM* mc0 = M + min(jb0, w - 1);
+  const TM* mc1 = M + min(jb1, w - 1);
+  const int steps = (K + 3) / 4;
+  dbl4 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a10 = a00, a11 = a00;
+  for (int st = 0; st < steps; st += kUnroll) {
+    TA ar[kUnroll];
+    TM b0[kUnroll], b1[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int kc = min((st + u) * 4 + kl, K - 1);
+      ar[u] = arow[kc];
+      b0[u] = mc0[(int64_t)kc * ldm];
+      b1[u] = mc1[(int64_t)kc * ldm];
+    }
+    double a[kUnroll], x0[kUnroll], x1[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool ok = (st + u < steps) && ((st + u) * 4 + kl < K);
+      a[u] = (rowok && ok) ? (double)ar[u] : 0.0;
+      x0[u] = (c0ok && ok) ? (double)b0[u] : 0.0;
+      x1[u] = (c1ok && ok) ? (double)b1[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u += 2) {
+      a00 = mfma_f64_16x16x4(a[u], x0[u], a00);
+      a01 = mfma_f64_16x16x4(a[u + 1], x0[u + 1], a01);
+      a10 = mfma_f64_16x16x4(a[u], x1[u], a10);
+      a11 = mfma_f64_16x16x4(a[u + 1], x1[u + 1], a11);
+    }
+  }
+  const dbl4 acc0 = a00 + a01, acc1 = a10 + a11;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = i0 + (lane >> 4) + 4 * v;
+    if (row >= rows) continue;
+    TO* o = out + (int64_t)row * ldo;
+    if (c0ok) o[jb0] = (TO)((beta == 0.0 ? 0.0 : beta * (double)o[jb0]) + alpha * acc0[v]);
+    if (c1ok) o[jb1] = (TO)((beta == 0.0 ? 0.0 : beta * (double)o[jb1]) + alpha * acc1[v]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Row-times-matrix product out[i, :] = beta out[i, :] + alpha A[i, 0:K] M[0:K, :] on the FP64
 // matrix cores: one 16 x 16 output tile per workgroup, the NW waves take contiguous slices of the
 // K steps and their accumulators are added in LDS in wave order.  NW = 16 when there are fewer
@@ -1409,6 +1476,9 @@ hipError_t launch_spmm_t_tiled(hipStream_t s, int m, int n, const int32_t* rowid
   return hipGetLastError();
 }
 
+// 16 x 16 tiles from which a product runs as k_rowmul_tall
+constexpr unsigned kTallMinTiles = 2048;
+
 template <class TA, class TM, class TO>
 hipError_t launch_rowmul_pair(hipStream_t s, const RowmulProblem<TA, TM, TO>& p0, const RowmulProblem<TA, TM, TO>& p1) {
   const RowmulProblem<TA, TM, TO>* pp[2] = {&p0, &p1};
@@ -1422,6 +1492,15 @@ hipError_t launch_rowmul_pair(hipStream_t s, const RowmulProblem<TA, TM, TO>& p0
     tiles += x * y;
   }
   if (tiles == 0) return hipSuccess;
+  if (tiles >= kTallMinTiles && p0.gpart == nullptr && p1.gpart == nullptr) {
+    unsigned tx = 0, ty = 0;
+    for (const auto* p : pp) {
+      tx = std::max(tx, (unsigned)((p->rows + kTallRows - 1) / kTallRows));
+      ty = std::max(ty, (unsigned)((p->w + kTallCols - 1) / kTallCols));
+    }
+    hipLaunchKernelGGL((k_rowmul_tall<TA, TM, TO>), dim3(tx, ty, 2), dim3(4 * kWave), 0, s, p0, p1);
+    return hipGetLastError();
+  }
   const dim3 grid(gx, gy, 2);
   if (tiles < 256)
     hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, p0, p1);
@@ -1439,6 +1518,11 @@ hipError_t launch_rowmul(hipStream_t s, int rows, int K, const TA* A, int lda, c
   RowmulProblem<TA, TM, TO> none = p;
   none.rows = 0;
   const dim3 grid((rows + 15) / 16, (w + 15) / 16, 1);
+  if (grid.x * grid.y >= kTallMinTiles && gpart == nullptr) {
+    hipLaunchKernelGGL((k_rowmul_tall<TA, TM, TO>), dim3((rows + kTallRows - 1) / kTallRows,
+                       (w + kTallCols - 1) / kTallCols, 1), dim3(4 * kWave), 0, s, p, none);
+    return hipGetLastError();
+  }
   if (grid.x * grid.y < 256)
     hipLaunchKernelGGL((k_rowmul<TA, TM, TO, 16>), grid, dim3(16 * kWave), 0, s, p, none);
   else

@@ -411,6 +411,21 @@ def test_image_workload_bench_configuration(gpu_lib):
         _compare_step(h.iterate(1), info, h, w, ("image", info.it))
 
 
+def test_tall_products_with_many_tiles(gpu_lib):
+    """40000 x 200 at 5% observed, rank 20: the factor products Q C over 40000 rows have more than
+    2048 16 x 16 tiles and run as the 64 x 32 workgroup variant (k_rowmul_tall); 8 iterations,
+    every step against the oracle."""
+    w = W.tiny_dense(40000, 200, 20, 0.05, seed=93)
+    prob = _problem(w)
+    p = Params(tau=w.tau, delta=w.delta, seed=93, maxit=8)
+    _, infos, k0 = svt_run(prob, p, keep_infos=True)
+    assert max(i.k for i in infos) >= 17  # two column tiles of the factors: 2500 x 2 tiles
+    h = _gpu(gpu_lib, w, k0, seed=93, maxit=8)
+    h.set_replay([i.blocks for i in infos], [int(i.annealed) for i in infos])
+    for info in infos:
+        _compare_step(h.iterate(1), info, h, w, ("tall", info.it))
+
+
 def test_ratings_workload_first_iterations(gpu_lib):
     """Recommendation shape (6040 x 3706, 900,188 power-law training entries, 4% observed: the
     gather kernels), tau and delta by the rule of Sec. 3, r_max = 1024: first 6 iterations,
